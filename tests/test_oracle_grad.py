@@ -1,0 +1,66 @@
+"""Pin for the oracle's analytic backward (render backward + preprocess
+backward through the conditional, the 4D rotor and the activations):
+central finite differences of the oracle's own FP64 forward, on a random
+linear loss L = sum(w * image), across all 20 parameter classes.
+
+A parameter is rejected (and counted) when the +-h perturbation changes any
+pixel's blend decisions (which entries blend, which clamp), since the
+forward is only piecewise smooth there.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_01119_amd import synth
+
+
+def _loss_and_sig(oracle_lib, p, views, w):
+    rec, rect, touched = oracle_lib.preprocess_f64(p, views)
+    dbits = oracle_lib.depth_bits(rec)
+    keys, vals, ranges = oracle_lib.bin_sort(rect, touched, dbits, views)
+    out = oracle_lib.render_fwd(rec, views, vals, ranges, signature=True)
+    return float((w * out["image"]).sum()), out["sig"]
+
+
+@pytest.mark.parametrize("seed,n_views", [(21, 1), (22, 2)])
+def test_backward_vs_central_differences(oracle_lib, seed, n_views):
+    n = 120
+    p = synth.small_set(n, seed=seed, log_s_xyz=(-2.0, 0.4), log_s_t=(-1.0, 0.3)).astype(np.float64)
+    p[3] = np.random.default_rng(seed).uniform(0.35, 0.65, n)
+    vs = np.stack([synth.front_view(48, 40, f=48.0, dist=3.0, t=0.45 + 0.1 * i)
+                   for i in range(n_views)])
+    w = synth.linear_loss_weights(n_views, 40, 48, seed=seed).astype(np.float64)
+    grad, _ = oracle_lib.backward(p, vs, w, precision="f64")
+    L0, sig0 = _loss_and_sig(oracle_lib, p, vs, w)
+    rec, _, touched = oracle_lib.preprocess_f64(p, vs)
+    vis = np.nonzero(touched.sum(axis=0) > 0)[0]
+    rng = np.random.default_rng(seed + 100)
+    h = 1e-6
+    checked, rejected = 0, 0
+    per_class = np.zeros(20, int)
+    for k in range(20):
+        gs = rng.choice(vis, size=6, replace=False)
+        for g in gs:
+            pp = p.copy()
+            pp[k, g] += h
+            Lp, sp = _loss_and_sig(oracle_lib, pp, vs, w)
+            pp[k, g] -= 2 * h
+            Lm, sm = _loss_and_sig(oracle_lib, pp, vs, w)
+            if not (np.array_equal(sp, sig0) and np.array_equal(sm, sig0)):
+                rejected += 1
+                continue
+            fd = (Lp - Lm) / (2 * h)
+            scale = max(abs(fd), 1e-3 * np.abs(grad[k]).max(), 1e-9)
+            assert abs(grad[k, g] - fd) <= 1e-5 * scale, (k, g, grad[k, g], fd)
+            checked += 1
+            per_class[k] += 1
+    assert rejected <= 0.1 * (checked + rejected)
+    assert np.all(per_class >= 3), per_class
+
+
+def test_culled_gaussians_have_zero_gradient(oracle_lib):
+    p = synth.small_set(200, seed=5).astype(np.float64)
+    view = synth.front_view(32, 32, f=32.0)
+    w = synth.linear_loss_weights(1, 32, 32).astype(np.float64)
+    grad, _ = oracle_lib.backward(p, view, w, precision="f64")
+    _, _, touched = oracle_lib.preprocess_f64(p, view)
+    assert np.all(grad[:, touched[0] == 0] == 0)
