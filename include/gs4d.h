@@ -1,0 +1,240 @@
+/*
+ * gs4d -- differentiable 4D Gaussian-splatting rasterizer for MI355X (gfx950).
+ *
+ * C ABI of libgs4d.so.  The method is Instant4D (arXiv 2510.01119): a native
+ * 4D Gaussian is sliced at render time t into a conditional 3D Gaussian
+ * (Sec. 3.3, Eq. "4dgs"), weighted by the temporal opacity o_t = o N(t; mu_4,
+ * Sigma_44) and culled when o_t is negligible (Sec. 3.3, "Motion-Aware
+ * Gaussian"), then rendered with the Gaussian-splatting rasterizer the paper
+ * inherits from 3D/4D Gaussian splatting (Sec. 3.1): EWA projection, 16x16
+ * tile binning, depth sort, front-to-back alpha compositing, and the analytic
+ * backward.  Point clouds are reduced by voxel grid pruning (Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller, unless marked
+ *     "host".  No entry point allocates or frees device memory: scratch
+ *     memory is a caller-provided workspace of the size reported by the
+ *     matching *_workspace_size() query.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream) and never synchronises the host.
+ *   - Arguments are validated on the host before any launch; a rejected call
+ *     launches nothing and returns GS4D_ERR_INVALID_ARG.  A failed launch
+ *     returns GS4D_ERR_HIP.  gs4d_last_error() gives a message for the
+ *     calling thread's last failure.
+ *   - Data-dependent overflow (pair capacity, prune capacity) is detected on
+ *     the device: the kernels never write past a capacity; they raise a
+ *     device status flag and store the size that was needed.
+ *   - Parameters are SoA planes: params is float [20][n]
+ *        0..3  mean (x, y, z, t)            4..7  log scale (x, y, z, t)
+ *        8..11 left quaternion (w, x, y, z)  12..15 right quaternion (w,x,y,z)
+ *        16    opacity logit                 17..19 rgb
+ *     The 4D rotation maps p = t + x i + y j + z k to q_l p q_r with the
+ *     normalised quaternions; Sigma = (R S)(R S)^T with S = diag(exp(log scale)).
+ *   - Non-finite parameters, degenerate quaternions, Gaussians behind the
+ *     near plane, temporally culled ones (255 o_t < 1) and ones whose exact
+ *     alpha >= 1/255 footprint misses the image are culled (zero tiles).
+ */
+#ifndef GS4D_H
+#define GS4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS4D_OK = 0,
+    GS4D_ERR_INVALID_ARG = -1,
+    GS4D_ERR_CAPACITY = -2,
+    GS4D_ERR_HIP = -3,
+    GS4D_ERR_UNSUPPORTED = -4
+} gs4d_status;
+
+#define GS4D_N_FIELDS 20     /* floats per Gaussian in params / dparams     */
+#define GS4D_REC_FLOATS 12   /* floats per (view, Gaussian) projected record */
+#define GS4D_GRAD2D_FLOATS 9 /* floats per (view, Gaussian) 2D gradient      */
+#define GS4D_TILE 16         /* tile edge in pixels                          */
+#define GS4D_MAX_VIEWS 16    /* views per call                               */
+
+/* One camera at one timestamp (host struct, 96 bytes).  All views passed to
+ * one call must share width and height. */
+typedef struct gs4d_view {
+    float Rt[12];       /* world -> camera [R | t], row-major 3x4; camera axes x right, y down, z forward */
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float t;            /* render timestamp                                  */
+    float near_z;       /* near plane (Gaussians with camera z < near_z are culled) */
+    float bg[3];        /* background rgb                                    */
+    int32_t reserved;   /* must be 0                                         */
+} gs4d_view;
+
+/* ---------------------------------------------------------------------------
+ * gs4d_preprocess -- slice, cull, project and bin every (view, Gaussian).
+ *   Sec. 3.3 Eq. "4dgs" (conditional mean/covariance at t), Sec. 3.3
+ *   "Motion-Aware Gaussian" (o_t and its cull), Sec. 3.1 (EWA splatting).
+ *   params   float [20][n]
+ *   views    host, n_views entries (1 <= n_views <= GS4D_MAX_VIEWS)
+ *   rec      out float [n_views][n][12]:
+ *              0 mean2D.x 1 mean2D.y 2 conic.a 3 conic.b 4 conic.c 5 o_t
+ *              6 camera depth z 7 zero 8..10 rgb 11 zero   (zeros if culled)
+ *   rect     out int32 [n_views][n][4]: tile rectangle [x0, y0, x1, y1) of
+ *              the exact alpha >= 1/255 footprint (zeros if culled)
+ *   touched  out int32 [n_views][n]: tiles covered, (x1-x0)*(y1-y0)
+ *   Everything that decides an integer here is computed in FP32 with a fixed
+ *   operation order, so results are reproducible bit for bit.
+ * ------------------------------------------------------------------------- */
+int gs4d_preprocess(const float *params, int64_t n, const gs4d_view *views, int32_t n_views,
+                    float *rec, int32_t *rect, int32_t *touched, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * gs4d_bin_sort -- duplicate each visible (view, Gaussian) once per touched
+ *   tile and sort the pairs by (tile, depth) (Sec. 3.1, the tile-based
+ *   splatting renderer).
+ *   key = (global tile << 32) | bits(FP32 depth), value = Gaussian index;
+ *   global tile = view * tiles_per_view + ty * tiles_x + tx.  Output is
+ *   ascending by (key, value): a total order, hence unique.
+ *   keys, vals     out, pair_capacity entries
+ *   ranges         out int32 [n_views * tiles_per_view][2]: [start, end) per
+ *                  tile in the sorted arrays, (0, 0) for an empty tile
+ *   n_pairs        out device int64: number of pairs (also when over capacity)
+ *   overflow       out device int32: 1 if n_pairs > pair_capacity (then keys,
+ *                  vals and ranges are not valid), else 0
+ *   ws, ws_bytes   workspace, >= gs4d_bin_sort_workspace_size(n, n_views, pair_capacity)
+ *   pair_capacity must be < 2^31.
+ * ------------------------------------------------------------------------- */
+size_t gs4d_bin_sort_workspace_size(int64_t n, int32_t n_views, int64_t pair_capacity);
+int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_t *touched, int64_t n,
+                  const gs4d_view *views, int32_t n_views, int64_t pair_capacity, uint64_t *keys,
+                  uint32_t *vals, int32_t *ranges, int64_t *n_pairs, int32_t *overflow, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* Render options.  Zero-initialise and set what is needed. */
+typedef struct gs4d_render_opts {
+    int32_t batch;          /* Gaussians staged in LDS per round: 64, 128 or 256 (0 -> 256) */
+    int32_t persistent;     /* 1: persistent launch over a largest-first (view, tile) queue */
+    int32_t n_workgroups;   /* persistent launch size (0 -> 4 per CU)                       */
+    int32_t reserved;
+    const float *target;    /* optional [n_views][3][H][W]: fused per-view L1 loss          */
+    float l1_weight;        /* weight of the fused L1 term                                  */
+    float *loss_per_view;   /* out [n_views], accumulated (caller zeroes), needs target     */
+    float *dL_dimage;       /* out [n_views][3][H][W] dL1/dimage * l1_weight, needs target  */
+    uint64_t *counters;     /* optional out [2], accumulated: evaluated entries, blends     */
+    const int32_t *order;   /* optional [n_views*tiles_per_view] tile processing order (persistent) */
+    int32_t *queue;         /* device int32 work counter for persistent mode (caller zeroes) */
+} gs4d_render_opts;
+
+/* ---------------------------------------------------------------------------
+ * gs4d_render_fwd -- front-to-back alpha compositing per pixel (Sec. 3.1):
+ *   power = -1/2 (a dx^2 + c dy^2) - b dx dy (skip if > 0), alpha =
+ *   min(0.99, o_t e^power) (skip if < 1/255), T' = T (1 - alpha) (stop
+ *   before blending if T' < 1e-4), C += rgb alpha T; output C + T bg.
+ *   Pixel centres at (x + 1/2, y + 1/2).
+ *   image    out float [n_views][3][H][W]
+ *   T_final  out float [n_views][H][W]
+ *   last     out int32 [n_views][H][W]: global pair index of the last blended
+ *            entry, -1 if none
+ *   opts     host, may be NULL
+ * ------------------------------------------------------------------------- */
+int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals, const int32_t *ranges,
+                    const gs4d_view *views, int32_t n_views, const gs4d_render_opts *opts,
+                    float *image, float *T_final, int32_t *last, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * gs4d_render_bwd -- analytic backward of gs4d_render_fwd and
+ *   gs4d_preprocess down to the 20 raw parameters.  Per pixel the entries are
+ *   replayed back to front from `last`; each transmittance is recovered as
+ *   T_i = T_{i+1} / (1 - alpha_i) from T_final, never stored.  Gradients are
+ *   zero through the 0.99 clamp, skipped entries and clamped guard-band
+ *   coordinates.
+ *   dL_dimage  float [n_views][3][H][W]
+ *   dparams    out float [20][n], overwritten (sum over views)
+ *   grad2d     optional out float [n_views][n][9] (d mean2D.xy, d conic.abc,
+ *              d o_t, d rgb); NULL -> kept in the workspace
+ *   ws         >= gs4d_render_bwd_workspace_size(n, n_views)
+ * ------------------------------------------------------------------------- */
+size_t gs4d_render_bwd_workspace_size(int64_t n, int32_t n_views);
+int gs4d_render_bwd(const float *params, int64_t n, const float *rec, const int32_t *touched,
+                    const uint32_t *vals, const int32_t *ranges, const gs4d_view *views,
+                    int32_t n_views, const float *dL_dimage, const float *T_final,
+                    const int32_t *last, float *dparams, float *grad2d, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * gs4d_grid_prune -- voxel grid pruning (Sec. 3.2): each point goes to the
+ *   voxel floor(fl32(x / S_v)) per axis of its motion class (static: voxel
+ *   edge voxel_static; dynamic: voxel_dynamic, the per-class sizes of the
+ *   Lite/Full presets, Sec. 4.1); points of one (class, voxel) are replaced
+ *   by their centroid and the mean of their attributes (FP64 sums); voxels
+ *   with fewer than min_count points are dropped.  A class with edge <= 0
+ *   is not pruned (each point is its own cell).
+ *   key = class << 63 | unpruned << 62 | (ix+2^19) << 40 | (iy+2^19) << 20 | (iz+2^19)
+ *   (unpruned: low 62 bits = point index); output ascending by key.
+ *   xyz       float [3][m]          attr  float [k_attr][m] (may be NULL if k_attr = 0)
+ *   cls       uint8 [m] (nonzero = dynamic) or NULL (all static)
+ *   out_xyz   out float [3][capacity]   out_attr out float [k_attr][capacity]
+ *   out_count out int32 [capacity]      out_key  out uint64 [capacity]
+ *   n_out     out device int64: number of kept voxels (also when over capacity)
+ *   status    out device int32: 0 ok, 1 over capacity, 2 voxel index outside [-2^19, 2^19)
+ *   m < 2^31; ws >= gs4d_grid_prune_workspace_size(m, k_attr).
+ * ------------------------------------------------------------------------- */
+size_t gs4d_grid_prune_workspace_size(int64_t m, int32_t k_attr);
+int gs4d_grid_prune(const float *xyz, const float *attr, int32_t k_attr, const uint8_t *cls,
+                    int64_t m, float voxel_static, float voxel_dynamic, int32_t min_count,
+                    int64_t capacity, float *out_xyz, float *out_attr, int32_t *out_count,
+                    uint64_t *out_key, int64_t *n_out, int32_t *status, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* ------------------------------------------------------------------------- *
+ * Optimisation-loop helpers (Sec. 4.1: a single photometric loss with the
+ * 3D Gaussian-splatting loss weights and optimiser, position learning rate
+ * 1e-5, learning-rate schedule stretched to the iteration budget).
+ * ------------------------------------------------------------------------- */
+
+/* Adam (bias-corrected) over rows x n SoA parameters.  Row r uses the
+ * learning rate lr0[r]^(1-u) lr1[r]^u with u = min(step / budget, 1).
+ * step is a device int32 holding the number of steps already taken; the call
+ * uses step + 1 and then increments it (graph-replay friendly). */
+typedef struct gs4d_adam_cfg {
+    float lr0[GS4D_N_FIELDS];
+    float lr1[GS4D_N_FIELDS];
+    int32_t budget;
+    int32_t rows;           /* <= GS4D_N_FIELDS */
+    float beta1, beta2, eps;
+} gs4d_adam_cfg;
+int gs4d_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                   const gs4d_adam_cfg *cfg, int32_t *step, void *stream);
+
+/* L1 = mean |img - target| over count values.  loss (device float) is
+ * accumulated with weight * L1; dL_dimg (if not NULL) is accumulated with
+ * weight * sign(img - target) / count. */
+int gs4d_loss_l1(const float *img, const float *target, int64_t count, float weight, float *loss,
+                 float *dL_dimg, void *stream);
+
+/* SSIM (11x11 Gaussian window, sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, zero
+ * padding, mean over images x channels x pixels) of img [b][c][h][w]
+ * against target.  ssim_sum (device float) is accumulated with the mean
+ * SSIM times `weight`; dL_dimg (if not NULL) is accumulated with
+ * weight * dSSIM/dimg. */
+size_t gs4d_ssim_workspace_size(int32_t b, int32_t c, int32_t h, int32_t w);
+int gs4d_ssim(const float *img, const float *target, int32_t b, int32_t c, int32_t h, int32_t w,
+              float weight, float *ssim_sum, float *dL_dimg, void *ws, size_t ws_bytes,
+              void *stream);
+
+/* Sum of squared differences, accumulated into sse (device double). */
+int gs4d_sse(const float *img, const float *target, int64_t count, double *sse, void *stream);
+
+/* Fill count floats with value (graph-capturable replacement of memset). */
+int gs4d_fill_f32(float *dst, float value, int64_t count, void *stream);
+int gs4d_fill_u32(uint32_t *dst, uint32_t value, int64_t count, void *stream);
+
+/* Diagnostics. */
+const char *gs4d_status_string(int status);
+const char *gs4d_last_error(void);
+int gs4d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS4D_H */

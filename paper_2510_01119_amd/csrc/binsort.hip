@@ -1,0 +1,534 @@
+// Tile binning and sorting (the tile-based splatting renderer of Sec. 3.1).
+//
+// Result: every visible (view, Gaussian) duplicated once per touched 16x16
+// tile, as (key, value) = ((global tile << 32) | bits(FP32 depth), Gaussian)
+// sorted ascending by (key, value).
+//
+// Work plan (one GPU, no host synchronisation):
+//   1. item keys: the depth bits of each (view, Gaussian) record (culled ->
+//      0xFFFFFFFF), value = view * n + Gaussian.
+//   2. stable LSD radix sort of the items on the 32 depth bits.
+//   3. gather tiles-touched in that order, device-wide exclusive scan -> each
+//      item's first pair slot and the pair count P (stored on device).
+//   4. emit pairs in depth order; inside one tile they are then already
+//      ascending in (depth bits, Gaussian).
+//   5. stable LSD radix sort of the P pairs on the tile bits only, which
+//      yields exactly the ascending (key, value) order while moving the pairs
+//      through 1-2 digit passes instead of 5-6.
+//   6. tile ranges from adjacent key differences.
+//
+// Radix sort: 8-bit digits; per pass a histogram kernel (per-block digit
+// counts + global digit totals), a scan kernel (one wave per digit over the
+// blocks), and a scatter kernel that ranks keys stably with wave ballots,
+// regroups them by digit in LDS and writes each digit run contiguously.
+#include "common.hpp"
+
+namespace gs4d {
+namespace {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;   // 4096 keys per block
+constexpr int RS_MAX_PASSES = 8;
+
+__device__ __forceinline__ int64_t read_count(const int64_t *count_dev, int64_t count_host,
+                                              int64_t capacity) {
+    int64_t n = count_dev ? *count_dev : count_host;
+    if (n > capacity) n = capacity;
+    if (n < 0) n = 0;
+    return n;
+}
+
+template <class K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift) {
+    return (uint32_t)((key >> shift) & (K)0xFF);
+}
+
+// Block b covers keys [b*4096, (b+1)*4096).  Wave w owns the contiguous 1024
+// keys starting at b*4096 + w*1024; item i of lane l is key w*1024 + i*64 + l,
+// so every wave load reads 64 consecutive keys.
+template <class K>
+__global__ void __launch_bounds__(RS_THREADS)
+rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t count_host,
+               int64_t capacity, int shift, uint32_t *__restrict__ hist,
+               uint32_t *__restrict__ digit_total) {
+    const int64_t n = read_count(count_dev, count_host, capacity);
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    __shared__ uint32_t cnt[RS_WAVES][256];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = b * RS_TILE + (int64_t)w * (RS_TILE / RS_WAVES);
+#pragma unroll 4
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = base + i * 64 + l;
+        if (idx < n) atomicAdd(&cnt[w][digit_of(keys[idx], shift)], 1u);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) c += cnt[k][t];
+    hist[(int64_t)t * nb + b] = c;
+    if (c) atomicAdd(&digit_total[t], c);
+}
+
+// One wave per digit: exclusive prefix of hist[d][0..nb) plus the count of
+// all smaller digits.
+__global__ void __launch_bounds__(64)
+rs_scan_kernel(uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_total,
+               const int64_t *count_dev, int64_t count_host, int64_t capacity) {
+    const int64_t n = read_count(count_dev, count_host, capacity);
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    if (nb == 0) return;
+    const int d = blockIdx.x, l = threadIdx.x;
+    uint32_t below = 0;
+    for (int k = l; k < d; k += 64) below += digit_total[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) below += __shfl_xor(below, off, 64);
+    uint32_t running = below;
+    uint32_t *row = hist + (int64_t)d * nb;
+    for (int64_t c0 = 0; c0 < nb; c0 += 64) {
+        const int64_t idx = c0 + l;
+        const uint32_t x = idx < nb ? row[idx] : 0u;
+        uint32_t incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (l >= off) incl += y;
+        }
+        if (idx < nb) row[idx] = running + incl - x;
+        running += __shfl(incl, 63, 64);
+    }
+}
+
+template <class K>
+__global__ void __launch_bounds__(RS_THREADS)
+rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+                  K *__restrict__ kout, uint32_t *__restrict__ vout, const int64_t *count_dev,
+                  int64_t count_host, int64_t capacity, int shift,
+                  const uint32_t *__restrict__ hist) {
+    const int64_t n = read_count(count_dev, count_host, capacity);
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    __shared__ K sk[RS_TILE];
+    __shared__ uint32_t sv[RS_TILE];
+    __shared__ uint32_t wcnt[RS_WAVES][256];   // per-wave running digit counts
+    __shared__ uint32_t dstart[256];           // block-local start of each digit
+    __shared__ uint32_t gbase[256];            // global start of this block's digit run
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const int64_t base = b * RS_TILE + (int64_t)w * (RS_TILE / RS_WAVES);
+    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    K key[RS_ITEMS];
+    uint32_t val[RS_ITEMS], rank[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = base + i * 64 + l;
+        const bool valid = idx < n;
+        key[i] = valid ? kin[idx] : (K)0;
+        val[i] = valid ? vin[idx] : 0u;
+        const uint32_t d = digit_of(key[i], shift);
+        // lanes holding the same digit (ballot-based match)
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+        const uint32_t before = __popcll(peers & lt_mask);
+        uint32_t r = 0;
+        if (valid) r = wcnt[w][d] + before;
+        const bool leader = valid && before == 0;
+        // all lanes have read wcnt[w][d] before the leader updates it
+        __builtin_amdgcn_wave_barrier();
+        if (leader) wcnt[w][d] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        rank[i] = valid ? r : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    // per digit: prefix over waves, block-local start, global start
+    {
+        const int d = t;
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < RS_WAVES; ++k) {
+            const uint32_t c = wcnt[k][d];
+            wcnt[k][d] = run;
+            run += c;
+        }
+        // block exclusive scan of run over the 256 digits
+        uint32_t incl = run;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (l >= off) incl += y;
+        }
+        __shared__ uint32_t wsum[RS_WAVES];
+        if (l == 63) wsum[w] = incl;
+        gbase[d] = hist[(int64_t)d * nb + b];
+        __syncthreads();
+        uint32_t off = 0;
+        for (int k = 0; k < w; ++k) off += wsum[k];
+        dstart[d] = off + incl - run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        if (rank[i] != 0xFFFFFFFFu) {
+            const uint32_t d = digit_of(key[i], shift);
+            const uint32_t pos = dstart[d] + wcnt[w][d] + rank[i];
+            sk[pos] = key[i];
+            sv[pos] = val[i];
+        }
+    }
+    __syncthreads();
+    const int64_t nvalid = (n - b * RS_TILE) < RS_TILE ? (n - b * RS_TILE) : RS_TILE;
+#pragma unroll 4
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int idx = i * RS_THREADS + t;
+        if (idx < nvalid) {
+            const K k = sk[idx];
+            const uint32_t d = digit_of(k, shift);
+            const uint32_t dst = gbase[d] + (uint32_t)idx - dstart[d];
+            kout[dst] = k;
+            vout[dst] = sv[idx];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- scan
+constexpr int SC_THREADS = 256;
+constexpr int SC_ITEMS = 16;
+constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+
+__device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *total) {
+    __shared__ int64_t ws[SC_THREADS / 64];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    int64_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(incl, off, 64);
+        if (l >= off) incl += y;
+    }
+    if (l == 63) ws[w] = incl;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+    for (int k = 0; k < SC_THREADS / 64; ++k) {
+        if (k < w) off += ws[k];
+        tot += ws[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - x;
+}
+
+__global__ void __launch_bounds__(SC_THREADS)
+scan_reduce_kernel(const int32_t *__restrict__ in, int64_t count, int64_t *__restrict__ bsum) {
+    const int64_t b = blockIdx.x;
+    const int64_t base = b * SC_TILE;
+    int64_t s = 0;
+    for (int i = 0; i < SC_ITEMS; ++i) {
+        const int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
+        if (idx < count) s += in[idx];
+    }
+    int64_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) bsum[b] = tot;
+}
+
+__global__ void __launch_bounds__(SC_THREADS)
+scan_top_kernel(int64_t *__restrict__ bsum, int64_t nblocks, int64_t *__restrict__ total) {
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblocks; c0 += SC_THREADS) {
+        const int64_t idx = c0 + threadIdx.x;
+        const int64_t x = idx < nblocks ? bsum[idx] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(x, &tot);
+        if (idx < nblocks) bsum[idx] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(SC_THREADS)
+scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t count,
+                 const int64_t *__restrict__ bsum) {
+    const int64_t b = blockIdx.x;
+    // each thread owns SC_ITEMS consecutive values
+    const int64_t base = b * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+    int32_t v[SC_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SC_ITEMS; ++i) {
+        v[i] = (base + i < count) ? in[base + i] : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t run = bsum[b] + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int i = 0; i < SC_ITEMS; ++i) {
+        if (base + i < count) out[base + i] = (int32_t)run;
+        run += v[i];
+    }
+}
+
+// ---------------------------------------------------------------- binning kernels
+__global__ void item_keys_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
+                                 int64_t m, uint32_t *__restrict__ keys,
+                                 uint32_t *__restrict__ vals) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= m) return;
+    const float z = rec[3 * o + 1].z;
+    keys[o] = touched[o] > 0 ? __float_as_uint(z) : 0xFFFFFFFFu;
+    vals[o] = (uint32_t)o;
+}
+
+__global__ void gather_touched_kernel(const uint32_t *__restrict__ order,
+                                      const int32_t *__restrict__ touched, int64_t m,
+                                      int32_t *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) out[k] = touched[order[k]];
+}
+
+__global__ void pair_status_kernel(const int64_t *__restrict__ total, int64_t capacity,
+                                   int64_t *__restrict__ n_pairs, int32_t *__restrict__ overflow) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t t = *total;
+        *n_pairs = t;
+        *overflow = t > capacity ? 1 : 0;
+    }
+}
+
+__global__ void emit_kernel(const uint32_t *__restrict__ dkeys, const uint32_t *__restrict__ order,
+                            const int32_t *__restrict__ tsorted, const int32_t *__restrict__ offs,
+                            const int4 *__restrict__ rect, int64_t m, int64_t n, int32_t tiles_x,
+                            int32_t tiles_per_view, int64_t capacity, uint64_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int32_t cnt = tsorted[k];
+    if (cnt == 0) return;
+    const int64_t off = offs[k];
+    if (off < 0 || off + cnt > capacity) return;
+    const uint32_t o = order[k];
+    const uint32_t vi = (uint32_t)(o / (uint64_t)n);
+    const uint32_t g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
+    const int4 r = rect[o];
+    const uint64_t lo = dkeys[k];
+    const uint64_t tbase = (uint64_t)vi * (uint64_t)tiles_per_view;
+    int64_t j = off;
+    for (int ty = r.y; ty < r.w; ++ty)
+        for (int tx = r.x; tx < r.z; ++tx) {
+            const uint64_t tile = tbase + (uint64_t)ty * tiles_x + tx;
+            keys[j] = (tile << 32) | lo;
+            vals[j] = g;
+            ++j;
+        }
+}
+
+__global__ void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *__restrict__ n_pairs,
+                              int64_t capacity, int64_t n_tiles, int2 *__restrict__ ranges) {
+    const int64_t n = *n_pairs;
+    if (n > capacity) return;   // overflow: every tile stays empty (0, 0)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t tile = keys[i] >> 32;
+    if (tile >= (uint64_t)n_tiles) return;
+    if (i == 0 || (keys[i - 1] >> 32) != tile) ranges[tile].x = (int32_t)i;
+    if (i == n - 1 || (keys[i + 1] >> 32) != tile) ranges[tile].y = (int32_t)(i + 1);
+}
+
+inline unsigned grid_for(int64_t count, int threads) {
+    int64_t b = (count + threads - 1) / threads;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+template <class K>
+int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
+                    int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
+                    hipStream_t st, int *result_in_alt) {
+    const int passes = (bit_hi - bit_lo + 7) / 8;
+    *result_in_alt = passes & 1;
+    if (passes <= 0 || capacity <= 0) return GS4D_OK;
+    const int64_t nb_max = (capacity + RS_TILE - 1) / RS_TILE;
+    Carve c(ws, ~size_t(0));
+    uint32_t *hist = c.take<uint32_t>((size_t)nb_max * 256);
+    uint32_t *totals = c.take<uint32_t>((size_t)RS_MAX_PASSES * 256);
+    GS4D_TRY(launch_fill<uint32_t>(totals, 0u, (int64_t)passes * 256, st));
+    K *src = k0, *dst = k1;
+    uint32_t *vsrc = v0, *vdst = v1;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = bit_lo + 8 * p;
+        uint32_t *tot = totals + p * 256;
+        rs_hist_kernel<K><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(src, count_dev, count_host,
+                                                                   capacity, shift, hist, tot);
+        rs_scan_kernel<<<256, 64, 0, st>>>(hist, tot, count_dev, count_host, capacity);
+        rs_scatter_kernel<K><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+            src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, hist);
+        GS4D_LAUNCH_CHECK("radix pass");
+        K *tk = src; src = dst; dst = tk;
+        uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
+    }
+    return GS4D_OK;
+}
+
+}  // namespace
+
+size_t radix_workspace_size(int64_t capacity) {
+    const int64_t nb_max = (capacity + RS_TILE - 1) / RS_TILE;
+    Carve c(nullptr, 0);
+    c.take<uint32_t>((size_t)(nb_max > 0 ? nb_max : 1) * 256);
+    c.take<uint32_t>((size_t)RS_MAX_PASSES * 256);
+    return c.used + 256;
+}
+
+int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const int64_t *count_dev,
+                   int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
+                   hipStream_t st, int *result_in_alt) {
+    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, count_dev, count_host, capacity, bit_lo,
+                                     bit_hi, ws, st, result_in_alt);
+}
+
+int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *count_dev,
+                   int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
+                   hipStream_t st, int *result_in_alt) {
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, count_dev, count_host, capacity, bit_lo,
+                                     bit_hi, ws, st, result_in_alt);
+}
+
+size_t scan_workspace_size(int64_t count) {
+    const int64_t nb = (count + SC_TILE - 1) / SC_TILE;
+    return (size_t)(nb > 0 ? nb : 1) * sizeof(int64_t) + 256;
+}
+
+int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count, int64_t *total, void *ws,
+                       hipStream_t st) {
+    const int64_t nb = (count + SC_TILE - 1) / SC_TILE;
+    int64_t *bsum = static_cast<int64_t *>(ws);
+    if (nb == 0) {
+        return launch_fill<int64_t>(total, (int64_t)0, 1, st);
+    }
+    scan_reduce_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, count, bsum);
+    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total);
+    scan_down_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, out, count, bsum);
+    GS4D_LAUNCH_CHECK("exclusive_scan");
+    return GS4D_OK;
+}
+
+namespace {
+struct BinLayout {
+    uint32_t *ik0, *iv0, *ik1, *iv1;   // item keys / values, two buffers
+    int32_t *tsorted, *offs;
+    void *scan_ws;
+    int64_t *total;
+    uint64_t *pk;                       // alternate pair buffers
+    uint32_t *pv;
+    void *radix_ws;
+};
+
+BinLayout carve_bin(void *ws, int64_t m, int64_t cap, size_t *used) {
+    Carve c(ws, ~size_t(0));
+    BinLayout L;
+    const size_t mm = (size_t)(m > 0 ? m : 1);
+    L.ik0 = c.take<uint32_t>(mm);
+    L.iv0 = c.take<uint32_t>(mm);
+    L.ik1 = c.take<uint32_t>(mm);
+    L.iv1 = c.take<uint32_t>(mm);
+    L.tsorted = c.take<int32_t>(mm);
+    L.offs = c.take<int32_t>(mm);
+    L.scan_ws = c.take<char>(scan_workspace_size(m));
+    L.total = c.take<int64_t>(1);
+    L.pk = c.take<uint64_t>((size_t)(cap > 0 ? cap : 1));
+    L.pv = c.take<uint32_t>((size_t)(cap > 0 ? cap : 1));
+    L.radix_ws = c.take<char>(radix_workspace_size(m > cap ? m : cap));
+    *used = c.used;
+    return L;
+}
+
+int tile_bits_for(int64_t n_tiles) {
+    int b = 1;
+    while (((int64_t)1 << b) < n_tiles) ++b;
+    return b;
+}
+}  // namespace
+
+}  // namespace gs4d
+
+using namespace gs4d;
+
+extern "C" size_t gs4d_bin_sort_workspace_size(int64_t n, int32_t n_views, int64_t pair_capacity) {
+    size_t used = 0;
+    carve_bin(nullptr, n * (int64_t)(n_views > 0 ? n_views : 1), pair_capacity, &used);
+    return used + 256;
+}
+
+extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_t *touched,
+                             int64_t n, const gs4d_view *views, int32_t n_views,
+                             int64_t pair_capacity, uint64_t *keys, uint32_t *vals,
+                             int32_t *ranges, int64_t *n_pairs, int32_t *overflow, void *ws,
+                             size_t ws_bytes, void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "gs4d_bin_sort: n out of range");
+    GS4D_REQUIRE((int64_t)n * n_views <= (int64_t)0xffffffffLL, "gs4d_bin_sort: n * n_views >= 2^32");
+    GS4D_REQUIRE(pair_capacity >= 0 && pair_capacity < ((int64_t)1 << 31),
+                 "gs4d_bin_sort: pair_capacity out of range");
+    GS4D_REQUIRE(ranges && n_pairs && overflow, "gs4d_bin_sort: null output pointer");
+    GS4D_REQUIRE(n == 0 || (rec && rect && touched), "gs4d_bin_sort: null input pointer");
+    GS4D_REQUIRE(pair_capacity == 0 || (keys && vals), "gs4d_bin_sort: null pair buffer");
+    const int64_t m = n * n_views;
+    size_t need = gs4d_bin_sort_workspace_size(n, n_views, pair_capacity);
+    GS4D_REQUIRE(ws != nullptr && ws_bytes >= need, "gs4d_bin_sort: workspace too small (%zu < %zu)",
+                 ws_bytes, need);
+    hipStream_t st = as_stream(stream);
+    size_t used = 0;
+    BinLayout L = carve_bin(ws, m, pair_capacity, &used);
+    const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
+
+    GS4D_TRY(launch_fill<int32_t>(ranges, 0, 2 * n_tiles, st));
+    if (m == 0) {
+        GS4D_TRY(launch_fill<int64_t>(n_pairs, (int64_t)0, 1, st));
+        GS4D_TRY(launch_fill<int32_t>(overflow, 0, 1, st));
+        return GS4D_OK;
+    }
+    // 1-2: items sorted by depth bits
+    item_keys_kernel<<<grid_for(m, 256), 256, 0, st>>>(reinterpret_cast<const float4 *>(rec), touched,
+                                                       m, L.ik0, L.iv0);
+    GS4D_LAUNCH_CHECK("item_keys");
+    int alt = 0;
+    GS4D_TRY(radix_sort_u32(L.ik0, L.iv0, L.ik1, L.iv1, nullptr, m, m, 0, 32, L.radix_ws, st, &alt));
+    const uint32_t *dkeys = alt ? L.ik1 : L.ik0;
+    const uint32_t *order = alt ? L.iv1 : L.iv0;
+    // 3: offsets in depth order
+    gather_touched_kernel<<<grid_for(m, 256), 256, 0, st>>>(order, touched, m, L.tsorted);
+    GS4D_LAUNCH_CHECK("gather_touched");
+    GS4D_TRY(exclusive_scan_i32(L.tsorted, L.offs, m, L.total, L.scan_ws, st));
+    pair_status_kernel<<<1, 64, 0, st>>>(L.total, pair_capacity, n_pairs, overflow);
+    GS4D_LAUNCH_CHECK("pair_status");
+    if (pair_capacity == 0) return GS4D_OK;
+    // 4-5: emit in depth order, stable sort on tile bits only
+    const int tbits = tile_bits_for(n_tiles);
+    const int tpasses = (tbits + 7) / 8;
+    uint64_t *ek = (tpasses & 1) ? L.pk : keys;
+    uint32_t *ev = (tpasses & 1) ? L.pv : vals;
+    uint64_t *ok = (tpasses & 1) ? keys : L.pk;
+    uint32_t *ov = (tpasses & 1) ? vals : L.pv;
+    emit_kernel<<<grid_for(m, 128), 128, 0, st>>>(dkeys, order, L.tsorted, L.offs,
+                                                  reinterpret_cast<const int4 *>(rect), m, n,
+                                                  vp.tiles_x, vp.tiles_per_view, pair_capacity, ek,
+                                                  ev);
+    GS4D_LAUNCH_CHECK("emit");
+    GS4D_TRY(radix_sort_u64(ek, ev, ok, ov, n_pairs, 0, pair_capacity, 32, 32 + tbits, L.radix_ws,
+                            st, &alt));
+    // 6: ranges
+    ranges_kernel<<<grid_for(pair_capacity, 256), 256, 0, st>>>(keys, n_pairs, pair_capacity, n_tiles,
+                                                                reinterpret_cast<int2 *>(ranges));
+    GS4D_LAUNCH_CHECK("ranges");
+    return GS4D_OK;
+}

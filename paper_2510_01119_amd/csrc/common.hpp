@@ -1,0 +1,133 @@
+// Internal helpers shared by the gs4d HIP translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "gs4d.h"
+
+namespace gs4d {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+
+#define GS4D_REQUIRE(cond, ...)                 \
+    do {                                        \
+        if (!(cond)) {                          \
+            ::gs4d::set_error(__VA_ARGS__);     \
+            return GS4D_ERR_INVALID_ARG;        \
+        }                                       \
+    } while (0)
+
+#define GS4D_LAUNCH_CHECK(what)                                                        \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess) {                                                        \
+            ::gs4d::set_error("%s: launch failed: %s", what, hipGetErrorString(e_));   \
+            return GS4D_ERR_HIP;                                                       \
+        }                                                                              \
+    } while (0)
+
+#define GS4D_TRY(expr)              \
+    do {                            \
+        int s_ = (expr);            \
+        if (s_ != GS4D_OK) return s_; \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- views
+// All views of one call travel by value in the kernel arguments.
+struct ViewPack {
+    gs4d_view v[GS4D_MAX_VIEWS];
+    int32_t n_views;
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int32_t tiles_per_view;
+};
+
+int make_view_pack(const gs4d_view *views, int32_t n_views, ViewPack *pack);
+
+// ---------------------------------------------------------------- workspace
+// Bump allocator over a caller-provided workspace (256-byte aligned slices).
+struct Carve {
+    char *base;
+    size_t size;
+    size_t used = 0;
+    Carve(void *b, size_t s) : base(static_cast<char *>(b)), size(s) {}
+    template <class T>
+    T *take(size_t count) {
+        used = (used + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base ? base + used : nullptr);
+        used += count * sizeof(T);
+        return p;
+    }
+    bool ok() const { return used <= size; }
+};
+
+// ---------------------------------------------------------------- device utils
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <class T>
+__global__ void fill_kernel(T *dst, T value, int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) dst[i] = value;
+}
+
+template <class T>
+inline int launch_fill(T *dst, T value, int64_t count, hipStream_t st) {
+    if (count <= 0) return GS4D_OK;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    fill_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(dst, value, count);
+    GS4D_LAUNCH_CHECK("fill");
+    return GS4D_OK;
+}
+
+// Wave64 sum; every lane receives the total.
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Exclusive prefix sums (radix sort, scans) ---------------------------------
+struct ScanWs;   // defined in binsort.hip
+
+// Device-wide exclusive scan of int32 values (count <= 2^31 - 1).  out may
+// alias nothing.  total (device int64) receives the sum.  ws from
+// scan_workspace_size(count).
+size_t scan_workspace_size(int64_t count);
+int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count, int64_t *total, void *ws,
+                       hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on bits [bit_lo, bit_hi).
+// Count is read from *count_dev if not NULL, else count_host.  Capacity
+// bounds the launch.  Buffers ping-pong between (k0, v0) and (k1, v1); the
+// result lands in (k0, v0) if the number of 8-bit passes is even, else in
+// (k1, v1): *result_in_alt reports which.
+size_t radix_workspace_size(int64_t capacity);
+int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const int64_t *count_dev,
+                   int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
+                   hipStream_t st, int *result_in_alt);
+int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *count_dev,
+                   int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
+                   hipStream_t st, int *result_in_alt);
+
+}  // namespace gs4d

@@ -1,0 +1,429 @@
+// Per-(view, Gaussian) slice + project, forward and backward.
+//
+// Forward (Sec. 3.3 Eq. "4dgs"; Sec. 3.3 "Motion-Aware Gaussian"; Sec. 3.1):
+//   activations -> 4D rotation from the left/right quaternion pair ->
+//   Sigma = (R S)(R S)^T -> conditional 3D Gaussian at time t and temporal
+//   opacity o_t -> temporal / near / determinant culls -> EWA projection
+//   (guard-banded Jacobian, 0.3 px^2 dilation) -> conic, mean2D -> exact
+//   alpha >= 1/255 footprint -> 16x16 tile rectangle.
+//
+// Every value here that decides an integer (cull, rectangle, the depth bits
+// of the sort key) must be reproducible bit for bit, so this file is compiled
+// without floating-point contraction, sums run left to right, divisions and
+// square roots are the correctly rounded IEEE operations, and exp / ln are
+// the two project-defined FP32 routines below.  One thread handles one
+// (view, Gaussian); parameters are read as coalesced SoA planes.
+#include "common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace gs4d {
+namespace {
+
+// exp(x): Cody-Waite reduction x = k ln2 + r (ln2 split so k * ln2_hi is
+// exact), degree-7 Taylor polynomial of e^r in Horner form, scale by 2^k.
+__device__ __forceinline__ float fixed_exp(float x) {
+    if (x != x) return x;
+    if (x < -87.0f) return 0.0f;
+    if (x > 88.0f) return __builtin_huge_valf();
+    const float k = rintf(x * 1.44269504088896341f);
+    float r = x - k * 0.693145751953125f;
+    r = r - k * 1.428606765330187e-06f;
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)k);
+}
+
+// ln(x): x = m 2^e with m in [1/sqrt2, sqrt2); ln m = 2 atanh(u),
+// u = (m - 1) / (m + 1), series through u^9.
+__device__ __forceinline__ float fixed_log(float x) {
+    if (x != x) return x;
+    if (x < 0.0f) return __builtin_nanf("");
+    if (x == 0.0f) return -__builtin_huge_valf();
+    if (x == __builtin_huge_valf()) return x;
+    int e;
+    float m = frexpf(x, &e);
+    if (m < 0.70710678118654752f) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    const float u = (m - 1.0f) / (m + 1.0f);
+    const float u2 = u * u;
+    float s = 1.0f / 9.0f;
+    s = fmaf(s, u2, 1.0f / 7.0f);
+    s = fmaf(s, u2, 1.0f / 5.0f);
+    s = fmaf(s, u2, 1.0f / 3.0f);
+    s = fmaf(s, u2, 1.0f);
+    return fmaf((float)e, 0.693147180559945309f, (2.0f * u) * s);
+}
+
+// Everything the backward needs from the forward of one (view, Gaussian).
+struct Slice {
+    float s[4], o;
+    float nl, nr, ql[4], qr[4];
+    float A[4][4], B[4][4];   // left / right multiplication matrices
+    float R[4][4];            // rotation in (x, y, z, t) order
+    float M[4][4];            // R diag(s)
+    float Sg[4][4];           // 4D covariance
+    float dt, ef, ot;         // t - mu_t, exp(-dt^2 / 2c), o_t
+    float mu[3], Sc[3][3];    // conditional mean / covariance
+    float xc[3];              // camera-space point
+    float ux, uy;             // guard-banded x/z, y/z
+    int clx, cly;             // guard band active
+    float J00, J02, J11, J12;
+    float T[2][3], U[2][3];   // T = J W, U = T Sc
+    float sa, sb, sc, det;    // Sigma2D = [[sa, sb], [sb, sc]]
+    float ca, cb, cc;         // conic
+    float mx, my;
+};
+
+// Returns 1 if the Gaussian is visible; `touched`/`rect` filled when asked.
+__device__ __forceinline__ int slice_project(const float (&p)[20], const gs4d_view &V, Slice &S,
+                                             int4 *rect_out) {
+    for (int k = 0; k < 20; ++k)
+        if (!isfinite(p[k])) return 0;
+
+    for (int k = 0; k < 4; ++k) S.s[k] = fixed_exp(p[4 + k]);
+    S.o = 1.0f / (1.0f + fixed_exp(-p[16]));
+
+    S.nl = sqrtf(p[8] * p[8] + p[9] * p[9] + p[10] * p[10] + p[11] * p[11]);
+    S.nr = sqrtf(p[12] * p[12] + p[13] * p[13] + p[14] * p[14] + p[15] * p[15]);
+    if (!(S.nl > 0.0f) || !(S.nr > 0.0f)) return 0;
+    for (int k = 0; k < 4; ++k) {
+        S.ql[k] = p[8 + k] / S.nl;
+        S.qr[k] = p[12 + k] / S.nr;
+    }
+    const float *a = S.ql, *b = S.qr;
+    // left multiplication by a, right multiplication by b, basis (1, i, j, k)
+    const float Am[4][4] = {{a[0], -a[1], -a[2], -a[3]},
+                            {a[1], a[0], -a[3], a[2]},
+                            {a[2], a[3], a[0], -a[1]},
+                            {a[3], -a[2], a[1], a[0]}};
+    const float Bm[4][4] = {{b[0], -b[1], -b[2], -b[3]},
+                            {b[1], b[0], b[3], -b[2]},
+                            {b[2], -b[3], b[0], b[1]},
+                            {b[3], b[2], -b[1], b[0]}};
+    float Q[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            S.A[i][j] = Am[i][j];
+            S.B[i][j] = Bm[i][j];
+            Q[i][j] = Am[i][0] * Bm[0][j] + Am[i][1] * Bm[1][j] + Am[i][2] * Bm[2][j] +
+                      Am[i][3] * Bm[3][j];
+        }
+    // (x, y, z, t) <- quaternion axes (i, j, k, 1)
+    const int perm[4] = {1, 2, 3, 0};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            S.R[i][j] = Q[perm[i]][perm[j]];
+            S.M[i][j] = S.R[i][j] * S.s[j];
+        }
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) {
+            const float v = S.M[i][0] * S.M[j][0] + S.M[i][1] * S.M[j][1] +
+                            S.M[i][2] * S.M[j][2] + S.M[i][3] * S.M[j][3];
+            S.Sg[i][j] = v;
+            S.Sg[j][i] = v;
+        }
+    const float c = S.Sg[3][3];
+    if (!(c > 0.0f)) return 0;
+
+    // conditional at time t
+    S.dt = V.t - p[3];
+    const float r = S.dt / c;
+    for (int i = 0; i < 3; ++i) S.mu[i] = p[i] + S.Sg[i][3] * r;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j) {
+            const float v = S.Sg[i][j] - (S.Sg[i][3] * S.Sg[j][3]) / c;
+            S.Sc[i][j] = v;
+            S.Sc[j][i] = v;
+        }
+    const float qd = (S.dt * S.dt) / c;
+    S.ef = fixed_exp(-0.5f * qd);
+    S.ot = S.o * S.ef;
+    if (!(255.0f * S.ot >= 1.0f)) return 0;
+
+    // camera space
+    const float *Rt = V.Rt;
+    for (int i = 0; i < 3; ++i)
+        S.xc[i] = Rt[4 * i] * S.mu[0] + Rt[4 * i + 1] * S.mu[1] + Rt[4 * i + 2] * S.mu[2] +
+                  Rt[4 * i + 3];
+    const float z = S.xc[2];
+    if (!(z >= V.near_z)) return 0;
+
+    // EWA Jacobian at the guard-banded direction
+    const float limx = 1.3f * ((0.5f * (float)V.width) / V.fx);
+    const float limy = 1.3f * ((0.5f * (float)V.height) / V.fy);
+    const float ux0 = S.xc[0] / z, uy0 = S.xc[1] / z;
+    S.ux = fminf(fmaxf(ux0, -limx), limx);
+    S.uy = fminf(fmaxf(uy0, -limy), limy);
+    S.clx = (ux0 < -limx) || (ux0 > limx);
+    S.cly = (uy0 < -limy) || (uy0 > limy);
+    S.J00 = V.fx / z;
+    S.J02 = -(V.fx * S.ux) / z;
+    S.J11 = V.fy / z;
+    S.J12 = -(V.fy * S.uy) / z;
+    for (int j = 0; j < 3; ++j) {
+        S.T[0][j] = S.J00 * Rt[j] + S.J02 * Rt[8 + j];
+        S.T[1][j] = S.J11 * Rt[4 + j] + S.J12 * Rt[8 + j];
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            S.U[i][j] = S.T[i][0] * S.Sc[0][j] + S.T[i][1] * S.Sc[1][j] + S.T[i][2] * S.Sc[2][j];
+    S.sa = S.U[0][0] * S.T[0][0] + S.U[0][1] * S.T[0][1] + S.U[0][2] * S.T[0][2] + 0.3f;
+    S.sb = S.U[0][0] * S.T[1][0] + S.U[0][1] * S.T[1][1] + S.U[0][2] * S.T[1][2];
+    S.sc = S.U[1][0] * S.T[1][0] + S.U[1][1] * S.T[1][1] + S.U[1][2] * S.T[1][2] + 0.3f;
+    S.det = S.sa * S.sc - S.sb * S.sb;
+    if (!(S.det > 0.0f)) return 0;
+    S.ca = S.sc / S.det;
+    S.cb = -S.sb / S.det;
+    S.cc = S.sa / S.det;
+    S.mx = V.fx * ux0 + V.cx;
+    S.my = V.fy * uy0 + V.cy;
+
+    // exact footprint: alpha >= 1/255 iff d^T conic d <= 2 ln(255 o_t)
+    const float tau = 2.0f * fixed_log(255.0f * S.ot);
+    const float taub = tau * 1.0009765625f + 0.0009765625f;
+    const float hx = sqrtf(taub * S.sa), hy = sqrtf(taub * S.sc);
+    if (!isfinite(S.mx) || !isfinite(S.my) || !isfinite(hx) || !isfinite(hy) ||
+        !isfinite(S.ca) || !isfinite(S.cb) || !isfinite(S.cc))
+        return 0;
+    float x0 = ceilf((S.mx - hx) - 0.5f), x1 = floorf((S.mx + hx) - 0.5f);
+    float y0 = ceilf((S.my - hy) - 0.5f), y1 = floorf((S.my + hy) - 0.5f);
+    x0 = fminf(fmaxf(x0, 0.0f), (float)V.width);
+    y0 = fminf(fmaxf(y0, 0.0f), (float)V.height);
+    x1 = fmaxf(fminf(x1, (float)(V.width - 1)), -1.0f);
+    y1 = fmaxf(fminf(y1, (float)(V.height - 1)), -1.0f);
+    const int px0 = (int)x0, px1 = (int)x1, py0 = (int)y0, py1 = (int)y1;
+    if (px0 > px1 || py0 > py1) return 0;
+    if (rect_out) *rect_out = make_int4(px0 >> 4, py0 >> 4, (px1 >> 4) + 1, (py1 >> 4) + 1);
+    return 1;
+}
+
+__global__ void __launch_bounds__(256)
+preprocess_fwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp, float4 *__restrict__ rec,
+                      int4 *__restrict__ rect, int32_t *__restrict__ touched) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int vi = blockIdx.y;
+    if (g >= n) return;
+    float p[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) p[k] = P[(int64_t)k * n + g];
+    Slice S;
+    int4 rc = make_int4(0, 0, 0, 0);
+    const int vis = slice_project(p, vp.v[vi], S, &rc);
+    const int64_t o = (int64_t)vi * n + g;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    int tt = 0;
+    if (vis) {
+        r0 = make_float4(S.mx, S.my, S.ca, S.cb);
+        r1 = make_float4(S.cc, S.ot, S.xc[2], 0.0f);
+        r2 = make_float4(p[17], p[18], p[19], 0.0f);
+        tt = (rc.z - rc.x) * (rc.w - rc.y);
+    } else {
+        rc = make_int4(0, 0, 0, 0);
+    }
+    rec[3 * o + 0] = r0;
+    rec[3 * o + 1] = r1;
+    rec[3 * o + 2] = r2;
+    rect[o] = rc;
+    touched[o] = tt;
+}
+
+// Backward: d(mean2D, conic, o_t, rgb) per (view, Gaussian) -> d(raw params),
+// summed over views.  Follows the forward above term by term (chain rule):
+// conic -> Sigma2D (dS = -Q dQ Q), Sigma2D -> (T, Sc), T = J W -> J -> camera
+// point (no gradient through a clamped guard-band coordinate), camera ->
+// conditional mean, conditional -> (Sigma blocks, mu_t, opacity), Sigma =
+// M M^T -> (R, s), R -> (left, right) unit quaternions -> raw quaternions.
+__global__ void __launch_bounds__(128)
+preprocess_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
+                      const int32_t *__restrict__ touched, const float *__restrict__ grad2d,
+                      float *__restrict__ dP) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    float p[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) p[k] = P[(int64_t)k * n + g];
+    float acc[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) acc[k] = 0.0f;
+
+    for (int vi = 0; vi < vp.n_views; ++vi) {
+        const int64_t o = (int64_t)vi * n + g;
+        if (touched[o] == 0) continue;
+        const gs4d_view &V = vp.v[vi];
+        Slice S;
+        if (!slice_project(p, V, S, nullptr)) continue;
+        float G[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) G[k] = grad2d[o * 9 + k];
+        const float *Rt = V.Rt;
+        const float z = S.xc[2];
+
+        // conic -> Sigma2D:  G_S = -Q Gq Q, Gq = [[ga, gb/2], [gb/2, gc]]
+        const float q00 = S.ca, q01 = S.cb, q11 = S.cc;
+        const float g00 = G[2], g01 = 0.5f * G[3], g11 = G[4];
+        const float t00 = g00 * q00 + g01 * q01, t01 = g00 * q01 + g01 * q11;
+        const float t10 = g01 * q00 + g11 * q01, t11 = g01 * q01 + g11 * q11;
+        const float S00 = -(q00 * t00 + q01 * t10);
+        const float S01 = -(q00 * t01 + q01 * t11);
+        const float S11 = -(q01 * t01 + q11 * t11);
+        const float GS2[2][2] = {{S00, S01}, {S01, S11}};
+
+        // Sigma2D = T Sc T^T: dSc = T^T GS2 T; dT = 2 GS2 U  (U = T Sc)
+        float GSc[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                float accv = 0.0f;
+                for (int k = 0; k < 2; ++k)
+                    for (int l = 0; l < 2; ++l) accv += S.T[k][i] * GS2[k][l] * S.T[l][j];
+                GSc[i][j] = accv;
+            }
+        float GT[2][3];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j)
+                GT[i][j] = 2.0f * (GS2[i][0] * S.U[0][j] + GS2[i][1] * S.U[1][j]);
+        // T = J W: dJ = dT W^T (only the non-constant entries of J)
+        const float GJ00 = GT[0][0] * Rt[0] + GT[0][1] * Rt[1] + GT[0][2] * Rt[2];
+        const float GJ02 = GT[0][0] * Rt[8] + GT[0][1] * Rt[9] + GT[0][2] * Rt[10];
+        const float GJ11 = GT[1][0] * Rt[4] + GT[1][1] * Rt[5] + GT[1][2] * Rt[6];
+        const float GJ12 = GT[1][0] * Rt[8] + GT[1][1] * Rt[9] + GT[1][2] * Rt[10];
+        const float iz = 1.0f / z, iz2 = iz * iz;
+        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+        gz += -(GJ00 * V.fx + GJ11 * V.fy) * iz2;
+        if (S.clx) {
+            gz += GJ02 * V.fx * S.ux * iz2;
+        } else {
+            gx += -GJ02 * V.fx * iz2;
+            gz += GJ02 * 2.0f * V.fx * S.xc[0] * iz2 * iz;
+        }
+        if (S.cly) {
+            gz += GJ12 * V.fy * S.uy * iz2;
+        } else {
+            gy += -GJ12 * V.fy * iz2;
+            gz += GJ12 * 2.0f * V.fy * S.xc[1] * iz2 * iz;
+        }
+        // mean2D = (fx x/z + cx, fy y/z + cy)
+        gx += G[0] * V.fx * iz;
+        gy += G[1] * V.fy * iz;
+        gz += -(G[0] * V.fx * S.xc[0] + G[1] * V.fy * S.xc[1]) * iz2;
+        // camera point -> conditional mean
+        float Gmu[3];
+        for (int j = 0; j < 3; ++j) Gmu[j] = Rt[j] * gx + Rt[4 + j] * gy + Rt[8 + j] * gz;
+
+        // conditional -> Sigma blocks (Sb, a, c), mu, opacity
+        const float c = S.Sg[3][3], ic = 1.0f / c;
+        const float a3[3] = {S.Sg[0][3], S.Sg[1][3], S.Sg[2][3]};
+        const float go = G[5];
+        float Gmua = 0.0f, aGa = 0.0f, Ga[3];
+        for (int i = 0; i < 3; ++i) {
+            Gmua += Gmu[i] * a3[i];
+            Ga[i] = GSc[i][0] * a3[0] + GSc[i][1] * a3[1] + GSc[i][2] * a3[2];
+            aGa += a3[i] * Ga[i];
+        }
+        const float dt = S.dt;
+        for (int i = 0; i < 3; ++i) acc[i] += Gmu[i];
+        acc[3] += -Gmua * ic + go * S.ot * dt * ic;
+        float Gda[3];
+        for (int i = 0; i < 3; ++i) Gda[i] = Gmu[i] * dt * ic - 2.0f * Ga[i] * ic;
+        const float Gdc = (-Gmua * dt + aGa + 0.5f * go * S.ot * dt * dt) * ic * ic;
+        const float Gdo = go * S.ef;
+
+        // symmetric gradient of Sigma; Sigma = M M^T -> dM = 2 G4 M
+        float G4[4][4];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) G4[i][j] = GSc[i][j];
+        for (int i = 0; i < 3; ++i) {
+            G4[i][3] = 0.5f * Gda[i];
+            G4[3][i] = 0.5f * Gda[i];
+        }
+        G4[3][3] = Gdc;
+        float GR[4][4], Gs[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                const float gm = 2.0f * (G4[i][0] * S.M[0][j] + G4[i][1] * S.M[1][j] +
+                                         G4[i][2] * S.M[2][j] + G4[i][3] * S.M[3][j]);
+                GR[i][j] = gm * S.s[j];
+                Gs[j] += gm * S.R[i][j];
+            }
+        // R = Pi (A B) Pi^T
+        const int perm[4] = {1, 2, 3, 0};
+        float GQ[4][4];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) GQ[perm[i]][perm[j]] = GR[i][j];
+        float GA[4][4], GB[4][4];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                GA[i][j] = GQ[i][0] * S.B[j][0] + GQ[i][1] * S.B[j][1] + GQ[i][2] * S.B[j][2] +
+                           GQ[i][3] * S.B[j][3];
+                GB[i][j] = S.A[0][i] * GQ[0][j] + S.A[1][i] * GQ[1][j] + S.A[2][i] * GQ[2][j] +
+                           S.A[3][i] * GQ[3][j];
+            }
+        // each matrix entry is +- one quaternion component
+        float gl[4], gr[4];
+        gl[0] = GA[0][0] + GA[1][1] + GA[2][2] + GA[3][3];
+        gl[1] = -GA[0][1] + GA[1][0] - GA[2][3] + GA[3][2];
+        gl[2] = -GA[0][2] + GA[1][3] + GA[2][0] - GA[3][1];
+        gl[3] = -GA[0][3] - GA[1][2] + GA[2][1] + GA[3][0];
+        gr[0] = GB[0][0] + GB[1][1] + GB[2][2] + GB[3][3];
+        gr[1] = -GB[0][1] + GB[1][0] + GB[2][3] - GB[3][2];
+        gr[2] = -GB[0][2] - GB[1][3] + GB[2][0] + GB[3][1];
+        gr[3] = -GB[0][3] + GB[1][2] - GB[2][1] + GB[3][0];
+        float dl = 0.0f, dr = 0.0f;
+        for (int k = 0; k < 4; ++k) {
+            dl += S.ql[k] * gl[k];
+            dr += S.qr[k] * gr[k];
+        }
+        const float inl = 1.0f / S.nl, inr = 1.0f / S.nr;
+        for (int k = 0; k < 4; ++k) {
+            acc[4 + k] += Gs[k] * S.s[k];
+            acc[8 + k] += (gl[k] - S.ql[k] * dl) * inl;
+            acc[12 + k] += (gr[k] - S.qr[k] * dr) * inr;
+        }
+        acc[16] += Gdo * S.o * (1.0f - S.o);
+        acc[17] += G[6];
+        acc[18] += G[7];
+        acc[19] += G[8];
+    }
+#pragma unroll
+    for (int k = 0; k < 20; ++k) dP[(int64_t)k * n + g] = acc[k];
+}
+
+}  // namespace
+
+int launch_preprocess_bwd(const float *params, int64_t n, const ViewPack &vp,
+                          const int32_t *touched, const float *grad2d, float *dparams,
+                          hipStream_t st) {
+    if (n == 0) return GS4D_OK;
+    const unsigned blocks = (unsigned)((n + 127) / 128);
+    preprocess_bwd_kernel<<<blocks, 128, 0, st>>>(params, n, vp, touched, grad2d, dparams);
+    GS4D_LAUNCH_CHECK("preprocess_bwd");
+    return GS4D_OK;
+}
+
+}  // namespace gs4d
+
+using namespace gs4d;
+
+extern "C" int gs4d_preprocess(const float *params, int64_t n, const gs4d_view *views,
+                               int32_t n_views, float *rec, int32_t *rect, int32_t *touched,
+                               void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_REQUIRE(n >= 0, "gs4d_preprocess: n < 0");
+    GS4D_REQUIRE(n <= (int64_t)0x7fffffff, "gs4d_preprocess: n >= 2^31");
+    if (n == 0) return GS4D_OK;
+    GS4D_REQUIRE(params && rec && rect && touched, "gs4d_preprocess: null pointer");
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
+    preprocess_fwd_kernel<<<grid, 256, 0, as_stream(stream)>>>(
+        params, n, vp, reinterpret_cast<float4 *>(rec), reinterpret_cast<int4 *>(rect), touched);
+    GS4D_LAUNCH_CHECK("gs4d_preprocess");
+    return GS4D_OK;
+}

@@ -1,0 +1,306 @@
+// Optimisation-loop kernels: Adam, L1, SSIM, squared error.
+//
+// The method trains with a single photometric loss using the loss weights
+// and optimiser of 3D Gaussian splatting, with the position learning rate
+// lowered to 1e-5 and the schedule stretched to the iteration budget
+// (Sec. 4.1).  Readings: Adam with bias correction; per-row exponential
+// learning-rate decay lr0^(1-u) lr1^u; SSIM with an 11x11 Gaussian window
+// (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2 and zero padding.
+#include "common.hpp"
+
+#include <cmath>
+
+namespace gs4d {
+namespace {
+
+// ---------------------------------------------------------------- Adam
+__global__ void __launch_bounds__(256)
+adam_kernel(float *__restrict__ P, const float *__restrict__ Gr, float *__restrict__ M,
+            float *__restrict__ Vv, int64_t n, gs4d_adam_cfg cfg, const int32_t *__restrict__ step) {
+    __shared__ float lr[GS4D_N_FIELDS];
+    __shared__ float bc1, bc2;
+    const int s = *step + 1;
+    if (threadIdx.x < (unsigned)cfg.rows) {
+        const int r = threadIdx.x;
+        float u = cfg.budget > 0 ? (float)s / (float)cfg.budget : 1.0f;
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        const float a = cfg.lr0[r], b = cfg.lr1[r];
+        lr[r] = (a > 0.0f && b > 0.0f) ? expf(logf(a) * (1.0f - u) + logf(b) * u) : a;
+    }
+    if (threadIdx.x == 0) {
+        bc1 = 1.0f - powf(cfg.beta1, (float)s);
+        bc2 = 1.0f - powf(cfg.beta2, (float)s);
+    }
+    __syncthreads();
+    const int64_t total = (int64_t)cfg.rows * n;
+    const float b1 = cfg.beta1, b2 = cfg.beta2, eps = cfg.eps;
+    const float ib1 = 1.0f / bc1, ib2 = 1.0f / bc2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i / n);
+        const float rate = lr[r];
+        if (rate == 0.0f) continue;
+        const float g = Gr[i];
+        const float m = b1 * M[i] + (1.0f - b1) * g;
+        const float v = b2 * Vv[i] + (1.0f - b2) * g * g;
+        M[i] = m;
+        Vv[i] = v;
+        P[i] -= rate * (m * ib1) / (sqrtf(v * ib2) + eps);
+    }
+}
+
+__global__ void tick_kernel(int32_t *step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+// ---------------------------------------------------------------- L1 / SSE
+__global__ void __launch_bounds__(256)
+l1_kernel(const float *__restrict__ x, const float *__restrict__ y, int64_t count, float weight,
+          float *__restrict__ loss, float *__restrict__ dx) {
+    const float scale = weight / (float)count;
+    float s = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = x[i] - y[i];
+        s += fabsf(d);
+        if (dx) dx[i] += d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0 && s != 0.0f) atomicAdd(loss, s * scale);
+}
+
+__global__ void __launch_bounds__(256)
+sse_kernel(const float *__restrict__ x, const float *__restrict__ y, int64_t count,
+           double *__restrict__ out) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)x[i] - (double)y[i];
+        s += d * d;
+    }
+    s = wave_sum_d(s);
+    if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(out, s);
+}
+
+// ---------------------------------------------------------------- SSIM
+constexpr int SS_R = 5;               // window radius (11 taps)
+constexpr int SS_T = 16;              // output tile edge
+constexpr int SS_E = SS_T + 2 * SS_R; // staged edge (26)
+constexpr float SS_C1 = 0.01f * 0.01f;
+constexpr float SS_C2 = 0.03f * 0.03f;
+
+struct Win {
+    float g[2 * SS_R + 1];
+};
+
+// Forward: per pixel SSIM and its partial derivatives with respect to the
+// windowed statistics mu_x, E[x^2], E[xy] (written to three maps).
+__global__ void __launch_bounds__(256)
+ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h, int w, Win win,
+                float weight, float inv_count, float *__restrict__ ssim_sum,
+                float *__restrict__ P1, float *__restrict__ P2, float *__restrict__ P3) {
+    __shared__ float sx[SS_E][SS_E], sy[SS_E][SS_E];
+    __shared__ float hs[5][SS_E][SS_T];
+    const int t = threadIdx.x;
+    const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
+    const int64_t plane = (int64_t)blockIdx.z * h * w;
+    for (int i = t; i < SS_E * SS_E; i += 256) {
+        const int r = i / SS_E, c = i - r * SS_E;
+        const int gy = oy + r, gx = ox + c;
+        const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
+        sx[r][c] = in ? X[plane + (int64_t)gy * w + gx] : 0.0f;
+        sy[r][c] = in ? Y[plane + (int64_t)gy * w + gx] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = t; i < SS_E * SS_T; i += 256) {
+        const int r = i / SS_T, c = i - r * SS_T;
+        float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+#pragma unroll
+        for (int k = 0; k < 2 * SS_R + 1; ++k) {
+            const float xv = sx[r][c + k], yv = sy[r][c + k], g = win.g[k];
+            a += g * xv;
+            b += g * yv;
+            aa += g * xv * xv;
+            bb += g * yv * yv;
+            ab += g * xv * yv;
+        }
+        hs[0][r][c] = a;
+        hs[1][r][c] = b;
+        hs[2][r][c] = aa;
+        hs[3][r][c] = bb;
+        hs[4][r][c] = ab;
+    }
+    __syncthreads();
+    const int c = t & 15, r = t >> 4;
+    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2 * SS_R + 1; ++k) {
+        const float g = win.g[k];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) m[q] += g * hs[q][r + k][c];
+    }
+    const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
+    float sv = 0.0f;
+    if (gx < w && gy < h) {
+        const float mx = m[0], my = m[1];
+        const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+        const float A1 = 2.f * mx * my + SS_C1, A2 = 2.f * sxy + SS_C2;
+        const float B1 = mx * mx + my * my + SS_C1, B2 = sxx + syy + SS_C2;
+        const float S = (A1 * A2) / (B1 * B2);
+        sv = S;
+        const int64_t o = plane + (int64_t)gy * w + gx;
+        if (P1) {
+            P1[o] = S * (2.f * my / A1 - 2.f * mx / B1 - 2.f * my / A2 + 2.f * mx / B2);
+            P2[o] = -S / B2;
+            P3[o] = 2.f * S / A2;
+        }
+    }
+    sv = wave_sum(sv);
+    if ((t & 63) == 0 && ssim_sum) atomicAdd(ssim_sum, sv * weight * inv_count);
+}
+
+// Backward: dSSIM/dx(q) = (G*P1)(q) + 2 x(q) (G*P2)(q) + y(q) (G*P3)(q),
+// the window being symmetric (its adjoint is itself).
+__global__ void __launch_bounds__(256)
+ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h, int w, Win win,
+                float scale, const float *__restrict__ P1, const float *__restrict__ P2,
+                const float *__restrict__ P3, float *__restrict__ dX) {
+    __shared__ float sp[3][SS_E][SS_E];
+    __shared__ float hs[3][SS_E][SS_T];
+    const int t = threadIdx.x;
+    const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
+    const int64_t plane = (int64_t)blockIdx.z * h * w;
+    for (int i = t; i < SS_E * SS_E; i += 256) {
+        const int r = i / SS_E, c = i - r * SS_E;
+        const int gy = oy + r, gx = ox + c;
+        const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
+        const int64_t o = plane + (int64_t)gy * w + gx;
+        sp[0][r][c] = in ? P1[o] : 0.0f;
+        sp[1][r][c] = in ? P2[o] : 0.0f;
+        sp[2][r][c] = in ? P3[o] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = t; i < SS_E * SS_T; i += 256) {
+        const int r = i / SS_T, c = i - r * SS_T;
+        float a = 0.f, b = 0.f, d = 0.f;
+#pragma unroll
+        for (int k = 0; k < 2 * SS_R + 1; ++k) {
+            const float g = win.g[k];
+            a += g * sp[0][r][c + k];
+            b += g * sp[1][r][c + k];
+            d += g * sp[2][r][c + k];
+        }
+        hs[0][r][c] = a;
+        hs[1][r][c] = b;
+        hs[2][r][c] = d;
+    }
+    __syncthreads();
+    const int c = t & 15, r = t >> 4;
+    float q[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2 * SS_R + 1; ++k) {
+        const float g = win.g[k];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) q[j] += g * hs[j][r + k][c];
+    }
+    const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
+    if (gx < w && gy < h) {
+        const int64_t o = plane + (int64_t)gy * w + gx;
+        dX[o] += scale * (q[0] + 2.f * X[o] * q[1] + Y[o] * q[2]);
+    }
+}
+
+Win make_window() {
+    Win wv;
+    double g[2 * SS_R + 1], s = 0.0;
+    for (int k = 0; k < 2 * SS_R + 1; ++k) {
+        const double x = k - SS_R;
+        g[k] = std::exp(-(x * x) / (2.0 * 1.5 * 1.5));
+        s += g[k];
+    }
+    for (int k = 0; k < 2 * SS_R + 1; ++k) wv.g[k] = (float)(g[k] / s);
+    return wv;
+}
+
+inline unsigned stride_grid(int64_t count) {
+    int64_t b = (count + 255) / 256;
+    if (b > 2048) b = 2048;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+}  // namespace
+}  // namespace gs4d
+
+using namespace gs4d;
+
+extern "C" int gs4d_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                              const gs4d_adam_cfg *cfg, int32_t *step, void *stream) {
+    GS4D_REQUIRE(cfg && step, "gs4d_adam_step: null cfg / step");
+    GS4D_REQUIRE(cfg->rows >= 1 && cfg->rows <= GS4D_N_FIELDS, "gs4d_adam_step: rows out of range");
+    GS4D_REQUIRE(n >= 0, "gs4d_adam_step: n < 0");
+    GS4D_REQUIRE(n == 0 || (params && grads && m && v), "gs4d_adam_step: null pointer");
+    hipStream_t st = as_stream(stream);
+    if (n > 0) {
+        adam_kernel<<<stride_grid((int64_t)cfg->rows * n), 256, 0, st>>>(params, grads, m, v, n, *cfg,
+                                                                          step);
+        GS4D_LAUNCH_CHECK("gs4d_adam_step");
+    }
+    tick_kernel<<<1, 64, 0, st>>>(step);
+    GS4D_LAUNCH_CHECK("gs4d_adam_step tick");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_loss_l1(const float *img, const float *target, int64_t count, float weight,
+                            float *loss, float *dL_dimg, void *stream) {
+    GS4D_REQUIRE(count >= 0 && loss, "gs4d_loss_l1: bad arguments");
+    if (count == 0) return GS4D_OK;
+    GS4D_REQUIRE(img && target, "gs4d_loss_l1: null pointer");
+    l1_kernel<<<stride_grid(count), 256, 0, as_stream(stream)>>>(img, target, count, weight, loss,
+                                                                  dL_dimg);
+    GS4D_LAUNCH_CHECK("gs4d_loss_l1");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_sse(const float *img, const float *target, int64_t count, double *sse,
+                        void *stream) {
+    GS4D_REQUIRE(count >= 0 && sse, "gs4d_sse: bad arguments");
+    if (count == 0) return GS4D_OK;
+    GS4D_REQUIRE(img && target, "gs4d_sse: null pointer");
+    sse_kernel<<<stride_grid(count), 256, 0, as_stream(stream)>>>(img, target, count, sse);
+    GS4D_LAUNCH_CHECK("gs4d_sse");
+    return GS4D_OK;
+}
+
+extern "C" size_t gs4d_ssim_workspace_size(int32_t b, int32_t c, int32_t h, int32_t w) {
+    return (size_t)3 * (size_t)b * c * h * w * sizeof(float) + 3 * 256;
+}
+
+extern "C" int gs4d_ssim(const float *img, const float *target, int32_t b, int32_t c, int32_t h,
+                         int32_t w, float weight, float *ssim_sum, float *dL_dimg, void *ws,
+                         size_t ws_bytes, void *stream) {
+    GS4D_REQUIRE(b > 0 && c > 0 && h > 0 && w > 0, "gs4d_ssim: bad shape");
+    GS4D_REQUIRE((int64_t)b * c <= 65535, "gs4d_ssim: too many planes");
+    GS4D_REQUIRE(img && target, "gs4d_ssim: null image");
+    hipStream_t st = as_stream(stream);
+    const int64_t count = (int64_t)b * c * h * w;
+    float *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
+    if (dL_dimg) {
+        GS4D_REQUIRE(ws && ws_bytes >= gs4d_ssim_workspace_size(b, c, h, w),
+                     "gs4d_ssim: workspace too small");
+        Carve cv(ws, ws_bytes);
+        P1 = cv.take<float>((size_t)count);
+        P2 = cv.take<float>((size_t)count);
+        P3 = cv.take<float>((size_t)count);
+    }
+    const Win win = make_window();
+    dim3 grid((unsigned)((w + SS_T - 1) / SS_T), (unsigned)((h + SS_T - 1) / SS_T), (unsigned)(b * c));
+    ssim_fwd_kernel<<<grid, 256, 0, st>>>(img, target, h, w, win, weight, 1.0f / (float)count,
+                                          ssim_sum, P1, P2, P3);
+    GS4D_LAUNCH_CHECK("gs4d_ssim fwd");
+    if (dL_dimg) {
+        ssim_bwd_kernel<<<grid, 256, 0, st>>>(img, target, h, w, win, weight / (float)count, P1, P2,
+                                              P3, dL_dimg);
+        GS4D_LAUNCH_CHECK("gs4d_ssim bwd");
+    }
+    return GS4D_OK;
+}

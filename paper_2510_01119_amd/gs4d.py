@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libgs4d.so.
+
+Every function here has the name of the C entry point it wraps and does
+argument marshalling only: torch tensors become device pointers, numpy view
+arrays become ``gs4d_view`` structs, and a non-zero status raises
+``GS4DError`` with the library's message.  All arithmetic happens in the
+HIP kernels.  There is no fallback: if the library is missing, loading
+fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs4d.so")
+
+N_FIELDS = 20
+REC_FLOATS = 12
+GRAD2D_FLOATS = 9
+TILE = 16
+MAX_VIEWS = 16
+
+
+class GS4DError(RuntimeError):
+    pass
+
+
+class gs4d_view(ctypes.Structure):
+    _fields_ = [("Rt", ctypes.c_float * 12), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("t", ctypes.c_float), ("near_z", ctypes.c_float),
+                ("bg", ctypes.c_float * 3), ("reserved", ctypes.c_int32)]
+
+
+class gs4d_render_opts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("n_workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("target", ctypes.c_void_p), ("l1_weight", ctypes.c_float),
+                ("loss_per_view", ctypes.c_void_p), ("dL_dimage", ctypes.c_void_p),
+                ("counters", ctypes.c_void_p), ("order", ctypes.c_void_p),
+                ("queue", ctypes.c_void_p)]
+
+
+class gs4d_adam_cfg(ctypes.Structure):
+    _fields_ = [("lr0", ctypes.c_float * N_FIELDS), ("lr1", ctypes.c_float * N_FIELDS),
+                ("budget", ctypes.c_int32), ("rows", ctypes.c_int32), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_f32 = ctypes.c_float
+_sz = ctypes.c_size_t
+
+_SIGS = {
+    "gs4d_preprocess": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
+    "gs4d_bin_sort_workspace_size": (_sz, [_i64, _i32, _i64]),
+    "gs4d_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _i32, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "gs4d_render_fwd": (_i32, [_p, _i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
+    "gs4d_render_bwd_workspace_size": (_sz, [_i64, _i32]),
+    "gs4d_render_bwd": (_i32, [_p, _i64, _p, _p, _p, _p, _p, _i32, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "gs4d_grid_prune_workspace_size": (_sz, [_i64, _i32]),
+    "gs4d_grid_prune": (_i32, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p, _p,
+                               _p, _p, _sz, _p]),
+    "gs4d_adam_step": (_i32, [_p, _p, _p, _p, _i64, _p, _p, _p]),
+    "gs4d_loss_l1": (_i32, [_p, _p, _i64, _f32, _p, _p, _p]),
+    "gs4d_ssim_workspace_size": (_sz, [_i32, _i32, _i32, _i32]),
+    "gs4d_ssim": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _f32, _p, _p, _p, _sz, _p]),
+    "gs4d_sse": (_i32, [_p, _p, _i64, _p, _p]),
+    "gs4d_fill_f32": (_i32, [_p, _f32, _i64, _p]),
+    "gs4d_fill_u32": (_i32, [_p, ctypes.c_uint32, _i64, _p]),
+    "gs4d_status_string": (ctypes.c_char_p, [_i32]),
+    "gs4d_last_error": (ctypes.c_char_p, []),
+    "gs4d_version": (_i32, []),
+}
+
+EXPORTED = tuple(_SIGS)
+_lib = None
+
+
+def lib():
+    """Load libgs4d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GS4DError(f"libgs4d.so not found at {LIB_PATH}; run paper_2510_01119_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            if not hasattr(L, name):
+                continue
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        L = lib()
+        raise GS4DError(f"{what}: {L.gs4d_status_string(status).decode()} "
+                        f"({L.gs4d_last_error().decode()})")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if t.numel() > 0 and not t.is_cuda:
+            raise GS4DError("expected a device tensor")
+        if not t.is_contiguous():
+            raise GS4DError("expected a contiguous tensor")
+        return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
+    return t
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_views(views) -> ctypes.Array:
+    """numpy [V, 23] (see synth.make_view) -> ctypes array of gs4d_view."""
+    v = np.atleast_2d(np.asarray(views, dtype=np.float64))
+    arr = (gs4d_view * v.shape[0])()
+    for i, row in enumerate(v):
+        s = arr[i]
+        for k in range(12):
+            s.Rt[k] = float(np.float32(row[k]))
+        s.fx, s.fy, s.cx, s.cy = (float(np.float32(x)) for x in row[12:16])
+        s.width, s.height = int(row[16]), int(row[17])
+        s.t = float(np.float32(row[18]))
+        s.near_z = float(np.float32(row[19]))
+        for k in range(3):
+            s.bg[k] = float(np.float32(row[20 + k]))
+        s.reserved = 0
+    return arr
+
+
+# ---------------------------------------------------------------- entry points
+def gs4d_preprocess(params, views, rec, rect, touched, stream=None):
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    n = params.shape[1]
+    _check(lib().gs4d_preprocess(_ptr(params), n, va, len(va), _ptr(rec), _ptr(rect),
+                                 _ptr(touched), _stream(stream)), "gs4d_preprocess")
+
+
+def gs4d_bin_sort_workspace_size(n, n_views, pair_capacity):
+    return int(lib().gs4d_bin_sort_workspace_size(n, n_views, pair_capacity))
+
+
+def gs4d_bin_sort(rec, rect, touched, n, views, pair_capacity, keys, vals, ranges, n_pairs,
+                  overflow, ws, stream=None):
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_bin_sort(_ptr(rec), _ptr(rect), _ptr(touched), n, va, len(va), pair_capacity,
+                               _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(n_pairs), _ptr(overflow),
+                               _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "gs4d_bin_sort")
+
+
+def gs4d_render_fwd(rec, n, vals, ranges, views, image, T_final, last, opts=None, stream=None):
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_render_fwd(_ptr(rec), n, _ptr(vals), _ptr(ranges), va, len(va),
+                                 ctypes.byref(opts) if opts is not None else None, _ptr(image),
+                                 _ptr(T_final), _ptr(last), _stream(stream)), "gs4d_render_fwd")
+
+
+def gs4d_render_bwd_workspace_size(n, n_views):
+    return int(lib().gs4d_render_bwd_workspace_size(n, n_views))
+
+
+def gs4d_render_bwd(params, rec, touched, vals, ranges, views, dL_dimage, T_final, last, dparams,
+                    grad2d=None, ws=None, stream=None):
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    n = params.shape[1]
+    _check(lib().gs4d_render_bwd(_ptr(params), n, _ptr(rec), _ptr(touched), _ptr(vals), _ptr(ranges),
+                                 va, len(va), _ptr(dL_dimage), _ptr(T_final), _ptr(last),
+                                 _ptr(dparams), _ptr(grad2d), _ptr(ws),
+                                 0 if ws is None else ws.numel() * ws.element_size(),
+                                 _stream(stream)), "gs4d_render_bwd")
+
+
+def gs4d_grid_prune_workspace_size(m, k_attr):
+    return int(lib().gs4d_grid_prune_workspace_size(m, k_attr))
+
+
+def gs4d_grid_prune(xyz, attr, cls, voxel_static, voxel_dynamic, min_count, capacity, out_xyz,
+                    out_attr, out_count, out_key, n_out, status, ws, stream=None):
+    m = xyz.shape[1]
+    k = 0 if attr is None else attr.shape[0]
+    _check(lib().gs4d_grid_prune(_ptr(xyz), _ptr(attr), k, _ptr(cls), m, float(voxel_static),
+                                 float(voxel_dynamic), int(min_count), int(capacity), _ptr(out_xyz),
+                                 _ptr(out_attr), _ptr(out_count), _ptr(out_key), _ptr(n_out),
+                                 _ptr(status), _ptr(ws), ws.numel() * ws.element_size(),
+                                 _stream(stream)), "gs4d_grid_prune")
+
+
+def gs4d_adam_step(params, grads, m, v, cfg, step, stream=None):
+    _check(lib().gs4d_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.shape[-1],
+                                ctypes.byref(cfg), _ptr(step), _stream(stream)), "gs4d_adam_step")
+
+
+def gs4d_loss_l1(img, target, weight, loss, dL_dimg=None, stream=None):
+    _check(lib().gs4d_loss_l1(_ptr(img), _ptr(target), img.numel(), float(weight), _ptr(loss),
+                              _ptr(dL_dimg), _stream(stream)), "gs4d_loss_l1")
+
+
+def gs4d_ssim_workspace_size(b, c, h, w):
+    return int(lib().gs4d_ssim_workspace_size(b, c, h, w))
+
+
+def gs4d_ssim(img, target, weight, ssim_sum, dL_dimg, ws, stream=None):
+    b, c, h, w = img.shape
+    _check(lib().gs4d_ssim(_ptr(img), _ptr(target), b, c, h, w, float(weight), _ptr(ssim_sum),
+                           _ptr(dL_dimg), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "gs4d_ssim")
+
+
+def gs4d_sse(img, target, sse, stream=None):
+    _check(lib().gs4d_sse(_ptr(img), _ptr(target), img.numel(), _ptr(sse), _stream(stream)),
+           "gs4d_sse")
+
+
+def gs4d_fill_f32(dst, value, stream=None):
+    _check(lib().gs4d_fill_f32(_ptr(dst), float(value), dst.numel(), _stream(stream)), "gs4d_fill_f32")
+
+
+def gs4d_fill_u32(dst, value, stream=None):
+    _check(lib().gs4d_fill_u32(_ptr(dst), int(value), dst.numel(), _stream(stream)), "gs4d_fill_u32")

@@ -1,0 +1,121 @@
+"""Device-buffer management around the C ABI, and the autograd Function.
+
+``Rasterizer`` owns every buffer one rasterization needs (records, pairs,
+workspaces, image, per-pixel state) so that a training step allocates
+nothing; torch provides the memory and the stream only.  The per-pixel
+state the backward needs (T_final and the last blended entry) is kept, the
+per-entry transmittance is recomputed by the backward kernel.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import gs4d as G
+
+
+class Rasterizer:
+    """Buffers for rendering ``n`` Gaussians into ``views`` (numpy [V, 23])."""
+
+    def __init__(self, n: int, views, device="cuda", pair_capacity: int | None = None,
+                 batch: int = 256, count_blends: bool = False):
+        self.device = torch.device(device)
+        self.views_np = np.atleast_2d(np.asarray(views, dtype=np.float64))
+        self.cviews = G.make_views(self.views_np)
+        self.V = self.views_np.shape[0]
+        self.W, self.H = int(self.views_np[0, 16]), int(self.views_np[0, 17])
+        self.tiles_x, self.tiles_y = (self.W + 15) // 16, (self.H + 15) // 16
+        self.n_tiles = self.V * self.tiles_x * self.tiles_y
+        self.n = int(n)
+        self.batch = batch
+        dev = self.device
+        V, H, W = self.V, self.H, self.W
+        self.rec = torch.zeros((V, max(n, 1), G.REC_FLOATS), dtype=torch.float32, device=dev)
+        self.rect = torch.zeros((V, max(n, 1), 4), dtype=torch.int32, device=dev)
+        self.touched = torch.zeros((V, max(n, 1)), dtype=torch.int32, device=dev)
+        self.ranges = torch.zeros((self.n_tiles, 2), dtype=torch.int32, device=dev)
+        self.n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.image = torch.zeros((V, 3, H, W), dtype=torch.float32, device=dev)
+        self.T_final = torch.zeros((V, H, W), dtype=torch.float32, device=dev)
+        self.last = torch.zeros((V, H, W), dtype=torch.int32, device=dev)
+        self.dparams = torch.zeros((G.N_FIELDS, max(n, 1)), dtype=torch.float32, device=dev)
+        self.grad2d = torch.zeros((V, max(n, 1), G.GRAD2D_FLOATS), dtype=torch.float32, device=dev)
+        self.counters = torch.zeros(2, dtype=torch.int64, device=dev) if count_blends else None
+        self._alloc_pairs(pair_capacity if pair_capacity else max(1 << 16, 8 * n * V))
+
+    def _alloc_pairs(self, cap: int):
+        self.capacity = int(cap)
+        dev = self.device
+        self.keys = torch.zeros(self.capacity, dtype=torch.int64, device=dev)
+        self.vals = torch.zeros(self.capacity, dtype=torch.int32, device=dev)
+        ws = G.gs4d_bin_sort_workspace_size(self.n, self.V, self.capacity)
+        self.ws = torch.zeros(ws, dtype=torch.uint8, device=dev)
+
+    # ------------------------------------------------------------------ stages
+    def preprocess(self, params: torch.Tensor):
+        G.gs4d_preprocess(params, self.cviews, self.rec, self.rect, self.touched)
+
+    def bin_sort(self, check: bool = True):
+        """Sort into tiles.  With ``check`` the host reads the pair count and
+        grows the pair buffers (and re-sorts) if they overflowed."""
+        while True:
+            G.gs4d_bin_sort(self.rec, self.rect, self.touched, self.n, self.cviews, self.capacity,
+                            self.keys, self.vals, self.ranges, self.n_pairs, self.overflow, self.ws)
+            if not check:
+                return
+            if int(self.overflow.item()) == 0:
+                return
+            need = int(self.n_pairs.item())
+            self._alloc_pairs(int(need * 1.25) + 1024)
+
+    def render(self, opts=None):
+        if self.counters is not None:
+            self.counters.zero_()
+            if opts is None:
+                opts = G.gs4d_render_opts()
+                opts.batch = self.batch
+            opts.counters = self.counters.data_ptr()
+        elif opts is None:
+            opts = G.gs4d_render_opts()
+            opts.batch = self.batch
+        G.gs4d_render_fwd(self.rec, self.n, self.vals, self.ranges, self.cviews, self.image,
+                          self.T_final, self.last, opts)
+
+    def forward(self, params: torch.Tensor, check: bool = True, opts=None):
+        assert params.shape == (G.N_FIELDS, self.n) and params.dtype == torch.float32
+        self.preprocess(params)
+        self.bin_sort(check)
+        self.render(opts)
+        return self.image
+
+    def backward(self, params: torch.Tensor, dL_dimage: torch.Tensor):
+        G.gs4d_render_bwd(params, self.rec, self.touched, self.vals, self.ranges, self.cviews,
+                          dL_dimage.contiguous(), self.T_final, self.last, self.dparams,
+                          grad2d=self.grad2d)
+        return self.dparams
+
+    def pairs(self):
+        P = int(self.n_pairs.item())
+        return self.keys[:P], self.vals[:P]
+
+
+class GS4DRasterize(torch.autograd.Function):
+    """image = GS4DRasterize.apply(params [20, N], rasterizer).
+
+    The backward runs gs4d_render_bwd on the state the forward left in the
+    rasterizer's buffers, so a second forward through the same rasterizer
+    before backward is not allowed."""
+
+    @staticmethod
+    def forward(ctx, params, rast):
+        rast.forward(params.detach().contiguous())
+        ctx.rast = rast
+        ctx.save_for_backward(params)
+        return rast.image.clone()
+
+    @staticmethod
+    def backward(ctx, dimg):
+        (params,) = ctx.saved_tensors
+        d = ctx.rast.backward(params.detach().contiguous(), dimg.contiguous())
+        return d.clone(), None

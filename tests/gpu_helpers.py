@@ -1,0 +1,94 @@
+"""Shared helpers for the GPU parity tests (run the HIP path, compare with
+the oracle, classify threshold-adjacent pixels)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+ALPHA_MIN = 1.0 / 255.0
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_01119_amd import gs4d
+    gs4d.lib()
+
+
+def gpu_forward(params_np, views, batch=256, capacity=None, count_blends=False):
+    from paper_2510_01119_amd.rasterizer import Rasterizer
+    p = torch.from_numpy(np.ascontiguousarray(params_np, np.float32)).cuda()
+    r = Rasterizer(p.shape[1], views, pair_capacity=capacity, batch=batch, count_blends=count_blends)
+    r.forward(p)
+    torch.cuda.synchronize()
+    return r, p
+
+
+def to_np(r):
+    P = int(r.n_pairs.item())
+    out = dict(
+        rec=r.rec.cpu().numpy(), rect=r.rect.cpu().numpy(), touched=r.touched.cpu().numpy(),
+        keys=r.keys[:P].cpu().numpy().view(np.uint64), vals=r.vals[:P].cpu().numpy().view(np.uint32),
+        ranges=r.ranges.cpu().numpy(), image=r.image.cpu().numpy(), T_final=r.T_final.cpu().numpy(),
+        last=r.last.cpu().numpy(), n_pairs=P)
+    if r.counters is not None:
+        c = r.counters.cpu().numpy()
+        out["n_eval"], out["n_blend"] = int(c[0]), int(c[1])
+    return out
+
+
+def near_threshold_pixels(rec64, views, vals, ranges, rtol=1e-5, return_tainted=False):
+    """Boolean [V, H, W]: pixels where some entry's FP64 alpha lies within
+    rtol of 1/255 or 0.99, or the transmittance test is within rtol of 1e-4.
+    Such pixels may legitimately differ between an FP32 and an FP64 render.
+    With return_tainted, also the ids of Gaussians that reach alpha >= 1/255
+    (less rtol) at such a pixel: their gradients may differ as well."""
+    views = np.atleast_2d(views)
+    V = views.shape[0]
+    n = rec64.shape[1]
+    W, H = int(views[0, 16]), int(views[0, 17])
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    flag = np.zeros((V, H, W), bool)
+    tainted = np.zeros(n, bool)
+    ys, xs = np.mgrid[0:16, 0:16]
+    for v in range(V):
+        for tile_y in range(ty):
+            for tile_x in range(tx):
+                tile = v * tx * ty + tile_y * tx + tile_x
+                b, e = ranges[tile]
+                if e <= b:
+                    continue
+                px = tile_x * 16 + xs + 0.5
+                py = tile_y * 16 + ys + 0.5
+                T = np.ones((16, 16))
+                near = np.zeros((16, 16), bool)
+                alive = np.ones((16, 16), bool)
+                alphas = []
+                for k in range(b, e):
+                    r = rec64[v, vals[k]]
+                    dx, dy = px - r[0], py - r[1]
+                    power = -0.5 * (r[2] * dx * dx + r[4] * dy * dy) - r[3] * dx * dy
+                    at = r[5] * np.exp(np.minimum(power, 0.0))
+                    a = np.minimum(0.99, at)
+                    alphas.append(a)
+                    near |= alive & ((np.abs(a - ALPHA_MIN) <= rtol * ALPHA_MIN)
+                                     | (np.abs(at - 0.99) <= rtol) | (np.abs(power) <= 1e-6))
+                    ok = alive & (power <= 0) & (a >= ALPHA_MIN)
+                    Tn = T * (1 - a)
+                    near |= ok & (np.abs(Tn - 1e-4) <= rtol * 1e-4)
+                    stop = ok & (Tn < 1e-4)
+                    alive &= ~stop
+                    T = np.where(ok & ~stop, Tn, T)
+                y0, x0 = tile_y * 16, tile_x * 16
+                hh, ww = min(16, H - y0), min(16, W - x0)
+                near[hh:, :] = False
+                near[:, ww:] = False
+                flag[v, y0:y0 + hh, x0:x0 + ww] = near[:hh, :ww]
+                if return_tainted and near.any():
+                    for k, a in zip(range(b, e), alphas):
+                        if np.any(near & (a >= ALPHA_MIN * (1 - rtol))):
+                            tainted[vals[k]] = True
+    if return_tainted:
+        return flag, tainted
+    return flag

@@ -1,0 +1,150 @@
+"""Edge cases of the HIP path (through the C ABI), the autograd wrapper and
+finite differences.
+
+* empty set, all Gaussians culled, one Gaussian, non-finite parameters;
+* pair-capacity overflow raises the device flag and leaves every tile empty;
+* the maximum of 16 views in one call;
+* GS4DRasterize under torch.autograd matches gs4d_render_bwd;
+* gradients against central differences (h = 1e-3) of the oracle's FP64
+  forward on 64 random parameters.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_01119_amd import gs4d as G
+from paper_2510_01119_amd import synth
+from paper_2510_01119_amd.rasterizer import GS4DRasterize, Rasterizer
+
+from gpu_helpers import gpu_forward, need_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def test_empty_and_culled():
+    need_gpu()
+    view = synth.front_view(40, 24, 40.0)
+    # all culled: far in time
+    p = synth.small_set(100, 1)
+    p[3] = 50.0
+    r, _ = gpu_forward(p, view)
+    g = to_np(r)
+    assert g["n_pairs"] == 0 and np.all(g["touched"] == 0)
+    assert np.all(g["image"] == 0) and np.all(g["T_final"] == 1) and np.all(g["last"] == -1)
+    assert np.all(g["ranges"] == 0)
+
+
+def test_single_and_nonfinite():
+    need_gpu()
+    view = synth.front_view(48, 48, 48.0)
+    p = synth.small_set(8, 2, log_s_xyz=(-1.5, 0.1), log_s_t=(0.0, 0.1))
+    p[0:3, :] = 0.0
+    p[0, 1] = np.nan
+    p[5, 2] = np.inf
+    p[8:12, 3] = 0.0
+    r, _ = gpu_forward(p, view)
+    g = to_np(r)
+    o = oracle.forward(p, view, "f32")
+    assert np.array_equal(g["touched"], o["touched"])
+    assert np.all(g["touched"][0, 1:4] == 0)
+    assert np.array_equal(g["keys"], o["keys"])
+    assert np.abs(g["image"] - o["image"]).max() < 1e-4
+
+
+def test_capacity_overflow_flag():
+    need_gpu()
+    p = synth.small_set(2000, 0)
+    view = synth.front_view(64, 64, 64.0)
+    r = Rasterizer(2000, view, pair_capacity=100)
+    P = torch.from_numpy(p).cuda()
+    r.preprocess(P)
+    r.bin_sort(check=False)
+    torch.cuda.synchronize()
+    assert int(r.overflow.item()) == 1
+    need = int(r.n_pairs.item())
+    assert need > 100
+    assert int(r.ranges.abs().sum().item()) == 0
+    r.render()                       # empty tiles: background only
+    torch.cuda.synchronize()
+    assert float(r.image.abs().max().item()) == 0.0
+    # the checked path grows the buffers and retries
+    r.forward(P)
+    torch.cuda.synchronize()
+    assert r.capacity >= need and int(r.overflow.item()) == 0
+    assert int(r.n_pairs.item()) == need
+
+
+def test_sixteen_views():
+    need_gpu()
+    p = synth.small_set(1500, 6)
+    vs = np.stack([synth.make_view(synth.look_at(3.0 * np.array([np.sin(a), 0.3, -np.cos(a)]),
+                                                 (0, 0, 0)), 40.0, 40.0, 20.0, 16.0, 40, 32,
+                                   0.1 + 0.05 * i) for i, a in enumerate(np.linspace(0, 2, 16))])
+    r, _ = gpu_forward(p, vs)
+    g = to_np(r)
+    o = oracle.forward(p, vs, "f32")
+    assert np.array_equal(g["keys"], o["keys"])
+    assert np.array_equal(g["ranges"], o["ranges"])
+    assert np.abs(g["image"] - o["image"]).max() < 1e-3
+
+
+def test_autograd_function():
+    need_gpu()
+    p = synth.small_set(2000, 0)
+    view = synth.front_view(64, 64, 64.0)
+    r = Rasterizer(2000, view)
+    P = torch.from_numpy(p).cuda().requires_grad_(True)
+    img = GS4DRasterize.apply(P, r)
+    w = torch.from_numpy(synth.linear_loss_weights(1, 64, 64, 5)).cuda()
+    (img * w).sum().backward()
+    r2 = Rasterizer(2000, view)
+    Q = torch.from_numpy(p).cuda()
+    r2.forward(Q)
+    d = r2.backward(Q, w)
+    torch.cuda.synchronize()
+    assert torch.allclose(P.grad, d, rtol=1e-5, atol=1e-6)
+
+
+def test_gradients_vs_central_differences():
+    """GPU analytic gradients against central differences (h = 1e-3) of the
+    oracle's FP64 forward, on 64 random (parameter, Gaussian) entries;
+    entries whose +-h step changes any blend decision are redrawn."""
+    need_gpu()
+    n = 400
+    p = synth.small_set(n, 31, log_s_xyz=(-2.2, 0.3), log_s_t=(-1.0, 0.2))
+    p[3] = np.random.default_rng(31).uniform(0.4, 0.6, n).astype(np.float32)
+    view = synth.front_view(64, 64, 64.0, 3.0, 0.5)
+    w = synth.linear_loss_weights(1, 64, 64, 13)
+    r, P = gpu_forward(p, view)
+    d = r.backward(P, torch.from_numpy(w).cuda()).cpu().numpy().astype(np.float64)
+    p64 = p.astype(np.float64)
+    w64 = w.astype(np.float64)
+
+    def loss_sig(q):
+        rec, rect, touched = oracle.preprocess_f64(q, view)
+        keys, vals, ranges = oracle.bin_sort(rect, touched, oracle.depth_bits(rec), view)
+        out = oracle.render_fwd(rec, view, vals, ranges, signature=True)
+        return float((w64 * out["image"]).sum()), out["sig"]
+
+    _, sig0 = loss_sig(p64)
+    _, _, touched = oracle.preprocess_f32(p, view)
+    vis = np.nonzero(touched[0] > 0)[0]
+    rng = np.random.default_rng(77)
+    h = 1e-3
+    checked = rejected = 0
+    while checked < 64 and rejected < 400:
+        k, g = int(rng.integers(0, 20)), int(rng.choice(vis))
+        q = p64.copy()
+        q[k, g] += h
+        Lp, sp = loss_sig(q)
+        q[k, g] -= 2 * h
+        Lm, sm = loss_sig(q)
+        if not (np.array_equal(sp, sig0) and np.array_equal(sm, sig0)):
+            rejected += 1
+            continue
+        fd = (Lp - Lm) / (2 * h)
+        scale = max(abs(fd), 1e-3 * np.abs(d[k]).max(), 1e-6)
+        assert abs(d[k, g] - fd) <= 1e-3 * scale, (k, g, d[k, g], fd)
+        checked += 1
+    assert checked == 64, (checked, rejected)
