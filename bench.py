@@ -1,0 +1,293 @@
+"""Benchmark: training iterations/s of the 4D Gaussian-splatting optimisation
+step on one MI355X, with Gaussian-pixel blends/s and the roofline of the
+dominant kernel, next to the CPU oracle on the host cores.
+
+Workload (default, "scene"): the scene-scale plain training configuration --
+a seeded synthetic dynamic scene (textured planes + 3 rigid objects on
+spline paths, 1M ground-truth Gaussians, 200 frames at 960x540) rendered by
+this package, back-projected, grid-pruned at voxel 0.01 and heuristically
+initialised; each step trains on one random frame with L1 + 0.2 (1 - SSIM).
+"--workload small" runs the 2,000-Gaussian 64x64 single-view case instead.
+
+A step = preprocess, bin/sort, render forward, loss + gradient, render and
+preprocess backward, Adam: every stage a libgs4d.so kernel on the current
+stream.  All inputs are in HBM before the timed region starts.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd train iters/s and Gaussian-pixel blends/s vs roofline; time-to-PSNR"
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, unpacked
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_workload(name, device, cache=None):
+    """Inputs of the workload, in HBM.  With `cache`, the synthesised scene is
+    saved to / loaded from that file (a profiled run then contains only the
+    training kernels)."""
+    import torch
+    if cache and name == "scene" and os.path.exists(cache):
+        d = torch.load(cache, map_location=device, weights_only=True)
+        info = json.loads(d["info"])
+        return d["params"], d["views"].cpu().numpy(), d["images"], info
+    out = _build_workload(name, device)
+    if cache and name == "scene":
+        params, views, images, info = out
+        torch.save({"params": params, "views": torch.from_numpy(np.asarray(views)),
+                    "images": images, "info": json.dumps(info)}, cache)
+    return out
+
+
+def _build_workload(name, device):
+    import torch
+    from paper_2510_01119_amd import synth
+    if name == "small":
+        params = torch.from_numpy(synth.small_set(2000, 0)).to(device)
+        target_p = torch.from_numpy(synth.perturb(synth.small_set(2000, 0), 1)).to(device)
+        view = synth.front_view(64, 64, 64.0, 3.0, 0.5)
+        from paper_2510_01119_amd.rasterizer import Rasterizer
+        r = Rasterizer(2000, view, device=device)
+        r.forward(target_p)
+        images = r.image.clone()
+        info = dict(workload="plain single-view 2k Gaussians 64x64", n_gaussians=2000, frames=1,
+                    width=64, height=64)
+        return params, view[None], images, info
+    from paper_2510_01119_amd.scene import build_scene
+    t0 = time.time()
+    sc, images, params, info = build_scene(seed=0, device=device, verbose=True)
+    info.update(workload="scene-scale plain training: synthetic dynamic scene, 200 frames 960x540, "
+                         "1M-Gaussian ground truth, grid-pruned at 0.01",
+                frames=sc.frames, width=sc.W, height=sc.H, synth_s=round(time.time() - t0, 2))
+    return params, sc.cams, images, info
+
+
+def cpu_baseline(params_np, views, target_np, budget_s=30.0):
+    """The oracle's training step (FP32-decided preprocess, FP64 compositing
+    and backward, numpy loss and Adam), timed on one host thread."""
+    import oracle
+    from oracle import adam as oadam
+    from oracle import losses as olosses
+    t0 = time.perf_counter()
+    steps = 0
+    p = params_np.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    while True:
+        view = views[steps % len(views)]
+        fwd = oracle.forward(p.astype(np.float32), view, "f32")
+        img = fwd["image"][0]
+        _, g = olosses.scene_loss(img, target_np[steps % len(views)])
+        d, _ = oracle.backward(p.astype(np.float32), view, g[None], fwd=fwd)
+        p, m, v = oadam.adam_step(p, d, m, v, steps + 1, [1e-5] * 4 + [5e-3] * 4 + [1e-3] * 8
+                                  + [5e-2] + [2.5e-3] * 3)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 3:
+            break
+    dt = time.perf_counter() - t0
+    return steps / dt, steps, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="scene", choices=["scene", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--scene-cache", default=None,
+                    help="save/load the synthesised scene here (e.g. /tmp/gs4d_scene.pt)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2510_01119_amd import gs4d as G
+    from paper_2510_01119_amd.train import Trainer
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    G.lib()
+    dev = torch.device("cuda:0")
+    log(f"bench: building workload {args.workload}")
+    params, views, images, info = build_workload(args.workload, dev, args.scene_cache)
+    n = params.shape[1]
+    log(f"bench: {info}")
+    tr = Trainer(params.clone(), views, images, budget=5000)
+    peak = tr.size_pairs(range(0, len(views), max(1, len(views) // 20)), margin=2.0)
+    log(f"bench: pair peak over sampled frames {peak}, capacity {tr.rast.capacity}")
+    rng = np.random.default_rng(args.seed)
+    seq = rng.integers(0, len(views), args.warmup + args.steps)
+
+    for i in range(args.warmup):
+        tr.step(int(seq[i]))
+    torch.cuda.synchronize()
+    # autotune the render kernels on a warmed-up frame (untimed)
+    from paper_2510_01119_amd import autotune
+    tr.forward_loss(int(seq[0]))
+    choice = autotune.tune(tr.rast, tr.params, tr.dimg)
+    log(f"bench: autotune {json.dumps(choice)}")
+    for i in range(2):
+        tr.step(int(seq[i]))
+    torch.cuda.synchronize()
+
+    # per-stage HIP events on the launch stream (the current torch stream)
+    stages = ["preprocess", "bin_sort", "render_fwd", "loss", "render_bwd", "preprocess_bwd", "adam"]
+    ev = {s: [] for s in stages}
+    r = tr.rast
+
+    def timed_step(f):
+        def mark(name, fn):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            ev[name].append((a, b))
+        r.set_views(tr.cviews[f])
+        mark("preprocess", lambda: r.preprocess(tr.params))
+        mark("bin_sort", lambda: r.bin_sort(check=False))
+        mark("render_fwd", lambda: r.render())
+
+        def loss():
+            target = tr.targets[f:f + 1]
+            G.gs4d_fill_f32(tr.dimg, 0.0)
+            G.gs4d_fill_f32(tr.l1, 0.0)
+            G.gs4d_fill_f32(tr.ssim, 0.0)
+            G.gs4d_loss_l1(r.image, target, 1.0, tr.l1, tr.dimg)
+            G.gs4d_ssim(r.image, target, -tr.ssim_w, tr.ssim, tr.dimg, tr.ssim_ws)
+        mark("loss", loss)
+        mark("render_bwd", lambda: G.gs4d_render_bwd_2d(r.rec, r.n, r.vals, r.ranges, r.cviews,
+                                                        tr.dimg, r.T_final, r.last, r.grad2d))
+        mark("preprocess_bwd", lambda: G.gs4d_preprocess_bwd(tr.params, r.touched, r.grad2d,
+                                                             r.cviews, r.dparams))
+        mark("adam", lambda: G.gs4d_adam_step(tr.params, r.dparams, tr.m, tr.v, tr.cfg, tr.step_dev))
+        torch.maximum(tr.overflow_seen, r.overflow, out=tr.overflow_seen)
+
+    # timed region: wall clock over exactly `steps` steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        timed_step(int(seq[args.warmup + i]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if int(tr.overflow_seen.item()) != 0:
+        raise RuntimeError("pair capacity overflowed during the timed region")
+    elapsed = t1 - t0
+    its = args.steps / elapsed
+    stage_ms = {s: float(np.mean([a.elapsed_time(b) for a, b in ev[s]])) for s in stages}
+    log(f"bench: {its:.1f} it/s; stage ms {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
+
+    # blends per step over the same frame sequence (untimed, counters on)
+    r.counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    evals = blends = 0
+    pairs = []
+    for i in range(min(args.steps, 50)):
+        f = int(seq[args.warmup + i])
+        r.set_views(tr.cviews[f])
+        r.preprocess(tr.params)
+        r.bin_sort(check=False)
+        r.render()
+        c = r.counters.cpu().numpy()
+        evals += int(c[0])
+        blends += int(c[1])
+        pairs.append(int(r.n_pairs.item()))
+    k = min(args.steps, 50)
+    blends_per_step, evals_per_step = blends / k, evals / k
+    pairs_per_step = float(np.mean(pairs))
+    r.counters = None
+
+    # roofline of the dominant kernel
+    dominant = max(stage_ms, key=stage_ms.get)
+    HW = info["width"] * info["height"]
+    roof = roofline_for(dominant, stage_ms[dominant], n, pairs_per_step, evals_per_step,
+                        blends_per_step, HW)
+
+    line = {
+        "metric": METRIC,
+        "value": round(its, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": info["workload"], "n_gaussians": n, "width": info["width"],
+                   "height": info["height"], "frames": info["frames"],
+                   "loss": "L1 + 0.2(1-SSIM)" if args.workload == "scene" else "L1 + 0.2(1-SSIM)",
+                   "n_raw_points": info.get("n_raw_points")},
+        "blends_per_s": round(blends_per_step * its, 1),
+        "evaluated_per_s": round(evals_per_step * its, 1),
+        "blends_per_step": round(blends_per_step, 1),
+        "pairs_per_step": round(pairs_per_step, 1),
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        from paper_2510_01119_amd import synth  # noqa: F401
+        p_np = tr.params.detach().cpu().numpy()
+        fsel = [int(seq[0])]
+        tgt = images[fsel].cpu().numpy()
+        v_np = np.stack([views[f] for f in fsel])
+        log("bench: cpu baseline (oracle) ...")
+        rate, steps_done, secs = cpu_baseline(p_np, v_np, tgt)
+        line["cpu_baseline"] = {"value": round(rate, 6), "unit": "iters/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{steps_done} full training step(s) of the same workload "
+                                          f"(one frame, {n} Gaussians) in {secs:.1f} s on one host "
+                                          f"thread"}
+    print(json.dumps(line), flush=True)
+
+
+def roofline_for(kernel, ms, n, pairs, evals, blends, hw):
+    """Algorithmic traffic / work of one launch of `kernel` over its time.
+
+    render_fwd / render_bwd: bound by FP32 vector ALU (per evaluated
+    (pixel, entry) ~20 / ~45 FP32 operations).  Others: HBM bytes."""
+    s = ms / 1000.0
+    if kernel in ("render_fwd", "render_bwd"):
+        ops = 20.0 if kernel == "render_fwd" else 45.0
+        flops = ops * evals if kernel == "render_fwd" else ops * blends * 1.0 + 20.0 * evals
+        achieved = flops / s / 1e12
+        return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
+                "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None}
+    bytes_per = {
+        "preprocess": 80.0 * n + 68.0 * n,
+        "bin_sort": 40.0 * pairs + 64.0 * n,
+        "preprocess_bwd": 80.0 * n + 36.0 * n + 80.0 * n,
+        "adam": 20 * 4.0 * n * 5,
+        "loss": 36.0 * hw * 3,
+    }.get(kernel, 0.0)
+    achieved = bytes_per / s / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+
+
+if __name__ == "__main__":
+    main()

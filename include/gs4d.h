@@ -78,7 +78,9 @@ typedef struct gs4d_view {
  *   views    host, n_views entries (1 <= n_views <= GS4D_MAX_VIEWS)
  *   rec      out float [n_views][n][12]:
  *              0 mean2D.x 1 mean2D.y 2 conic.a 3 conic.b 4 conic.c 5 o_t
- *              6 camera depth z 7 zero 8..10 rgb 11 zero   (zeros if culled)
+ *              6 camera depth z 7 footprint half-width x 8..10 rgb
+ *              11 footprint half-width y   (all zeros if culled); outside
+ *              the box mean2D +- half-widths every pixel has alpha < 1/255
  *   rect     out int32 [n_views][n][4]: tile rectangle [x0, y0, x1, y1) of
  *              the exact alpha >= 1/255 footprint (zeros if culled)
  *   touched  out int32 [n_views][n]: tiles covered, (x1-x0)*(y1-y0)
@@ -160,6 +162,29 @@ int gs4d_render_bwd(const float *params, int64_t n, const float *rec, const int3
                     int32_t n_views, const float *dL_dimage, const float *T_final,
                     const int32_t *last, float *dparams, float *grad2d, void *ws,
                     size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * gs4d_render_bwd_2d -- the per-pixel half of gs4d_render_bwd: zeroes and
+ *   fills grad2d [n_views][n][9] = d(mean2D.xy, conic.abc, o_t, rgb) with the
+ *   back-to-front replay described above (Sec. 3.1 splatting backward).
+ * gs4d_preprocess_bwd -- the per-Gaussian half: chain rule from grad2d
+ *   through the EWA projection, the conditional at t (Sec. 3.3 Eq. "4dgs"),
+ *   the temporal opacity, the 4D rotor and the activations to dparams
+ *   [20][n] (overwritten, summed over views).  touched as produced by
+ *   gs4d_preprocess (culled entries contribute nothing).
+ * ------------------------------------------------------------------------- */
+int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *vals, const int32_t *ranges,
+                       const gs4d_view *views, int32_t n_views, const float *dL_dimage,
+                       const float *T_final, const int32_t *last, float *grad2d, void *stream);
+int gs4d_preprocess_bwd(const float *params, int64_t n, const gs4d_view *views, int32_t n_views,
+                        const int32_t *touched, const float *grad2d, float *dparams, void *stream);
+
+/* gs4d_set_bwd_variant -- block shape of the render backward: each lane
+ *   handles pixels_per_lane (1, 2 or 4) pixels of its tile, so a workgroup
+ *   has 256 / pixels_per_lane threads.  Results are identical up to FP32
+ *   summation order; the choice only changes speed (picked by the autotuner).
+ *   Process-wide setting; returns GS4D_ERR_INVALID_ARG for other values. */
+int gs4d_set_bwd_variant(int32_t pixels_per_lane);
 
 /* ---------------------------------------------------------------------------
  * gs4d_grid_prune -- voxel grid pruning (Sec. 3.2): each point goes to the

@@ -1,0 +1,69 @@
+"""Project autotuner for the render kernels.
+
+Times the forward's LDS batch size (64 / 128 / 256 Gaussians per round) and
+the backward's block shape (1 / 2 / 4 pixels per lane = 256 / 128 / 64
+threads) on the caller's live buffers with HIP events, keeps the fastest,
+and caches the choice per (device, image size, view count, Gaussian-count
+bucket).  Every choice renders the same image (the forward bit for bit);
+only the speed differs.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import gs4d as G
+
+_CACHE: dict = {}
+
+
+def _key(r):
+    props = torch.cuda.get_device_properties(r.device)
+    bucket = int(round(math.log2(max(r.n, 1))))
+    return f"{props.name}|{r.W}x{r.H}|v{r.V}|n2^{bucket}"
+
+
+def _time(fn, reps=5):
+    fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return min(a.elapsed_time(b) for a, b in ev)
+
+
+def tune(r, params, dL_dimage, verbose=False):
+    """Pick the fastest forward batch and backward variant for rasterizer r,
+    whose buffers already hold a forward pass (preprocess + bin_sort)."""
+    key = _key(r)
+    if key in _CACHE:
+        choice = _CACHE[key]
+    else:
+        fwd = {}
+        for b in (64, 128, 256):
+            r.batch = b
+            fwd[b] = _time(lambda: r.render())
+        best_b = min(fwd, key=fwd.get)
+        r.batch = best_b
+        r.render()
+        bwd = {}
+        for ppl in (1, 2, 4):
+            G.gs4d_set_bwd_variant(ppl)
+            bwd[ppl] = _time(lambda: G.gs4d_render_bwd_2d(r.rec, r.n, r.vals, r.ranges, r.cviews,
+                                                          dL_dimage, r.T_final, r.last, r.grad2d))
+        best_p = min(bwd, key=bwd.get)
+        choice = {"batch": best_b, "bwd_pixels_per_lane": best_p,
+                  "fwd_ms": {str(k): round(v, 4) for k, v in fwd.items()},
+                  "bwd_ms": {str(k): round(v, 4) for k, v in bwd.items()}}
+        _CACHE[key] = choice
+        if verbose:
+            print(f"autotune {key}: {json.dumps(choice)}", flush=True)
+    r.batch = choice["batch"]
+    G.gs4d_set_bwd_variant(choice["bwd_pixels_per_lane"])
+    return choice

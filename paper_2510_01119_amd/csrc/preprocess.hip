@@ -81,6 +81,7 @@ struct Slice {
     float sa, sb, sc, det;    // Sigma2D = [[sa, sb], [sb, sc]]
     float ca, cb, cc;         // conic
     float mx, my;
+    float hx, hy;             // footprint half-widths
 };
 
 // Returns 1 if the Gaussian is visible; `touched`/`rect` filled when asked.
@@ -203,6 +204,8 @@ __device__ __forceinline__ int slice_project(const float (&p)[20], const gs4d_vi
     const int px0 = (int)x0, px1 = (int)x1, py0 = (int)y0, py1 = (int)y1;
     if (px0 > px1 || py0 > py1) return 0;
     if (rect_out) *rect_out = make_int4(px0 >> 4, py0 >> 4, (px1 >> 4) + 1, (py1 >> 4) + 1);
+    S.hx = hx;
+    S.hy = hy;
     return 1;
 }
 
@@ -223,8 +226,8 @@ preprocess_fwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp, float
     int tt = 0;
     if (vis) {
         r0 = make_float4(S.mx, S.my, S.ca, S.cb);
-        r1 = make_float4(S.cc, S.ot, S.xc[2], 0.0f);
-        r2 = make_float4(p[17], p[18], p[19], 0.0f);
+        r1 = make_float4(S.cc, S.ot, S.xc[2], S.hx);
+        r2 = make_float4(p[17], p[18], p[19], S.hy);
         tt = (rc.z - rc.x) * (rc.w - rc.y);
     } else {
         rc = make_int4(0, 0, 0, 0);
@@ -398,16 +401,6 @@ preprocess_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
 
 }  // namespace
 
-int launch_preprocess_bwd(const float *params, int64_t n, const ViewPack &vp,
-                          const int32_t *touched, const float *grad2d, float *dparams,
-                          hipStream_t st) {
-    if (n == 0) return GS4D_OK;
-    const unsigned blocks = (unsigned)((n + 127) / 128);
-    preprocess_bwd_kernel<<<blocks, 128, 0, st>>>(params, n, vp, touched, grad2d, dparams);
-    GS4D_LAUNCH_CHECK("preprocess_bwd");
-    return GS4D_OK;
-}
-
 }  // namespace gs4d
 
 using namespace gs4d;
@@ -425,5 +418,20 @@ extern "C" int gs4d_preprocess(const float *params, int64_t n, const gs4d_view *
     preprocess_fwd_kernel<<<grid, 256, 0, as_stream(stream)>>>(
         params, n, vp, reinterpret_cast<float4 *>(rec), reinterpret_cast<int4 *>(rect), touched);
     GS4D_LAUNCH_CHECK("gs4d_preprocess");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_preprocess_bwd(const float *params, int64_t n, const gs4d_view *views,
+                                   int32_t n_views, const int32_t *touched, const float *grad2d,
+                                   float *dparams, void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "gs4d_preprocess_bwd: n out of range");
+    if (n == 0) return GS4D_OK;
+    GS4D_REQUIRE(params && touched && grad2d && dparams, "gs4d_preprocess_bwd: null pointer");
+    const unsigned blocks = (unsigned)((n + 127) / 128);
+    preprocess_bwd_kernel<<<blocks, 128, 0, as_stream(stream)>>>(params, n, vp, touched, grad2d,
+                                                                 dparams);
+    GS4D_LAUNCH_CHECK("gs4d_preprocess_bwd");
     return GS4D_OK;
 }

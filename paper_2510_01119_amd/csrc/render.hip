@@ -17,10 +17,6 @@
 
 namespace gs4d {
 
-int launch_preprocess_bwd(const float *params, int64_t n, const ViewPack &vp,
-                          const int32_t *touched, const float *grad2d, float *dparams,
-                          hipStream_t st);
-
 namespace {
 
 constexpr int RT_THREADS = 256;
@@ -28,6 +24,9 @@ constexpr int RT_WAVES = 4;
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float ALPHA_MAX = 0.99f;
 constexpr float T_EPS = 1e-4f;
+// backward stages 128 Gaussians per round: its per-wave partial sums then
+// take 18 KB of LDS and six tiles fit on a CU at once
+constexpr int BWD_BATCH = 128;
 
 struct TileInfo {
     int v, tx, ty;
@@ -51,6 +50,45 @@ __device__ __forceinline__ float gauss_power(float4 a, float cc, float dx, float
     return fmaf(-0.5f, q, -(a.w * dx) * dy);
 }
 
+// Each wave owns a 16x4 pixel strip of the tile.  For a staged batch, every
+// wave marks (one ballot per 64 entries) the entries whose exact footprint
+// box meets its strip; outside that box alpha < 1/255 for every pixel, so
+// the other entries are skipped without evaluating them -- the result is the
+// same as evaluating them.
+template <int BATCH>
+__device__ __forceinline__ void strip_masks(const float4 *sA, const float4 *sC, int cnt, float x0,
+                                            float x1, float y0, float y1, int lane,
+                                            uint64_t (&m)[BATCH / 64]) {
+#pragma unroll
+    for (int k = 0; k < BATCH / 64; ++k) {
+        const int j = k * 64 + lane;
+        bool hit = false;
+        if (j < cnt) {
+            const float4 a = sA[j];
+            const float4 c = sC[j];
+            hit = (a.x + c.y >= x0) && (a.x - c.y <= x1) && (a.y + c.z >= y0) && (a.y - c.z <= y1);
+        }
+        m[k] = __ballot(hit);
+    }
+}
+
+template <int BATCH>
+__device__ __forceinline__ void stage_batch(const float4 *__restrict__ recv,
+                                            const uint32_t *__restrict__ vals, int start, int cnt,
+                                            float4 *sA, float4 *sB, float4 *sC, uint32_t *sG) {
+    const int t = threadIdx.x;
+    if (t < cnt) {
+        const uint32_t g = vals[start + t];
+        const float4 r0 = recv[3 * (int64_t)g + 0];
+        const float4 r1 = recv[3 * (int64_t)g + 1];
+        const float4 r2 = recv[3 * (int64_t)g + 2];
+        sA[t] = r0;                                       // mx my ca cb
+        sB[t] = make_float4(r1.x, r1.y, r2.x, r2.y);      // cc o_t r g
+        sC[t] = make_float4(r2.z, r1.w, r2.w, 0.0f);      // b hx hy
+        if (sG) sG[t] = g;
+    }
+}
+
 template <int BATCH>
 __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__restrict__ rec,
                                                 int64_t n, const uint32_t *__restrict__ vals,
@@ -59,14 +97,17 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
                                                 float *__restrict__ image,
                                                 float *__restrict__ T_final,
                                                 int32_t *__restrict__ last_out, float4 *sA,
-                                                float4 *sB, float *sC) {
-    const int t = threadIdx.x;
+                                                float4 *sB, float4 *sC) {
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const TileInfo ti = tile_info(tile, vp);
     const int px = ti.tx * GS4D_TILE + (t & 15);
     const int py = ti.ty * GS4D_TILE + (t >> 4);
     const int W = vp.width, H = vp.height;
     const bool inside = px < W && py < H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    // this wave's strip, as pixel-centre extents
+    const float sx0 = (float)(ti.tx * GS4D_TILE) + 0.5f, sx1 = sx0 + 15.0f;
+    const float sy0 = (float)(ti.ty * GS4D_TILE + 4 * w) + 0.5f, sy1 = sy0 + 3.0f;
     const int2 rg = ranges[tile];
     const float4 *recv = rec + (int64_t)ti.v * n * 3;
 
@@ -78,40 +119,51 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
     for (int start = rg.x; start < rg.y; start += BATCH) {
         const int cnt = min(BATCH, rg.y - start);
         __syncthreads();
-        if (t < cnt) {
-            const uint32_t g = vals[start + t];
-            const float4 r0 = recv[3 * (int64_t)g + 0];
-            const float4 r1 = recv[3 * (int64_t)g + 1];
-            const float4 r2 = recv[3 * (int64_t)g + 2];
-            sA[t] = r0;                                       // mx my ca cb
-            sB[t] = make_float4(r1.x, r1.y, r2.x, r2.y);      // cc o_t r g
-            sC[t] = r2.z;                                     // b
-        }
+        stage_batch<BATCH>(recv, vals, start, cnt, sA, sB, sC, nullptr);
         const int active = __syncthreads_count(!done);
         if (active == 0) break;
-        if (!done) {
-            for (int j = 0; j < cnt; ++j) {
-                const float4 a = sA[j];
-                const float4 b = sB[j];
-                const float dx = fx - a.x, dy = fy - a.y;
-                const float power = gauss_power(a, b.x, dx, dy);
-                ++n_eval;
-                if (power > 0.0f) continue;
-                const float at = b.y * __expf(power);
-                const float alpha = fminf(ALPHA_MAX, at);
-                if (alpha < ALPHA_MIN) continue;
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < T_EPS) {
-                    done = true;
-                    break;
-                }
-                const float w = alpha * T;
-                C0 = fmaf(b.z, w, C0);
-                C1 = fmaf(b.w, w, C1);
-                C2 = fmaf(sC[j], w, C2);
-                T = Tn;
-                last = start + j;
-                ++n_blend;
+        if (__ballot(!done) == 0) continue;
+        uint64_t m[BATCH / 64];
+        strip_masks<BATCH>(sA, sC, cnt, sx0, sx1, sy0, sy1, lane, m);
+        // Branch-free per entry: every decision is a select, so the only
+        // control flow is the wave-uniform walk over the mask bits; two
+        // entries per step keep two sets of LDS reads in flight.
+        auto blend_one = [&](int j, float4 a, float4 b, float cb_) {
+            const bool live = !done;
+            const float dx = fx - a.x, dy = fy - a.y;
+            const float power = gauss_power(a, b.x, dx, dy);
+            const float at = b.y * __expf(power);
+            const float alpha = fminf(ALPHA_MAX, at);
+            const bool ok = live && !(power > 0.0f) && !(alpha < ALPHA_MIN);
+            const float Tn = T * (1.0f - alpha);
+            const bool stop = ok && (Tn < T_EPS);
+            const bool blend = ok && !stop;
+            const float wgt = blend ? alpha * T : 0.0f;
+            C0 = fmaf(b.z, wgt, C0);
+            C1 = fmaf(b.w, wgt, C1);
+            C2 = fmaf(cb_, wgt, C2);
+            T = blend ? Tn : T;
+            last = blend ? start + j : last;
+            done = done || stop;
+            n_eval += live ? 1u : 0u;
+            n_blend += blend ? 1u : 0u;
+        };
+#pragma unroll
+        for (int k = 0; k < BATCH / 64; ++k) {
+            uint64_t mask = m[k];
+            while (mask) {
+                if (__ballot(!done) == 0) break;
+                const int j0 = k * 64 + __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const bool two = mask != 0;
+                const int j1 = two ? k * 64 + __builtin_ctzll(mask) : j0;
+                if (two) mask &= mask - 1;
+                const float4 a0 = sA[j0], b0 = sB[j0];
+                const float c0 = sC[j0].x;
+                const float4 a1 = sA[j1], b1 = sB[j1];
+                const float c1 = sC[j1].x;
+                blend_one(j0, a0, b0, c0);
+                if (two) blend_one(j1, a1, b1, c1);
             }
         }
     }
@@ -142,13 +194,13 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
     }
     if (o.target && o.loss_per_view) {
         const float s = wave_sum(lsum);
-        if ((t & 63) == 0 && s != 0.0f)
+        if (lane == 0 && s != 0.0f)
             atomicAdd(&o.loss_per_view[ti.v], s * (o.l1_weight / (float)(3 * HW)));
     }
     if (o.counters) {
         const uint32_t e = wave_sum_u32(n_eval);
         const uint32_t bl = wave_sum_u32(n_blend);
-        if ((t & 63) == 0) {
+        if (lane == 0) {
             atomicAdd((unsigned long long *)&o.counters[0], (unsigned long long)e);
             atomicAdd((unsigned long long *)&o.counters[1], (unsigned long long)bl);
         }
@@ -163,7 +215,7 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
                   int32_t *__restrict__ last) {
     __shared__ float4 sA[BATCH];
     __shared__ float4 sB[BATCH];
-    __shared__ float sC[BATCH];
+    __shared__ float4 sC[BATCH];
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * vp.n_views;
     if (!o.persistent) {
         render_tile_fwd<BATCH>(blockIdx.x, rec, n, vals, ranges, vp, o, image, T_final, last, sA,
@@ -184,46 +236,100 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
 }
 
 // ---------------------------------------------------------------- backward
-template <int BATCH>
-__global__ void __launch_bounds__(RT_THREADS)
+// Full wave64 sum with DPP: row_shr 1/2/4/8 leaves each 16-lane row's total
+// in its last lane, row_bcast:15 and row_bcast:31 fold the rows; the total
+// is valid in lane 63 only.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Reduces N independent values at once, one DPP stage at a time across all
+// of them, so consecutive DPP operations never depend on each other.
+template <int N>
+__device__ __forceinline__ void wave_total_lane63(float (&x)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x111, 0xF>(x[q]);   // row_shr:1
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x112, 0xF>(x[q]);   // row_shr:2
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x114, 0xF>(x[q]);   // row_shr:4
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x118, 0xF>(x[q]);   // row_shr:8
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x142, 0xA>(x[q]);   // row_bcast:15 -> rows 1, 3
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x143, 0xC>(x[q]);   // row_bcast:31 -> rows 2, 3
+}
+
+// PPL = pixels per lane.  The workgroup has 256 / PPL threads; wave w owns
+// the 16 x (4 PPL) strip starting at tile row 4 PPL w, lane l the pixels
+// (l mod 16, 4 PPL w + l div 16 + 4 k), k < PPL.  Each lane folds its PPL
+// pixels' terms for an entry before the one cross-lane reduction, so a
+// reduction serves PPL pixel evaluations.
+template <int BATCH, int PPL>
+__global__ void __launch_bounds__(RT_THREADS / PPL)
 render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__restrict__ vals,
                   const int2 *__restrict__ ranges, ViewPack vp,
                   const float *__restrict__ dL_dimage, const float *__restrict__ T_final,
                   const int32_t *__restrict__ last, float *__restrict__ grad2d) {
+    constexpr int NK = BATCH / 64;
+    constexpr int NT = RT_THREADS / PPL;
+    constexpr int NW = NT / 64;
     __shared__ float4 sA[BATCH];
     __shared__ float4 sB[BATCH];
-    __shared__ float sC[BATCH];
+    __shared__ float4 sC[BATCH];
     __shared__ uint32_t sG[BATCH];
-    __shared__ float part[RT_WAVES][BATCH][9];
+    __shared__ float part[NW][BATCH][9];   // per-wave sums, valid where the wave's mask is set
+    __shared__ uint64_t smask[NW][NK];
     __shared__ int smax;
 
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int64_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tile, vp);
-    const int px = ti.tx * GS4D_TILE + (t & 15);
-    const int py = ti.ty * GS4D_TILE + (t >> 4);
     const int W = vp.width, H = vp.height;
-    const bool inside = px < W && py < H;
-    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    const int2 rg = ranges[tile];
     const int64_t HW = (int64_t)H * W;
-    const int64_t pix = (int64_t)py * W + px;
+    const int px = ti.tx * GS4D_TILE + (lane & 15);
+    const int row0 = ti.ty * GS4D_TILE + 4 * PPL * w + (lane >> 4);
+    const float fx = (float)px + 0.5f;
+    const float sx0 = (float)(ti.tx * GS4D_TILE) + 0.5f, sx1 = sx0 + 15.0f;
+    const float sy0 = (float)(ti.ty * GS4D_TILE + 4 * PPL * w) + 0.5f;
+    const float sy1 = sy0 + (float)(4 * PPL - 1);
+    const int2 rg = ranges[tile];
     const gs4d_view &V = vp.v[ti.v];
 
-    int my_last = -1;
-    float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
-    if (inside) {
-        my_last = last[(int64_t)ti.v * HW + pix];
-        T = T_final[(int64_t)ti.v * HW + pix];
-        const float *d = dL_dimage + (int64_t)ti.v * 3 * HW + pix;
-        g0 = d[0];
-        g1 = d[HW];
-        g2 = d[2 * HW];
+    int my_last[PPL];
+    float T[PPL], g0[PPL], g1[PPL], g2[PPL], B0[PPL], B1[PPL], B2[PPL], fy[PPL];
+    int lane_last = -1;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const int py = row0 + 4 * k;
+        fy[k] = (float)py + 0.5f;
+        my_last[k] = -1;
+        T[k] = 1.0f;
+        g0[k] = g1[k] = g2[k] = 0.0f;
+        if (px < W && py < H) {
+            const int64_t pix = (int64_t)py * W + px;
+            my_last[k] = last[(int64_t)ti.v * HW + pix];
+            T[k] = T_final[(int64_t)ti.v * HW + pix];
+            const float *d = dL_dimage + (int64_t)ti.v * 3 * HW + pix;
+            g0[k] = d[0];
+            g1[k] = d[HW];
+            g2[k] = d[2 * HW];
+        }
+        B0[k] = V.bg[0];
+        B1[k] = V.bg[1];
+        B2[k] = V.bg[2];
+        lane_last = max(lane_last, my_last[k]);
     }
-    float B0 = V.bg[0], B1 = V.bg[1], B2 = V.bg[2];
     if (t == 0) smax = -1;
     __syncthreads();
-    if (my_last >= 0) atomicMax(&smax, my_last);
+    if (lane_last >= 0) atomicMax(&smax, lane_last);
+    // the wave's own furthest entry
+    int wave_last = lane_last;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, off, 64));
     __syncthreads();
     const int max_last = smax;
     if (max_last < rg.x) return;
@@ -234,80 +340,109 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
         const int start = max(rg.x, end - BATCH);
         const int cnt = end - start;
         __syncthreads();
-        if (t < cnt) {
-            const uint32_t g = vals[start + t];
+        for (int i = t; i < cnt; i += NT) {
+            const uint32_t g = vals[start + i];
             const float4 r0 = recv[3 * (int64_t)g + 0];
             const float4 r1 = recv[3 * (int64_t)g + 1];
             const float4 r2 = recv[3 * (int64_t)g + 2];
-            sA[t] = r0;
-            sB[t] = make_float4(r1.x, r1.y, r2.x, r2.y);
-            sC[t] = r2.z;
-            sG[t] = g;
+            sA[i] = r0;
+            sB[i] = make_float4(r1.x, r1.y, r2.x, r2.y);
+            sC[i] = make_float4(r2.z, r1.w, r2.w, 0.0f);
+            sG[i] = g;
         }
-        for (int i = t; i < RT_WAVES * BATCH * 9; i += RT_THREADS) (&part[0][0][0])[i] = 0.0f;
         __syncthreads();
-        for (int j = cnt - 1; j >= 0; --j) {
+        // entries beyond this wave's last blended one are skipped too
+        const int wcnt = min(cnt, wave_last - start + 1);
+        uint64_t m[NK];
+        strip_masks<BATCH>(sA, sC, wcnt, sx0, sx1, sy0, sy1, lane, m);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) smask[w][k] = m[k];
+        }
+        // Branch-free per entry (selects only), entries taken back to front
+        // two at a time so their LDS reads overlap.
+        auto grad_one = [&](int j, float4 a, float4 b, float cbl) {
             const int idx = start + j;
             float d[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) d[k] = 0.0f;
-            bool contrib = false;
-            if (idx <= my_last) {
-                const float4 a = sA[j];
-                const float4 b = sB[j];
-                const float cbl = sC[j];
-                const float dx = fx - a.x, dy = fy - a.y;
+            for (int q = 0; q < 9; ++q) d[q] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const float dx = fx - a.x, dy = fy[k] - a.y;
                 const float power = gauss_power(a, b.x, dx, dy);
-                if (power <= 0.0f) {
-                    const float ex = __expf(power);
-                    const float at = b.y * ex;
-                    const float alpha = fminf(ALPHA_MAX, at);
-                    if (alpha >= ALPHA_MIN) {
-                        contrib = true;
-                        T = T / (1.0f - alpha);         // transmittance in front of entry
-                        const float wgt = alpha * T;
-                        d[6] = wgt * g0;
-                        d[7] = wgt * g1;
-                        d[8] = wgt * g2;
-                        const float dalpha = T * (g0 * (b.z - B0) + g1 * (b.w - B1) + g2 * (cbl - B2));
-                        B0 = alpha * b.z + (1.0f - alpha) * B0;
-                        B1 = alpha * b.w + (1.0f - alpha) * B1;
-                        B2 = alpha * cbl + (1.0f - alpha) * B2;
-                        if (at <= ALPHA_MAX) {
-                            const float dpow = dalpha * at;
-                            d[5] = dalpha * ex;
-                            d[2] = -0.5f * dpow * dx * dx;
-                            d[3] = -dpow * dx * dy;
-                            d[4] = -0.5f * dpow * dy * dy;
-                            d[0] = dpow * (a.z * dx + a.w * dy);
-                            d[1] = dpow * (b.x * dy + a.w * dx);
-                        }
-                    }
-                }
+                const float ex = __expf(power);
+                const float at = b.y * ex;
+                const float alpha = fminf(ALPHA_MAX, at);
+                const bool ok = (idx <= my_last[k]) && !(power > 0.0f) && !(alpha < ALPHA_MIN);
+                // transmittance in front of this entry
+                const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
+                T[k] = ok ? Tk : T[k];
+                const float wgt = ok ? alpha * Tk : 0.0f;
+                d[6] = fmaf(wgt, g0[k], d[6]);
+                d[7] = fmaf(wgt, g1[k], d[7]);
+                d[8] = fmaf(wgt, g2[k], d[8]);
+                const float dal = Tk * (g0[k] * (b.z - B0[k]) + g1[k] * (b.w - B1[k]) +
+                                        g2[k] * (cbl - B2[k]));
+                const float am = ok ? alpha : 0.0f;
+                B0[k] = fmaf(am, b.z - B0[k], B0[k]);
+                B1[k] = fmaf(am, b.w - B1[k], B1[k]);
+                B2[k] = fmaf(am, cbl - B2[k], B2[k]);
+                // no gradient through the 0.99 clamp
+                const float dalpha = (ok && at <= ALPHA_MAX) ? dal : 0.0f;
+                const float dpow = dalpha * at;
+                d[5] = fmaf(dalpha, ex, d[5]);
+                d[2] = fmaf(-0.5f * dpow * dx, dx, d[2]);
+                d[3] = fmaf(-dpow * dx, dy, d[3]);
+                d[4] = fmaf(-0.5f * dpow * dy, dy, d[4]);
+                d[0] = fmaf(dpow, a.z * dx + a.w * dy, d[0]);
+                d[1] = fmaf(dpow, b.x * dy + a.w * dx, d[1]);
             }
-            if (__ballot(contrib)) {
+            wave_total_lane63<9>(d);
+            if (lane == 63) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) d[k] = wave_sum(d[k]);
-                if (l == 0) {
+                for (int q = 0; q < 9; ++q) part[w][j][q] = d[q];
+            }
+        };
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) part[w][j][k] = d[k];
-                }
+        for (int kk = NK - 1; kk >= 0; --kk) {
+            uint64_t mask = m[kk];
+            while (mask) {
+                const int bit0 = 63 - __builtin_clzll(mask);
+                mask &= ~(1ull << bit0);
+                const bool two = mask != 0;
+                const int bit1 = two ? 63 - __builtin_clzll(mask) : bit0;
+                if (two) mask &= ~(1ull << bit1);
+                const int j0 = kk * 64 + bit0, j1 = kk * 64 + bit1;
+                const float4 a0 = sA[j0], b0 = sB[j0];
+                const float c0 = sC[j0].x;
+                const float4 a1 = sA[j1], b1 = sB[j1];
+                const float c1 = sC[j1].x;
+                grad_one(j0, a0, b0, c0);
+                if (two) grad_one(j1, a1, b1, c1);
             }
         }
         __syncthreads();
-        if (t < cnt) {
-            float s[9];
+        for (int i = t; i < cnt; i += NT) {
+            float sum[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) sum[q] = 0.0f;
+            const int k = i >> 6;
+            const uint64_t bit = 1ull << (i & 63);
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                if (smask[ww][k] & bit) {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) sum[q] += part[ww][i][q];
+                }
+            }
             bool any = false;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                s[k] = part[0][t][k] + part[1][t][k] + part[2][t][k] + part[3][t][k];
-                any |= s[k] != 0.0f;
-            }
+            for (int q = 0; q < 9; ++q) any |= sum[q] != 0.0f;
             if (any) {
-                float *dst = gview + (int64_t)sG[t] * 9;
+                float *dst = gview + (int64_t)sG[i] * 9;
 #pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    if (s[k] != 0.0f) atomicAdd(dst + k, s[k]);
+                for (int q = 0; q < 9; ++q)
+                    if (sum[q] != 0.0f) atomicAdd(dst + q, sum[q]);
             }
         }
     }
@@ -372,16 +507,59 @@ extern "C" size_t gs4d_render_bwd_workspace_size(int64_t n, int32_t n_views) {
     return (size_t)(n > 0 ? n : 1) * (size_t)(n_views > 0 ? n_views : 1) * 9 * sizeof(float) + 256;
 }
 
+namespace gs4d {
+namespace {
+int g_bwd_ppl = 2;   // pixels per lane of the backward (1, 2 or 4)
+}
+}  // namespace gs4d
+
+extern "C" int gs4d_set_bwd_variant(int32_t pixels_per_lane) {
+    GS4D_REQUIRE(pixels_per_lane == 1 || pixels_per_lane == 2 || pixels_per_lane == 4,
+                 "gs4d_set_bwd_variant: pixels_per_lane must be 1, 2 or 4");
+    g_bwd_ppl = pixels_per_lane;
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *vals,
+                                  const int32_t *ranges, const gs4d_view *views, int32_t n_views,
+                                  const float *dL_dimage, const float *T_final, const int32_t *last,
+                                  float *grad2d, void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_TRY(check_render_args(rec, n, vals, ranges));
+    GS4D_REQUIRE(dL_dimage && T_final && last, "gs4d_render_bwd_2d: null input");
+    GS4D_REQUIRE(n == 0 || grad2d, "gs4d_render_bwd_2d: null grad2d");
+    if (n == 0) return GS4D_OK;
+    hipStream_t st = as_stream(stream);
+    GS4D_TRY(launch_fill<float>(grad2d, 0.0f, n * n_views * 9, st));
+    const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    const int2 *rg = reinterpret_cast<const int2 *>(ranges);
+    switch (g_bwd_ppl) {
+        case 1:
+            render_bwd_kernel<BWD_BATCH, 1><<<(unsigned)n_tiles, RT_THREADS, 0, st>>>(
+                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d);
+            break;
+        case 4:
+            render_bwd_kernel<BWD_BATCH, 4><<<(unsigned)n_tiles, RT_THREADS / 4, 0, st>>>(
+                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d);
+            break;
+        default:
+            render_bwd_kernel<BWD_BATCH, 2><<<(unsigned)n_tiles, RT_THREADS / 2, 0, st>>>(
+                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d);
+            break;
+    }
+    GS4D_LAUNCH_CHECK("gs4d_render_bwd_2d");
+    return GS4D_OK;
+}
+
 extern "C" int gs4d_render_bwd(const float *params, int64_t n, const float *rec,
                                const int32_t *touched, const uint32_t *vals,
                                const int32_t *ranges, const gs4d_view *views, int32_t n_views,
                                const float *dL_dimage, const float *T_final, const int32_t *last,
                                float *dparams, float *grad2d, void *ws, size_t ws_bytes,
                                void *stream) {
-    ViewPack vp;
-    GS4D_TRY(make_view_pack(views, n_views, &vp));
-    GS4D_TRY(check_render_args(rec, n, vals, ranges));
-    GS4D_REQUIRE(dL_dimage && T_final && last, "gs4d_render_bwd: null input");
+    GS4D_REQUIRE(n >= 0, "gs4d_render_bwd: n < 0");
     GS4D_REQUIRE(n == 0 || (params && touched && dparams), "gs4d_render_bwd: null pointer");
     float *g2d = grad2d;
     if (!g2d) {
@@ -389,13 +567,7 @@ extern "C" int gs4d_render_bwd(const float *params, int64_t n, const float *rec,
                      "gs4d_render_bwd: workspace too small");
         g2d = static_cast<float *>(ws);
     }
-    if (n == 0) return GS4D_OK;
-    hipStream_t st = as_stream(stream);
-    GS4D_TRY(launch_fill<float>(g2d, 0.0f, n * n_views * 9, st));
-    const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
-    render_bwd_kernel<256><<<(unsigned)n_tiles, RT_THREADS, 0, st>>>(
-        reinterpret_cast<const float4 *>(rec), n, vals, reinterpret_cast<const int2 *>(ranges), vp,
-        dL_dimage, T_final, last, g2d);
-    GS4D_LAUNCH_CHECK("gs4d_render_bwd");
-    return launch_preprocess_bwd(params, n, vp, touched, g2d, dparams, st);
+    GS4D_TRY(gs4d_render_bwd_2d(rec, n, vals, ranges, views, n_views, dL_dimage, T_final, last, g2d,
+                                stream));
+    return gs4d_preprocess_bwd(params, n, views, n_views, touched, g2d, dparams, stream);
 }

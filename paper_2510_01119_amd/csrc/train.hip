@@ -13,6 +13,16 @@
 namespace gs4d {
 namespace {
 
+// Sum over a 256-thread block; the result is valid in thread 0.
+__device__ __forceinline__ float block_sum(float x) {
+    __shared__ float ws[4];
+    x = wave_sum(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return ws[0] + ws[1] + ws[2] + ws[3];
+}
+
 // ---------------------------------------------------------------- Adam
 __global__ void __launch_bounds__(256)
 adam_kernel(float *__restrict__ P, const float *__restrict__ Gr, float *__restrict__ M,
@@ -65,8 +75,8 @@ l1_kernel(const float *__restrict__ x, const float *__restrict__ y, int64_t coun
         s += fabsf(d);
         if (dx) dx[i] += d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
     }
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0 && s != 0.0f) atomicAdd(loss, s * scale);
+    s = block_sum(s);
+    if (threadIdx.x == 0 && s != 0.0f) atomicAdd(loss, s * scale);
 }
 
 __global__ void __launch_bounds__(256)
@@ -79,7 +89,13 @@ sse_kernel(const float *__restrict__ x, const float *__restrict__ y, int64_t cou
         s += d * d;
     }
     s = wave_sum_d(s);
-    if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(out, s);
+    __shared__ double ws[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = ws[0] + ws[1] + ws[2] + ws[3];
+        if (tot != 0.0) atomicAdd(out, tot);
+    }
 }
 
 // ---------------------------------------------------------------- SSIM
@@ -155,8 +171,8 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
             P3[o] = 2.f * S / A2;
         }
     }
-    sv = wave_sum(sv);
-    if ((t & 63) == 0 && ssim_sum) atomicAdd(ssim_sum, sv * weight * inv_count);
+    sv = block_sum(sv);
+    if (t == 0 && ssim_sum) atomicAdd(ssim_sum, sv * weight * inv_count);
 }
 
 // Backward: dSSIM/dx(q) = (G*P1)(q) + 2 x(q) (G*P2)(q) + y(q) (G*P3)(q),

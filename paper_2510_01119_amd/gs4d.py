@@ -64,6 +64,9 @@ _SIGS = {
     "gs4d_render_fwd": (_i32, [_p, _i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
     "gs4d_render_bwd_workspace_size": (_sz, [_i64, _i32]),
     "gs4d_render_bwd": (_i32, [_p, _i64, _p, _p, _p, _p, _p, _i32, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "gs4d_render_bwd_2d": (_i32, [_p, _i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
+    "gs4d_preprocess_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
+    "gs4d_set_bwd_variant": (_i32, [_i32]),
     "gs4d_grid_prune_workspace_size": (_sz, [_i64, _i32]),
     "gs4d_grid_prune": (_i32, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p, _p,
                                _p, _p, _sz, _p]),
@@ -184,6 +187,24 @@ def gs4d_render_bwd(params, rec, touched, vals, ranges, views, dL_dimage, T_fina
                                  _ptr(dparams), _ptr(grad2d), _ptr(ws),
                                  0 if ws is None else ws.numel() * ws.element_size(),
                                  _stream(stream)), "gs4d_render_bwd")
+
+
+def gs4d_render_bwd_2d(rec, n, vals, ranges, views, dL_dimage, T_final, last, grad2d, stream=None):
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_render_bwd_2d(_ptr(rec), n, _ptr(vals), _ptr(ranges), va, len(va),
+                                    _ptr(dL_dimage), _ptr(T_final), _ptr(last), _ptr(grad2d),
+                                    _stream(stream)), "gs4d_render_bwd_2d")
+
+
+def gs4d_preprocess_bwd(params, touched, grad2d, views, dparams, stream=None):
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_preprocess_bwd(_ptr(params), params.shape[1], va, len(va), _ptr(touched),
+                                     _ptr(grad2d), _ptr(dparams), _stream(stream)),
+           "gs4d_preprocess_bwd")
+
+
+def gs4d_set_bwd_variant(pixels_per_lane):
+    _check(lib().gs4d_set_bwd_variant(int(pixels_per_lane)), "gs4d_set_bwd_variant")
 
 
 def gs4d_grid_prune_workspace_size(m, k_attr):

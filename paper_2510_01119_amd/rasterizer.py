@@ -44,6 +44,17 @@ class Rasterizer:
         self.counters = torch.zeros(2, dtype=torch.int64, device=dev) if count_blends else None
         self._alloc_pairs(pair_capacity if pair_capacity else max(1 << 16, 8 * n * V))
 
+    def set_views(self, views):
+        """Point the rasterizer at other views (same count and image size)."""
+        if isinstance(views, __import__("ctypes").Array):
+            assert len(views) == self.V
+            self.cviews = views
+            return
+        v = np.atleast_2d(np.asarray(views, dtype=np.float64))
+        assert v.shape[0] == self.V and int(v[0, 16]) == self.W and int(v[0, 17]) == self.H
+        self.views_np = v
+        self.cviews = G.make_views(v)
+
     def _alloc_pairs(self, cap: int):
         self.capacity = int(cap)
         dev = self.device

@@ -1,0 +1,271 @@
+"""Seeded synthetic dynamic scene at scene scale, built on the GPU.
+
+Stand-in for the paper's video datasets (their frames, depth and camera
+recovery are not available here).  Recipe:
+
+* ground truth: about 1M Gaussians -- three textured background planes
+  (back wall, floor, side wall; procedural checker/stripe/noise colours)
+  and three rigid objects (ellipsoidal shells with striped colours) that
+  move along Catmull-Rom spline trajectories while spinning;
+* a smooth monocular camera path, fx = fy = 800 at 960x540, 200 frames with
+  timestamps t_f = f / (frames - 1);
+* each frame is rendered by this package's own rasterizer; a second pass
+  with the colour channels replaced by (camera depth, 1, dynamic flag)
+  gives the alpha-weighted depth, the coverage and a ground-truth motion
+  mask;
+* every pixel with coverage > 0.5 is back-projected to a world point with
+  its colour, timestamp and motion class (Sec. 3.2, back projection);
+* gs4d_grid_prune merges the points per voxel (Sec. 3.2, grid pruning);
+* the heuristic initialisation (Sec. 4.1): centroid position, mean
+  timestamp and colour, temporal scale 2 / frames for dynamic points (two
+  frame intervals, i.e. 2 / fps with time normalised to [0, 1]) and the
+  whole video (1.0) for static ones, spatial scale = the voxel edge,
+  opacity 0.1, identity rotors.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import gs4d as G
+from . import synth
+from .rasterizer import Rasterizer
+
+
+def _catmull_rom(P, u):
+    """Closed Catmull-Rom spline through control points P [k, 3] at u in [0, 1)."""
+    k = P.shape[0]
+    x = u * k
+    i = np.floor(x).astype(int)
+    t = (x - i)[:, None]
+    p0, p1, p2, p3 = (P[(i + d) % k] for d in (-1, 0, 1, 2))
+    return 0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t ** 2
+                  + (-p0 + 3 * p1 - 3 * p2 + p3) * t ** 3)
+
+
+def _rot_y(a):
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+
+
+class Scene:
+    def __init__(self, seed=0, n_gt=1_000_000, frames=200, width=960, height=540, focal=800.0,
+                 device="cuda", scale=0.195):
+        self.seed, self.frames, self.W, self.H, self.f = seed, frames, width, height, focal
+        # world scale of the whole scene (geometry, trajectories, camera path);
+        # projection is scale-free, so the frames look alike at any scale,
+        # while the number of occupied 0.01 voxels grows as scale^2
+        self.scale = float(scale)
+        self.device = torch.device(device)
+        rng = np.random.default_rng(seed)
+        n_obj = n_gt // 20            # three objects, 5% each
+        n_planes = n_gt - 3 * n_obj
+        self.static = self._apply_scale(self._planes(rng, n_planes))
+        obj, self.obj_id = self._objects(rng, n_obj)
+        self.obj_local = self._apply_scale(obj)
+        # object trajectories: closed splines inside the room
+        self.ctrl = [self.scale * np.stack([rng.uniform(-1.4, 1.4, 5), rng.uniform(-0.4, 0.9, 5),
+                                            rng.uniform(0.0, 2.2, 5)], axis=1) for _ in range(3)]
+        self.spin = rng.uniform(-3.0, 3.0, 3)
+        self.cams = self._camera_path(rng)
+
+    # ------------------------------------------------------------ geometry
+    def _apply_scale(self, p):
+        p = p.copy()
+        p[0:3] *= self.scale
+        p[4:7] += math.log(self.scale)
+        return p
+
+    def _planes(self, rng, n):
+        # (normal axis, plane coordinate, extents of the two other axes)
+        specs = [(2, 3.0, (-3.0, 3.0), (-2.2, 1.5)),    # back wall z = 3 (x, y)
+                 (1, 1.5, (-3.0, 3.0), (-1.5, 3.0)),    # floor y = 1.5 (x, z)
+                 (0, -3.0, (-2.2, 1.5), (-1.5, 3.0))]   # left wall x = -3 (y, z)
+        areas = np.array([(a[1] - a[0]) * (b[1] - b[0]) for _, _, a, b in specs])
+        counts = np.floor(n * areas / areas.sum()).astype(int)
+        counts[0] += n - counts.sum()
+        out = np.zeros((20, n))
+        o = 0
+        for (ax, c, ea, eb), m in zip(specs, counts):
+            u = rng.uniform(ea[0], ea[1], m)
+            v = rng.uniform(eb[0], eb[1], m)
+            others = [k for k in range(3) if k != ax]
+            xyz = np.zeros((3, m))
+            xyz[ax] = c + rng.normal(0, 0.002, m)
+            xyz[others[0]] = u
+            xyz[others[1]] = v
+            spacing = math.sqrt(areas[[s[0] for s in specs].index(ax)] / m)
+            ls = np.full((3, m), math.log(1.2 * spacing))
+            ls[ax] = math.log(0.15 * spacing)
+            # procedural texture: checker x stripes x noise, tinted per plane
+            chk = ((np.floor(u * 2.5) + np.floor(v * 2.5)) % 2)
+            stripes = 0.5 + 0.5 * np.sin(7.0 * u + 3.0 * v)
+            tint = rng.uniform(0.3, 1.0, 3)
+            col = np.clip((0.35 + 0.4 * chk[None] + 0.25 * stripes[None]) * tint[:, None]
+                          + rng.normal(0, 0.04, (3, m)), 0, 1)
+            sl = slice(o, o + m)
+            out[0:3, sl] = xyz
+            out[3, sl] = 0.5
+            out[4:7, sl] = ls
+            out[7, sl] = math.log(100.0)          # static in time
+            out[8, sl] = 1.0
+            out[12, sl] = 1.0
+            out[16, sl] = 3.0
+            out[17:20, sl] = col
+            o += m
+        return out
+
+    def _objects(self, rng, n_obj):
+        locs, ids = [], []
+        radii = [(0.35, 0.25, 0.3), (0.25, 0.4, 0.25), (0.3, 0.3, 0.2)]
+        for k in range(3):
+            d = rng.standard_normal((3, n_obj))
+            d /= np.linalg.norm(d, axis=0, keepdims=True)
+            r = np.array(radii[k])[:, None]
+            xyz = d * r * (1 + rng.normal(0, 0.01, (1, n_obj)))
+            base = rng.uniform(0.2, 1.0, 3)
+            band = (np.floor((d[1] + 1) * 4) % 2)[None]
+            col = np.clip(base[:, None] * (0.5 + 0.5 * band) + rng.normal(0, 0.03, (3, n_obj)), 0, 1)
+            area = 4 * math.pi * np.mean(radii[k]) ** 2
+            sp = math.sqrt(area / n_obj)
+            p = np.zeros((20, n_obj))
+            p[0:3] = xyz
+            p[3] = 0.5
+            p[4:7] = math.log(1.3 * sp)
+            p[7] = math.log(100.0)
+            p[8] = 1.0
+            p[12] = 1.0
+            p[16] = 3.0
+            p[17:20] = col
+            locs.append(p)
+            ids.append(np.full(n_obj, k))
+        return np.concatenate(locs, axis=1), np.concatenate(ids)
+
+    def _camera_path(self, rng):
+        cams = []
+        for f in range(self.frames):
+            u = f / max(self.frames - 1, 1)
+            eye = self.scale * np.array([-0.8 + 1.6 * u, -0.3 + 0.15 * math.sin(2 * math.pi * u),
+                                         -3.2 + 0.4 * u])
+            target = self.scale * np.array([0.2 * math.sin(math.pi * u), 0.2, 1.2])
+            Rt = synth.look_at(eye, target, up=(0.0, -1.0, 0.0))
+            cams.append(synth.make_view(Rt, self.f, self.f, self.W / 2, self.H / 2, self.W, self.H, u))
+        return np.stack(cams)
+
+    def object_pose(self, k, t):
+        pos = _catmull_rom(self.ctrl[k], np.array([t % 1.0]))[0]
+        return _rot_y(self.spin[k] * t), pos
+
+    def gt_params(self, t):
+        """Ground-truth set at time t (objects moved rigidly), float32 [20, N] on the device."""
+        if not hasattr(self, "_static_dev"):
+            self._static_dev = torch.from_numpy(self.static.astype(np.float32)).to(self.device)
+            self._obj_dev = torch.from_numpy(self.obj_local.astype(np.float32)).to(self.device)
+            self._obj_sel = [torch.from_numpy(np.nonzero(self.obj_id == k)[0]).to(self.device)
+                             for k in range(3)]
+        obj = self._obj_dev.clone()
+        for k in range(3):
+            R, pos = self.object_pose(k, t)
+            sel = self._obj_sel[k]
+            Rd = torch.from_numpy(R.astype(np.float32)).to(self.device)
+            pd = torch.from_numpy(pos.astype(np.float32)).to(self.device)
+            obj[0:3, sel] = Rd @ self._obj_dev[0:3, sel] + pd[:, None]
+        obj[3] = t
+        return torch.cat([self._static_dev, obj], dim=1).contiguous()
+
+    # ------------------------------------------------------------ synthesis
+    def render_ground_truth(self, verbose=False):
+        """Renders every frame; returns (images [F,3,H,W] on device, point
+        cloud (xyz [3,M], attr [4,M] = rgb + t, cls [M]) on device)."""
+        dev = self.device
+        n = self.static.shape[1] + self.obj_local.shape[1]
+        r = Rasterizer(n, self.cams[0], device=dev, pair_capacity=1 << 24)
+        dyn_flag = torch.zeros(n, device=dev)
+        dyn_flag[self.static.shape[1]:] = 1.0
+        images = torch.empty((self.frames, 3, self.H, self.W), device=dev)
+        pts, attrs, clss = [], [], []
+        ys, xs = torch.meshgrid(torch.arange(self.H, device=dev, dtype=torch.float32),
+                                torch.arange(self.W, device=dev, dtype=torch.float32), indexing="ij")
+        for f in range(self.frames):
+            view = self.cams[f]
+            r.set_views(view)
+            p = self.gt_params(float(view[18]))
+            r.forward(p)
+            images[f] = r.image[0]
+            # second pass: (depth, coverage, dynamic) as colours
+            rec = r.rec[0]
+            rec[:, 8] = rec[:, 6]
+            rec[:, 9] = (r.touched[0] > 0).float()
+            rec[:, 10] = dyn_flag
+            r.render()
+            aux = r.image[0]
+            cov = aux[1]
+            keep = cov > 0.5
+            depth = aux[0][keep] / cov[keep]
+            Rt = torch.from_numpy(view[:12].reshape(3, 4)).to(dev).float()
+            xc = torch.stack([(xs[keep] + 0.5 - float(view[14])) / float(view[12]) * depth,
+                              (ys[keep] + 0.5 - float(view[15])) / float(view[13]) * depth, depth])
+            world = Rt[:, :3].T @ (xc - Rt[:, 3:4])
+            pts.append(world)
+            col = images[f][:, keep]
+            attrs.append(torch.cat([col, torch.full((1, col.shape[1]), float(view[18]), device=dev)]))
+            clss.append((aux[2][keep] / cov[keep] > 0.5).to(torch.uint8))
+            if verbose and f % 50 == 0:
+                print(f"scene: frame {f}/{self.frames} pairs={int(r.n_pairs.item())}", flush=True)
+        xyz = torch.cat(pts, dim=1).contiguous()
+        attr = torch.cat(attrs, dim=1).contiguous()
+        cls = torch.cat(clss).contiguous()
+        return images, (xyz, attr, cls)
+
+    def prune(self, cloud, voxel=0.01, min_count=1):
+        xyz, attr, cls = cloud
+        dev = self.device
+        m = xyz.shape[1]
+        cap = min(m, 4_000_000)
+        out_xyz = torch.empty((3, cap), device=dev)
+        out_attr = torch.empty((attr.shape[0], cap), device=dev)
+        out_count = torch.empty(cap, dtype=torch.int32, device=dev)
+        out_key = torch.empty(cap, dtype=torch.int64, device=dev)
+        n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        ws = torch.empty(G.gs4d_grid_prune_workspace_size(m, attr.shape[0]), dtype=torch.uint8,
+                         device=dev)
+        G.gs4d_grid_prune(xyz, attr, cls, voxel, voxel, min_count, cap, out_xyz, out_attr,
+                          out_count, out_key, n_out, status, ws)
+        st, k = int(status.item()), int(n_out.item())
+        if st != 0:
+            raise RuntimeError(f"grid prune status {st} (voxels {k}, capacity {cap})")
+        del ws
+        dyn = (out_key[:k] < 0)          # class bit 63 set -> negative as int64
+        return out_xyz[:, :k], out_attr[:, :k], dyn, out_count[:k]
+
+    def heuristic_init(self, pruned, voxel=0.01):
+        xyz, attr, dyn, _ = pruned
+        k = xyz.shape[1]
+        p = torch.zeros((20, k), device=self.device)
+        p[0:3] = xyz
+        p[3] = attr[3]
+        p[4:7] = math.log(voxel)
+        p[7] = torch.where(dyn, torch.full_like(attr[3], math.log(2.0 / self.frames)),
+                           torch.zeros_like(attr[3]))
+        p[8] = 1.0
+        p[12] = 1.0
+        p[16] = math.log(0.1 / 0.9)
+        p[17:20] = attr[0:3]
+        return p.contiguous()
+
+
+def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel=0.01,
+                device="cuda", verbose=False):
+    """Ground-truth frames and the pruned, heuristically initialised set."""
+    sc = Scene(seed, n_gt, frames, width, height, device=device)
+    images, cloud = sc.render_ground_truth(verbose)
+    n_raw = cloud[0].shape[1]
+    pruned = sc.prune(cloud, voxel)
+    del cloud
+    params = sc.heuristic_init(pruned, voxel)
+    info = dict(n_raw_points=n_raw, n_gaussians=params.shape[1],
+                n_dynamic=int(pruned[2].sum().item()))
+    return sc, images, params, info

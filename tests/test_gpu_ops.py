@@ -41,10 +41,12 @@ def test_adam_matches_oracle():
     torch.cuda.synchronize()
     assert int(step.item()) == 5
     assert np.allclose(M.cpu().numpy(), rm, rtol=1e-5, atol=1e-7)
-    assert np.allclose(V.cpu().numpy(), rv, rtol=1e-5, atol=1e-9)
+    # beta2 = 0.999 is not representable in FP32: 1 - fl32(0.999) differs
+    # from 0.001 by 1.3e-5 relative, which the second moment inherits
+    assert np.allclose(V.cpu().numpy(), rv, rtol=5e-5, atol=1e-9)
     got = P.cpu().numpy().astype(np.float64)
     for k in range(20):
-        assert np.allclose(got[k], rp[k], rtol=1e-4, atol=1e-6 * lr0[k])
+        assert np.allclose(got[k], rp[k], rtol=1e-4, atol=1e-5 * lr0[k])
 
 
 @pytest.mark.parametrize("shape", [(1, 3, 64, 64), (2, 3, 37, 50)])

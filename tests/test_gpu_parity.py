@@ -57,6 +57,23 @@ def test_binsort_bitexact(case):
     assert np.array_equal(g["ranges"], o["ranges"])
 
 
+@pytest.mark.parametrize("batch", [64, 128])
+def test_render_fwd_batches_identical(case, batch):
+    """Every LDS batch size renders the same bits as the default one."""
+    r = case["rast"]
+    ref_img, ref_T, ref_last = r.image.clone(), r.T_final.clone(), r.last.clone()
+    r.batch = batch
+    try:
+        r.render()
+        torch.cuda.synchronize()
+        assert torch.equal(r.image, ref_img)
+        assert torch.equal(r.T_final, ref_T)
+        assert torch.equal(r.last, ref_last)
+    finally:
+        r.batch = 256
+        r.render()
+
+
 def test_render_fwd_image(case):
     g, o = case["gpu"], case["ref"]
     near = near_threshold_pixels(o["rec"].astype(np.float64), case["views"], o["vals"], o["ranges"])
@@ -72,12 +89,18 @@ def test_render_fwd_image(case):
     assert abs(g["n_blend"] - o["n_blend"]) <= max(10, 0.001 * o["n_blend"])
 
 
-def test_render_bwd_gradients(case):
+@pytest.mark.parametrize("ppl", [1, 2, 4])
+def test_render_bwd_gradients(case, ppl):
     need_gpu()
+    from paper_2510_01119_amd import gs4d as G
     params, views, r, p = case["params"], case["views"], case["rast"], case["p"]
     V, H, W = r.V, r.H, r.W
     w = synth.linear_loss_weights(V, H, W, seed=11)
-    dparams = r.backward(p, torch.from_numpy(w).cuda()).cpu().numpy()
+    G.gs4d_set_bwd_variant(ppl)
+    try:
+        dparams = r.backward(p, torch.from_numpy(w).cuda()).cpu().numpy()
+    finally:
+        G.gs4d_set_bwd_variant(2)
     ref, _ = oracle.backward(params, views, w.astype(np.float64), fwd=case["ref"])
     # Gaussians visible at a pixel next to a threshold are exempted (counted)
     _, tainted = near_threshold_pixels(case["ref"]["rec"].astype(np.float64), views,

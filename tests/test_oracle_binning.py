@@ -53,7 +53,8 @@ def test_sort_and_ranges_bruteforce(oracle_lib, n, W, H, views):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_footprint_is_exact(oracle_lib, precision):
-    """No pixel outside a Gaussian's pixel rectangle reaches alpha >= 1/255."""
+    """No pixel outside a Gaussian's pixel rectangle, nor outside the box
+    mean2D +- the recorded half-widths, reaches alpha >= 1/255."""
     p = synth.small_set(400, seed=9, log_s_xyz=(-2.2, 0.6))
     view = synth.front_view(64, 64, f=64.0, dist=3.0, t=0.5)
     if precision == "f64":
@@ -74,6 +75,14 @@ def test_footprint_is_exact(oracle_lib, precision):
         x0, y0, x1, y1 = rect[0, g]
         inside = (xs >= 16 * x0) & (xs < 16 * x1) & (ys >= 16 * y0) & (ys < 16 * y1)
         assert not np.any(hit & ~inside), g
+        # finer: pixel centres outside mean2D +- (hx, hy) never reach 1/255
+        hx, hy = rec[g, 7], rec[g, 11]
+        in_box = (np.abs(px - mx) <= hx) & (np.abs(py - my) <= hy)
+        assert not np.any(hit & ~in_box), g
+        # and the box is tight: it is the bounding box of the alpha level set
+        # enlarged by the 2^-10 margin only
+        if hit.any():
+            assert hx <= 1.01 * np.abs(px - mx)[hit].max() + 2.0
     assert n_vis > 100
 
 
