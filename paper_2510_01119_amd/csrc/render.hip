@@ -24,9 +24,9 @@ constexpr int RT_WAVES = 4;
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float ALPHA_MAX = 0.99f;
 constexpr float T_EPS = 1e-4f;
-// backward stages 128 Gaussians per round: its per-wave partial sums then
-// take 18 KB of LDS and six tiles fit on a CU at once
-constexpr int BWD_BATCH = 128;
+// backward stages 64 Gaussians per round: its per-wave, per-row partial sums
+// then take 36 KB of LDS and four tiles fit on a CU at once
+constexpr int BWD_BATCH = 64;
 
 struct TileInfo {
     int v, tx, ty;
@@ -245,6 +245,21 @@ __device__ __forceinline__ float dpp_f(float x) {
         __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
 }
 
+// Sums N values over each 16-lane DPP row (row_shr 1/2/4/8, all N values per
+// stage so consecutive DPP operations are independent); each row's total is
+// valid in its last lane (15, 31, 47, 63).
+template <int N>
+__device__ __forceinline__ void row_totals(float (&x)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x111, 0xF>(x[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x112, 0xF>(x[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x114, 0xF>(x[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x118, 0xF>(x[q]);
+}
+
 // Reduces N independent values at once, one DPP stage at a time across all
 // of them, so consecutive DPP operations never depend on each other.
 template <int N>
@@ -266,8 +281,15 @@ __device__ __forceinline__ void wave_total_lane63(float (&x)[N]) {
 // PPL = pixels per lane.  The workgroup has 256 / PPL threads; wave w owns
 // the 16 x (4 PPL) strip starting at tile row 4 PPL w, lane l the pixels
 // (l mod 16, 4 PPL w + l div 16 + 4 k), k < PPL.  Each lane folds its PPL
-// pixels' terms for an entry before the one cross-lane reduction, so a
-// reduction serves PPL pixel evaluations.
+// pixels' terms for an entry before the cross-lane reduction.
+//
+// Reduction of the nine gradient terms of one entry over one wave: DPP sums
+// over each 16-lane row, then the four row-leader lanes store their row
+// totals into LDS slots part[wave][row][entry][term] (one store instruction
+// per term).  After the batch, each entry's slots are summed and added to
+// HBM with one atomic per term.  A wave skips every entry its strip-box test
+// rejects and every entry no lane of it actually blends; the per-wave,
+// per-row "written" masks record which slots hold data.
 template <int BATCH, int PPL>
 __global__ void __launch_bounds__(RT_THREADS / PPL)
 render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__restrict__ vals,
@@ -281,8 +303,8 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
     __shared__ float4 sB[BATCH];
     __shared__ float4 sC[BATCH];
     __shared__ uint32_t sG[BATCH];
-    __shared__ float part[NW][BATCH][9];   // per-wave sums, valid where the wave's mask is set
-    __shared__ uint64_t smask[NW][NK];
+    __shared__ float part[NW][4][BATCH][9];
+    __shared__ uint64_t written[NW][NK];
     __shared__ int smax;
 
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -335,6 +357,8 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
     if (max_last < rg.x) return;
     const float4 *recv = rec + (int64_t)ti.v * n * 3;
     float *gview = grad2d + (int64_t)ti.v * n * 9;
+    const int drow = lane >> 4;
+    const bool row_leader = (lane & 15) == 15;
 
     for (int end = max_last + 1; end > rg.x; end -= BATCH) {
         const int start = max(rg.x, end - BATCH);
@@ -353,12 +377,10 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
         __syncthreads();
         // entries beyond this wave's last blended one are skipped too
         const int wcnt = min(cnt, wave_last - start + 1);
-        uint64_t m[NK];
+        uint64_t m[NK], wr[NK];
         strip_masks<BATCH>(sA, sC, wcnt, sx0, sx1, sy0, sy1, lane, m);
-        if (lane == 0) {
 #pragma unroll
-            for (int k = 0; k < NK; ++k) smask[w][k] = m[k];
-        }
+        for (int k = 0; k < NK; ++k) wr[k] = 0;
         // Branch-free per entry (selects only), entries taken back to front
         // two at a time so their LDS reads overlap.
         auto grad_one = [&](int j, float4 a, float4 b, float cbl) {
@@ -366,6 +388,7 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
             float d[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) d[q] = 0.0f;
+            bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 const float dx = fx - a.x, dy = fy[k] - a.y;
@@ -374,6 +397,7 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
                 const float at = b.y * ex;
                 const float alpha = fminf(ALPHA_MAX, at);
                 const bool ok = (idx <= my_last[k]) && !(power > 0.0f) && !(alpha < ALPHA_MIN);
+                any = any || ok;
                 // transmittance in front of this entry
                 const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
                 T[k] = ok ? Tk : T[k];
@@ -397,10 +421,12 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
                 d[0] = fmaf(dpow, a.z * dx + a.w * dy, d[0]);
                 d[1] = fmaf(dpow, b.x * dy + a.w * dx, d[1]);
             }
-            wave_total_lane63<9>(d);
-            if (lane == 63) {
+            if (__ballot(any) == 0) return;   // no lane of this wave blends the entry
+            wr[j >> 6] |= 1ull << (j & 63);
+            row_totals<9>(d);
+            if (row_leader) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) part[w][j][q] = d[q];
+                for (int q = 0; q < 9; ++q) part[w][drow][j][q] = d[q];
             }
         };
 #pragma unroll
@@ -421,29 +447,24 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
                 if (two) grad_one(j1, a1, b1, c1);
             }
         }
-        __syncthreads();
-        for (int i = t; i < cnt; i += NT) {
-            float sum[9];
+        if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) sum[q] = 0.0f;
-            const int k = i >> 6;
-            const uint64_t bit = 1ull << (i & 63);
+            for (int k = 0; k < NK; ++k) written[w][k] = wr[k];
+        }
+        __syncthreads();
+        // one thread per (entry, term): sum the written slots, one atomic
+        for (int i = t; i < cnt * 9; i += NT) {
+            const int e = i / 9, q = i - 9 * e;
+            const uint64_t bit = 1ull << (e & 63);
+            float sum = 0.0f;
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
-                if (smask[ww][k] & bit) {
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) sum[q] += part[ww][i][q];
+                if (written[ww][e >> 6] & bit) {
+                    sum += part[ww][0][e][q] + part[ww][1][e][q] + part[ww][2][e][q] +
+                           part[ww][3][e][q];
                 }
             }
-            bool any = false;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) any |= sum[q] != 0.0f;
-            if (any) {
-                float *dst = gview + (int64_t)sG[i] * 9;
-#pragma unroll
-                for (int q = 0; q < 9; ++q)
-                    if (sum[q] != 0.0f) atomicAdd(dst + q, sum[q]);
-            }
+            if (sum != 0.0f) atomicAdd(gview + (int64_t)sG[e] * 9 + q, sum);
         }
     }
 }

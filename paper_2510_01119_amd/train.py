@@ -100,12 +100,56 @@ class Trainer:
         if self.ssim_w > 0:
             G.gs4d_ssim(r.image, target, -self.ssim_w, self.ssim, self.dimg, self.ssim_ws)
 
-    def step(self, f: int):
+    def stage_forward(self, f: int):
         self.forward_loss(f)
+        torch.maximum(self.overflow_seen, self.rast.overflow, out=self.overflow_seen)
+
+    def stage_render_bwd(self, f: int):
         r = self.rast
-        r.backward(self.params, self.dimg)
+        G.gs4d_render_bwd_2d(r.rec, r.n, r.vals, r.ranges, self.cviews[f], self.dimg, r.T_final,
+                             r.last, r.grad2d)
+
+    def stage_update(self, f: int):
+        r = self.rast
+        G.gs4d_preprocess_bwd(self.params, r.touched, r.grad2d, self.cviews[f], r.dparams)
         G.gs4d_adam_step(self.params, r.dparams, self.m, self.v, self.cfg, self.step_dev)
-        torch.maximum(self.overflow_seen, r.overflow, out=self.overflow_seen)
+
+    def step(self, f: int):
+        self.stage_forward(f)
+        self.stage_render_bwd(f)
+        self.stage_update(f)
+
+    # ------------------------------------------------------------ graphs
+    def capture(self, frames):
+        """Capture each frame's step as three HIP graphs: [preprocess, bin/sort,
+        render, loss], [render backward], [preprocess backward, Adam].  The
+        split lets a caller time the render backward with events between
+        replays.  Every buffer is preallocated, so replays allocate nothing."""
+        self.graphs = {}
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        for f in frames:
+            gs = []
+            for stage in (self.stage_forward, self.stage_render_bwd, self.stage_update):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=side):
+                    stage(f)
+                gs.append(g)
+            self.graphs[f] = gs
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+
+    def step_graph(self, f: int, events=None):
+        """Replay frame f's captured step; with events=(a, b), a and b are
+        recorded around the render-backward graph."""
+        g0, g1, g2 = self.graphs[f]
+        g0.replay()
+        if events is not None:
+            events[0].record()
+        g1.replay()
+        if events is not None:
+            events[1].record()
+        g2.replay()
 
     def loss_value(self) -> float:
         """L1 + w (1 - SSIM) of the last forward (synchronises)."""
