@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--scene-cache", default=None,
                     help="save/load the synthesised scene here (e.g. /tmp/gs4d_scene.pt)")
     args = ap.parse_args()
@@ -130,6 +132,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     G.lib()
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per byte
+        # calibrates the counters read for the gs4d kernels
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("bench: calibration copy 256 MiB x 2 done")
     log(f"bench: building workload {args.workload}")
     params, views, images, info = build_workload(args.workload, dev, args.scene_cache)
     n = params.shape[1]
@@ -206,14 +218,8 @@ def main():
         mark("bin_sort", lambda: r.bin_sort(check=False))
         mark("render_fwd", lambda: r.render())
 
-        def loss():
-            target = tr.targets[f:f + 1]
-            G.gs4d_fill_f32(tr.dimg, 0.0)
-            G.gs4d_fill_f32(tr.l1, 0.0)
-            G.gs4d_fill_f32(tr.ssim, 0.0)
-            G.gs4d_loss_l1(r.image, target, 1.0, tr.l1, tr.dimg)
-            G.gs4d_ssim(r.image, target, -tr.ssim_w, tr.ssim, tr.dimg, tr.ssim_ws)
-        mark("loss", loss)
+        mark("loss", lambda: G.gs4d_photometric_loss(r.image, tr.targets[f:f + 1], 1.0, tr.ssim_w,
+                                                     tr.loss, tr.dimg, tr.ssim_ws))
         mark("render_bwd", lambda: tr.stage_render_bwd(f))
         mark("preprocess_bwd", lambda: G.gs4d_preprocess_bwd(tr.params, r.touched, r.grad2d,
                                                              tr.cviews[f], r.dparams))

@@ -241,11 +241,24 @@ int gs4d_loss_l1(const float *img, const float *target, int64_t count, float wei
  * padding, mean over images x channels x pixels) of img [b][c][h][w]
  * against target.  ssim_sum (device float) is accumulated with the mean
  * SSIM times `weight`; dL_dimg (if not NULL) is accumulated with
- * weight * dSSIM/dimg. */
+ * weight * dSSIM/dimg.  Calls that can run concurrently must not share a
+ * workspace. */
 size_t gs4d_ssim_workspace_size(int32_t b, int32_t c, int32_t h, int32_t w);
 int gs4d_ssim(const float *img, const float *target, int32_t b, int32_t c, int32_t h, int32_t w,
               float weight, float *ssim_sum, float *dL_dimg, void *ws, size_t ws_bytes,
               void *stream);
+
+/* The photometric loss of the optimisation loop in one call (Sec. 4.1, the
+ * single photometric loss; reading: w_l1 L1 + w_ssim (1 - SSIM), with
+ * w_l1 = 1, w_ssim = 0.2 at scene scale):
+ *   loss (device float, overwritten) = w_l1 mean|img - target|
+ *                                      + w_ssim (1 - mean SSIM)
+ *   dL_dimg (overwritten) = its gradient.
+ * img, target [b][c][h][w]; ws >= gs4d_photometric_loss_workspace_size(). */
+size_t gs4d_photometric_loss_workspace_size(int32_t b, int32_t c, int32_t h, int32_t w);
+int gs4d_photometric_loss(const float *img, const float *target, int32_t b, int32_t c, int32_t h,
+                          int32_t w, float w_l1, float w_ssim, float *loss, float *dL_dimg,
+                          void *ws, size_t ws_bytes, void *stream);
 
 /* Sum of squared differences, accumulated into sse (device double). */
 int gs4d_sse(const float *img, const float *target, int64_t count, double *sse, void *stream);

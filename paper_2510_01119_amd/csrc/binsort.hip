@@ -28,9 +28,12 @@ namespace {
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = RS_THREADS * RS_ITEMS;   // 4096 keys per block
 constexpr int RS_MAX_PASSES = 8;
+// keys per block = 256 threads x ITEMS; small inputs use ITEMS = 4 so that
+// enough blocks exist to fill the GPU, large ones ITEMS = 16
+constexpr int RS_SMALL_ITEMS = 4;
+constexpr int RS_LARGE_ITEMS = 16;
+constexpr int64_t RS_SMALL_LIMIT = 1 << 20;
 
 __device__ __forceinline__ int64_t read_count(const int64_t *count_dev, int64_t count_host,
                                               int64_t capacity) {
@@ -45,14 +48,16 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
     return (uint32_t)((key >> shift) & (K)0xFF);
 }
 
-// Block b covers keys [b*4096, (b+1)*4096).  Wave w owns the contiguous 1024
-// keys starting at b*4096 + w*1024; item i of lane l is key w*1024 + i*64 + l,
-// so every wave load reads 64 consecutive keys.
-template <class K>
+// Block b covers keys [b*TILE, (b+1)*TILE), TILE = 256 * ITEMS.  Wave w owns
+// the contiguous 64*ITEMS keys starting at b*TILE + w*64*ITEMS; item i of
+// lane l is key w*64*ITEMS + i*64 + l, so every wave load reads 64
+// consecutive keys.
+template <class K, int RS_ITEMS>
 __global__ void __launch_bounds__(RS_THREADS)
 rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t count_host,
                int64_t capacity, int shift, uint32_t *__restrict__ hist,
                uint32_t *__restrict__ digit_total) {
+    constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
     const int64_t n = read_count(count_dev, count_host, capacity);
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
     const int64_t b = blockIdx.x;
@@ -79,7 +84,7 @@ rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t cou
 // all smaller digits.
 __global__ void __launch_bounds__(64)
 rs_scan_kernel(uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_total,
-               const int64_t *count_dev, int64_t count_host, int64_t capacity) {
+               const int64_t *count_dev, int64_t count_host, int64_t capacity, int RS_TILE) {
     const int64_t n = read_count(count_dev, count_host, capacity);
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
     if (nb == 0) return;
@@ -104,12 +109,13 @@ rs_scan_kernel(uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_t
     }
 }
 
-template <class K>
+template <class K, int RS_ITEMS>
 __global__ void __launch_bounds__(RS_THREADS)
 rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                   K *__restrict__ kout, uint32_t *__restrict__ vout, const int64_t *count_dev,
                   int64_t count_host, int64_t capacity, int shift,
                   const uint32_t *__restrict__ hist) {
+    constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
     const int64_t n = read_count(count_dev, count_host, capacity);
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
     const int64_t b = blockIdx.x;
@@ -349,27 +355,21 @@ inline unsigned grid_for(int64_t count, int threads) {
     return (unsigned)(b > 0 ? b : 1);
 }
 
-template <class K>
-int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
-                    int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
-                    hipStream_t st, int *result_in_alt) {
-    const int passes = (bit_hi - bit_lo + 7) / 8;
-    *result_in_alt = passes & 1;
-    if (passes <= 0 || capacity <= 0) return GS4D_OK;
-    const int64_t nb_max = (capacity + RS_TILE - 1) / RS_TILE;
-    Carve c(ws, ~size_t(0));
-    uint32_t *hist = c.take<uint32_t>((size_t)nb_max * 256);
-    uint32_t *totals = c.take<uint32_t>((size_t)RS_MAX_PASSES * 256);
-    GS4D_TRY(launch_fill<uint32_t>(totals, 0u, (int64_t)passes * 256, st));
+template <class K, int ITEMS>
+int radix_passes(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
+                 int64_t count_host, int64_t capacity, int bit_lo, int passes, uint32_t *hist,
+                 uint32_t *totals, hipStream_t st) {
+    constexpr int TILE = RS_THREADS * ITEMS;
+    const int64_t nb_max = (capacity + TILE - 1) / TILE;
     K *src = k0, *dst = k1;
     uint32_t *vsrc = v0, *vdst = v1;
     for (int p = 0; p < passes; ++p) {
         const int shift = bit_lo + 8 * p;
         uint32_t *tot = totals + p * 256;
-        rs_hist_kernel<K><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(src, count_dev, count_host,
-                                                                   capacity, shift, hist, tot);
-        rs_scan_kernel<<<256, 64, 0, st>>>(hist, tot, count_dev, count_host, capacity);
-        rs_scatter_kernel<K><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+        rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+            src, count_dev, count_host, capacity, shift, hist, tot);
+        rs_scan_kernel<<<256, 64, 0, st>>>(hist, tot, count_dev, count_host, capacity, TILE);
+        rs_scatter_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
             src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, hist);
         GS4D_LAUNCH_CHECK("radix pass");
         K *tk = src; src = dst; dst = tk;
@@ -378,10 +378,29 @@ int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *cou
     return GS4D_OK;
 }
 
+template <class K>
+int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
+                    int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
+                    hipStream_t st, int *result_in_alt) {
+    const int passes = (bit_hi - bit_lo + 7) / 8;
+    *result_in_alt = passes & 1;
+    if (passes <= 0 || capacity <= 0) return GS4D_OK;
+    const int64_t nb_max = (capacity + RS_THREADS * RS_SMALL_ITEMS - 1) / (RS_THREADS * RS_SMALL_ITEMS);
+    Carve c(ws, ~size_t(0));
+    uint32_t *hist = c.take<uint32_t>((size_t)nb_max * 256);
+    uint32_t *totals = c.take<uint32_t>((size_t)RS_MAX_PASSES * 256);
+    GS4D_TRY(launch_fill<uint32_t>(totals, 0u, (int64_t)passes * 256, st));
+    if (capacity <= RS_SMALL_LIMIT)
+        return radix_passes<K, RS_SMALL_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
+                                                bit_lo, passes, hist, totals, st);
+    return radix_passes<K, RS_LARGE_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity, bit_lo,
+                                            passes, hist, totals, st);
+}
+
 }  // namespace
 
 size_t radix_workspace_size(int64_t capacity) {
-    const int64_t nb_max = (capacity + RS_TILE - 1) / RS_TILE;
+    const int64_t nb_max = (capacity + RS_THREADS * RS_SMALL_ITEMS - 1) / (RS_THREADS * RS_SMALL_ITEMS);
     Carve c(nullptr, 0);
     c.take<uint32_t>((size_t)(nb_max > 0 ? nb_max : 1) * 256);
     c.take<uint32_t>((size_t)RS_MAX_PASSES * 256);

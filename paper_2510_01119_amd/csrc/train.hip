@@ -110,11 +110,16 @@ struct Win {
 };
 
 // Forward: per pixel SSIM and its partial derivatives with respect to the
-// windowed statistics mu_x, E[x^2], E[xy] (written to three maps).
+// windowed statistics mu_x, E[x^2], E[xy] (written to three maps).  Each
+// block stores its SSIM sum (and, when fused, its L1 sum) as a partial;
+// partial_sum_kernel adds them up, so no block ever waits on another.  With
+// l1_grad set, the kernel also writes dL/dimg = l1_scale sign(x - y)
+// (overwriting), the L1 term of the photometric loss.
 __global__ void __launch_bounds__(256)
 ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h, int w, Win win,
-                float weight, float inv_count, float *__restrict__ ssim_sum,
-                float *__restrict__ P1, float *__restrict__ P2, float *__restrict__ P3) {
+                float *__restrict__ P1, float *__restrict__ P2, float *__restrict__ P3,
+                float *__restrict__ part_ssim, float *__restrict__ part_l1, float l1_scale,
+                float *__restrict__ l1_grad) {
     __shared__ float sx[SS_E][SS_E], sy[SS_E][SS_E];
     __shared__ float hs[5][SS_E][SS_T];
     const int t = threadIdx.x;
@@ -156,7 +161,7 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
         for (int q = 0; q < 5; ++q) m[q] += g * hs[q][r + k][c];
     }
     const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
-    float sv = 0.0f;
+    float sv = 0.0f, lv = 0.0f;
     if (gx < w && gy < h) {
         const float mx = m[0], my = m[1];
         const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
@@ -170,9 +175,38 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
             P2[o] = -S / B2;
             P3[o] = 2.f * S / A2;
         }
+        if (part_l1) {
+            const float d = sx[r + SS_R][c + SS_R] - sy[r + SS_R][c + SS_R];
+            lv = fabsf(d);
+            if (l1_grad) l1_grad[o] = d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f);
+        }
     }
+    const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     sv = block_sum(sv);
-    if (t == 0 && ssim_sum) atomicAdd(ssim_sum, sv * weight * inv_count);
+    if (part_l1) lv = block_sum(lv);
+    if (t == 0) {
+        part_ssim[bid] = sv;
+        if (part_l1) part_l1[bid] = lv;
+    }
+}
+
+// One block: out[0] += a * sum(pa) + b * sum(pb) + c (pb may be NULL); with
+// overwrite set the output is replaced instead of accumulated.  Partial
+// sums are added in a fixed order, so the result is deterministic.
+__global__ void __launch_bounds__(256)
+partial_sum_kernel(const float *__restrict__ pa, const float *__restrict__ pb, int count, float a,
+                   float b, float c, float *__restrict__ out, int overwrite) {
+    float sa = 0.0f, sb = 0.0f;
+    for (int i = threadIdx.x; i < count; i += 256) {
+        sa += pa[i];
+        if (pb) sb += pb[i];
+    }
+    sa = block_sum(sa);
+    sb = block_sum(sb);
+    if (threadIdx.x == 0) {
+        const float v = a * sa + b * sb + c;
+        out[0] = overwrite ? v : out[0] + v;
+    }
 }
 
 // Backward: dSSIM/dx(q) = (G*P1)(q) + 2 x(q) (G*P2)(q) + y(q) (G*P3)(q),
@@ -271,8 +305,9 @@ extern "C" int gs4d_loss_l1(const float *img, const float *target, int64_t count
     GS4D_REQUIRE(count >= 0 && loss, "gs4d_loss_l1: bad arguments");
     if (count == 0) return GS4D_OK;
     GS4D_REQUIRE(img && target, "gs4d_loss_l1: null pointer");
-    l1_kernel<<<stride_grid(count), 256, 0, as_stream(stream)>>>(img, target, count, weight, loss,
-                                                                  dL_dimg);
+    // four blocks per CU: enough loads in flight, few same-address atomics
+    const unsigned blocks = stride_grid(count) < 1024 ? stride_grid(count) : 1024;
+    l1_kernel<<<blocks, 256, 0, as_stream(stream)>>>(img, target, count, weight, loss, dL_dimg);
     GS4D_LAUNCH_CHECK("gs4d_loss_l1");
     return GS4D_OK;
 }
@@ -282,14 +317,38 @@ extern "C" int gs4d_sse(const float *img, const float *target, int64_t count, do
     GS4D_REQUIRE(count >= 0 && sse, "gs4d_sse: bad arguments");
     if (count == 0) return GS4D_OK;
     GS4D_REQUIRE(img && target, "gs4d_sse: null pointer");
-    sse_kernel<<<stride_grid(count), 256, 0, as_stream(stream)>>>(img, target, count, sse);
+    const unsigned blocks = stride_grid(count) < 256 ? stride_grid(count) : 256;
+    sse_kernel<<<blocks, 256, 0, as_stream(stream)>>>(img, target, count, sse);
     GS4D_LAUNCH_CHECK("gs4d_sse");
     return GS4D_OK;
 }
 
 extern "C" size_t gs4d_ssim_workspace_size(int32_t b, int32_t c, int32_t h, int32_t w) {
-    return (size_t)3 * (size_t)b * c * h * w * sizeof(float) + 3 * 256;
+    const size_t blocks = (size_t)((w + 15) / 16) * ((h + 15) / 16) * b * c;
+    return (size_t)3 * (size_t)b * c * h * w * sizeof(float) + 2 * blocks * sizeof(float) + 6 * 256;
 }
+
+namespace {
+struct SsimWs {
+    float *P1, *P2, *P3, *part_ssim, *part_l1;
+    dim3 grid;
+};
+
+SsimWs carve_ssim(void *ws, size_t ws_bytes, int32_t b, int32_t c, int32_t h, int32_t w) {
+    SsimWs S;
+    const int64_t count = (int64_t)b * c * h * w;
+    Carve cv(ws, ws_bytes);
+    S.P1 = cv.take<float>((size_t)count);
+    S.P2 = cv.take<float>((size_t)count);
+    S.P3 = cv.take<float>((size_t)count);
+    S.grid = dim3((unsigned)((w + SS_T - 1) / SS_T), (unsigned)((h + SS_T - 1) / SS_T),
+                  (unsigned)(b * c));
+    const size_t nb = (size_t)S.grid.x * S.grid.y * S.grid.z;
+    S.part_ssim = cv.take<float>(nb);
+    S.part_l1 = cv.take<float>(nb);
+    return S;
+}
+}  // namespace
 
 extern "C" int gs4d_ssim(const float *img, const float *target, int32_t b, int32_t c, int32_t h,
                          int32_t w, float weight, float *ssim_sum, float *dL_dimg, void *ws,
@@ -297,26 +356,56 @@ extern "C" int gs4d_ssim(const float *img, const float *target, int32_t b, int32
     GS4D_REQUIRE(b > 0 && c > 0 && h > 0 && w > 0, "gs4d_ssim: bad shape");
     GS4D_REQUIRE((int64_t)b * c <= 65535, "gs4d_ssim: too many planes");
     GS4D_REQUIRE(img && target, "gs4d_ssim: null image");
+    GS4D_REQUIRE(ws && ws_bytes >= gs4d_ssim_workspace_size(b, c, h, w),
+                 "gs4d_ssim: workspace too small");
     hipStream_t st = as_stream(stream);
     const int64_t count = (int64_t)b * c * h * w;
-    float *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
-    if (dL_dimg) {
-        GS4D_REQUIRE(ws && ws_bytes >= gs4d_ssim_workspace_size(b, c, h, w),
-                     "gs4d_ssim: workspace too small");
-        Carve cv(ws, ws_bytes);
-        P1 = cv.take<float>((size_t)count);
-        P2 = cv.take<float>((size_t)count);
-        P3 = cv.take<float>((size_t)count);
-    }
+    SsimWs S = carve_ssim(ws, ws_bytes, b, c, h, w);
     const Win win = make_window();
-    dim3 grid((unsigned)((w + SS_T - 1) / SS_T), (unsigned)((h + SS_T - 1) / SS_T), (unsigned)(b * c));
-    ssim_fwd_kernel<<<grid, 256, 0, st>>>(img, target, h, w, win, weight, 1.0f / (float)count,
-                                          ssim_sum, P1, P2, P3);
+    ssim_fwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, dL_dimg ? S.P1 : nullptr, S.P2,
+                                            S.P3, S.part_ssim, nullptr, 0.0f, nullptr);
     GS4D_LAUNCH_CHECK("gs4d_ssim fwd");
+    if (ssim_sum) {
+        partial_sum_kernel<<<1, 256, 0, st>>>(S.part_ssim, nullptr, (int)(S.grid.x * S.grid.y * S.grid.z),
+                                              weight / (float)count, 0.0f, 0.0f, ssim_sum, 0);
+        GS4D_LAUNCH_CHECK("gs4d_ssim sum");
+    }
     if (dL_dimg) {
-        ssim_bwd_kernel<<<grid, 256, 0, st>>>(img, target, h, w, win, weight / (float)count, P1, P2,
-                                              P3, dL_dimg);
+        ssim_bwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, weight / (float)count, S.P1,
+                                                S.P2, S.P3, dL_dimg);
         GS4D_LAUNCH_CHECK("gs4d_ssim bwd");
+    }
+    return GS4D_OK;
+}
+
+extern "C" size_t gs4d_photometric_loss_workspace_size(int32_t b, int32_t c, int32_t h, int32_t w) {
+    return gs4d_ssim_workspace_size(b, c, h, w);
+}
+
+extern "C" int gs4d_photometric_loss(const float *img, const float *target, int32_t b, int32_t c,
+                                     int32_t h, int32_t w, float w_l1, float w_ssim, float *loss,
+                                     float *dL_dimg, void *ws, size_t ws_bytes, void *stream) {
+    GS4D_REQUIRE(b > 0 && c > 0 && h > 0 && w > 0, "gs4d_photometric_loss: bad shape");
+    GS4D_REQUIRE((int64_t)b * c <= 65535, "gs4d_photometric_loss: too many planes");
+    GS4D_REQUIRE(img && target && loss && dL_dimg, "gs4d_photometric_loss: null pointer");
+    GS4D_REQUIRE(ws && ws_bytes >= gs4d_photometric_loss_workspace_size(b, c, h, w),
+                 "gs4d_photometric_loss: workspace too small");
+    hipStream_t st = as_stream(stream);
+    const int64_t count = (int64_t)b * c * h * w;
+    const float inv = 1.0f / (float)count;
+    SsimWs S = carve_ssim(ws, ws_bytes, b, c, h, w);
+    const Win win = make_window();
+    ssim_fwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, S.P1, S.P2, S.P3, S.part_ssim,
+                                            S.part_l1, w_l1 * inv, dL_dimg);
+    GS4D_LAUNCH_CHECK("gs4d_photometric_loss fwd");
+    // loss = w_l1 mean|x - y| + w_ssim (1 - mean SSIM)
+    partial_sum_kernel<<<1, 256, 0, st>>>(S.part_l1, S.part_ssim, (int)(S.grid.x * S.grid.y * S.grid.z),
+                                          w_l1 * inv, -w_ssim * inv, w_ssim, loss, 1);
+    GS4D_LAUNCH_CHECK("gs4d_photometric_loss sum");
+    if (w_ssim != 0.0f) {
+        ssim_bwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, -w_ssim * inv, S.P1, S.P2,
+                                                S.P3, dL_dimg);
+        GS4D_LAUNCH_CHECK("gs4d_photometric_loss bwd");
     }
     return GS4D_OK;
 }

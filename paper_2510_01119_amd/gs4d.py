@@ -74,6 +74,9 @@ _SIGS = {
     "gs4d_loss_l1": (_i32, [_p, _p, _i64, _f32, _p, _p, _p]),
     "gs4d_ssim_workspace_size": (_sz, [_i32, _i32, _i32, _i32]),
     "gs4d_ssim": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _f32, _p, _p, _p, _sz, _p]),
+    "gs4d_photometric_loss_workspace_size": (_sz, [_i32, _i32, _i32, _i32]),
+    "gs4d_photometric_loss": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _f32, _f32, _p, _p, _p, _sz,
+                                     _p]),
     "gs4d_sse": (_i32, [_p, _p, _i64, _p, _p]),
     "gs4d_fill_f32": (_i32, [_p, _f32, _i64, _p]),
     "gs4d_fill_u32": (_i32, [_p, ctypes.c_uint32, _i64, _p]),
@@ -241,6 +244,18 @@ def gs4d_ssim(img, target, weight, ssim_sum, dL_dimg, ws, stream=None):
     _check(lib().gs4d_ssim(_ptr(img), _ptr(target), b, c, h, w, float(weight), _ptr(ssim_sum),
                            _ptr(dL_dimg), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
            "gs4d_ssim")
+
+
+def gs4d_photometric_loss_workspace_size(b, c, h, w):
+    return int(lib().gs4d_photometric_loss_workspace_size(b, c, h, w))
+
+
+def gs4d_photometric_loss(img, target, w_l1, w_ssim, loss, dL_dimg, ws, stream=None):
+    b, c, h, w = img.shape
+    _check(lib().gs4d_photometric_loss(_ptr(img), _ptr(target), b, c, h, w, float(w_l1),
+                                       float(w_ssim), _ptr(loss), _ptr(dL_dimg), _ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream(stream)),
+           "gs4d_photometric_loss")
 
 
 def gs4d_sse(img, target, sse, stream=None):

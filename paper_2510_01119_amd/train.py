@@ -66,10 +66,9 @@ class Trainer:
         self.ssim_w = float(ssim_weight)
         H, W = self.rast.H, self.rast.W
         self.dimg = torch.zeros((1, 3, H, W), device=dev)
-        self.l1 = torch.zeros(1, device=dev)
-        self.ssim = torch.zeros(1, device=dev)
-        self.ssim_ws = torch.zeros(G.gs4d_ssim_workspace_size(1, 3, H, W), dtype=torch.uint8,
-                                   device=dev)
+        self.loss = torch.zeros(1, device=dev)
+        self.ssim_ws = torch.zeros(G.gs4d_photometric_loss_workspace_size(1, 3, H, W),
+                                   dtype=torch.uint8, device=dev)
         self.overflow_seen = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def size_pairs(self, frames=None, margin=1.5):
@@ -93,12 +92,8 @@ class Trainer:
         r.bin_sort(check=False)
         r.render()
         target = self.targets[f:f + 1]
-        G.gs4d_fill_f32(self.dimg, 0.0)
-        G.gs4d_fill_f32(self.l1, 0.0)
-        G.gs4d_fill_f32(self.ssim, 0.0)
-        G.gs4d_loss_l1(r.image, target, 1.0, self.l1, self.dimg)
-        if self.ssim_w > 0:
-            G.gs4d_ssim(r.image, target, -self.ssim_w, self.ssim, self.dimg, self.ssim_ws)
+        G.gs4d_photometric_loss(r.image, target, 1.0, self.ssim_w, self.loss, self.dimg,
+                                self.ssim_ws)
 
     def stage_forward(self, f: int):
         self.forward_loss(f)
@@ -153,7 +148,7 @@ class Trainer:
 
     def loss_value(self) -> float:
         """L1 + w (1 - SSIM) of the last forward (synchronises)."""
-        return float(self.l1.item()) + self.ssim_w + float(self.ssim.item())
+        return float(self.loss.item())
 
     def psnr(self, frames) -> float:
         """Mean PSNR over frames (synchronises)."""

@@ -135,3 +135,24 @@ def test_grid_prune_capacity_and_range_flags():
                       status, ws)
     torch.cuda.synchronize()
     assert status.item() == 2
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 64, 64), (1, 3, 37, 50)])
+def test_photometric_loss_matches_oracle(shape):
+    """loss = L1 + 0.2 (1 - SSIM) and its gradient in one call."""
+    need_gpu()
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, 1, shape).astype(np.float32)
+    y = np.clip(x + rng.normal(0, 0.1, shape), 0, 1).astype(np.float32)
+    X, Y = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    loss = torch.full((1,), 123.0, device="cuda")
+    d = torch.full_like(X, 7.0)           # overwritten, not accumulated
+    ws = torch.zeros(G.gs4d_photometric_loss_workspace_size(*shape), dtype=torch.uint8,
+                     device="cuda")
+    for _ in range(2):                     # a second call gives the same result
+        G.gs4d_photometric_loss(X, Y, 1.0, 0.2, loss, d, ws)
+        torch.cuda.synchronize()
+        lv, g = olosses.scene_loss(x[0], y[0])
+        assert np.isclose(loss.item(), lv, rtol=1e-5)
+        gg = d.cpu().numpy()[0]
+        assert np.abs(gg - g).max() <= 1e-3 * np.abs(g).max()
