@@ -32,7 +32,9 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd train iters/s and Gaussian-pixel blends/s vs roofline; time-to-PSNR"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, unpacked
+# FP32 vector peak without packed FP32 (the library is built with packed FP32
+# disabled): 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6
+# TFLOP/s (packed FP32 would double it to 157.3)
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
@@ -302,19 +304,45 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def roofline_for(kernel, ms, n, pairs, evals, blends, hw):
-    """Algorithmic traffic / work of one launch of `kernel` over its time.
+def profiled_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none or the kernel's source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_scene_960x540_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", " ")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = fields.get("kernel_source")
+    if not src or "traffic_bytes_per_launch" not in fields:
+        return None
+    digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+    if digest != fields.get("kernel_source_sha256_16"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
-    render_fwd / render_bwd: bound by FP32 vector ALU (per evaluated
-    (pixel, entry) ~20 / ~45 FP32 operations).  Others: HBM bytes."""
+
+def roofline_for(kernel, ms, n, pairs, evals, blends, hw):
+    """Algorithmic work of one launch of `kernel` over its measured time.
+
+    render_fwd / render_bwd are bound by the FP32 vector ALU.  Algorithmic
+    FP32 operations (exp counted as one): forward 20 per evaluated
+    (pixel, Gaussian); backward 20 per evaluated plus 45 per blended one.
+    Evaluated and blended counts come from the forward's counters over the
+    same frames.  Other kernels: algorithmic HBM bytes."""
     s = ms / 1000.0
     if kernel in ("render_fwd", "render_bwd"):
-        ops = 20.0 if kernel == "render_fwd" else 45.0
-        flops = ops * evals if kernel == "render_fwd" else ops * blends * 1.0 + 20.0 * evals
+        flops = 20.0 * evals if kernel == "render_fwd" else 20.0 * evals + 45.0 * blends
         achieved = flops / s / 1e12
+        traffic = profiled_traffic(kernel)
         return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
                 "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None}
+                "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_GBps": None if traffic is None else round(traffic / s / 1e9, 1)}
     bytes_per = {
         "preprocess": 80.0 * n + 68.0 * n,
         "bin_sort": 40.0 * pairs + 64.0 * n,
