@@ -150,6 +150,9 @@ int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals, const int
  *   T_i = T_{i+1} / (1 - alpha_i) from T_final, never stored.  Gradients are
  *   zero through the 0.99 clamp, skipped entries and clamped guard-band
  *   coordinates.
+ *   opts       host, may be NULL: persistent / n_workgroups / order / queue as
+ *              for gs4d_render_fwd (a separate queue counter, zeroed); the
+ *              other fields are ignored
  *   dL_dimage  float [n_views][3][H][W]
  *   dparams    out float [20][n], overwritten (sum over views)
  *   grad2d     optional out float [n_views][n][9] (d mean2D.xy, d conic.abc,
@@ -159,9 +162,9 @@ int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals, const int
 size_t gs4d_render_bwd_workspace_size(int64_t n, int32_t n_views);
 int gs4d_render_bwd(const float *params, int64_t n, const float *rec, const int32_t *touched,
                     const uint32_t *vals, const int32_t *ranges, const gs4d_view *views,
-                    int32_t n_views, const float *dL_dimage, const float *T_final,
-                    const int32_t *last, float *dparams, float *grad2d, void *ws,
-                    size_t ws_bytes, void *stream);
+                    int32_t n_views, const gs4d_render_opts *opts, const float *dL_dimage,
+                    const float *T_final, const int32_t *last, float *dparams, float *grad2d,
+                    void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * gs4d_render_bwd_2d -- the per-pixel half of gs4d_render_bwd: zeroes and
@@ -174,10 +177,21 @@ int gs4d_render_bwd(const float *params, int64_t n, const float *rec, const int3
  *   gs4d_preprocess (culled entries contribute nothing).
  * ------------------------------------------------------------------------- */
 int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *vals, const int32_t *ranges,
-                       const gs4d_view *views, int32_t n_views, const float *dL_dimage,
-                       const float *T_final, const int32_t *last, float *grad2d, void *stream);
+                       const gs4d_view *views, int32_t n_views, const gs4d_render_opts *opts,
+                       const float *dL_dimage, const float *T_final, const int32_t *last,
+                       float *grad2d, void *stream);
 int gs4d_preprocess_bwd(const float *params, int64_t n, const gs4d_view *views, int32_t n_views,
                         const int32_t *touched, const float *grad2d, float *dparams, void *stream);
+
+/* gs4d_tile_order -- work order for the persistent render launches: the
+ *   global tiles sorted by descending number of pairs (ties by tile id),
+ *   computed on the device from `ranges`, so that the longest tiles start
+ *   first and the short ones fill the tail.  Also zeroes n_queues int32
+ *   work counters (the `queue` fields of gs4d_render_opts).
+ *   order  out int32 [n_tiles]; ws >= gs4d_tile_order_workspace_size(n_tiles). */
+size_t gs4d_tile_order_workspace_size(int64_t n_tiles);
+int gs4d_tile_order(const int32_t *ranges, int64_t n_tiles, int32_t *order, int32_t *queues,
+                    int32_t n_queues, void *ws, size_t ws_bytes, void *stream);
 
 /* gs4d_set_bwd_variant -- block shape of the render backward: each lane
  *   handles pixels_per_lane (1, 2 or 4) pixels of its tile, so a workgroup

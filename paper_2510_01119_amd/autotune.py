@@ -55,8 +55,7 @@ def tune(r, params, dL_dimage, verbose=False):
         bwd = {}
         for ppl in (1, 2, 4):
             G.gs4d_set_bwd_variant(ppl)
-            bwd[ppl] = _time(lambda: G.gs4d_render_bwd_2d(r.rec, r.n, r.vals, r.ranges, r.cviews,
-                                                          dL_dimage, r.T_final, r.last, r.grad2d))
+            bwd[ppl] = _time(lambda: r.render_bwd_2d(dL_dimage))
         best_p = min(bwd, key=bwd.get)
         choice = {"batch": best_b, "bwd_pixels_per_lane": best_p,
                   "fwd_ms": {str(k): round(v, 4) for k, v in fwd.items()},

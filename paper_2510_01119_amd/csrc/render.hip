@@ -291,24 +291,37 @@ __device__ __forceinline__ void wave_total_lane63(float (&x)[N]) {
 // rejects and every entry no lane of it actually blends; the per-wave,
 // per-row "written" masks record which slots hold data.
 template <int BATCH, int PPL>
-__global__ void __launch_bounds__(RT_THREADS / PPL)
-render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__restrict__ vals,
-                  const int2 *__restrict__ ranges, ViewPack vp,
-                  const float *__restrict__ dL_dimage, const float *__restrict__ T_final,
-                  const int32_t *__restrict__ last, float *__restrict__ grad2d) {
+struct BwdShared {
+    float4 sA[BATCH];
+    float4 sB[BATCH];
+    float4 sC[BATCH];
+    uint32_t sG[BATCH];
+    float part[RT_THREADS / PPL / 64][4][BATCH][9];
+    uint64_t written[RT_THREADS / PPL / 64][BATCH / 64];
+    int smax;
+};
+
+template <int BATCH, int PPL>
+__device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__restrict__ rec,
+                                                int64_t n, const uint32_t *__restrict__ vals,
+                                                const int2 *__restrict__ ranges, const ViewPack &vp,
+                                                const float *__restrict__ dL_dimage,
+                                                const float *__restrict__ T_final,
+                                                const int32_t *__restrict__ last,
+                                                float *__restrict__ grad2d,
+                                                BwdShared<BATCH, PPL> &sh) {
     constexpr int NK = BATCH / 64;
     constexpr int NT = RT_THREADS / PPL;
     constexpr int NW = NT / 64;
-    __shared__ float4 sA[BATCH];
-    __shared__ float4 sB[BATCH];
-    __shared__ float4 sC[BATCH];
-    __shared__ uint32_t sG[BATCH];
-    __shared__ float part[NW][4][BATCH][9];
-    __shared__ uint64_t written[NW][NK];
-    __shared__ int smax;
+    float4 *sA = sh.sA;
+    float4 *sB = sh.sB;
+    float4 *sC = sh.sC;
+    uint32_t *sG = sh.sG;
+    auto &part = sh.part;
+    auto &written = sh.written;
+    int &smax = sh.smax;
 
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    const int64_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tile, vp);
     const int W = vp.width, H = vp.height;
     const int64_t HW = (int64_t)H * W;
@@ -469,6 +482,34 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
     }
 }
 
+template <int BATCH, int PPL>
+__global__ void __launch_bounds__(RT_THREADS / PPL)
+render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__restrict__ vals,
+                  const int2 *__restrict__ ranges, ViewPack vp,
+                  const float *__restrict__ dL_dimage, const float *__restrict__ T_final,
+                  const int32_t *__restrict__ last, float *__restrict__ grad2d, int persistent,
+                  const int32_t *__restrict__ order, int32_t *__restrict__ queue) {
+    __shared__ BwdShared<BATCH, PPL> sh;
+    if (!persistent) {
+        render_tile_bwd<BATCH, PPL>(blockIdx.x, rec, n, vals, ranges, vp, dL_dimage, T_final, last,
+                                    grad2d, sh);
+        return;
+    }
+    // persistent: take tiles from the (largest-first) queue until it is empty
+    const int64_t n_tiles = (int64_t)vp.tiles_per_view * vp.n_views;
+    __shared__ int next;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int k = next;
+        if (k >= n_tiles) break;
+        const int64_t tile = order ? order[k] : k;
+        render_tile_bwd<BATCH, PPL>(tile, rec, n, vals, ranges, vp, dL_dimage, T_final, last,
+                                    grad2d, sh);
+    }
+}
+
 int check_render_args(const float *rec, int64_t n, const uint32_t *vals, const int32_t *ranges) {
     GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "render: n out of range");
     GS4D_REQUIRE(ranges != nullptr, "render: null ranges");
@@ -530,7 +571,7 @@ extern "C" size_t gs4d_render_bwd_workspace_size(int64_t n, int32_t n_views) {
 
 namespace gs4d {
 namespace {
-int g_bwd_ppl = 2;   // pixels per lane of the backward (1, 2 or 4)
+int g_bwd_ppl = 1;   // pixels per lane of the backward (1, 2 or 4)
 }
 }  // namespace gs4d
 
@@ -543,31 +584,43 @@ extern "C" int gs4d_set_bwd_variant(int32_t pixels_per_lane) {
 
 extern "C" int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *vals,
                                   const int32_t *ranges, const gs4d_view *views, int32_t n_views,
-                                  const float *dL_dimage, const float *T_final, const int32_t *last,
-                                  float *grad2d, void *stream) {
+                                  const gs4d_render_opts *opts, const float *dL_dimage,
+                                  const float *T_final, const int32_t *last, float *grad2d,
+                                  void *stream) {
     ViewPack vp;
     GS4D_TRY(make_view_pack(views, n_views, &vp));
     GS4D_TRY(check_render_args(rec, n, vals, ranges));
     GS4D_REQUIRE(dL_dimage && T_final && last, "gs4d_render_bwd_2d: null input");
     GS4D_REQUIRE(n == 0 || grad2d, "gs4d_render_bwd_2d: null grad2d");
+    gs4d_render_opts o{};
+    if (opts) o = *opts;
+    GS4D_REQUIRE(!o.persistent || o.queue, "gs4d_render_bwd_2d: persistent mode needs a queue counter");
     if (n == 0) return GS4D_OK;
     hipStream_t st = as_stream(stream);
     GS4D_TRY(launch_fill<float>(grad2d, 0.0f, n * n_views * 9, st));
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
+    unsigned grid = (unsigned)n_tiles;
+    if (o.persistent) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = (unsigned)(o.n_workgroups > 0 ? o.n_workgroups : 4 * cus);
+    }
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const int2 *rg = reinterpret_cast<const int2 *>(ranges);
+    const int ps = o.persistent ? 1 : 0;
     switch (g_bwd_ppl) {
         case 1:
-            render_bwd_kernel<BWD_BATCH, 1><<<(unsigned)n_tiles, RT_THREADS, 0, st>>>(
-                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d);
+            render_bwd_kernel<BWD_BATCH, 1><<<grid, RT_THREADS, 0, st>>>(
+                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d, ps, o.order, o.queue);
             break;
         case 4:
-            render_bwd_kernel<BWD_BATCH, 4><<<(unsigned)n_tiles, RT_THREADS / 4, 0, st>>>(
-                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d);
+            render_bwd_kernel<BWD_BATCH, 4><<<grid, RT_THREADS / 4, 0, st>>>(
+                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d, ps, o.order, o.queue);
             break;
         default:
-            render_bwd_kernel<BWD_BATCH, 2><<<(unsigned)n_tiles, RT_THREADS / 2, 0, st>>>(
-                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d);
+            render_bwd_kernel<BWD_BATCH, 2><<<grid, RT_THREADS / 2, 0, st>>>(
+                r4, n, vals, rg, vp, dL_dimage, T_final, last, grad2d, ps, o.order, o.queue);
             break;
     }
     GS4D_LAUNCH_CHECK("gs4d_render_bwd_2d");
@@ -577,9 +630,9 @@ extern "C" int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *v
 extern "C" int gs4d_render_bwd(const float *params, int64_t n, const float *rec,
                                const int32_t *touched, const uint32_t *vals,
                                const int32_t *ranges, const gs4d_view *views, int32_t n_views,
-                               const float *dL_dimage, const float *T_final, const int32_t *last,
-                               float *dparams, float *grad2d, void *ws, size_t ws_bytes,
-                               void *stream) {
+                               const gs4d_render_opts *opts, const float *dL_dimage,
+                               const float *T_final, const int32_t *last, float *dparams,
+                               float *grad2d, void *ws, size_t ws_bytes, void *stream) {
     GS4D_REQUIRE(n >= 0, "gs4d_render_bwd: n < 0");
     GS4D_REQUIRE(n == 0 || (params && touched && dparams), "gs4d_render_bwd: null pointer");
     float *g2d = grad2d;
@@ -588,7 +641,58 @@ extern "C" int gs4d_render_bwd(const float *params, int64_t n, const float *rec,
                      "gs4d_render_bwd: workspace too small");
         g2d = static_cast<float *>(ws);
     }
-    GS4D_TRY(gs4d_render_bwd_2d(rec, n, vals, ranges, views, n_views, dL_dimage, T_final, last, g2d,
-                                stream));
+    GS4D_TRY(gs4d_render_bwd_2d(rec, n, vals, ranges, views, n_views, opts, dL_dimage, T_final, last,
+                                g2d, stream));
     return gs4d_preprocess_bwd(params, n, views, n_views, touched, g2d, dparams, stream);
+}
+
+// ---------------------------------------------------------------- tile order
+namespace gs4d {
+namespace {
+__global__ void tile_cost_kernel(const int2 *__restrict__ ranges, int64_t n_tiles,
+                                 uint32_t *__restrict__ keys, uint32_t *__restrict__ ids) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tiles) return;
+    const int2 r = ranges[i];
+    // ascending sort of (2^32 - 1 - length) = descending length, stable in tile id
+    keys[i] = 0xFFFFFFFFu - (uint32_t)(r.y - r.x);
+    ids[i] = (uint32_t)i;
+}
+}  // namespace
+}  // namespace gs4d
+
+extern "C" size_t gs4d_tile_order_workspace_size(int64_t n_tiles) {
+    Carve c(nullptr, 0);
+    const size_t m = (size_t)(n_tiles > 0 ? n_tiles : 1);
+    c.take<uint32_t>(m);
+    c.take<uint32_t>(m);
+    c.take<uint32_t>(m);
+    c.take<char>(radix_workspace_size(n_tiles));
+    return c.used + 256;
+}
+
+extern "C" int gs4d_tile_order(const int32_t *ranges, int64_t n_tiles, int32_t *order,
+                               int32_t *queues, int32_t n_queues, void *ws, size_t ws_bytes,
+                               void *stream) {
+    GS4D_REQUIRE(n_tiles > 0 && n_tiles < ((int64_t)1 << 31), "gs4d_tile_order: n_tiles out of range");
+    GS4D_REQUIRE(ranges && order, "gs4d_tile_order: null pointer");
+    GS4D_REQUIRE(n_queues >= 0 && (n_queues == 0 || queues), "gs4d_tile_order: bad queues");
+    GS4D_REQUIRE(ws && ws_bytes >= gs4d_tile_order_workspace_size(n_tiles),
+                 "gs4d_tile_order: workspace too small");
+    hipStream_t st = as_stream(stream);
+    Carve c(ws, ws_bytes);
+    const size_t m = (size_t)n_tiles;
+    uint32_t *k0 = c.take<uint32_t>(m);
+    uint32_t *k1 = c.take<uint32_t>(m);
+    uint32_t *v1 = c.take<uint32_t>(m);
+    void *rws = c.take<char>(radix_workspace_size(n_tiles));
+    uint32_t *v0 = reinterpret_cast<uint32_t *>(order);
+    tile_cost_kernel<<<(unsigned)((n_tiles + 255) / 256), 256, 0, st>>>(
+        reinterpret_cast<const int2 *>(ranges), n_tiles, k0, v0);
+    GS4D_LAUNCH_CHECK("gs4d_tile_order");
+    int alt = 0;
+    // lengths are < 2^31: 32 bits, 4 passes (an even count: result in k0/v0 = order)
+    GS4D_TRY(radix_sort_u32(k0, v0, k1, v1, nullptr, n_tiles, n_tiles, 0, 32, rws, st, &alt));
+    if (n_queues > 0) GS4D_TRY(launch_fill<int32_t>(queues, 0, n_queues, st));
+    return GS4D_OK;
 }

@@ -63,8 +63,11 @@ _SIGS = {
     "gs4d_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _i32, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "gs4d_render_fwd": (_i32, [_p, _i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
     "gs4d_render_bwd_workspace_size": (_sz, [_i64, _i32]),
-    "gs4d_render_bwd": (_i32, [_p, _i64, _p, _p, _p, _p, _p, _i32, _p, _p, _p, _p, _p, _p, _sz, _p]),
-    "gs4d_render_bwd_2d": (_i32, [_p, _i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
+    "gs4d_render_bwd": (_i32, [_p, _i64, _p, _p, _p, _p, _p, _i32, _p, _p, _p, _p, _p, _p, _p, _sz,
+                               _p]),
+    "gs4d_render_bwd_2d": (_i32, [_p, _i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p, _p]),
+    "gs4d_tile_order_workspace_size": (_sz, [_i64]),
+    "gs4d_tile_order": (_i32, [_p, _i64, _p, _p, _i32, _p, _sz, _p]),
     "gs4d_preprocess_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "gs4d_set_bwd_variant": (_i32, [_i32]),
     "gs4d_grid_prune_workspace_size": (_sz, [_i64, _i32]),
@@ -182,19 +185,22 @@ def gs4d_render_bwd_workspace_size(n, n_views):
 
 
 def gs4d_render_bwd(params, rec, touched, vals, ranges, views, dL_dimage, T_final, last, dparams,
-                    grad2d=None, ws=None, stream=None):
+                    grad2d=None, ws=None, opts=None, stream=None):
     va = views if isinstance(views, ctypes.Array) else make_views(views)
     n = params.shape[1]
     _check(lib().gs4d_render_bwd(_ptr(params), n, _ptr(rec), _ptr(touched), _ptr(vals), _ptr(ranges),
-                                 va, len(va), _ptr(dL_dimage), _ptr(T_final), _ptr(last),
-                                 _ptr(dparams), _ptr(grad2d), _ptr(ws),
+                                 va, len(va), ctypes.byref(opts) if opts is not None else None,
+                                 _ptr(dL_dimage), _ptr(T_final), _ptr(last), _ptr(dparams),
+                                 _ptr(grad2d), _ptr(ws),
                                  0 if ws is None else ws.numel() * ws.element_size(),
                                  _stream(stream)), "gs4d_render_bwd")
 
 
-def gs4d_render_bwd_2d(rec, n, vals, ranges, views, dL_dimage, T_final, last, grad2d, stream=None):
+def gs4d_render_bwd_2d(rec, n, vals, ranges, views, dL_dimage, T_final, last, grad2d, opts=None,
+                       stream=None):
     va = views if isinstance(views, ctypes.Array) else make_views(views)
     _check(lib().gs4d_render_bwd_2d(_ptr(rec), n, _ptr(vals), _ptr(ranges), va, len(va),
+                                    ctypes.byref(opts) if opts is not None else None,
                                     _ptr(dL_dimage), _ptr(T_final), _ptr(last), _ptr(grad2d),
                                     _stream(stream)), "gs4d_render_bwd_2d")
 
@@ -204,6 +210,17 @@ def gs4d_preprocess_bwd(params, touched, grad2d, views, dparams, stream=None):
     _check(lib().gs4d_preprocess_bwd(_ptr(params), params.shape[1], va, len(va), _ptr(touched),
                                      _ptr(grad2d), _ptr(dparams), _stream(stream)),
            "gs4d_preprocess_bwd")
+
+
+def gs4d_tile_order_workspace_size(n_tiles):
+    return int(lib().gs4d_tile_order_workspace_size(n_tiles))
+
+
+def gs4d_tile_order(ranges, order, queues, ws, stream=None):
+    nq = 0 if queues is None else queues.numel()
+    _check(lib().gs4d_tile_order(_ptr(ranges), ranges.shape[0], _ptr(order), _ptr(queues), nq,
+                                 _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "gs4d_tile_order")
 
 
 def gs4d_set_bwd_variant(pixels_per_lane):

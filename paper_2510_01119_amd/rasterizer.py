@@ -18,7 +18,8 @@ class Rasterizer:
     """Buffers for rendering ``n`` Gaussians into ``views`` (numpy [V, 23])."""
 
     def __init__(self, n: int, views, device="cuda", pair_capacity: int | None = None,
-                 batch: int = 256, count_blends: bool = False):
+                 batch: int = 256, count_blends: bool = False, persistent: bool = False,
+                 n_workgroups: int = 0):
         self.device = torch.device(device)
         self.views_np = np.atleast_2d(np.asarray(views, dtype=np.float64))
         self.cviews = G.make_views(self.views_np)
@@ -42,6 +43,18 @@ class Rasterizer:
         self.dparams = torch.zeros((G.N_FIELDS, max(n, 1)), dtype=torch.float32, device=dev)
         self.grad2d = torch.zeros((V, max(n, 1), G.GRAD2D_FLOATS), dtype=torch.float32, device=dev)
         self.counters = torch.zeros(2, dtype=torch.int64, device=dev) if count_blends else None
+        # persistent launches: largest-first tile order + one work counter per kernel
+        self.persistent = persistent
+        self.n_workgroups = n_workgroups
+        self.order = torch.zeros(self.n_tiles, dtype=torch.int32, device=dev)
+        self.queues = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.order_ws = torch.zeros(G.gs4d_tile_order_workspace_size(self.n_tiles), dtype=torch.uint8,
+                                    device=dev)
+        # fused per-view L1 (set_target)
+        self.target = None
+        self.l1_weight = 1.0
+        self.loss_per_view = torch.zeros(V, dtype=torch.float32, device=dev)
+        self.dL_dimage = torch.zeros((V, 3, H, W), dtype=torch.float32, device=dev)
         self._alloc_pairs(pair_capacity if pair_capacity else max(1 << 16, 8 * n * V))
 
     def set_views(self, views):
@@ -80,18 +93,47 @@ class Rasterizer:
             need = int(self.n_pairs.item())
             self._alloc_pairs(int(need * 1.25) + 1024)
 
+    def set_target(self, target, l1_weight=1.0):
+        """Fuse the per-view L1 loss into the forward: render() then also
+        writes loss_per_view (zeroed first) and dL_dimage."""
+        self.target = target
+        self.l1_weight = float(l1_weight)
+
+    def _opts(self, queue_index):
+        o = G.gs4d_render_opts()
+        o.batch = self.batch
+        if self.persistent:
+            o.persistent = 1
+            o.n_workgroups = self.n_workgroups
+            o.order = self.order.data_ptr()
+            o.queue = self.queues.data_ptr() + 4 * queue_index
+        return o
+
+    def tile_order(self):
+        G.gs4d_tile_order(self.ranges, self.order, self.queues, self.order_ws)
+
     def render(self, opts=None):
+        if opts is None:
+            opts = self._opts(0)
+            if self.persistent:
+                self.tile_order()
         if self.counters is not None:
-            self.counters.zero_()
-            if opts is None:
-                opts = G.gs4d_render_opts()
-                opts.batch = self.batch
+            G.gs4d_fill_u32(self.counters.view(torch.int32), 0)
             opts.counters = self.counters.data_ptr()
-        elif opts is None:
-            opts = G.gs4d_render_opts()
-            opts.batch = self.batch
+        if self.target is not None:
+            G.gs4d_fill_f32(self.loss_per_view, 0.0)
+            opts.target = self.target.data_ptr()
+            opts.l1_weight = self.l1_weight
+            opts.loss_per_view = self.loss_per_view.data_ptr()
+            opts.dL_dimage = self.dL_dimage.data_ptr()
         G.gs4d_render_fwd(self.rec, self.n, self.vals, self.ranges, self.cviews, self.image,
                           self.T_final, self.last, opts)
+
+    def render_bwd_2d(self, dL_dimage):
+        if self.persistent:
+            G.gs4d_fill_u32(self.queues[1:2], 0)     # fresh work counter for this launch
+        G.gs4d_render_bwd_2d(self.rec, self.n, self.vals, self.ranges, self.cviews, dL_dimage,
+                             self.T_final, self.last, self.grad2d, self._opts(1))
 
     def forward(self, params: torch.Tensor, check: bool = True, opts=None):
         assert params.shape == (G.N_FIELDS, self.n) and params.dtype == torch.float32
@@ -101,9 +143,11 @@ class Rasterizer:
         return self.image
 
     def backward(self, params: torch.Tensor, dL_dimage: torch.Tensor):
+        if self.persistent:
+            G.gs4d_fill_u32(self.queues[1:2], 0)
         G.gs4d_render_bwd(params, self.rec, self.touched, self.vals, self.ranges, self.cviews,
                           dL_dimage.contiguous(), self.T_final, self.last, self.dparams,
-                          grad2d=self.grad2d)
+                          grad2d=self.grad2d, opts=self._opts(1))
         return self.dparams
 
     def pairs(self):

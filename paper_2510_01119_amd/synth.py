@@ -126,3 +126,52 @@ def linear_loss_weights(n_views, height, width, seed=7):
     """Random upstream gradient dL/dimage for a linear loss sum(w * C)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1.0, 1.0, (n_views, 3, height, width)).astype(np.float32)
+
+
+def batched_set(n=500_000, seed=3):
+    """Many-view set: the small-set distributions with two changes so that
+    per-view visibility is set by the view frustum: smaller spatial scales
+    (log s ~ N(-5, 0.5); the views zoom in, so the small set's scales would
+    make splats of ~60 px) and a wider temporal scale (log s_t ~ N(0, 0.3))."""
+    p = small_set(n, seed, log_s_xyz=(-5.0, 0.5)).astype(np.float64)
+    rng = np.random.default_rng(seed + 7)
+    p[7] = rng.normal(0.0, 0.3, n)
+    return p.astype(np.float32)
+
+
+def frustum_count(params, view):
+    """Number of Gaussian means inside a view's image and in front of its
+    near plane (plain pinhole geometry; used to pick camera intrinsics)."""
+    Rt = np.asarray(view[:12]).reshape(3, 4)
+    X = Rt[:, :3] @ params[0:3].astype(np.float64) + Rt[:, 3:4]
+    z = X[2]
+    ok = z > view[19]
+    u = view[12] * X[0] / np.where(ok, z, 1.0) + view[14]
+    v = view[13] * X[1] / np.where(ok, z, 1.0) + view[15]
+    ok &= (u >= 0) & (u < view[16]) & (v >= 0) & (v < view[17])
+    return int(ok.sum())
+
+
+def batched_views(params, targets=(57_000, 115_000, 175_000, 235_000, 295_000, 355_000, 410_000,
+                                   460_000), width=960, height=540, dist=3.0, seed=5):
+    """One camera per target count, around the set at distance `dist`, time
+    t spread over [0.1, 0.9]; each focal length is bisected until the view
+    frustum holds about `target` Gaussian means."""
+    rng = np.random.default_rng(seed)
+    views = []
+    for i, target in enumerate(targets):
+        a = 2 * np.pi * i / len(targets) + rng.uniform(-0.2, 0.2)
+        eye = dist * np.array([np.sin(a), rng.uniform(-0.3, 0.3), -np.cos(a)])
+        Rt = look_at(eye, (0.0, 0.0, 0.0), up=(0.0, -1.0, 0.0))
+        t = 0.1 + 0.8 * i / max(len(targets) - 1, 1)
+        lo, hi = 50.0, 20000.0          # focal length bracket (pixels)
+        for _ in range(40):
+            f = np.sqrt(lo * hi)
+            v = make_view(Rt, f, f, width / 2, height / 2, width, height, t)
+            if frustum_count(params, v) > target:
+                lo = f
+            else:
+                hi = f
+        views.append(make_view(Rt, np.sqrt(lo * hi), np.sqrt(lo * hi), width / 2, height / 2,
+                               width, height, t))
+    return np.stack(views)

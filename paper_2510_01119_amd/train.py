@@ -100,9 +100,7 @@ class Trainer:
         torch.maximum(self.overflow_seen, self.rast.overflow, out=self.overflow_seen)
 
     def stage_render_bwd(self, f: int):
-        r = self.rast
-        G.gs4d_render_bwd_2d(r.rec, r.n, r.vals, r.ranges, self.cviews[f], self.dimg, r.T_final,
-                             r.last, r.grad2d)
+        self.rast.render_bwd_2d(self.dimg)
 
     def stage_update(self, f: int):
         r = self.rast
@@ -163,3 +161,97 @@ class Trainer:
             mse = float(sse.item()) / r.image.numel()
             vals.append(-10.0 * math.log10(max(mse, 1e-20)))
         return float(np.mean(vals))
+
+
+class BatchedTrainer:
+    """All views in every launch: one preprocess over (view, Gaussian), one
+    sort over view-major tiles, persistent render forward (largest tiles
+    first) with the per-view L1 loss and its gradient reduced in-kernel,
+    persistent render backward, preprocess backward summed over views, Adam.
+    targets: [V, 3, H, W] on the device."""
+
+    def __init__(self, params: torch.Tensor, views, targets: torch.Tensor, budget: int = 5000,
+                 pair_capacity: int | None = None, lrs=None, batch: int = 256,
+                 persistent: bool = True, n_workgroups: int = 0):
+        self.params = params.contiguous()
+        dev = self.params.device
+        self.n = self.params.shape[1]
+        self.views = np.atleast_2d(views)
+        self.V = self.views.shape[0]
+        self.rast = Rasterizer(self.n, self.views, device=dev, pair_capacity=pair_capacity,
+                               batch=batch, persistent=persistent, n_workgroups=n_workgroups)
+        self.targets = targets.contiguous()
+        self.rast.set_target(self.targets, 1.0)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.cfg = adam_config(budget, lrs)
+        self.overflow_seen = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.graphs = None
+
+    def size_pairs(self, margin=1.5):
+        self.rast.preprocess(self.params)
+        self.rast.bin_sort(check=True)
+        peak = int(self.rast.n_pairs.item())
+        cap = int(peak * margin) + 4096
+        if cap > self.rast.capacity:
+            self.rast._alloc_pairs(cap)
+        return peak
+
+    def stage_forward(self):
+        r = self.rast
+        r.preprocess(self.params)
+        r.bin_sort(check=False)
+        r.render()
+        torch.maximum(self.overflow_seen, r.overflow, out=self.overflow_seen)
+
+    def stage_backward(self):
+        r = self.rast
+        r.render_bwd_2d(r.dL_dimage)
+        G.gs4d_preprocess_bwd(self.params, r.touched, r.grad2d, r.cviews, r.dparams)
+        G.gs4d_adam_step(self.params, r.dparams, self.m, self.v, self.cfg, self.step_dev)
+
+    def stage_render_bwd(self):
+        r = self.rast
+        r.render_bwd_2d(r.dL_dimage)
+
+    def stage_update(self):
+        r = self.rast
+        G.gs4d_preprocess_bwd(self.params, r.touched, r.grad2d, r.cviews, r.dparams)
+        G.gs4d_adam_step(self.params, r.dparams, self.m, self.v, self.cfg, self.step_dev)
+
+    def stage_backward(self):
+        self.stage_render_bwd()
+        self.stage_update()
+
+    def step(self):
+        self.stage_forward()
+        self.stage_backward()
+
+    def capture(self):
+        """The step as three HIP graphs ([forward + fused loss], [render
+        backward], [preprocess backward + Adam]) so that the render backward
+        can be timed with events between replays."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        self.graphs = []
+        for stage in (self.stage_forward, self.stage_render_bwd, self.stage_update):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                stage()
+            self.graphs.append(g)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+
+    def step_graph(self, events=None):
+        g0, g1, g2 = self.graphs
+        g0.replay()
+        if events is not None:
+            events[0].record()
+        g1.replay()
+        if events is not None:
+            events[1].record()
+        g2.replay()
+
+    def loss_per_view(self):
+        return self.rast.loss_per_view.detach().cpu().numpy()
