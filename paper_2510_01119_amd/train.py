@@ -205,12 +205,6 @@ class BatchedTrainer:
         r.render()
         torch.maximum(self.overflow_seen, r.overflow, out=self.overflow_seen)
 
-    def stage_backward(self):
-        r = self.rast
-        r.render_bwd_2d(r.dL_dimage)
-        G.gs4d_preprocess_bwd(self.params, r.touched, r.grad2d, r.cviews, r.dparams)
-        G.gs4d_adam_step(self.params, r.dparams, self.m, self.v, self.cfg, self.step_dev)
-
     def stage_render_bwd(self):
         r = self.rast
         r.render_bwd_2d(r.dL_dimage)

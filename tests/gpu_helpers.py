@@ -40,10 +40,19 @@ def to_np(r):
 
 def near_threshold_pixels(rec64, views, vals, ranges, rtol=1e-5, return_tainted=False):
     """Boolean [V, H, W]: pixels where some entry's FP64 alpha lies within
-    rtol of 1/255 or 0.99, or the transmittance test is within rtol of 1e-4.
-    Such pixels may legitimately differ between an FP32 and an FP64 render.
+    the FP32 evaluation error of 1/255 or 0.99, its exponent within that
+    error of 0, or the transmittance test within it of 1e-4.  Such pixels
+    may legitimately differ between an FP32 and an FP64 render.
+
+    The FP32 error of the exponent -(a dx^2 + c dy^2)/2 - b dx dy is bounded
+    by a few units of roundoff times the sum of its terms' magnitudes S (the
+    terms can cancel for thin splats, so S can be much larger than the
+    exponent); exp turns that absolute error into the same relative error of
+    alpha.  Transmittance after n blends carries about 2n roundoffs.  rtol
+    covers the exp approximation and the rest.
     With return_tainted, also the ids of Gaussians that reach alpha >= 1/255
-    (less rtol) at such a pixel: their gradients may differ as well."""
+    (less the tolerance) at such a pixel: their gradients may differ as well."""
+    u = 2.0 ** -24
     views = np.atleast_2d(views)
     V = views.shape[0]
     n = rec64.shape[1]
@@ -62,6 +71,7 @@ def near_threshold_pixels(rec64, views, vals, ranges, rtol=1e-5, return_tainted=
                 px = tile_x * 16 + xs + 0.5
                 py = tile_y * 16 + ys + 0.5
                 T = np.ones((16, 16))
+                nb = np.zeros((16, 16))
                 near = np.zeros((16, 16), bool)
                 alive = np.ones((16, 16), bool)
                 alphas = []
@@ -69,25 +79,30 @@ def near_threshold_pixels(rec64, views, vals, ranges, rtol=1e-5, return_tainted=
                     r = rec64[v, vals[k]]
                     dx, dy = px - r[0], py - r[1]
                     power = -0.5 * (r[2] * dx * dx + r[4] * dy * dy) - r[3] * dx * dy
+                    S = 0.5 * (abs(r[2]) * dx * dx + abs(r[4]) * dy * dy) + abs(r[3] * dx * dy)
+                    tol = rtol + 8.0 * u * S
                     at = r[5] * np.exp(np.minimum(power, 0.0))
                     a = np.minimum(0.99, at)
-                    alphas.append(a)
-                    near |= alive & ((np.abs(a - ALPHA_MIN) <= rtol * ALPHA_MIN)
-                                     | (np.abs(at - 0.99) <= rtol) | (np.abs(power) <= 1e-6))
+                    alphas.append((a, tol))
+                    near |= alive & ((np.abs(a - ALPHA_MIN) <= tol * ALPHA_MIN)
+                                     | (np.abs(at - 0.99) <= tol * 0.99)
+                                     | (np.abs(power) <= 8.0 * u * S + 1e-6))
                     ok = alive & (power <= 0) & (a >= ALPHA_MIN)
                     Tn = T * (1 - a)
-                    near |= ok & (np.abs(Tn - 1e-4) <= rtol * 1e-4)
+                    near |= ok & (np.abs(Tn - 1e-4) <= (rtol + 4.0 * u * (nb + 1)) * 1e-4)
                     stop = ok & (Tn < 1e-4)
                     alive &= ~stop
-                    T = np.where(ok & ~stop, Tn, T)
+                    blend = ok & ~stop
+                    T = np.where(blend, Tn, T)
+                    nb += blend
                 y0, x0 = tile_y * 16, tile_x * 16
                 hh, ww = min(16, H - y0), min(16, W - x0)
                 near[hh:, :] = False
                 near[:, ww:] = False
                 flag[v, y0:y0 + hh, x0:x0 + ww] = near[:hh, :ww]
                 if return_tainted and near.any():
-                    for k, a in zip(range(b, e), alphas):
-                        if np.any(near & (a >= ALPHA_MIN * (1 - rtol))):
+                    for k, (a, tol) in zip(range(b, e), alphas):
+                        if np.any(near & (a >= ALPHA_MIN * (1 - tol))):
                             tainted[vals[k]] = True
     if return_tainted:
         return flag, tainted

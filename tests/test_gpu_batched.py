@@ -75,16 +75,39 @@ def test_tile_order(small_batch):
     assert r.queues.cpu().numpy().tolist() == [0, 0]
 
 
+def _grad_bar(d, ref, ok=None):
+    """Gradient parity bar: 1e-3 relative, floored at 1e-3 of the row's
+    largest magnitude (FP32 sums in a different order cancel differently)."""
+    for k in range(ref.shape[0]):
+        floor = 1e-3 * np.abs(ref[k]).max()
+        err = np.abs(d[k] - ref[k])
+        tol = 1e-3 * np.maximum(np.abs(ref[k]), floor) + 1e-7
+        bad = err > tol
+        if ok is not None:
+            bad &= ok
+        worst = int(np.argmax(np.where(bad, err / tol, 0)))
+        assert not np.any(bad), (k, int(bad.sum()), err[worst], tol[worst], ref[k][worst])
+
+
 def test_persistent_backward(small_batch):
     p, vs = small_batch
-    w = torch.from_numpy(synth.linear_loss_weights(len(vs), 90, 160, 3)).cuda()
+    w = synth.linear_loss_weights(len(vs), 90, 160, 3)
+    wt = torch.from_numpy(w).cuda()
     ref, P = _render(p, vs, persistent=False)
-    dref = ref.backward(P, w).clone()
+    dref = ref.backward(P, wt).cpu().numpy()
     r, _ = _render(p, vs, persistent=True)
-    d = r.backward(P, w)
-    torch.cuda.synchronize()
-    scale = dref.abs().amax(dim=1, keepdim=True)
-    assert torch.all((d - dref).abs() <= 1e-4 * scale + 1e-7)
+    d = r.backward(P, wt).cpu().numpy()
+    d2 = r.backward(P, wt).cpu().numpy()      # queue counters are re-armed per call
+    # same arithmetic, only the order of the per-Gaussian atomic sums differs
+    _grad_bar(d, dref)
+    _grad_bar(d2, dref)
+    # and the oracle's FP64 gradient (Gaussians seen at threshold pixels exempted)
+    o = oracle.forward(p, vs, "f32")
+    g, _ = oracle.backward(p, vs, w.astype(np.float64), fwd=o)
+    _, tainted = near_threshold_pixels(o["rec"].astype(np.float64), vs, o["vals"], o["ranges"],
+                                       return_tainted=True)
+    assert (~tainted).mean() > 0.85
+    _grad_bar(d, g, ok=~tainted)
 
 
 def test_fused_per_view_l1(small_batch):
@@ -104,6 +127,10 @@ def test_fused_per_view_l1(small_batch):
 
 
 def test_batched_graph_replay(small_batch):
+    """Each replay starts from the state the eager trainer is given (the
+    graph's own parameters and moments): the forward must match bit for bit
+    and the gradient to the parity bar (only the order of float atomics
+    differs); eager work and synchronisations run between replays."""
     p, vs = small_batch
     P0 = torch.from_numpy(p).cuda()
     rt = Rasterizer(p.shape[1], vs)
@@ -116,15 +143,18 @@ def test_batched_graph_replay(small_batch):
     graph.rast._alloc_pairs(eager.rast.capacity)
     graph.capture()
     for i in range(5):
+        for a, b in ((eager.params, graph.params), (eager.m, graph.m), (eager.v, graph.v),
+                     (eager.step_dev, graph.step_dev)):
+            a.copy_(b)
         eager.step()
         graph.step_graph()
         torch.cuda.synchronize()
         _ = float(eager.params.sum().item())   # eager work between replays
-        if i == 0:
-            assert torch.equal(eager.rast.image, graph.rast.image)
-            assert torch.equal(eager.rast.loss_per_view, graph.rast.loss_per_view)
-        d = (eager.params - graph.params).abs().max().item()
-        assert d <= 1e-3 * (eager.params - P0).abs().max().item() + 1e-7
+        assert torch.equal(eager.rast.image, graph.rast.image), i
+        # per-view sums are accumulated by atomics in completion order
+        assert torch.allclose(eager.rast.loss_per_view, graph.rast.loss_per_view, rtol=1e-5), i
+        _grad_bar(graph.rast.dparams.cpu().numpy(), eager.rast.dparams.cpu().numpy())
     assert int(graph.step_dev.item()) == 5
     assert int(graph.overflow_seen.item()) == 0
     assert float(graph.rast.loss_per_view.sum().item()) > 0
+    assert (graph.params - P0).abs().max().item() > 0

@@ -100,7 +100,7 @@ def test_render_bwd_gradients(case, ppl):
     try:
         dparams = r.backward(p, torch.from_numpy(w).cuda()).cpu().numpy()
     finally:
-        G.gs4d_set_bwd_variant(2)
+        G.gs4d_set_bwd_variant(1)      # the library's default
     ref, _ = oracle.backward(params, views, w.astype(np.float64), fwd=case["ref"])
     # Gaussians visible at a pixel next to a threshold are exempted (counted)
     _, tainted = near_threshold_pixels(case["ref"]["rec"].astype(np.float64), views,
