@@ -1,0 +1,147 @@
+"""Differentiation at scale: 1M 4D Gaussians (80% in 20 blobs of sigma 0.1,
+20% on a shell of radius 4-5, other attributes as the 2,000-Gaussian set)
+rendered at 1280x720 with fx = fy = 1000 from distance 3, full backward
+through the slice, projection, sort and compositing.
+
+* records, tile counts, sort keys and tile ranges of the whole frame match
+  the oracle bit for bit;
+* on the densest 128x128 tile-aligned crop the image matches the oracle to
+  1e-4 and the gradients of a random linear loss over the crop match the
+  oracle's FP64 chain rule to 1e-3 relative (Gaussians seen at a pixel
+  next to a threshold exempted); every Gaussian that misses the crop gets
+  an exactly zero gradient;
+* 64 random (Gaussian, parameter) entries of Gaussians that blend in the
+  crop match central differences (h = 1e-3) of the oracle's FP64 forward;
+  entries whose +-h step changes a blend decision are redrawn.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_01119_amd import synth
+
+from crop_oracle import CropFD, densest_crop
+from gpu_helpers import gpu_forward, near_threshold_pixels, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+W, H = 1280, 720
+
+
+@pytest.fixture(scope="module")
+def scale():
+    need_gpu()
+    p = synth.clustered_set(1_000_000, seed=4)
+    view = synth.front_view(W, H, 1000.0, 3.0, 0.5)
+    print("scale: oracle preprocess + full sort", flush=True)
+    rec, rect, touched = oracle.preprocess_f32(p, view)
+    keys, vals, ranges = oracle.bin_sort(rect, touched, oracle.depth_bits(rec), view)
+    crop, crop_pairs = densest_crop(view, rect, touched, size=8)
+    w = synth.linear_loss_weights(1, H, W, 21)
+    w[:, :, ~crop.pixel_mask()] = 0.0
+    print(f"scale: GPU forward/backward, {len(vals)} pairs, crop pairs {crop_pairs}", flush=True)
+    r, P = gpu_forward(p, view, capacity=len(vals) + 1024)
+    d = r.backward(P, torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    n_pairs = int(r.n_pairs.item())
+    gpu = dict(rec=r.rec.cpu().numpy(), rect=r.rect.cpu().numpy(), touched=r.touched.cpu().numpy(),
+               ranges=r.ranges.cpu().numpy(), n_pairs=n_pairs,
+               keys=r.keys[:n_pairs].cpu().numpy().view(np.uint64),
+               vals=r.vals[:n_pairs].cpu().numpy().view(np.uint32),
+               image=r.image.cpu().numpy(), T_final=r.T_final.cpu().numpy(),
+               d=d.cpu().numpy().astype(np.float64))
+    del r, P, d
+    torch.cuda.empty_cache()
+    ref = dict(rec=rec, rect=rect, touched=touched, keys=keys, vals=vals, ranges=ranges)
+    return dict(p=p, view=view, crop=crop, w=w, gpu=gpu, ref=ref)
+
+
+def test_full_frame_bitexact(scale):
+    g, o = scale["gpu"], scale["ref"]
+    assert np.array_equal(g["touched"], o["touched"])
+    assert np.array_equal(g["rect"], o["rect"])
+    vis = o["touched"] > 0
+    assert np.array_equal(g["rec"][vis], o["rec"][vis])
+    assert g["n_pairs"] == len(o["keys"]) and g["n_pairs"] > 10_000_000
+    assert np.array_equal(g["keys"], o["keys"])
+    assert np.array_equal(g["vals"], o["vals"])
+    assert np.array_equal(g["ranges"], o["ranges"])
+
+
+@pytest.fixture(scope="module")
+def crop_ref(scale):
+    p, view, crop, w = scale["p"], scale["view"], scale["crop"], scale["w"]
+    o = scale["ref"]
+    sub = np.nonzero(crop.meets(o["rect"], o["touched"]))[0]
+    rs = np.ascontiguousarray(o["rec"][:, sub])
+    _, vs, rg = oracle.bin_sort(o["rect"][:, sub], o["touched"][:, sub], oracle.depth_bits(rs), view)
+    crg = crop.restrict(rg)
+    rs64 = rs.astype(np.float64)
+    out = oracle.render_fwd(rs64, view, vs, crg)
+    grec = oracle.render_bwd(rs64, view, vs, crg, w.astype(np.float64))
+    dsub = oracle.preprocess_bwd(p[:, sub], view, grec)
+    near, tainted = near_threshold_pixels(rs64, view, vs, crg, return_tainted=True,
+                                         taint="entry")
+    return dict(sub=sub, vals=vs, ranges=crg, image=out["image"], T_final=out["T_final"],
+                d=dsub, near=near, tainted=tainted)
+
+
+def test_crop_image_and_lists(scale, crop_ref):
+    g, c, crop = scale["gpu"], crop_ref, scale["crop"]
+    sub = c["sub"]
+    # the crop tiles' lists, mapped back to full-set ids
+    for t in np.nonzero(crop.tile_mask())[0]:
+        b, e = g["ranges"][t]
+        b2, e2 = c["ranges"][t]
+        assert np.array_equal(g["vals"][b:e], sub[c["vals"][b2:e2]]), t
+    m = crop.pixel_mask()
+    diff = np.abs(g["image"][0][:, m] - c["image"][0][:, m]).max(axis=0)
+    near = c["near"][0][m]
+    assert not np.any((diff > 1e-4) & ~near), float(diff[~near].max())
+    assert near.mean() < 1e-2
+    assert np.abs(c["image"][0][:, m]).max() > 0.1
+
+
+def test_crop_gradients(scale, crop_ref):
+    g, c = scale["gpu"], crop_ref
+    sub = c["sub"]
+    outside = np.ones(g["d"].shape[1], bool)
+    outside[sub] = False
+    assert np.all(g["d"][:, outside] == 0.0)
+    d = g["d"][:, sub]
+    ref = c["d"]
+    ok = ~c["tainted"]
+    contributing = np.abs(ref[17]) > 0
+    assert contributing.sum() > 500
+    # in a crop this dense an exponent next to 0 at one pixel exempts the few
+    # hundred Gaussians blended there after it
+    assert ok[contributing].mean() > 0.7, ok[contributing].mean()
+    for k in range(20):
+        floor = 1e-3 * np.abs(ref[k]).max()
+        err = np.abs(d[k] - ref[k])
+        tol = 1e-3 * np.maximum(np.abs(ref[k]), floor) + 1e-7
+        bad = (err > tol) & ok
+        worst = int(np.argmax(np.where(ok, err / tol, 0)))
+        assert not np.any(bad), (k, int(bad.sum()), err[worst], tol[worst], ref[k][worst])
+
+
+def test_central_differences(scale, crop_ref):
+    p, crop, w = scale["p"], scale["crop"], scale["w"]
+    sub, ref = crop_ref["sub"], crop_ref["d"]
+    d = scale["gpu"]["d"][:, sub]
+    fd = CropFD(p[:, sub].astype(np.float64), crop, w)
+    contrib = np.nonzero(np.abs(ref[17]) > 0)[0]
+    rng = np.random.default_rng(9)
+    cands = [(int(rng.choice(contrib)), int(rng.integers(0, 20))) for _ in range(640)]
+    res = fd.fd_many(cands, 1e-3)
+    checked = 0
+    for (gi, k), (val, same) in zip(cands, res):
+        if not same:
+            continue
+        scale_ = max(abs(val), 1e-3 * np.abs(d[k]).max(), 1e-6)
+        assert abs(d[k, gi] - val) <= 1e-3 * scale_, (k, int(sub[gi]), d[k, gi], val)
+        checked += 1
+        if checked == 64:
+            break
+    assert checked == 64, checked
