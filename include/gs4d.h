@@ -277,6 +277,94 @@ int gs4d_photometric_loss(const float *img, const float *target, int32_t b, int3
 /* Sum of squared differences, accumulated into sse (device double). */
 int gs4d_sse(const float *img, const float *target, int64_t count, double *sse, void *stream);
 
+/* ------------------------------------------------------------------------- *
+ * Learned initialisation (not in the paper; it refines the heuristic
+ * initialisation of Sec. 4.1, which fixes every back-projected point's
+ * temporal scale from its motion class and gives it no velocity).  Per
+ * pruned point: 8 nearest neighbours -> 16 standardised features -> a
+ * 16-64-64-64-4 SiLU network with BF16 parameters and FP32 accumulation ->
+ * (log s_t, v) -> the rotor-form 4D Gaussian whose slice at any t has
+ * covariance s^2 I (s = the initial spatial scale), velocity v (the slope of
+ * the conditional mean, Sec. 3.3 Eq. "4dgs") and temporal variance s_t^2.
+ * ------------------------------------------------------------------------- */
+
+/* gs4d_knn8 -- for every point of xyz [3][n], the 8 other points of
+ *   smallest Euclidean distance (FP32 squared distances, ties by smaller
+ *   index; duplicates are other points).  Exact: points are sorted by
+ *   cell (edge `cell`), cubes of cells around each point grow until no
+ *   unvisited cell can hold a closer point, and a point still unresolved
+ *   after 8 rings is answered by a scan of all points.
+ *   nbr  out int32 [8][n] (-1 where fewer than 8 other points exist)
+ *   d2   out float [8][n] (squared distances, ascending; +inf with -1)
+ *   status out device int32: 0, or 1 if some point was non-finite or had
+ *          |coordinate / cell| >= 2^20 -- such points are left out of the
+ *          neighbour graph and get nbr = -1.
+ *   cell > 0; n < 2^31; ws >= gs4d_knn8_workspace_size(n). */
+size_t gs4d_knn8_workspace_size(int64_t n);
+int gs4d_knn8(const float *xyz, int64_t n, float cell, int32_t *nbr, float *d2, int32_t *status,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* gs4d_init_features -- the network's 16 inputs per point, standardised
+ *   as (f - shift[i]) * scale[i]:
+ *     0-2 xyz, 3 depth, 4 2D flow magnitude, 5-7 mean and 8-10 per-axis
+ *     variance of the offsets to the 8 neighbours, 11-13 rgb, 14 t,
+ *     15 motion class (1 dynamic).
+ *   attr float [6][n] = (r, g, b, t, depth, flow magnitude), the per-voxel
+ *   means of the pruned cloud; dyn uint8 [n] or NULL; nbr from gs4d_knn8
+ *   (entries -1 are skipped; no neighbour gives offset mean and variance 0).
+ *   shift, scale: host float [16].  feat out float [16][n]. */
+int gs4d_init_features(const float *xyz, const float *attr, const uint8_t *dyn,
+                       const int32_t *nbr, int64_t n, const float *shift, const float *scale,
+                       float *feat, void *stream);
+
+/* The network: flat parameters in the order W1 [64][16], b1 [64],
+ * W2 [64][64], b2, W3 [64][64], b3, W4 [4][64], b4 [4] (GS4D_MLP_PARAMS
+ * values), held as BF16 (uint16 bit patterns); h_l = silu(W_l h_{l-1} + b_l),
+ * y = W4 h3 + b4, silu(z) = z / (1 + e^-z); FP32 accumulation. */
+#define GS4D_MLP_PARAMS 9668
+/* y out float [4][n] for x float [16][n]. */
+int gs4d_mlp_fwd(const uint16_t *w_bf16, const float *x, int64_t n, float *y, void *stream);
+
+/* Backward of the network.  Exactly one of dy, target is non-NULL:
+ *   dy     float [4][n]: upstream gradient of y;
+ *   target float [4][n]: the loss L = (1/n) sum_p sum_o w_o (y_po - t_po)^2
+ *          with w_o = out_weight[o] (host float [4]) is differentiated and,
+ *          if loss is not NULL, written to loss (device float).
+ *   grad out float [GS4D_MLP_PARAMS]: gradient of the parameters (summed
+ *        over points in a fixed order: deterministic), overwritten.
+ *   dx   out float [16][n] or NULL: gradient of the inputs.
+ *   ws >= gs4d_mlp_bwd_workspace_size(n).  n = 0 zeroes grad (and loss). */
+size_t gs4d_mlp_bwd_workspace_size(int64_t n);
+int gs4d_mlp_bwd(const uint16_t *w_bf16, const float *x, int64_t n, const float *dy,
+                 const float *target, const float *out_weight, float *grad, float *dx,
+                 float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* Adam on the FP32 master copy (count values), then the BF16 working copy
+ * w_bf16 = master rounded to nearest (ties to even).  step: device int32,
+ * steps taken so far; the call uses step + 1 and increments it. */
+int gs4d_mlp_adam(float *master, const float *grad, float *m, float *v, uint16_t *w_bf16,
+                  int64_t count, float lr, float beta1, float beta2, float eps, int32_t *step,
+                  void *stream);
+
+/* Round count FP32 values to BF16 (nearest, ties to even). */
+int gs4d_to_bf16(const float *src, uint16_t *dst, int64_t count, void *stream);
+
+/* gs4d_motion_init -- params [20][n] in/out: rows 4..15 (log scales and the
+ *   two quaternions) are replaced by the rotor form of
+ *       Sigma = [[s^2 I + s_t^2 v v^T, s_t^2 v], [s_t^2 v^T, s_t^2]]
+ *   with s = exp(params[4]) (the isotropic initial spatial scale),
+ *   log s_t = pred[0], v = pred[1..3] (pred float [4][n]).  Its slice at
+ *   any t has covariance s^2 I, conditional-mean slope v and temporal
+ *   variance s_t^2 (closed form: a spatial rotation taking x to v / |v|
+ *   composed with an x-t plane rotation; scales from the 2x2 eigenproblem). */
+int gs4d_motion_init(float *params, const float *pred, int64_t n, void *stream);
+
+/* gs4d_motion_of -- out float [4][n] = (1/2 ln Sigma_tt, Sigma_{xyz,t} /
+ *   Sigma_tt) of each Gaussian's 4D covariance: its log temporal scale and
+ *   velocity (the training targets of the network, taken from Gaussians the
+ *   optimiser converged).  Non-finite or degenerate parameters give NaN. */
+int gs4d_motion_of(const float *params, int64_t n, float *out, void *stream);
+
 /* Fill count floats with value (graph-capturable replacement of memset). */
 int gs4d_fill_f32(float *dst, float value, int64_t count, void *stream);
 int gs4d_fill_u32(uint32_t *dst, uint32_t value, int64_t count, void *stream);

@@ -28,34 +28,43 @@ K = 8
 N_FEATURES = 16
 
 
-def knn(xyz, k=K, queries=None, chunk=2048):
+def knn(xyz, k=K, queries=None, chunk=None):
     """Neighbour ids [len(queries), k] and squared distances, FP64."""
     X = np.asarray(xyz, np.float64).T            # [N, 3]
     n = X.shape[0]
     q = np.arange(n) if queries is None else np.asarray(queries)
-    ids = np.zeros((len(q), k), np.int64)
-    d2s = np.zeros((len(q), k))
-    idx = np.arange(n)
+    ids = np.full((len(q), k), -1, np.int64)
+    d2s = np.full((len(q), k), np.inf)
+    chunk = chunk or max(1, min(2048, 4_000_000 // max(n, 1)))
+    kk = min(k, n - 1)
+    if kk <= 0:
+        return ids, d2s
     for s in range(0, len(q), chunk):
         qq = q[s:s + chunk]
         d2 = ((X[None, :, :] - X[qq][:, None, :]) ** 2).sum(axis=2)
-        for r, i in enumerate(qq):
-            row = d2[r].copy()
-            row[i] = np.inf
-            order = np.lexsort((idx, row))[:k]
-            ids[s + r] = order
-            d2s[s + r] = row[order]
+        d2[np.arange(len(qq)), qq] = np.inf
+        thr = np.partition(d2, kk - 1, axis=1)[:, kk - 1]
+        for r in range(len(qq)):
+            cand = np.nonzero(d2[r] <= thr[r])[0]          # every tie at the k-th distance
+            order = cand[np.lexsort((cand, d2[r, cand]))][:kk]
+            ids[s + r, :kk] = order
+            d2s[s + r, :kk] = d2[r, order]
     return ids, d2s
 
 
 def features(xyz, depth, flow, rgb, t, dyn, nbr):
     """Raw (unstandardised) features [16, N] from pruned points (xyz [3, N],
     depth [N], flow [N], rgb [3, N], t [N], dyn [N]) and their neighbour
-    ids nbr [N, 8]."""
+    ids nbr [N, 8] (-1 = no neighbour; with none, offset mean and variance
+    are 0)."""
     X = np.asarray(xyz, np.float64)
-    off = X[:, nbr] - X[:, :, None]                 # [3, N, 8]
-    mean = off.mean(axis=2)
-    var = ((off - mean[:, :, None]) ** 2).mean(axis=2)
+    nbr = np.asarray(nbr)
+    ok = nbr >= 0                                   # missing neighbours (-1) are skipped
+    cnt = ok.sum(axis=1)
+    off = np.where(ok[None], X[:, np.where(ok, nbr, 0)] - X[:, :, None], 0.0)   # [3, N, 8]
+    den = np.maximum(cnt, 1)
+    mean = off.sum(axis=2) / den
+    var = np.where(ok[None], (off - mean[:, :, None]) ** 2, 0.0).sum(axis=2) / den
     F = np.zeros((N_FEATURES, X.shape[1]))
     F[0:3] = X
     F[3] = depth

@@ -25,6 +25,8 @@ SOURCES = {
     "render.hip": [],
     "train.hip": [],
     "prune.hip": [],
+    # the network's layers are fully unrolled so activations stay in registers
+    "learned.hip": ["-mllvm", "-pragma-unroll-threshold=2000000"],
 }
 
 BASE_FLAGS = [

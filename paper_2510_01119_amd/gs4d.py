@@ -81,6 +81,16 @@ _SIGS = {
     "gs4d_photometric_loss": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _f32, _f32, _p, _p, _p, _sz,
                                      _p]),
     "gs4d_sse": (_i32, [_p, _p, _i64, _p, _p]),
+    "gs4d_knn8_workspace_size": (_sz, [_i64]),
+    "gs4d_knn8": (_i32, [_p, _i64, _f32, _p, _p, _p, _p, _sz, _p]),
+    "gs4d_init_features": (_i32, [_p, _p, _p, _p, _i64, _p, _p, _p, _p]),
+    "gs4d_mlp_fwd": (_i32, [_p, _p, _i64, _p, _p]),
+    "gs4d_mlp_bwd_workspace_size": (_sz, [_i64]),
+    "gs4d_mlp_bwd": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "gs4d_mlp_adam": (_i32, [_p, _p, _p, _p, _p, _i64, _f32, _f32, _f32, _f32, _p, _p]),
+    "gs4d_to_bf16": (_i32, [_p, _p, _i64, _p]),
+    "gs4d_motion_init": (_i32, [_p, _p, _i64, _p]),
+    "gs4d_motion_of": (_i32, [_p, _i64, _p, _p]),
     "gs4d_fill_f32": (_i32, [_p, _f32, _i64, _p]),
     "gs4d_fill_u32": (_i32, [_p, ctypes.c_uint32, _i64, _p]),
     "gs4d_status_string": (ctypes.c_char_p, [_i32]),
@@ -278,6 +288,67 @@ def gs4d_photometric_loss(img, target, w_l1, w_ssim, loss, dL_dimg, ws, stream=N
 def gs4d_sse(img, target, sse, stream=None):
     _check(lib().gs4d_sse(_ptr(img), _ptr(target), img.numel(), _ptr(sse), _stream(stream)),
            "gs4d_sse")
+
+
+def _host_f32(values, count):
+    arr = (ctypes.c_float * count)(*[float(v) for v in values])
+    if len(values) != count:
+        raise GS4DError(f"expected {count} host values")
+    return arr
+
+
+def gs4d_knn8_workspace_size(n):
+    return int(lib().gs4d_knn8_workspace_size(n))
+
+
+def gs4d_knn8(xyz, cell, nbr, d2, status, ws, stream=None):
+    n = xyz.shape[1]
+    _check(lib().gs4d_knn8(_ptr(xyz), n, float(cell), _ptr(nbr), _ptr(d2), _ptr(status), _ptr(ws),
+                           ws.numel() * ws.element_size(), _stream(stream)), "gs4d_knn8")
+
+
+def gs4d_init_features(xyz, attr, dyn, nbr, shift, scale, feat, stream=None):
+    n = xyz.shape[1]
+    _check(lib().gs4d_init_features(_ptr(xyz), _ptr(attr), _ptr(dyn), _ptr(nbr), n,
+                                    _host_f32(shift, 16), _host_f32(scale, 16), _ptr(feat),
+                                    _stream(stream)), "gs4d_init_features")
+
+
+def gs4d_mlp_fwd(w_bf16, x, y, stream=None):
+    _check(lib().gs4d_mlp_fwd(_ptr(w_bf16), _ptr(x), x.shape[1], _ptr(y), _stream(stream)),
+           "gs4d_mlp_fwd")
+
+
+def gs4d_mlp_bwd_workspace_size(n):
+    return int(lib().gs4d_mlp_bwd_workspace_size(n))
+
+
+def gs4d_mlp_bwd(w_bf16, x, grad, ws, dy=None, target=None, out_weight=None, dx=None, loss=None,
+                 stream=None):
+    ow = _host_f32(out_weight, 4) if out_weight is not None else None
+    _check(lib().gs4d_mlp_bwd(_ptr(w_bf16), _ptr(x), x.shape[1], _ptr(dy), _ptr(target), ow,
+                              _ptr(grad), _ptr(dx), _ptr(loss), _ptr(ws),
+                              ws.numel() * ws.element_size(), _stream(stream)), "gs4d_mlp_bwd")
+
+
+def gs4d_mlp_adam(master, grad, m, v, w_bf16, lr, beta1, beta2, eps, step, stream=None):
+    _check(lib().gs4d_mlp_adam(_ptr(master), _ptr(grad), _ptr(m), _ptr(v), _ptr(w_bf16),
+                               master.numel(), float(lr), float(beta1), float(beta2), float(eps),
+                               _ptr(step), _stream(stream)), "gs4d_mlp_adam")
+
+
+def gs4d_to_bf16(src, dst, stream=None):
+    _check(lib().gs4d_to_bf16(_ptr(src), _ptr(dst), src.numel(), _stream(stream)), "gs4d_to_bf16")
+
+
+def gs4d_motion_init(params, pred, stream=None):
+    _check(lib().gs4d_motion_init(_ptr(params), _ptr(pred), params.shape[1], _stream(stream)),
+           "gs4d_motion_init")
+
+
+def gs4d_motion_of(params, out, stream=None):
+    _check(lib().gs4d_motion_of(_ptr(params), params.shape[1], _ptr(out), _stream(stream)),
+           "gs4d_motion_of")
 
 
 def gs4d_fill_f32(dst, value, stream=None):

@@ -214,3 +214,13 @@ def test_knn_against_kdtree():
     ids, d2 = K.knn(X)
     dd, _ = cKDTree(X.T).query(X.T, k=9)
     assert np.allclose(np.sqrt(d2), dd[:, 1:], rtol=1e-12)
+
+
+def test_features_missing_neighbours():
+    X = np.array([[0.0, 1.0, 3.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    nbr = np.array([[1, 2, -1, -1, -1, -1, -1, -1], [-1] * 8, [0, -1, -1, -1, -1, -1, -1, -1]])
+    F = K.features(X, np.zeros(3), np.zeros(3), np.zeros((3, 3)), np.zeros(3), np.zeros(3), nbr)
+    # point 0: offsets 1 and 3 -> mean 2, variance 1; point 1: none -> 0, 0
+    assert np.allclose(F[5:8, 0], [2, 0, 0]) and np.allclose(F[8:11, 0], [1, 0, 0])
+    assert np.all(F[5:11, 1] == 0)
+    assert np.allclose(F[5:8, 2], [-3, 0, 0]) and np.all(F[8:11, 2] == 0)
