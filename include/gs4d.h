@@ -306,12 +306,13 @@ int gs4d_knn8(const float *xyz, int64_t n, float cell, int32_t *nbr, float *d2, 
 
 /* gs4d_init_features -- the network's 16 inputs per point, standardised
  *   as (f - shift[i]) * scale[i]:
- *     0-2 xyz, 3 depth, 4 2D flow magnitude, 5-7 mean and 8-10 per-axis
- *     variance of the offsets to the 8 neighbours, 11-13 rgb, 14 t,
- *     15 motion class (1 dynamic).
- *   attr float [6][n] = (r, g, b, t, depth, flow magnitude), the per-voxel
- *   means of the pruned cloud; dyn uint8 [n] or NULL; nbr from gs4d_knn8
- *   (entries -1 are skipped; no neighbour gives offset mean and variance 0).
+ *     0-2 xyz, 3 depth, 4 2D optical-flow magnitude, 5-7 mean and 8-10
+ *     per-axis variance of the offsets to the 8 neighbours, 11-13 scene
+ *     flow (world displacement per frame), 14 t, 15 motion class (1 dynamic).
+ *   attr float [9][n] = (r, g, b, t, depth, flow magnitude, scene flow x, y,
+ *   z), the per-voxel means of the pruned cloud (colour is not an input);
+ *   dyn uint8 [n] or NULL; nbr from gs4d_knn8 (entries -1 are skipped; no
+ *   neighbour gives offset mean and variance 0).
  *   shift, scale: host float [16].  feat out float [16][n]. */
 int gs4d_init_features(const float *xyz, const float *attr, const uint8_t *dyn,
                        const int32_t *nbr, int64_t n, const float *shift, const float *scale,
@@ -356,7 +357,9 @@ int gs4d_to_bf16(const float *src, uint16_t *dst, int64_t count, void *stream);
  *   log s_t = pred[0], v = pred[1..3] (pred float [4][n]).  Its slice at
  *   any t has covariance s^2 I, conditional-mean slope v and temporal
  *   variance s_t^2 (closed form: a spatial rotation taking x to v / |v|
- *   composed with an x-t plane rotation; scales from the 2x2 eigenproblem). */
+ *   composed with an x-t plane rotation; scales from the 2x2 eigenproblem).
+ *   A column whose prediction or spatial scale is not finite is left as it
+ *   was (the heuristic initialisation stands). */
 int gs4d_motion_init(float *params, const float *pred, int64_t n, void *stream);
 
 /* gs4d_motion_of -- out float [4][n] = (1/2 ln Sigma_tt, Sigma_{xyz,t} /

@@ -10,13 +10,14 @@ the learned initialisation.
     4     mean 2D optical-flow magnitude of those pixels (pixels per frame)
     5-7   mean of the offsets x_nbr - x over the 8 neighbours
     8-10  variance (population, per axis) of those offsets
-    11-13 mean colour
+    11-13 mean scene flow (world displacement per frame)
     14    mean timestamp (normalised to [0, 1])
     15    motion class (1 dynamic, 0 static)
   then standardised: (f - shift) * scale per feature.
 The pruned-point attributes averaged per voxel are those the grid pruning
-of Sec. 3.2 carries (colour, timestamp, motion probability) plus depth and
-flow magnitude.
+of Sec. 3.2 carries (timestamp, motion probability) plus depth, optical-flow
+magnitude and scene flow (optical flow back-projected with depth and
+camera poses).
 
 Only ``tests/`` may import this module.
 """
@@ -52,9 +53,9 @@ def knn(xyz, k=K, queries=None, chunk=None):
     return ids, d2s
 
 
-def features(xyz, depth, flow, rgb, t, dyn, nbr):
+def features(xyz, depth, flow, sflow, t, dyn, nbr):
     """Raw (unstandardised) features [16, N] from pruned points (xyz [3, N],
-    depth [N], flow [N], rgb [3, N], t [N], dyn [N]) and their neighbour
+    depth [N], flow [N], scene flow [3, N], t [N], dyn [N]) and their neighbour
     ids nbr [N, 8] (-1 = no neighbour; with none, offset mean and variance
     are 0)."""
     X = np.asarray(xyz, np.float64)
@@ -71,7 +72,7 @@ def features(xyz, depth, flow, rgb, t, dyn, nbr):
     F[4] = flow
     F[5:8] = mean
     F[8:11] = var
-    F[11:14] = rgb
+    F[11:14] = sflow
     F[14] = t
     F[15] = np.asarray(dyn, np.float64)
     return F

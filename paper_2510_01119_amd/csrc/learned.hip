@@ -214,9 +214,9 @@ __global__ void features_kernel(const float *__restrict__ xyz, const float *__re
     f[8] = vx * inv;
     f[9] = vy * inv;
     f[10] = vz * inv;
-    f[11] = attr[i];
-    f[12] = attr[n + i];
-    f[13] = attr[2 * n + i];
+    f[11] = attr[6 * n + i];
+    f[12] = attr[7 * n + i];
+    f[13] = attr[8 * n + i];
     f[14] = attr[3 * n + i];
     f[15] = (dyn != nullptr && dyn[i] != 0) ? 1.0f : 0.0f;
 #pragma unroll
@@ -521,10 +521,12 @@ __global__ void motion_init_kernel(float *__restrict__ params, const float *__re
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float ls = params[4 * n + g];
-    const float s2 = expf(2.0f * ls);
     const float lst = pred[g];
-    const float st2 = expf(2.0f * lst);
     const float vx = pred[n + g], vy = pred[2 * n + g], vz = pred[3 * n + g];
+    // no usable prediction: the heuristic parameters stand
+    if (!(isfinite(ls) && isfinite(lst) && isfinite(vx) && isfinite(vy) && isfinite(vz))) return;
+    const float s2 = expf(2.0f * ls);
+    const float st2 = expf(2.0f * lst);
     const float vn = sqrtf(vx * vx + vy * vy + vz * vz);
     // 2x2 block of Sigma in the plane spanned by (v/|v|, 0) and the t axis
     const float a = fmaf(st2 * vn, vn, s2), c = st2, b = st2 * vn;

@@ -1,0 +1,329 @@
+"""Learned initialisation of the temporal scale and velocity of each
+back-projected point (not in the paper: it replaces the constants of the
+heuristic initialisation of Sec. 4.1 -- s_t = 2/fps for dynamic and the
+video length for static points, no motion -- with a prediction, and falls
+back to them where no prediction is available).
+
+Per pruned point: 8 nearest neighbours (gs4d_knn8) -> 16 standardised
+features (gs4d_init_features) -> a 16-64-64-64-4 SiLU network with BF16
+parameters and FP32 accumulation (gs4d_mlp_fwd) -> (log s_t, v) -> the
+rotor-form 4D Gaussian whose slice at any time keeps the heuristic spatial
+scale, moves with velocity v and has temporal scale s_t (gs4d_motion_init).
+
+The network is trained on the GPU by the library's own kernels
+(gs4d_mlp_bwd in its regression mode, gs4d_mlp_adam) on Gaussians that the
+plain optimiser converged (targets from gs4d_motion_of; the correspondence
+point -> Gaussian is one to one because the method has no densification).
+
+Command line (run on the GPU):
+  python -m paper_2510_01119_amd.learned_init gen   --seeds 100-199 --out DIR
+  python -m paper_2510_01119_amd.learned_init train --data DIR [DIR...] --out MODEL.npz
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import gs4d as G
+
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "init_mlp.npz")
+N_PARAMS = 9668
+KNN_CELL = 0.02          # neighbour-grid cell: twice the 0.01 pruning voxel
+
+
+class InitModel:
+    """Feature standardisation (shift, scale [16]) and the network's FP32
+    master parameters [9668]; the BF16 working copy is derived on load.
+    Stored as a plain .npz (no pickled objects)."""
+
+    def __init__(self, shift, scale, master, meta=None):
+        self.shift = np.asarray(shift, np.float32).reshape(16)
+        self.scale = np.asarray(scale, np.float32).reshape(16)
+        self.master = np.asarray(master, np.float32).reshape(N_PARAMS)
+        self.meta = dict(meta or {})
+
+    @classmethod
+    def load(cls, path=MODEL_PATH):
+        with np.load(path, allow_pickle=False) as d:
+            meta = json.loads(str(d["meta"])) if "meta" in d else {}
+            return cls(d["shift"], d["scale"], d["master"], meta)
+
+    def save(self, path):
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        np.savez(path, shift=self.shift, scale=self.scale, master=self.master,
+                 meta=np.array(json.dumps(self.meta)))
+
+    def weights_bf16(self, device="cuda"):
+        w = torch.empty(N_PARAMS, dtype=torch.int16, device=device)
+        G.gs4d_to_bf16(torch.from_numpy(self.master).to(device), w)
+        return w
+
+
+def neighbours(xyz, cell=KNN_CELL):
+    n = xyz.shape[1]
+    nbr = torch.empty((8, n), dtype=torch.int32, device=xyz.device)
+    d2 = torch.empty((8, n), dtype=torch.float32, device=xyz.device)
+    status = torch.zeros(1, dtype=torch.int32, device=xyz.device)
+    ws = torch.empty(max(G.gs4d_knn8_workspace_size(n), 1), dtype=torch.uint8, device=xyz.device)
+    G.gs4d_knn8(xyz.contiguous(), cell, nbr, d2, status, ws)
+    return nbr, d2
+
+
+def features(pruned, shift=None, scale=None, cell=KNN_CELL):
+    """[16, N] features of the pruned cloud (xyz, attr [9] = rgb, t, depth,
+    flow magnitude, scene flow, dynamic flag); raw when shift/scale are None."""
+    xyz, attr, dyn = pruned[0].contiguous(), pruned[1].contiguous(), pruned[2]
+    nbr, _ = neighbours(xyz, cell)
+    feat = torch.empty((16, xyz.shape[1]), device=xyz.device)
+    shift = np.zeros(16) if shift is None else shift
+    scale = np.ones(16) if scale is None else scale
+    G.gs4d_init_features(xyz, attr, dyn.to(torch.uint8).contiguous(), nbr, shift, scale, feat)
+    return feat
+
+
+def predict(model: InitModel, feat, w_bf16=None):
+    w = model.weights_bf16(feat.device) if w_bf16 is None else w_bf16
+    pred = torch.empty((4, feat.shape[1]), device=feat.device)
+    G.gs4d_mlp_fwd(w, feat, pred)
+    return pred
+
+
+def apply(params, pruned, model: InitModel | None = None, path=MODEL_PATH):
+    """Learned initialisation in place on heuristic parameters [20, N]; with
+    no model (and no model file) the heuristic initialisation stands."""
+    if model is None:
+        if not os.path.exists(path):
+            return params
+        model = InitModel.load(path)
+    feat = features(pruned, model.shift, model.scale)
+    pred = predict(model, feat)
+    G.gs4d_motion_init(params, pred)
+    return params
+
+
+def motion_targets(params):
+    out = torch.empty((4, params.shape[1]), device=params.device)
+    G.gs4d_motion_of(params.contiguous(), out)
+    return out
+
+
+# ---------------------------------------------------------------- training
+class MLPTrainer:
+    """Regression of standardised targets with the library's kernels."""
+
+    def __init__(self, master, device="cuda", lr=1e-3):
+        self.master = torch.from_numpy(np.asarray(master, np.float32).copy()).to(device)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.w = torch.empty(N_PARAMS, dtype=torch.int16, device=device)
+        G.gs4d_to_bf16(self.master, self.w)
+        self.grad = torch.empty_like(self.master)
+        self.loss = torch.zeros(1, device=device)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
+        self.lr = lr
+        self.ws = None
+
+    def step(self, X, T, lr, out_weight=(1.0, 1.0, 1.0, 1.0)):
+        n = X.shape[1]
+        need = G.gs4d_mlp_bwd_workspace_size(n)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+        G.gs4d_mlp_bwd(self.w, X, self.grad, self.ws, target=T, out_weight=out_weight,
+                       loss=self.loss)
+        G.gs4d_mlp_adam(self.master, self.grad, self.m, self.v, self.w, lr, 0.9, 0.999, 1e-8,
+                        self.step_dev)
+
+    def eval_loss(self, X, T, out_weight=(1.0, 1.0, 1.0, 1.0)):
+        n = X.shape[1]
+        need = G.gs4d_mlp_bwd_workspace_size(n)
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+        g = torch.empty_like(self.grad)
+        G.gs4d_mlp_bwd(self.w, X, g, ws, target=T, out_weight=out_weight, loss=self.loss)
+        return float(self.loss.item())
+
+
+def init_master(seed=0):
+    """He-style initialisation of the flat parameters (biases 0)."""
+    rng = np.random.default_rng(seed)
+    sizes = (16, 64, 64, 64, 4)
+    out = []
+    for i in range(4):
+        fi, fo = sizes[i], sizes[i + 1]
+        out.append(rng.normal(0, np.sqrt(2.0 / fi) * (0.5 if i == 3 else 1.0), fo * fi))
+        out.append(np.zeros(fo))
+    return np.concatenate(out).astype(np.float32)
+
+
+def fold_output(master, out_shift, out_scale):
+    """Fold y = out_scale * y_std + out_shift into the last layer."""
+    m = np.asarray(master, np.float64).copy()
+    o_w4, o_b4 = 9408, 9664
+    W4 = m[o_w4:o_b4].reshape(4, 64)
+    b4 = m[o_b4:o_b4 + 4]
+    m[o_w4:o_b4] = (out_scale[:, None] * W4).reshape(-1)
+    m[o_b4:o_b4 + 4] = out_scale * b4 + out_shift
+    return m.astype(np.float32)
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def cmd_gen(args):
+    from .pipeline import Evaluator, plain_schedule, run, split_frames
+    from .scene import build_scene
+    from .train import Trainer
+    os.makedirs(args.out, exist_ok=True)
+    lo, hi = (int(x) for x in args.seeds.split("-"))
+    for seed in range(lo, hi + 1):
+        path = os.path.join(args.out, f"scene_{seed:04d}.npz")
+        if os.path.exists(path):
+            continue
+        t0 = time.time()
+        sc, images, params0, info, pruned = build_scene(seed=seed, keep_pruned=True)
+        train_f, held_f = split_frames(sc.frames)
+        tr = Trainer(params0.clone(), sc.cams, images, budget=args.budget)
+        tr.size_pairs(train_f[::9], margin=2.0)
+        ev = Evaluator(params0.shape[1], sc.cams, images, held_f)
+        p0 = ev.psnr(params0)
+        hist, _ = run(tr, plain_schedule(train_f, args.budget, seed), ev, args.budget // 5,
+                      args.budget)
+        T = motion_targets(tr.params)
+        F = features(pruned)
+        ok = torch.isfinite(T).all(dim=0) & torch.isfinite(F).all(dim=0)
+        dyn = pruned[2] & ok
+        sta = (~pruned[2]) & ok
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        pick = []
+        for mask in (dyn, sta):
+            idx = torch.nonzero(mask).flatten().cpu()
+            take = idx[torch.randperm(len(idx), generator=g)[:args.per_class]]
+            pick.append(take)
+        pick = torch.cat(pick).to(F.device)
+        np.savez(path, X=F[:, pick].cpu().numpy(), T=T[:, pick].cpu().numpy(),
+                 dyn=pruned[2][pick].cpu().numpy().astype(np.uint8),
+                 meta=np.array(json.dumps(dict(seed=seed, info=info, psnr_init=p0,
+                                               history=hist))))
+        Tn = T[:, pick].cpu().numpy()
+        dn = pruned[2][pick].cpu().numpy()
+        sp = np.linalg.norm(Tn[1:4], axis=0)
+        _log(f"gen: seed {seed}: {params0.shape[1]} Gaussians, PSNR {p0:.2f} -> {hist[-1][2]:.2f} "
+             f"in {hist[-1][1]:.1f} s; {time.time() - t0:.1f} s total; log s_t dyn/static "
+             f"{Tn[0, dn].mean():.3f}/{Tn[0, ~dn].mean():.3f}, |v| dyn/static "
+             f"{np.median(sp[dn]):.4f}/{np.median(sp[~dn]):.4f}")
+        del sc, images, params0, pruned, tr, ev
+        torch.cuda.empty_cache()
+
+
+def cmd_train(args):
+    files = sorted(sum((glob.glob(os.path.join(d, "scene_*.npz")) for d in args.data), []))
+    if not files:
+        raise SystemExit("no training data")
+    Xs, Ts, seeds = [], [], []
+    for f in files:
+        with np.load(f, allow_pickle=False) as d:
+            Xs.append(d["X"])
+            Ts.append(d["T"])
+            seeds.append(json.loads(str(d["meta"]))["seed"])
+    n_val = max(1, len(files) // 10)
+    Xtr, Ttr = np.concatenate(Xs[:-n_val], 1), np.concatenate(Ts[:-n_val], 1)
+    Xva, Tva = np.concatenate(Xs[-n_val:], 1), np.concatenate(Ts[-n_val:], 1)
+    shift = Xtr.mean(axis=1)
+    sd = Xtr.std(axis=1)
+    scale = np.where(sd > 1e-12, 1.0 / np.maximum(sd, 1e-12), 1.0)
+    out_shift = Ttr.mean(axis=1)
+    out_scale = np.maximum(Ttr.std(axis=1), 1e-6)
+    dev = "cuda"
+
+    def prep(X, T):
+        Xs_ = torch.from_numpy(((X - shift[:, None]) * scale[:, None]).astype(np.float32)).to(dev)
+        Ts_ = torch.from_numpy(((T - out_shift[:, None]) / out_scale[:, None]).astype(np.float32)).to(dev)
+        return Xs_.contiguous(), Ts_.contiguous()
+    Xt, Tt = prep(Xtr, Ttr)
+    Xv, Tv = prep(Xva, Tva)
+    tr = MLPTrainer(init_master(args.seed), dev)
+    n = Xt.shape[1]
+    gen = torch.Generator(device=dev).manual_seed(args.seed)
+    t0 = time.time()
+    lr0, lr1 = args.lr, args.lr * 0.01
+    xb = torch.empty((16, args.batch), device=dev)
+    tb = torch.empty((4, args.batch), device=dev)
+    for s in range(args.steps):
+        idx = torch.randint(0, n, (args.batch,), device=dev, generator=gen)
+        torch.index_select(Xt, 1, idx, out=xb)
+        torch.index_select(Tt, 1, idx, out=tb)
+        u = s / max(args.steps - 1, 1)
+        tr.step(xb, tb, lr0 ** (1 - u) * lr1 ** u)
+        if (s + 1) % max(args.steps // 10, 1) == 0:
+            _log(f"train: step {s + 1}: train {tr.eval_loss(Xt, Tt):.4f} val {tr.eval_loss(Xv, Tv):.4f} "
+                 f"({time.time() - t0:.1f} s)")
+    val = tr.eval_loss(Xv, Tv)
+    base = float(((Tv.cpu().numpy()) ** 2).sum(axis=0).mean())   # predicting the mean
+    master = fold_output(tr.master.cpu().numpy(), out_shift, out_scale)
+    meta = dict(train_scenes=seeds[:-n_val], val_scenes=seeds[-n_val:], n_train=int(n),
+                steps=args.steps, batch=args.batch, lr=args.lr, val_loss=val,
+                val_loss_of_mean=base, train_seconds=round(time.time() - t0, 2),
+                knn_cell=KNN_CELL)
+    InitModel(shift, scale, master, meta).save(args.out)
+    _log(f"train: saved {args.out}: {json.dumps(meta)}")
+
+
+def cmd_eval(args):
+    from .pipeline import init_gain, time_to_psnr
+    from .scene import build_scene
+    model = InitModel.load(args.model) if args.model else None
+    lo, hi = (int(x) for x in args.seeds.split("-"))
+    results = []
+    for seed in range(lo, hi + 1):
+        sc, images, params0, info, pruned = build_scene(seed=seed, keep_pruned=True)
+        if args.gain_only:
+            r = init_gain(sc, images, params0, pruned, model, budget=args.budget,
+                          lr_mult=args.lr_mult, group=args.group)
+        else:
+            r = time_to_psnr(sc, images, params0, pruned, model, budget=args.budget,
+                             lr_mult=args.lr_mult, group=args.group)
+        r.update(seed=seed, n_gaussians=int(params0.shape[1]))
+        _log("eval: " + json.dumps({k: v for k, v in r.items() if k != "history"}))
+        results.append(r)
+        del sc, images, params0, pruned
+        torch.cuda.empty_cache()
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(results, f)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2510_01119_amd.learned_init")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("gen")
+    g.add_argument("--seeds", required=True)
+    g.add_argument("--out", required=True)
+    g.add_argument("--budget", type=int, default=5000)
+    g.add_argument("--per-class", type=int, default=3000)
+    t = sub.add_parser("train")
+    t.add_argument("--data", nargs="+", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--steps", type=int, default=6000)
+    t.add_argument("--batch", type=int, default=8192)
+    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--seed", type=int, default=0)
+    e = sub.add_parser("eval")
+    e.add_argument("--seeds", required=True)
+    e.add_argument("--model", default=MODEL_PATH)
+    e.add_argument("--out", default=None)
+    e.add_argument("--budget", type=int, default=1200)
+    e.add_argument("--lr-mult", type=float, default=2.0)
+    e.add_argument("--group", type=int, default=8)
+    e.add_argument("--gain-only", action="store_true")
+    args = ap.parse_args(argv)
+    {"gen": cmd_gen, "train": cmd_train, "eval": cmd_eval}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()

@@ -14,7 +14,10 @@ recovery are not available here).  Recipe:
   gives the alpha-weighted depth, the coverage and a ground-truth motion
   mask;
 * every pixel with coverage > 0.5 is back-projected to a world point with
-  its colour, timestamp and motion class (Sec. 3.2, back projection);
+  its colour, timestamp and motion class (Sec. 3.2, back projection), plus
+  its depth, optical-flow magnitude and scene flow (further passes render
+  each ground-truth Gaussian's pixel and world displacement to the next
+  frame), the inputs of the learned initialisation;
 * gs4d_grid_prune merges the points per voxel (Sec. 3.2, grid pruning);
 * the heuristic initialisation (Sec. 4.1): centroid position, mean
   timestamp and colour, temporal scale 2 / frames for dynamic points (two
@@ -176,9 +179,29 @@ class Scene:
         return torch.cat([self._static_dev, obj], dim=1).contiguous()
 
     # ------------------------------------------------------------ synthesis
+    def _flow(self, f):
+        """Per ground-truth Gaussian, from frame f to the next frame (from
+        the previous one for the last frame): the pixel displacement of its
+        centre (optical-flow magnitude: camera and object motion together)
+        and its world-space displacement (scene flow: what back-projecting
+        the optical flow with depth and camera poses recovers)."""
+        a, b = (f, f + 1) if f + 1 < self.frames else (f - 1, f)
+        px, mus = [], []
+        for k in (a, b):
+            v = self.cams[k]
+            mu = self.gt_params(float(v[18]))[0:3]
+            Rt = torch.from_numpy(v[:12].reshape(3, 4)).to(self.device).float()
+            xc = Rt[:, :3] @ mu + Rt[:, 3:4]
+            z = xc[2].clamp_min(1e-3)
+            px.append(torch.stack([float(v[12]) * xc[0] / z + float(v[14]),
+                                   float(v[13]) * xc[1] / z + float(v[15])]))
+            mus.append(mu)
+        return torch.linalg.norm(px[1] - px[0], dim=0), mus[1] - mus[0]
+
     def render_ground_truth(self, verbose=False):
         """Renders every frame; returns (images [F,3,H,W] on device, point
-        cloud (xyz [3,M], attr [4,M] = rgb + t, cls [M]) on device)."""
+        cloud (xyz [3,M], attr [9,M] = rgb, t, depth, optical-flow
+        magnitude, scene flow xyz; cls [M]) on device)."""
         dev = self.device
         n = self.static.shape[1] + self.obj_local.shape[1]
         r = Rasterizer(n, self.cams[0], device=dev, pair_capacity=1 << 24)
@@ -200,17 +223,29 @@ class Scene:
             rec[:, 9] = (r.touched[0] > 0).float()
             rec[:, 10] = dyn_flag
             r.render()
-            aux = r.image[0]
+            aux = r.image[0].clone()
             cov = aux[1]
             keep = cov > 0.5
             depth = aux[0][keep] / cov[keep]
+            # third and fourth passes: optical-flow magnitude (pixels per frame)
+            # and scene flow (world units per frame) as colours
+            fmag, sflow = self._flow(f)
+            rec[:, 8] = fmag
+            rec[:, 9] = sflow[0]
+            rec[:, 10] = sflow[1]
+            r.render()
+            flow = r.image[0][:, keep] / cov[keep]
+            rec[:, 8] = sflow[2]
+            r.render()
+            sfz = r.image[0][0][keep] / cov[keep]
             Rt = torch.from_numpy(view[:12].reshape(3, 4)).to(dev).float()
             xc = torch.stack([(xs[keep] + 0.5 - float(view[14])) / float(view[12]) * depth,
                               (ys[keep] + 0.5 - float(view[15])) / float(view[13]) * depth, depth])
             world = Rt[:, :3].T @ (xc - Rt[:, 3:4])
             pts.append(world)
             col = images[f][:, keep]
-            attrs.append(torch.cat([col, torch.full((1, col.shape[1]), float(view[18]), device=dev)]))
+            attrs.append(torch.cat([col, torch.full((1, col.shape[1]), float(view[18]), device=dev),
+                                    depth[None], flow, sfz[None]]))
             clss.append((aux[2][keep] / cov[keep] > 0.5).to(torch.uint8))
             if verbose and f % 50 == 0:
                 print(f"scene: frame {f}/{self.frames} pairs={int(r.n_pairs.item())}", flush=True)
@@ -258,8 +293,10 @@ class Scene:
 
 
 def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel=0.01,
-                device="cuda", verbose=False):
-    """Ground-truth frames and the pruned, heuristically initialised set."""
+                device="cuda", verbose=False, keep_pruned=False):
+    """Ground-truth frames and the pruned, heuristically initialised set
+    (with keep_pruned, also the pruned cloud: xyz, attr, dynamic flag,
+    count)."""
     sc = Scene(seed, n_gt, frames, width, height, device=device)
     images, cloud = sc.render_ground_truth(verbose)
     n_raw = cloud[0].shape[1]
@@ -268,4 +305,6 @@ def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel
     params = sc.heuristic_init(pruned, voxel)
     info = dict(n_raw_points=n_raw, n_gaussians=params.shape[1],
                 n_dynamic=int(pruned[2].sum().item()))
+    if keep_pruned:
+        return sc, images, params, info, pruned
     return sc, images, params, info
