@@ -356,8 +356,11 @@ int gs4d_to_bf16(const float *src, uint16_t *dst, int64_t count, void *stream);
  *   with s = exp(params[4]) (the isotropic initial spatial scale),
  *   log s_t = pred[0], v = pred[1..3] (pred float [4][n]).  Its slice at
  *   any t has covariance s^2 I, conditional-mean slope v and temporal
- *   variance s_t^2 (closed form: a spatial rotation taking x to v / |v|
- *   composed with an x-t plane rotation; scales from the 2x2 eigenproblem).
+ *   variance s_t^2 (closed form, the rotation nearest to identity: a
+ *   spatial rotation of at most ~55 degrees taking the axis closest to +-v
+ *   onto it, then a rotation in that axis' plane with t; scales from the
+ *   2x2 eigenproblem; v = 0 gives identity quaternions and log scales
+ *   (log s, log s, log s, log s_t)).
  *   A column whose prediction or spatial scale is not finite is left as it
  *   was (the heuristic initialisation stands). */
 int gs4d_motion_init(float *params, const float *pred, int64_t n, void *stream);

@@ -528,46 +528,60 @@ __global__ void motion_init_kernel(float *__restrict__ params, const float *__re
     const float s2 = expf(2.0f * ls);
     const float st2 = expf(2.0f * lst);
     const float vn = sqrtf(vx * vx + vy * vy + vz * vz);
-    // 2x2 block of Sigma in the plane spanned by (v/|v|, 0) and the t axis
-    const float a = fmaf(st2 * vn, vn, s2), c = st2, b = st2 * vn;
+    // The rotation nearest to identity with the right eigenvectors: the
+    // spatial axis k closest to +-v carries the moving eigenvector (a
+    // spatial rotation of at most ~55 degrees takes e_k to d = sign * v/|v|),
+    // then a rotation in the (e_k, t) plane.  v = 0 gives identity rotors.
+    int k = 0;
+    float qs[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+    float bsign = 1.0f;
+    if (vn > 0.0f) {
+        const float u[3] = {vx / vn, vy / vn, vz / vn};
+        k = (fabsf(u[1]) > fabsf(u[0])) ? 1 : 0;
+        k = (fabsf(u[2]) > fabsf(u[k])) ? 2 : k;
+        bsign = u[k] < 0.0f ? -1.0f : 1.0f;
+        const float d[3] = {bsign * u[0], bsign * u[1], bsign * u[2]};
+        // quaternion taking e_k to d: (1 + e_k . d, e_k x d), normalised
+        float c3[3];
+        c3[0] = (k == 1 ? d[2] : 0.0f) + (k == 2 ? -d[1] : 0.0f);
+        c3[1] = (k == 0 ? -d[2] : 0.0f) + (k == 2 ? d[0] : 0.0f);
+        c3[2] = (k == 0 ? d[1] : 0.0f) + (k == 1 ? -d[0] : 0.0f);
+        const float w0 = 1.0f + d[k];
+        const float nq = sqrtf(w0 * w0 + c3[0] * c3[0] + c3[1] * c3[1] + c3[2] * c3[2]);
+        qs[0] = w0 / nq;
+        qs[1] = c3[0] / nq;
+        qs[2] = c3[1] / nq;
+        qs[3] = c3[2] / nq;
+    }
+    // 2x2 block of Sigma in the plane spanned by (d, 0) and the t axis
+    const float a = fmaf(st2 * vn, vn, s2), c = st2, b = bsign * st2 * vn;
     const float half = 0.5f * (a - c);
     const float rad = sqrtf(half * half + b * b);
-    const float lam1 = 0.5f * (a + c) + rad;
-    const float lam2 = (s2 * st2) / lam1;          // det = s^2 s_t^2, no cancellation
-    const float phi = 0.5f * atan2f(2.0f * b, a - c);
-    // spatial rotation taking x to v / |v|
-    float qs[4] = {1.0f, 0.0f, 0.0f, 0.0f};
-    if (vn > 0.0f) {
-        const float ux = vx / vn, uy = vy / vn, uz = vz / vn;
-        if (1.0f + ux > 1e-6f) {
-            const float w0 = 1.0f + ux;
-            const float nq = sqrtf(w0 * w0 + uz * uz + uy * uy);
-            qs[0] = w0 / nq;
-            qs[1] = 0.0f;
-            qs[2] = -uz / nq;
-            qs[3] = uy / nq;
-        } else {
-            qs[0] = 0.0f;
-            qs[1] = 0.0f;
-            qs[2] = 0.0f;
-            qs[3] = 1.0f;
-        }
+    const float lam_big = 0.5f * (a + c) + rad;
+    const float lam_small = (s2 * st2) / lam_big;      // det = s^2 s_t^2, no cancellation
+    float phi = 0.5f * atan2f(2.0f * b, a - c);        // eigenvector of lam_big
+    float lam_k = lam_big, lam_t = lam_small;
+    const float quarter = 0.785398163397448f;
+    if (fabsf(phi) > quarter) {                        // keep the rotation small
+        phi -= copysignf(2.0f * quarter, phi);
+        lam_k = lam_small;
+        lam_t = lam_big;
     }
-    // x-t plane rotation taking x to cos(phi) x + sin(phi) t: rotor (cos th/2, sin th/2, 0, 0)
-    // on both sides with th = -phi
-    const float axt[4] = {cosf(-0.5f * phi), sinf(-0.5f * phi), 0.0f, 0.0f};
+    // (e_k, t) plane rotation taking e_k to cos(phi) e_k + sin(phi) t: the
+    // rotor (cos th/2, sin th/2 e_k) on both sides with th = -phi
+    float axt[4] = {cosf(-0.5f * phi), 0.0f, 0.0f, 0.0f};
+    axt[1 + k] = sinf(-0.5f * phi);
     const float qsc[4] = {qs[0], -qs[1], -qs[2], -qs[3]};
     float ql[4], qr[4];
     qmul(qs, axt, ql);
     qmul(axt, qsc, qr);
-    params[4 * n + g] = 0.5f * logf(lam1);
-    params[5 * n + g] = ls;
-    params[6 * n + g] = ls;
-    params[7 * n + g] = 0.5f * logf(lam2);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        params[(8 + k) * n + g] = ql[k];
-        params[(12 + k) * n + g] = qr[k];
+    for (int j = 0; j < 3; ++j) params[(4 + j) * n + g] = (j == k) ? 0.5f * logf(lam_k) : ls;
+    params[7 * n + g] = 0.5f * logf(lam_t);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        params[(8 + j) * n + g] = ql[j];
+        params[(12 + j) * n + g] = qr[j];
     }
 }
 

@@ -301,6 +301,32 @@ def test_motion_init_through_oracle():
         assert np.allclose(C, s * s * np.eye(3), atol=2e-3 * s * s + 1e-5 * st2 * (v @ v)), g
 
 
+def test_motion_init_near_identity():
+    """Zero velocity keeps identity quaternions and puts s_t in the t slot;
+    a small velocity gives a small rotation (the map picks the rotation
+    nearest to identity); the slope still reads back as v."""
+    need_gpu()
+    n = 4
+    base = np.zeros((20, n), np.float32)
+    base[4:7] = np.log(0.01)
+    base[8] = base[12] = 1.0
+    pred = np.zeros((4, n), np.float32)
+    pred[0] = np.log([1.0, 0.01, 0.5, 0.02])
+    pred[1:4, 2] = (0.0, -0.02, 0.005)
+    pred[1:4, 3] = (0.3, 0.1, -0.2)
+    P = torch.from_numpy(base.copy()).cuda()
+    G.gs4d_motion_init(P, torch.from_numpy(pred).cuda())
+    out = P.cpu().numpy()
+    for g in (0, 1):
+        assert np.array_equal(out[8:16, g], [1, 0, 0, 0, 1, 0, 0, 0])
+        assert np.allclose(out[4:8, g], [np.log(0.01)] * 3 + [pred[0, g]], atol=1e-6)
+    ang = 2 * np.arccos(np.clip(np.abs(out[8, 2]), 0, 1))
+    assert ang < 0.3, ang
+    for g in (2, 3):
+        S = oracle.covariance(out.astype(np.float64), g)
+        assert np.allclose(S[:3, 3] / S[3, 3], pred[1:4, g], atol=1e-5)
+
+
 def test_motion_of_against_oracle():
     need_gpu()
     rng = np.random.default_rng(60)
