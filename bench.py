@@ -50,12 +50,14 @@ def build_workload(name, device, cache=None):
     if cache and name == "scene" and os.path.exists(cache):
         d = torch.load(cache, map_location=device, weights_only=True)
         info = json.loads(d["info"])
-        return d["params"], d["views"].cpu().numpy(), d["images"], info
+        pruned = (d["pruned_xyz"], d["pruned_attr"], d["pruned_dyn"]) if "pruned_xyz" in d else None
+        return d["params"], d["views"].cpu().numpy(), d["images"], info, pruned
     out = _build_workload(name, device)
     if cache and name == "scene":
-        params, views, images, info = out
+        params, views, images, info, pruned = out
         torch.save({"params": params, "views": torch.from_numpy(np.asarray(views)),
-                    "images": images, "info": json.dumps(info)}, cache)
+                    "images": images, "info": json.dumps(info), "pruned_xyz": pruned[0],
+                    "pruned_attr": pruned[1], "pruned_dyn": pruned[2]}, cache)
     return out
 
 
@@ -72,14 +74,15 @@ def _build_workload(name, device):
         images = r.image.clone()
         info = dict(workload="plain single-view 2k Gaussians 64x64", n_gaussians=2000, frames=1,
                     width=64, height=64)
-        return params, view[None], images, info
+        return params, view[None], images, info, None
     from paper_2510_01119_amd.scene import build_scene
     t0 = time.time()
-    sc, images, params, info = build_scene(seed=0, device=device, verbose=True)
+    sc, images, params, info, pruned = build_scene(seed=0, device=device, verbose=True,
+                                                   keep_pruned=True)
     info.update(workload="scene-scale plain training: synthetic dynamic scene, 200 frames 960x540, "
                          "1M-Gaussian ground truth, grid-pruned at 0.01",
                 frames=sc.frames, width=sc.W, height=sc.H, synth_s=round(time.time() - t0, 2))
-    return params, sc.cams, images, info
+    return params, sc.cams, images, info, pruned[:3]
 
 
 def cpu_baseline(params_np, views, target_np, budget_s=30.0):
@@ -115,6 +118,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="scene", choices=["scene", "small", "batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR leg")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--calib-copy", action="store_true",
@@ -147,7 +151,7 @@ def main():
     if args.workload == "batched":
         return run_batched(args, dev)
     log(f"bench: building workload {args.workload}")
-    params, views, images, info = build_workload(args.workload, dev, args.scene_cache)
+    params, views, images, info, pruned = build_workload(args.workload, dev, args.scene_cache)
     n = params.shape[1]
     log(f"bench: {info}")
     tr = Trainer(params.clone(), views, images, budget=5000)
@@ -303,7 +307,32 @@ def main():
                                 "sample": f"{steps_done} full training step(s) of the same workload "
                                           f"(one frame, {n} Gaussians) in {secs:.1f} s on one host "
                                           f"thread"}
+    if args.workload == "scene" and not args.no_ttp and pruned is not None:
+        line["time_to_psnr"] = time_to_psnr_leg(params, views, images, pruned)
     print(json.dumps(line), flush=True)
+
+
+def time_to_psnr_leg(params, views, images, pruned):
+    """Wall time to the plain single-view form's PSNR: plain training (one
+    frame per step, 5,000 steps) fixes the reference on the held-out frames;
+    the batched form (8 frames per step) from the heuristic and from the
+    learned initialisation trains until it is within 0.1 dB."""
+    import types
+    import torch
+    from paper_2510_01119_amd import learned_init as LI
+    from paper_2510_01119_amd.pipeline import time_to_psnr
+    log("bench: time-to-PSNR (plain 5000 steps, then batched from both initialisations)")
+    sc = types.SimpleNamespace(frames=len(views), cams=np.asarray(views))
+    model = LI.InitModel.load() if os.path.exists(LI.MODEL_PATH) else None
+    r = time_to_psnr(sc, images, params, pruned, model)
+    torch.cuda.empty_cache()
+    out = {k: v for k, v in r.items() if k not in ("heuristic", "learned")}
+    for name in ("heuristic", "learned"):
+        if name in r:
+            out[name] = {k: v for k, v in r[name].items() if k != "history"}
+    out["held_out"] = "every 10th frame; the others train"
+    log(f"bench: time-to-PSNR {json.dumps(out)}")
+    return out
 
 
 def profiled_traffic(kernel):

@@ -241,8 +241,10 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
 // is valid in lane 63 only.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f(float x) {
+    // bound_ctrl: a source lane outside the row reads 0, so `x + dpp_f(x)`
+    // folds into one v_add_f32_dpp with no zero-initialised temporary
     return __int_as_float(
-        __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
 }
 
 // Sums N values over each 16-lane DPP row (row_shr 1/2/4/8, all N values per

@@ -284,10 +284,10 @@ def cmd_eval(args):
         sc, images, params0, info, pruned = build_scene(seed=seed, keep_pruned=True)
         if args.gain_only:
             r = init_gain(sc, images, params0, pruned, model, budget=args.budget,
-                          lr_mult=args.lr_mult, group=args.group)
+                          lr_mult=args.lr_mult, group=args.group, decay=args.decay)
         else:
             r = time_to_psnr(sc, images, params0, pruned, model, budget=args.budget,
-                             lr_mult=args.lr_mult, group=args.group)
+                             lr_mult=args.lr_mult, decay=args.decay, group=args.group)
         r.update(seed=seed, n_gaussians=int(params0.shape[1]))
         _log("eval: " + json.dumps({k: v for k, v in r.items() if k != "history"}))
         results.append(r)
@@ -317,8 +317,9 @@ def main(argv=None):
     e.add_argument("--seeds", required=True)
     e.add_argument("--model", default=MODEL_PATH)
     e.add_argument("--out", default=None)
-    e.add_argument("--budget", type=int, default=1200)
-    e.add_argument("--lr-mult", type=float, default=2.0)
+    e.add_argument("--budget", type=int, default=900)
+    e.add_argument("--lr-mult", type=float, default=4.0)
+    e.add_argument("--decay", type=float, default=0.1)
     e.add_argument("--group", type=int, default=8)
     e.add_argument("--gain-only", action="store_true")
     args = ap.parse_args(argv)
