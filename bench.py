@@ -236,7 +236,8 @@ def main():
     for i in range(min(args.steps, 50)):
         staged_step(int(seq[args.warmup + i]))
     torch.cuda.synchronize()
-    stage_ms = {s_: float(np.mean([a.elapsed_time(b) for a, b in ev[s_]])) for s_ in stages}
+    # median: a host hiccup between two recorded events would inflate a mean
+    stage_ms = {s_: float(np.median([a.elapsed_time(b) for a, b in ev[s_]])) for s_ in stages}
     log(f"bench: {its:.1f} it/s ({'graph' if use_graph else 'eager'}); render_bwd timed "
         f"{bwd_ms_timed:.4f} ms; eager stage ms {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
 

@@ -50,15 +50,28 @@ __device__ __forceinline__ float gauss_power(float4 a, float cc, float dx, float
     return fmaf(-0.5f, q, -(a.w * dx) * dy);
 }
 
-// Each wave owns a 16x4 pixel strip of the tile.  For a staged batch, every
-// wave marks (one ballot per 64 entries) the entries whose exact footprint
-// box meets its strip; outside that box alpha < 1/255 for every pixel, so
-// the other entries are skipped without evaluating them -- the result is the
-// same as evaluating them.
+// Each wave owns a block of pixels of the tile.  For a staged batch, every
+// wave marks (one ballot per 64 entries) the entries whose alpha >= 1/255
+// ellipse meets its block (footprint box test, then the exact minimum of
+// the quadratic form over the block); for the others alpha < 1/255 at every
+// pixel of the block, so they are skipped without evaluating them -- the
+// result is the same as evaluating them.
+// Pixel block of one wave inside its 16x16 tile: BW columns by BH rows.
+// PPL (pixels per lane) 1 and 2 use 8-wide blocks (8x8, 8x16): squarer
+// blocks meet fewer footprints than 16-wide strips of the same area.  Lane l
+// covers column l mod BW and rows l div BW + k * RPS, k < PPL.
+template <int PPL>
+struct WaveBlock {
+    static constexpr int BW = PPL == 4 ? 16 : 8;
+    static constexpr int RPS = 64 / BW;
+    static constexpr int BH = RPS * PPL;
+    static constexpr int CB = GS4D_TILE / BW;
+};
+
 template <int BATCH>
-__device__ __forceinline__ void strip_masks(const float4 *sA, const float4 *sC, int cnt, float x0,
-                                            float x1, float y0, float y1, int lane,
-                                            uint64_t (&m)[BATCH / 64]) {
+__device__ __forceinline__ void strip_masks(const float4 *sA, const float4 *sB, const float4 *sC,
+                                            int cnt, float x0, float x1, float y0, float y1,
+                                            int lane, uint64_t (&m)[BATCH / 64]) {
 #pragma unroll
     for (int k = 0; k < BATCH / 64; ++k) {
         const int j = k * 64 + lane;
@@ -67,6 +80,30 @@ __device__ __forceinline__ void strip_masks(const float4 *sA, const float4 *sC, 
             const float4 a = sA[j];
             const float4 c = sC[j];
             hit = (a.x + c.y >= x0) && (a.x - c.y <= x1) && (a.y + c.z >= y0) && (a.y - c.z <= y1);
+            if (hit) {
+                // Refine: the alpha >= 1/255 ellipse q(d) = a dx^2 + 2 b dx dy + c dy^2
+                // <= tau must meet the block's rectangle of pixel centres.  q is convex, so
+                // its minimum over the rectangle is 0 (centre inside) or on an edge,
+                // where it is the clamped 1D minimum.  Each candidate is lowered by
+                // a bound on its FP32 rounding (its terms can cancel), and tau
+                // carries the footprint's padding, so no entry that reaches
+                // alpha >= 1/255 at a pixel of the block is dropped.
+                const float ca = a.z, cb = a.w, cc = sB[j].x, tau = c.w;
+                const float X0 = x0 - a.x, X1 = x1 - a.x, Y0 = y0 - a.y, Y1 = y1 - a.y;
+                const bool inside = X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f;
+                const float ia = __builtin_amdgcn_rcpf(ca), ic = __builtin_amdgcn_rcpf(cc);
+                float qmin = __builtin_inff();
+                auto edge = [&](float X, float Y) {
+                    const float t1 = ca * X * X, t2 = 2.0f * cb * X * Y, t3 = cc * Y * Y;
+                    const float q = t1 + t2 + t3;
+                    qmin = fminf(qmin, q - 1e-5f * (t1 + fabsf(t2) + t3));
+                };
+                edge(X0, fminf(fmaxf(-cb * X0 * ic, Y0), Y1));
+                edge(X1, fminf(fmaxf(-cb * X1 * ic, Y0), Y1));
+                edge(fminf(fmaxf(-cb * Y0 * ia, X0), X1), Y0);
+                edge(fminf(fmaxf(-cb * Y1 * ia, X0), X1), Y1);
+                hit = inside || qmin <= tau;
+            }
         }
         m[k] = __ballot(hit);
     }
@@ -84,7 +121,11 @@ __device__ __forceinline__ void stage_batch(const float4 *__restrict__ recv,
         const float4 r2 = recv[3 * (int64_t)g + 2];
         sA[t] = r0;                                       // mx my ca cb
         sB[t] = make_float4(r1.x, r1.y, r2.x, r2.y);      // cc o_t r g
-        sC[t] = make_float4(r2.z, r1.w, r2.w, 0.0f);      // b hx hy
+        // b hx hy tau: the level q <= tau of alpha >= 1/255, tau = 2 ln(255 o_t),
+        // padded like the footprint (relative and absolute 2^-10) plus 2^-12
+        // for the hardware logarithm
+        const float tau = 2.0f * __logf(255.0f * r1.y);
+        sC[t] = make_float4(r2.z, r1.w, r2.w, fmaf(tau, 1.0f + 1.25f / 1024.0f, 1.25f / 1024.0f));
         if (sG) sG[t] = g;
     }
 }
@@ -98,16 +139,19 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
                                                 float *__restrict__ T_final,
                                                 int32_t *__restrict__ last_out, float4 *sA,
                                                 float4 *sB, float4 *sC) {
+    using B = WaveBlock<1>;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const TileInfo ti = tile_info(tile, vp);
-    const int px = ti.tx * GS4D_TILE + (t & 15);
-    const int py = ti.ty * GS4D_TILE + (t >> 4);
+    const int bx = ti.tx * GS4D_TILE + (w % B::CB) * B::BW;
+    const int by = ti.ty * GS4D_TILE + (w / B::CB) * B::BH;
+    const int px = bx + lane % B::BW;
+    const int py = by + lane / B::BW;
     const int W = vp.width, H = vp.height;
     const bool inside = px < W && py < H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    // this wave's strip, as pixel-centre extents
-    const float sx0 = (float)(ti.tx * GS4D_TILE) + 0.5f, sx1 = sx0 + 15.0f;
-    const float sy0 = (float)(ti.ty * GS4D_TILE + 4 * w) + 0.5f, sy1 = sy0 + 3.0f;
+    // this wave's block, as pixel-centre extents
+    const float sx0 = (float)bx + 0.5f, sx1 = sx0 + (float)(B::BW - 1);
+    const float sy0 = (float)by + 0.5f, sy1 = sy0 + (float)(B::BH - 1);
     const int2 rg = ranges[tile];
     const float4 *recv = rec + (int64_t)ti.v * n * 3;
 
@@ -124,7 +168,7 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
         if (active == 0) break;
         if (__ballot(!done) == 0) continue;
         uint64_t m[BATCH / 64];
-        strip_masks<BATCH>(sA, sC, cnt, sx0, sx1, sy0, sy1, lane, m);
+        strip_masks<BATCH>(sA, sB, sC, cnt, sx0, sx1, sy0, sy1, lane, m);
         // Branch-free per entry: every decision is a select, so the only
         // control flow is the wave-uniform walk over the mask bits; two
         // entries per step keep two sets of LDS reads in flight.
@@ -281,15 +325,15 @@ __device__ __forceinline__ void wave_total_lane63(float (&x)[N]) {
 }
 
 // PPL = pixels per lane.  The workgroup has 256 / PPL threads; wave w owns
-// the 16 x (4 PPL) strip starting at tile row 4 PPL w, lane l the pixels
-// (l mod 16, 4 PPL w + l div 16 + 4 k), k < PPL.  Each lane folds its PPL
-// pixels' terms for an entry before the cross-lane reduction.
+// the block given by WaveBlock<PPL> (8x8 for PPL 1, 8x16 for PPL 2, 16x16
+// for PPL 4).  Each lane folds its PPL pixels' terms for an entry before the
+// cross-lane reduction.
 //
 // Reduction of the nine gradient terms of one entry over one wave: DPP sums
 // over each 16-lane row, then the four row-leader lanes store their row
 // totals into LDS slots part[wave][row][entry][term] (one store instruction
 // per term).  After the batch, each entry's slots are summed and added to
-// HBM with one atomic per term.  A wave skips every entry its strip-box test
+// HBM with one atomic per term.  A wave skips every entry its block test
 // rejects and every entry no lane of it actually blends; the per-wave,
 // per-row "written" masks record which slots hold data.
 template <int BATCH, int PPL>
@@ -323,16 +367,18 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
     auto &written = sh.written;
     int &smax = sh.smax;
 
+    using B = WaveBlock<PPL>;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const TileInfo ti = tile_info(tile, vp);
     const int W = vp.width, H = vp.height;
     const int64_t HW = (int64_t)H * W;
-    const int px = ti.tx * GS4D_TILE + (lane & 15);
-    const int row0 = ti.ty * GS4D_TILE + 4 * PPL * w + (lane >> 4);
+    const int bx = ti.tx * GS4D_TILE + (w % B::CB) * B::BW;
+    const int by = ti.ty * GS4D_TILE + (w / B::CB) * B::BH;
+    const int px = bx + lane % B::BW;
+    const int row0 = by + lane / B::BW;
     const float fx = (float)px + 0.5f;
-    const float sx0 = (float)(ti.tx * GS4D_TILE) + 0.5f, sx1 = sx0 + 15.0f;
-    const float sy0 = (float)(ti.ty * GS4D_TILE + 4 * PPL * w) + 0.5f;
-    const float sy1 = sy0 + (float)(4 * PPL - 1);
+    const float sx0 = (float)bx + 0.5f, sx1 = sx0 + (float)(B::BW - 1);
+    const float sy0 = (float)by + 0.5f, sy1 = sy0 + (float)(B::BH - 1);
     const int2 rg = ranges[tile];
     const gs4d_view &V = vp.v[ti.v];
 
@@ -341,7 +387,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
     int lane_last = -1;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
-        const int py = row0 + 4 * k;
+        const int py = row0 + B::RPS * k;
         fy[k] = (float)py + 0.5f;
         my_last[k] = -1;
         T[k] = 1.0f;
@@ -386,14 +432,15 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             const float4 r2 = recv[3 * (int64_t)g + 2];
             sA[i] = r0;
             sB[i] = make_float4(r1.x, r1.y, r2.x, r2.y);
-            sC[i] = make_float4(r2.z, r1.w, r2.w, 0.0f);
+            const float tau = 2.0f * __logf(255.0f * r1.y);     // as in stage_batch
+            sC[i] = make_float4(r2.z, r1.w, r2.w, fmaf(tau, 1.0f + 1.25f / 1024.0f, 1.25f / 1024.0f));
             sG[i] = g;
         }
         __syncthreads();
         // entries beyond this wave's last blended one are skipped too
         const int wcnt = min(cnt, wave_last - start + 1);
         uint64_t m[NK], wr[NK];
-        strip_masks<BATCH>(sA, sC, wcnt, sx0, sx1, sy0, sy1, lane, m);
+        strip_masks<BATCH>(sA, sB, sC, wcnt, sx0, sx1, sy0, sy1, lane, m);
 #pragma unroll
         for (int k = 0; k < NK; ++k) wr[k] = 0;
         // Branch-free per entry (selects only), entries taken back to front
