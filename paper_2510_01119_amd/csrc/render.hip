@@ -306,6 +306,34 @@ __device__ __forceinline__ void row_totals(float (&x)[N]) {
     for (int q = 0; q < N; ++q) x[q] += dpp_f<0x118, 0xF>(x[q]);
 }
 
+// The nine-term case of row_totals.  After row_shr 1/2/4 lane 15 of a row
+// holds the sum of lanes 8..15 and lane 7 that of lanes 0..7, so the last
+// stage is x += row_ror:8(x): one fused DPP add per term with every lane
+// active (the compiler otherwise moves the add under the row-leader branch
+// and splits it into a DPP move and an add).  Register operands only; the
+// s_nop covers the two wait states a DPP read needs after a VALU write.
+__device__ __forceinline__ void row_totals9(float (&x)[9]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) x[q] += dpp_f<0x111, 0xF>(x[q]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) x[q] += dpp_f<0x112, 0xF>(x[q]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) x[q] += dpp_f<0x114, 0xF>(x[q]);
+    asm volatile(
+        "s_nop 1\n"
+        "v_add_f32_dpp %0, %0, %0 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %4, %4, %4 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %5, %5, %5 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %6, %6, %6 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %7, %7, %7 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %8, %8, %8 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+          "+v"(x[7]), "+v"(x[8]));
+}
+
 // Reduces N independent values at once, one DPP stage at a time across all
 // of them, so consecutive DPP operations never depend on each other.
 template <int N>
@@ -485,7 +513,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             }
             if (__ballot(any) == 0) return;   // no lane of this wave blends the entry
             wr[j >> 6] |= 1ull << (j & 63);
-            row_totals<9>(d);
+            row_totals9(d);
             if (row_leader) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) part[w][drow][j][q] = d[q];
