@@ -291,8 +291,9 @@ def main():
         "blends_per_step": round(blends_per_step, 1),
         "pairs_per_step": round(pairs_per_step, 1),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "launch": "hip graphs" if use_graph else "eager",
-        "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"]},
+        "launch": ("hip graphs" if use_graph else "eager") + f", {choice.get('mode', 'grid')} (autotuned)",
+        "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"],
+                     "mode": choice.get("mode"), "mode_ms": choice.get("mode_ms")},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -423,8 +424,9 @@ def run_batched(args, dev):
         "views_per_s": round(its * len(views), 2),
         "blends_per_s": round(float(c[1]) * its, 1),
         "pairs_per_step": pairs,
-        "launch": "hip graphs, persistent largest-first",
-        "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"]},
+        "launch": f"hip graphs, {choice.get('mode', 'grid')} (autotuned)",
+        "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"],
+                     "mode": choice.get("mode"), "mode_ms": choice.get("mode_ms")},
         "loss_per_view": [round(float(x), 5) for x in tr.loss_per_view()],
         "roofline": roof,
     }

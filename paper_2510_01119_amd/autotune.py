@@ -1,11 +1,13 @@
 """Project autotuner for the render kernels.
 
-Times the forward's LDS batch size (64 / 128 / 256 Gaussians per round) and
+Times the forward's LDS batch size (64 / 128 / 256 Gaussians per round),
 the backward's block shape (1 / 2 / 4 pixels per lane = 256 / 128 / 64
-threads) on the caller's live buffers with HIP events, keeps the fastest,
-and caches the choice per (device, image size, view count, Gaussian-count
-bucket).  Every choice renders the same image (the forward bit for bit);
-only the speed differs.
+threads) and the launch mode (one workgroup per tile, or persistent
+workgroups pulling tiles from a counter in index order or largest first) on
+the caller's live buffers with HIP events, keeps the fastest, and caches the
+choice per (device, image size, view count, Gaussian-count bucket).  Every
+choice renders the same image (the forward bit for bit); only the speed
+differs.
 """
 from __future__ import annotations
 
@@ -57,12 +59,27 @@ def tune(r, params, dL_dimage, verbose=False):
             G.gs4d_set_bwd_variant(ppl)
             bwd[ppl] = _time(lambda: r.render_bwd_2d(dL_dimage))
         best_p = min(bwd, key=bwd.get)
-        choice = {"batch": best_b, "bwd_pixels_per_lane": best_p,
+        G.gs4d_set_bwd_variant(best_p)
+        # launch mode: one workgroup per tile, or persistent workgroups taking
+        # tiles from a counter in index order or largest first (the order costs
+        # a small sort per frame); timed as forward + backward
+        keep = (r.persistent, r.order_tiles)
+        modes = {}
+        for name, pers, ordered in (("grid", False, True), ("persistent", True, False),
+                                    ("persistent_sorted", True, True)):
+            r.persistent, r.order_tiles = pers, ordered
+            modes[name] = _time(lambda: (r.render(), r.render_bwd_2d(dL_dimage)))
+        r.persistent, r.order_tiles = keep
+        best_m = min(modes, key=modes.get)
+        choice = {"batch": best_b, "bwd_pixels_per_lane": best_p, "mode": best_m,
                   "fwd_ms": {str(k): round(v, 4) for k, v in fwd.items()},
-                  "bwd_ms": {str(k): round(v, 4) for k, v in bwd.items()}}
+                  "bwd_ms": {str(k): round(v, 4) for k, v in bwd.items()},
+                  "mode_ms": {k: round(v, 4) for k, v in modes.items()}}
         _CACHE[key] = choice
         if verbose:
             print(f"autotune {key}: {json.dumps(choice)}", flush=True)
     r.batch = choice["batch"]
     G.gs4d_set_bwd_variant(choice["bwd_pixels_per_lane"])
+    m = choice.get("mode", "grid")
+    r.persistent, r.order_tiles = m != "grid", m == "persistent_sorted"
     return choice

@@ -370,7 +370,9 @@ struct BwdShared {
     float4 sB[BATCH];
     float4 sC[BATCH];
     uint32_t sG[BATCH];
-    float part[RT_THREADS / PPL / 64][4][BATCH][9];
+    // [wave][row][entry * 9 + term]; each row padded by 4 floats so the four
+    // row leaders' simultaneous stores fall into different banks
+    float part[RT_THREADS / PPL / 64][4][BATCH * 9 + 4];
     uint64_t written[RT_THREADS / PPL / 64][BATCH / 64];
     int smax;
 };
@@ -516,7 +518,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             row_totals9(d);
             if (row_leader) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) part[w][drow][j][q] = d[q];
+                for (int q = 0; q < 9; ++q) part[w][drow][j * 9 + q] = d[q];
             }
         };
 #pragma unroll
@@ -550,8 +552,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
                 if (written[ww][e >> 6] & bit) {
-                    sum += part[ww][0][e][q] + part[ww][1][e][q] + part[ww][2][e][q] +
-                           part[ww][3][e][q];
+                    sum += part[ww][0][i] + part[ww][1][i] + part[ww][2][i] + part[ww][3][i];
                 }
             }
             if (sum != 0.0f) atomicAdd(gview + (int64_t)sG[e] * 9 + q, sum);

@@ -45,6 +45,7 @@ class Rasterizer:
         self.counters = torch.zeros(2, dtype=torch.int64, device=dev) if count_blends else None
         # persistent launches: largest-first tile order + one work counter per kernel
         self.persistent = persistent
+        self.order_tiles = True      # persistent: largest tiles first (else index order)
         self.n_workgroups = n_workgroups
         self.order = torch.zeros(self.n_tiles, dtype=torch.int32, device=dev)
         self.queues = torch.zeros(2, dtype=torch.int32, device=dev)
@@ -105,7 +106,7 @@ class Rasterizer:
         if self.persistent:
             o.persistent = 1
             o.n_workgroups = self.n_workgroups
-            o.order = self.order.data_ptr()
+            o.order = self.order.data_ptr() if self.order_tiles else 0
             o.queue = self.queues.data_ptr() + 4 * queue_index
         return o
 
@@ -116,7 +117,10 @@ class Rasterizer:
         if opts is None:
             opts = self._opts(0)
             if self.persistent:
-                self.tile_order()
+                if self.order_tiles:
+                    self.tile_order()
+                else:
+                    G.gs4d_fill_u32(self.queues, 0)
         if self.counters is not None:
             G.gs4d_fill_u32(self.counters.view(torch.int32), 0)
             opts.counters = self.counters.data_ptr()
