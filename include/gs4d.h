@@ -184,11 +184,15 @@ int gs4d_preprocess_bwd(const float *params, int64_t n, const gs4d_view *views, 
                         const int32_t *touched, const float *grad2d, float *dparams, void *stream);
 
 /* gs4d_tile_order -- work order for the persistent render launches: the
- *   global tiles sorted by descending number of pairs (ties by tile id),
- *   computed on the device from `ranges`, so that the longest tiles start
- *   first and the short ones fill the tail.  Also zeroes n_queues int32
- *   work counters (the `queue` fields of gs4d_render_opts).
- *   order  out int32 [n_tiles]; ws >= gs4d_tile_order_workspace_size(n_tiles). */
+ *   global tiles by decreasing size class (pairs n >= 1: 1 + 8 floor(log2 n)
+ *   + the three bits of n below its leading one, eight classes per octave;
+ *   empty tiles last), by tile id within a class, computed on the device from
+ *   `ranges` in one workgroup, so that the longest tiles start first and the
+ *   short ones fill the tail.  Also zeroes n_queues (<= 64) int32 work
+ *   counters (the `queue` fields of gs4d_render_opts).  The order only
+ *   schedules work: results do not depend on it.
+ *   order  out int32 [n_tiles]; ws >= gs4d_tile_order_workspace_size(n_tiles)
+ *   (no workspace is used; the query is kept for a stable interface). */
 size_t gs4d_tile_order_workspace_size(int64_t n_tiles);
 int gs4d_tile_order(const int32_t *ranges, int64_t n_tiles, int32_t *order, int32_t *queues,
                     int32_t n_queues, void *ws, size_t ws_bytes, void *stream);

@@ -727,50 +727,83 @@ extern "C" int gs4d_render_bwd(const float *params, int64_t n, const float *rec,
 // ---------------------------------------------------------------- tile order
 namespace gs4d {
 namespace {
-__global__ void tile_cost_kernel(const int2 *__restrict__ ranges, int64_t n_tiles,
-                                 uint32_t *__restrict__ keys, uint32_t *__restrict__ ids) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_tiles) return;
-    const int2 r = ranges[i];
-    // ascending sort of (2^32 - 1 - length) = descending length, stable in tile id
-    keys[i] = 0xFFFFFFFFu - (uint32_t)(r.y - r.x);
-    ids[i] = (uint32_t)i;
+// Work order of the persistent launches in one workgroup: tiles by
+// decreasing size class (empty tiles, class 0, last), by index within a
+// class -- a stable counting sort.  A pair count n >= 1 has class
+// 1 + 8 floor(log2 n) + its three bits below the leading one, i.e. eight
+// classes per octave (lengths within 12.5% share a class).  The whole block
+// counts the classes; wave 0 then walks the tiles in index order, 64 at a
+// time, ranking each lane among the lanes of the same class with ballots.
+// Also zeroes the work counters.
+constexpr int ORDER_CLASSES = 257;
+
+__device__ __forceinline__ int tile_class(const int2 r) {
+    const uint32_t len = (uint32_t)(r.y - r.x);
+    if (len == 0) return 0;
+    const int e = 31 - __builtin_clz(len);
+    const uint32_t m = e >= 3 ? (len >> (e - 3)) & 7u : (len << (3 - e)) & 7u;
+    return 1 + 8 * e + (int)m;
+}
+
+__global__ void __launch_bounds__(1024)
+tile_order_kernel(const int2 *__restrict__ ranges, int64_t n_tiles, int32_t *__restrict__ order,
+                  int32_t *__restrict__ queues, int n_queues) {
+    __shared__ uint32_t cnt[ORDER_CLASSES];
+    __shared__ uint32_t base[ORDER_CLASSES];
+    const int t = threadIdx.x;
+    for (int c = t; c < ORDER_CLASSES; c += blockDim.x) cnt[c] = 0;
+    if (t < n_queues) queues[t] = 0;
+    __syncthreads();
+    for (int64_t i = t; i < n_tiles; i += blockDim.x) atomicAdd(&cnt[tile_class(ranges[i])], 1u);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int c = ORDER_CLASSES - 1; c >= 0; --c) {
+            base[c] = run;
+            run += cnt[c];
+        }
+    }
+    __syncthreads();
+    if (t >= 64) return;
+    const uint64_t lt_mask = (t == 0) ? 0ull : (~0ull >> (64 - t));
+    for (int64_t c0 = 0; c0 < n_tiles; c0 += 64) {
+        const int64_t i = c0 + t;
+        const bool valid = i < n_tiles;
+        const int c = valid ? tile_class(ranges[i]) : 0;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 9; ++bit) {
+            const uint64_t m = __ballot((c >> bit) & 1);
+            peers &= ((c >> bit) & 1) ? m : ~m;
+        }
+        const uint32_t before = __popcll(peers & lt_mask);
+        if (valid) order[base[c] + before] = (int32_t)i;
+        // all lanes have read base[c] before the class leader advances it
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) base[c] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 }  // namespace
 }  // namespace gs4d
 
 extern "C" size_t gs4d_tile_order_workspace_size(int64_t n_tiles) {
-    Carve c(nullptr, 0);
-    const size_t m = (size_t)(n_tiles > 0 ? n_tiles : 1);
-    c.take<uint32_t>(m);
-    c.take<uint32_t>(m);
-    c.take<uint32_t>(m);
-    c.take<char>(radix_workspace_size(n_tiles));
-    return c.used + 256;
+    (void)n_tiles;
+    return 256;   // the order is computed in LDS; kept for a stable interface
 }
 
 extern "C" int gs4d_tile_order(const int32_t *ranges, int64_t n_tiles, int32_t *order,
                                int32_t *queues, int32_t n_queues, void *ws, size_t ws_bytes,
                                void *stream) {
+    (void)ws;
+    (void)ws_bytes;
     GS4D_REQUIRE(n_tiles > 0 && n_tiles < ((int64_t)1 << 31), "gs4d_tile_order: n_tiles out of range");
     GS4D_REQUIRE(ranges && order, "gs4d_tile_order: null pointer");
-    GS4D_REQUIRE(n_queues >= 0 && (n_queues == 0 || queues), "gs4d_tile_order: bad queues");
-    GS4D_REQUIRE(ws && ws_bytes >= gs4d_tile_order_workspace_size(n_tiles),
-                 "gs4d_tile_order: workspace too small");
+    GS4D_REQUIRE(n_queues >= 0 && n_queues <= 64 && (n_queues == 0 || queues),
+                 "gs4d_tile_order: bad queues (at most 64)");
     hipStream_t st = as_stream(stream);
-    Carve c(ws, ws_bytes);
-    const size_t m = (size_t)n_tiles;
-    uint32_t *k0 = c.take<uint32_t>(m);
-    uint32_t *k1 = c.take<uint32_t>(m);
-    uint32_t *v1 = c.take<uint32_t>(m);
-    void *rws = c.take<char>(radix_workspace_size(n_tiles));
-    uint32_t *v0 = reinterpret_cast<uint32_t *>(order);
-    tile_cost_kernel<<<(unsigned)((n_tiles + 255) / 256), 256, 0, st>>>(
-        reinterpret_cast<const int2 *>(ranges), n_tiles, k0, v0);
+    tile_order_kernel<<<1, 1024, 0, st>>>(reinterpret_cast<const int2 *>(ranges), n_tiles, order,
+                                          queues, n_queues);
     GS4D_LAUNCH_CHECK("gs4d_tile_order");
-    int alt = 0;
-    // lengths are < 2^31: 32 bits, 4 passes (an even count: result in k0/v0 = order)
-    GS4D_TRY(radix_sort_u32(k0, v0, k1, v1, nullptr, n_tiles, n_tiles, 0, 32, rws, st, &alt));
-    if (n_queues > 0) GS4D_TRY(launch_fill<int32_t>(queues, 0, n_queues, st));
     return GS4D_OK;
 }

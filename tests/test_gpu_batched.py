@@ -5,7 +5,8 @@ training step captured as a HIP graph.
 * the persistent forward renders the same bits as one workgroup per tile,
   for every LDS batch size, and matches the oracle's 8-view image;
 * the persistent backward matches the per-tile backward;
-* gs4d_tile_order yields the tiles by descending pair count (ties by id);
+* gs4d_tile_order yields the tiles by descending size class (eight per
+  octave of the pair count; ties by id);
 * the fused loss equals mean |C - C*| per view and its gradient;
 * graph replays of the batched step reproduce the eager step.
 """
@@ -68,9 +69,16 @@ def test_tile_order(small_batch):
     torch.cuda.synchronize()
     order = r.order.cpu().numpy()
     rg = r.ranges.cpu().numpy()
-    length = rg[:, 1] - rg[:, 0]
+    length = (rg[:, 1] - rg[:, 0]).astype(np.int64)
     assert sorted(order.tolist()) == list(range(len(order)))
-    ref = sorted(range(len(order)), key=lambda i: (-length[i], i))
+    def size_class(n):
+        if n == 0:
+            return 0
+        e = int(n).bit_length() - 1
+        m = (n >> (e - 3)) & 7 if e >= 3 else (n << (3 - e)) & 7
+        return 1 + 8 * e + m
+    cls = np.array([size_class(int(x)) for x in length])
+    ref = sorted(range(len(order)), key=lambda i: (-cls[i], i))
     assert order.tolist() == ref
     assert r.queues.cpu().numpy().tolist() == [0, 0]
 
