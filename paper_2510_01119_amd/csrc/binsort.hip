@@ -8,8 +8,9 @@
 //   1. item keys: the depth bits of each (view, Gaussian) record (culled ->
 //      0xFFFFFFFF), value = view * n + Gaussian.
 //   2. stable LSD radix sort of the items on the 32 depth bits.
-//   3. gather tiles-touched in that order, device-wide exclusive scan -> each
-//      item's first pair slot and the pair count P (stored on device).
+//   3. device-wide exclusive scan of tiles-touched read in that order -> each
+//      item's first pair slot, the pair count P and the capacity flag (on
+//      device).
 //   4. emit pairs in depth order; inside one tile they are then already
 //      ascending in (depth bits, Gaussian).
 //   5. stable LSD radix sort of the P pairs on the tile bits only, which
@@ -234,22 +235,32 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *total) {
     return off + incl - x;
 }
 
+// value i of a scan input: in[i], or in[gather[i]] when a gather index is given
+__device__ __forceinline__ int32_t scan_in(const int32_t *__restrict__ in,
+                                           const uint32_t *__restrict__ gather, int64_t i) {
+    return gather ? in[gather[i]] : in[i];
+}
+
 __global__ void __launch_bounds__(SC_THREADS)
-scan_reduce_kernel(const int32_t *__restrict__ in, int64_t count, int64_t *__restrict__ bsum) {
+scan_reduce_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
+                   int64_t count, int64_t *__restrict__ bsum) {
     const int64_t b = blockIdx.x;
     const int64_t base = b * SC_TILE;
     int64_t s = 0;
     for (int i = 0; i < SC_ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
-        if (idx < count) s += in[idx];
+        if (idx < count) s += scan_in(in, gather, idx);
     }
     int64_t tot;
     block_excl_scan(s, &tot);
     if (threadIdx.x == 0) bsum[b] = tot;
 }
 
+// Exclusive scan of the block sums; with `n_pairs`, also the pair count and
+// the capacity flag of the binning (the scanned values are pair counts).
 __global__ void __launch_bounds__(SC_THREADS)
-scan_top_kernel(int64_t *__restrict__ bsum, int64_t nblocks, int64_t *__restrict__ total) {
+scan_top_kernel(int64_t *__restrict__ bsum, int64_t nblocks, int64_t *__restrict__ total,
+                int64_t capacity, int64_t *__restrict__ n_pairs, int32_t *__restrict__ overflow) {
     int64_t carry = 0;
     for (int64_t c0 = 0; c0 < nblocks; c0 += SC_THREADS) {
         const int64_t idx = c0 + threadIdx.x;
@@ -259,12 +270,18 @@ scan_top_kernel(int64_t *__restrict__ bsum, int64_t nblocks, int64_t *__restrict
         if (idx < nblocks) bsum[idx] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) {
+        *total = carry;
+        if (n_pairs) {
+            *n_pairs = carry;
+            *overflow = carry > capacity ? 1 : 0;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(SC_THREADS)
-scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t count,
-                 const int64_t *__restrict__ bsum) {
+scan_down_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
+                 int32_t *__restrict__ out, int64_t count, const int64_t *__restrict__ bsum) {
     const int64_t b = blockIdx.x;
     // each thread owns SC_ITEMS consecutive values
     const int64_t base = b * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
@@ -272,7 +289,7 @@ scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int6
     int64_t s = 0;
 #pragma unroll
     for (int i = 0; i < SC_ITEMS; ++i) {
-        v[i] = (base + i < count) ? in[base + i] : 0;
+        v[i] = (base + i < count) ? scan_in(in, gather, base + i) : 0;
         s += v[i];
     }
     int64_t tot;
@@ -285,44 +302,32 @@ scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int6
 }
 
 // ---------------------------------------------------------------- binning kernels
+// Item keys (depth bits, culled last) and, in the same pass, the zeroed
+// tile ranges (a tile no pair reaches stays (0, 0)).
 __global__ void item_keys_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
                                  int64_t m, uint32_t *__restrict__ keys,
-                                 uint32_t *__restrict__ vals) {
+                                 uint32_t *__restrict__ vals, int32_t *__restrict__ ranges,
+                                 int64_t n_range_ints) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < n_range_ints) ranges[o] = 0;
     if (o >= m) return;
     const float z = rec[3 * o + 1].z;
     keys[o] = touched[o] > 0 ? __float_as_uint(z) : 0xFFFFFFFFu;
     vals[o] = (uint32_t)o;
 }
 
-__global__ void gather_touched_kernel(const uint32_t *__restrict__ order,
-                                      const int32_t *__restrict__ touched, int64_t m,
-                                      int32_t *__restrict__ out) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) out[k] = touched[order[k]];
-}
-
-__global__ void pair_status_kernel(const int64_t *__restrict__ total, int64_t capacity,
-                                   int64_t *__restrict__ n_pairs, int32_t *__restrict__ overflow) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const int64_t t = *total;
-        *n_pairs = t;
-        *overflow = t > capacity ? 1 : 0;
-    }
-}
-
 __global__ void emit_kernel(const uint32_t *__restrict__ dkeys, const uint32_t *__restrict__ order,
-                            const int32_t *__restrict__ tsorted, const int32_t *__restrict__ offs,
+                            const int32_t *__restrict__ touched, const int32_t *__restrict__ offs,
                             const int4 *__restrict__ rect, int64_t m, int64_t n, int32_t tiles_x,
                             int32_t tiles_per_view, int64_t capacity, uint64_t *__restrict__ keys,
                             uint32_t *__restrict__ vals) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
-    const int32_t cnt = tsorted[k];
+    const uint32_t o = order[k];
+    const int32_t cnt = touched[o];
     if (cnt == 0) return;
     const int64_t off = offs[k];
     if (off < 0 || off + cnt > capacity) return;
-    const uint32_t o = order[k];
     const uint32_t vi = (uint32_t)(o / (uint64_t)n);
     const uint32_t g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
     const int4 r = rect[o];
@@ -433,17 +438,33 @@ int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count, int64_t *
     if (nb == 0) {
         return launch_fill<int64_t>(total, (int64_t)0, 1, st);
     }
-    scan_reduce_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, count, bsum);
-    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total);
-    scan_down_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, out, count, bsum);
+    scan_reduce_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, nullptr, count, bsum);
+    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, 0, nullptr, nullptr);
+    scan_down_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, nullptr, out, count, bsum);
     GS4D_LAUNCH_CHECK("exclusive_scan");
     return GS4D_OK;
 }
 
 namespace {
+// Pair offsets of the depth-ordered items: exclusive scan of touched[order[k]],
+// the pair count and the capacity flag, in three kernels (count >= 1).
+int pair_offsets(const int32_t *touched, const uint32_t *order, int32_t *offs, int64_t count,
+                 int64_t *total, void *ws, int64_t capacity, int64_t *n_pairs, int32_t *overflow,
+                 hipStream_t st) {
+    const int64_t nb = (count + SC_TILE - 1) / SC_TILE;
+    int64_t *bsum = static_cast<int64_t *>(ws);
+    scan_reduce_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(touched, order, count, bsum);
+    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, capacity, n_pairs, overflow);
+    scan_down_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(touched, order, offs, count, bsum);
+    GS4D_LAUNCH_CHECK("pair_offsets");
+    return GS4D_OK;
+}
+}  // namespace
+
+namespace {
 struct BinLayout {
     uint32_t *ik0, *iv0, *ik1, *iv1;   // item keys / values, two buffers
-    int32_t *tsorted, *offs;
+    int32_t *offs;
     void *scan_ws;
     int64_t *total;
     uint64_t *pk;                       // alternate pair buffers
@@ -459,7 +480,6 @@ BinLayout carve_bin(void *ws, int64_t m, int64_t cap, size_t *used) {
     L.iv0 = c.take<uint32_t>(mm);
     L.ik1 = c.take<uint32_t>(mm);
     L.iv1 = c.take<uint32_t>(mm);
-    L.tsorted = c.take<int32_t>(mm);
     L.offs = c.take<int32_t>(mm);
     L.scan_ws = c.take<char>(scan_workspace_size(m));
     L.total = c.take<int64_t>(1);
@@ -510,26 +530,23 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
     BinLayout L = carve_bin(ws, m, pair_capacity, &used);
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
 
-    GS4D_TRY(launch_fill<int32_t>(ranges, 0, 2 * n_tiles, st));
     if (m == 0) {
+        GS4D_TRY(launch_fill<int32_t>(ranges, 0, 2 * n_tiles, st));
         GS4D_TRY(launch_fill<int64_t>(n_pairs, (int64_t)0, 1, st));
         GS4D_TRY(launch_fill<int32_t>(overflow, 0, 1, st));
         return GS4D_OK;
     }
-    // 1-2: items sorted by depth bits
-    item_keys_kernel<<<grid_for(m, 256), 256, 0, st>>>(reinterpret_cast<const float4 *>(rec), touched,
-                                                       m, L.ik0, L.iv0);
+    // 1-2: items sorted by depth bits (the same pass zeroes the ranges)
+    item_keys_kernel<<<grid_for(m > 2 * n_tiles ? m : 2 * n_tiles, 256), 256, 0, st>>>(
+        reinterpret_cast<const float4 *>(rec), touched, m, L.ik0, L.iv0, ranges, 2 * n_tiles);
     GS4D_LAUNCH_CHECK("item_keys");
     int alt = 0;
     GS4D_TRY(radix_sort_u32(L.ik0, L.iv0, L.ik1, L.iv1, nullptr, m, m, 0, 32, L.radix_ws, st, &alt));
     const uint32_t *dkeys = alt ? L.ik1 : L.ik0;
     const uint32_t *order = alt ? L.iv1 : L.iv0;
-    // 3: offsets in depth order
-    gather_touched_kernel<<<grid_for(m, 256), 256, 0, st>>>(order, touched, m, L.tsorted);
-    GS4D_LAUNCH_CHECK("gather_touched");
-    GS4D_TRY(exclusive_scan_i32(L.tsorted, L.offs, m, L.total, L.scan_ws, st));
-    pair_status_kernel<<<1, 64, 0, st>>>(L.total, pair_capacity, n_pairs, overflow);
-    GS4D_LAUNCH_CHECK("pair_status");
+    // 3: offsets in depth order, pair count and capacity flag
+    GS4D_TRY(pair_offsets(touched, order, L.offs, m, L.total, L.scan_ws, pair_capacity, n_pairs,
+                          overflow, st));
     if (pair_capacity == 0) return GS4D_OK;
     // 4-5: emit in depth order, stable sort on tile bits only
     const int tbits = tile_bits_for(n_tiles);
@@ -538,7 +555,7 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
     uint32_t *ev = (tpasses & 1) ? L.pv : vals;
     uint64_t *ok = (tpasses & 1) ? keys : L.pk;
     uint32_t *ov = (tpasses & 1) ? vals : L.pv;
-    emit_kernel<<<grid_for(m, 128), 128, 0, st>>>(dkeys, order, L.tsorted, L.offs,
+    emit_kernel<<<grid_for(m, 128), 128, 0, st>>>(dkeys, order, touched, L.offs,
                                                   reinterpret_cast<const int4 *>(rect), m, n,
                                                   vp.tiles_x, vp.tiles_per_view, pair_capacity, ek,
                                                   ev);

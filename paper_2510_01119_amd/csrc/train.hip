@@ -100,8 +100,9 @@ sse_kernel(const float *__restrict__ x, const float *__restrict__ y, int64_t cou
 
 // ---------------------------------------------------------------- SSIM
 constexpr int SS_R = 5;               // window radius (11 taps)
-constexpr int SS_T = 16;              // output tile edge
-constexpr int SS_E = SS_T + 2 * SS_R; // staged edge (26)
+constexpr int SS_T = 32;              // output tile edge (256 threads, 4 rows each)
+constexpr int SS_E = SS_T + 2 * SS_R; // staged edge (42)
+constexpr int SS_RPT = SS_T * SS_T / 256;   // output rows per thread
 constexpr float SS_C1 = 0.01f * 0.01f;
 constexpr float SS_C2 = 0.03f * 0.03f;
 
@@ -152,33 +153,37 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
         hs[4][r][c] = ab;
     }
     __syncthreads();
-    const int c = t & 15, r = t >> 4;
-    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 2 * SS_R + 1; ++k) {
-        const float g = win.g[k];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) m[q] += g * hs[q][r + k][c];
-    }
-    const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
+    const int c = t % SS_T;
     float sv = 0.0f, lv = 0.0f;
-    if (gx < w && gy < h) {
-        const float mx = m[0], my = m[1];
-        const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
-        const float A1 = 2.f * mx * my + SS_C1, A2 = 2.f * sxy + SS_C2;
-        const float B1 = mx * mx + my * my + SS_C1, B2 = sxx + syy + SS_C2;
-        const float S = (A1 * A2) / (B1 * B2);
-        sv = S;
-        const int64_t o = plane + (int64_t)gy * w + gx;
-        if (P1) {
-            P1[o] = S * (2.f * my / A1 - 2.f * mx / B1 - 2.f * my / A2 + 2.f * mx / B2);
-            P2[o] = -S / B2;
-            P3[o] = 2.f * S / A2;
+#pragma unroll
+    for (int rr = 0; rr < SS_RPT; ++rr) {
+        const int r = t / SS_T + rr * (256 / SS_T);
+        float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 2 * SS_R + 1; ++k) {
+            const float g = win.g[k];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) m[q] += g * hs[q][r + k][c];
         }
-        if (part_l1) {
-            const float d = sx[r + SS_R][c + SS_R] - sy[r + SS_R][c + SS_R];
-            lv = fabsf(d);
-            if (l1_grad) l1_grad[o] = d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f);
+        const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
+        if (gx < w && gy < h) {
+            const float mx = m[0], my = m[1];
+            const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+            const float A1 = 2.f * mx * my + SS_C1, A2 = 2.f * sxy + SS_C2;
+            const float B1 = mx * mx + my * my + SS_C1, B2 = sxx + syy + SS_C2;
+            const float S = (A1 * A2) / (B1 * B2);
+            sv += S;
+            const int64_t o = plane + (int64_t)gy * w + gx;
+            if (P1) {
+                P1[o] = S * (2.f * my / A1 - 2.f * mx / B1 - 2.f * my / A2 + 2.f * mx / B2);
+                P2[o] = -S / B2;
+                P3[o] = 2.f * S / A2;
+            }
+            if (part_l1) {
+                const float d = sx[r + SS_R][c + SS_R] - sy[r + SS_R][c + SS_R];
+                lv += fabsf(d);
+                if (l1_grad) l1_grad[o] = d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f);
+            }
         }
     }
     const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
@@ -245,18 +250,22 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
         hs[2][r][c] = d;
     }
     __syncthreads();
-    const int c = t & 15, r = t >> 4;
-    float q[3] = {0.f, 0.f, 0.f};
+    const int c = t % SS_T;
 #pragma unroll
-    for (int k = 0; k < 2 * SS_R + 1; ++k) {
-        const float g = win.g[k];
+    for (int rr = 0; rr < SS_RPT; ++rr) {
+        const int r = t / SS_T + rr * (256 / SS_T);
+        float q[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 3; ++j) q[j] += g * hs[j][r + k][c];
-    }
-    const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
-    if (gx < w && gy < h) {
-        const int64_t o = plane + (int64_t)gy * w + gx;
-        dX[o] += scale * (q[0] + 2.f * X[o] * q[1] + Y[o] * q[2]);
+        for (int k = 0; k < 2 * SS_R + 1; ++k) {
+            const float g = win.g[k];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) q[j] += g * hs[j][r + k][c];
+        }
+        const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
+        if (gx < w && gy < h) {
+            const int64_t o = plane + (int64_t)gy * w + gx;
+            dX[o] += scale * (q[0] + 2.f * X[o] * q[1] + Y[o] * q[2]);
+        }
     }
 }
 
