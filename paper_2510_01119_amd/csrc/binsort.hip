@@ -19,8 +19,8 @@
 //   6. tile ranges from adjacent key differences.
 //
 // Radix sort: 8-bit digits; per pass a histogram kernel (per-block digit
-// counts + global digit totals), a scan kernel (one wave per digit over the
-// blocks), and a scatter kernel that ranks keys stably with wave ballots,
+// counts), a scan kernel (one wave per digit over the blocks, giving each
+// digit's total), and a scatter kernel that ranks keys stably with wave ballots,
 // regroups them by digit in LDS and writes each digit run contiguously.
 #include "common.hpp"
 
@@ -29,12 +29,14 @@ namespace {
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_MAX_PASSES = 8;
-// keys per block = 256 threads x ITEMS; small inputs use ITEMS = 4 so that
-// enough blocks exist to fill the GPU, large ones ITEMS = 16
+// keys per block = 256 threads x ITEMS, by capacity: short blocks for the
+// sorts of a few hundred thousand keys a training step makes, so that they
+// still spread over all 256 compute units; long ones for tens of millions
+constexpr int RS_TINY_ITEMS = 2;
 constexpr int RS_SMALL_ITEMS = 4;
 constexpr int RS_LARGE_ITEMS = 16;
-constexpr int64_t RS_SMALL_LIMIT = 1 << 20;
+constexpr int64_t RS_TINY_LIMIT = 1 << 18;
+constexpr int64_t RS_SMALL_LIMIT = 1 << 22;
 
 __device__ __forceinline__ int64_t read_count(const int64_t *count_dev, int64_t count_host,
                                               int64_t capacity) {
@@ -56,8 +58,7 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
 template <class K, int RS_ITEMS>
 __global__ void __launch_bounds__(RS_THREADS)
 rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t count_host,
-               int64_t capacity, int shift, uint32_t *__restrict__ hist,
-               uint32_t *__restrict__ digit_total) {
+               int64_t capacity, int shift, uint32_t *__restrict__ hist) {
     constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
     const int64_t n = read_count(count_dev, count_host, capacity);
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
@@ -78,36 +79,41 @@ rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t cou
 #pragma unroll
     for (int k = 0; k < RS_WAVES; ++k) c += cnt[k][t];
     hist[(int64_t)t * nb + b] = c;
-    if (c) atomicAdd(&digit_total[t], c);
 }
 
-// One wave per digit: exclusive prefix of hist[d][0..nb) plus the count of
-// all smaller digits.
+// One wave per digit: exclusive prefix of hist[d][0..nb) in place and the
+// digit's total count in row_total[d] (the offsets between digits are left to
+// the scatter blocks, so no kernel needs device-wide atomics).
 __global__ void __launch_bounds__(64)
-rs_scan_kernel(uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_total,
+rs_scan_kernel(uint32_t *__restrict__ hist, uint32_t *__restrict__ row_total,
                const int64_t *count_dev, int64_t count_host, int64_t capacity, int RS_TILE) {
     const int64_t n = read_count(count_dev, count_host, capacity);
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
     if (nb == 0) return;
     const int d = blockIdx.x, l = threadIdx.x;
-    uint32_t below = 0;
-    for (int k = l; k < d; k += 64) below += digit_total[k];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) below += __shfl_xor(below, off, 64);
-    uint32_t running = below;
+    uint32_t running = 0;
     uint32_t *row = hist + (int64_t)d * nb;
-    for (int64_t c0 = 0; c0 < nb; c0 += 64) {
-        const int64_t idx = c0 + l;
-        const uint32_t x = idx < nb ? row[idx] : 0u;
-        uint32_t incl = x;
+    for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+        uint32_t x[4];
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (l >= off) incl += y;
+        for (int i = 0; i < 4; ++i) {
+            const int64_t idx = c0 + i * 64 + l;
+            x[i] = idx < nb ? row[idx] : 0u;
         }
-        if (idx < nb) row[idx] = running + incl - x;
-        running += __shfl(incl, 63, 64);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t incl = x[i];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (l >= off) incl += y;
+            }
+            const int64_t idx = c0 + i * 64 + l;
+            if (idx < nb) row[idx] = running + incl - x[i];
+            running += __shfl(incl, 63, 64);
+        }
     }
+    if (l == 0) row_total[d] = running;
 }
 
 template <class K, int RS_ITEMS>
@@ -115,7 +121,7 @@ __global__ void __launch_bounds__(RS_THREADS)
 rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                   K *__restrict__ kout, uint32_t *__restrict__ vout, const int64_t *count_dev,
                   int64_t count_host, int64_t capacity, int shift,
-                  const uint32_t *__restrict__ hist) {
+                  const uint32_t *__restrict__ hist, const uint32_t *__restrict__ row_total) {
     constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
     const int64_t n = read_count(count_dev, count_host, capacity);
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
@@ -159,7 +165,8 @@ rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
         rank[i] = valid ? r : 0xFFFFFFFFu;
     }
     __syncthreads();
-    // per digit: prefix over waves, block-local start, global start
+    // per digit: prefix over waves, block-local start, global start (the
+    // keys of all smaller digits plus this digit's keys in earlier blocks)
     {
         const int d = t;
         uint32_t run = 0;
@@ -169,20 +176,24 @@ rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
             wcnt[k][d] = run;
             run += c;
         }
-        // block exclusive scan of run over the 256 digits
-        uint32_t incl = run;
+        // block exclusive scans over the 256 digits of this block's counts
+        // and of the digit totals
+        const uint32_t tot = row_total[d];
+        uint32_t incl = run, tincl = tot;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(incl, off, 64);
-            if (l >= off) incl += y;
+            const uint32_t z = __shfl_up(tincl, off, 64);
+            if (l >= off) { incl += y; tincl += z; }
         }
-        __shared__ uint32_t wsum[RS_WAVES];
-        if (l == 63) wsum[w] = incl;
-        gbase[d] = hist[(int64_t)d * nb + b];
+        __shared__ uint32_t wsum[2][RS_WAVES];
+        if (l == 63) { wsum[0][w] = incl; wsum[1][w] = tincl; }
+        const uint32_t in_row = hist[(int64_t)d * nb + b];
         __syncthreads();
-        uint32_t off = 0;
-        for (int k = 0; k < w; ++k) off += wsum[k];
+        uint32_t off = 0, toff = 0;
+        for (int k = 0; k < w; ++k) { off += wsum[0][k]; toff += wsum[1][k]; }
         dstart[d] = off + incl - run;
+        gbase[d] = toff + tincl - tot + in_row;
     }
     __syncthreads();
 #pragma unroll
@@ -370,17 +381,27 @@ int radix_passes(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_
     uint32_t *vsrc = v0, *vdst = v1;
     for (int p = 0; p < passes; ++p) {
         const int shift = bit_lo + 8 * p;
-        uint32_t *tot = totals + p * 256;
         rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-            src, count_dev, count_host, capacity, shift, hist, tot);
-        rs_scan_kernel<<<256, 64, 0, st>>>(hist, tot, count_dev, count_host, capacity, TILE);
+            src, count_dev, count_host, capacity, shift, hist);
+        rs_scan_kernel<<<256, 64, 0, st>>>(hist, totals, count_dev, count_host, capacity, TILE);
         rs_scatter_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-            src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, hist);
+            src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, hist, totals);
         GS4D_LAUNCH_CHECK("radix pass");
         K *tk = src; src = dst; dst = tk;
         uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
     }
     return GS4D_OK;
+}
+
+inline int rs_items(int64_t capacity) {
+    return capacity <= RS_TINY_LIMIT ? RS_TINY_ITEMS
+                                     : capacity <= RS_SMALL_LIMIT ? RS_SMALL_ITEMS : RS_LARGE_ITEMS;
+}
+
+inline int64_t rs_blocks(int64_t capacity) {
+    const int64_t tile = (int64_t)RS_THREADS * rs_items(capacity);
+    const int64_t nb = (capacity + tile - 1) / tile;
+    return nb > 0 ? nb : 1;
 }
 
 template <class K>
@@ -390,25 +411,35 @@ int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *cou
     const int passes = (bit_hi - bit_lo + 7) / 8;
     *result_in_alt = passes & 1;
     if (passes <= 0 || capacity <= 0) return GS4D_OK;
-    const int64_t nb_max = (capacity + RS_THREADS * RS_SMALL_ITEMS - 1) / (RS_THREADS * RS_SMALL_ITEMS);
     Carve c(ws, ~size_t(0));
-    uint32_t *hist = c.take<uint32_t>((size_t)nb_max * 256);
-    uint32_t *totals = c.take<uint32_t>((size_t)RS_MAX_PASSES * 256);
-    GS4D_TRY(launch_fill<uint32_t>(totals, 0u, (int64_t)passes * 256, st));
-    if (capacity <= RS_SMALL_LIMIT)
+    uint32_t *hist = c.take<uint32_t>((size_t)rs_blocks(capacity) * 256);
+    uint32_t *totals = c.take<uint32_t>(256);
+    switch (rs_items(capacity)) {
+    case RS_TINY_ITEMS:
+        return radix_passes<K, RS_TINY_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
+                                               bit_lo, passes, hist, totals, st);
+    case RS_SMALL_ITEMS:
         return radix_passes<K, RS_SMALL_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
                                                 bit_lo, passes, hist, totals, st);
-    return radix_passes<K, RS_LARGE_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity, bit_lo,
-                                            passes, hist, totals, st);
+    default:
+        return radix_passes<K, RS_LARGE_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
+                                                bit_lo, passes, hist, totals, st);
+    }
 }
 
 }  // namespace
 
 size_t radix_workspace_size(int64_t capacity) {
-    const int64_t nb_max = (capacity + RS_THREADS * RS_SMALL_ITEMS - 1) / (RS_THREADS * RS_SMALL_ITEMS);
+    // enough block histograms for any capacity up to this one (a smaller
+    // capacity may use shorter blocks, hence more of them)
+    int64_t nb = rs_blocks(capacity);
+    for (const int64_t lim : {RS_TINY_LIMIT, RS_SMALL_LIMIT}) {
+        const int64_t q = rs_blocks(capacity < lim ? capacity : lim);
+        nb = q > nb ? q : nb;
+    }
     Carve c(nullptr, 0);
-    c.take<uint32_t>((size_t)(nb_max > 0 ? nb_max : 1) * 256);
-    c.take<uint32_t>((size_t)RS_MAX_PASSES * 256);
+    c.take<uint32_t>((size_t)nb * 256);
+    c.take<uint32_t>(256);
     return c.used + 256;
 }
 
