@@ -221,9 +221,12 @@ rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
 }
 
 // ---------------------------------------------------------------- scan
+// values per block = 256 threads x ITEMS: 4 up to 2^20 values, so that the
+// few hundred thousand of a training step still make enough blocks, else 16
 constexpr int SC_THREADS = 256;
-constexpr int SC_ITEMS = 16;
-constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+constexpr int SC_SMALL_ITEMS = 4;
+constexpr int SC_LARGE_ITEMS = 16;
+constexpr int64_t SC_SMALL_LIMIT = 1 << 20;
 
 __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *total) {
     __shared__ int64_t ws[SC_THREADS / 64];
@@ -252,13 +255,15 @@ __device__ __forceinline__ int32_t scan_in(const int32_t *__restrict__ in,
     return gather ? in[gather[i]] : in[i];
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(SC_THREADS)
 scan_reduce_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
                    int64_t count, int64_t *__restrict__ bsum) {
     const int64_t b = blockIdx.x;
-    const int64_t base = b * SC_TILE;
+    const int64_t base = b * (SC_THREADS * ITEMS);
     int64_t s = 0;
-    for (int i = 0; i < SC_ITEMS; ++i) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
         if (idx < count) s += scan_in(in, gather, idx);
     }
@@ -290,26 +295,71 @@ scan_top_kernel(int64_t *__restrict__ bsum, int64_t nblocks, int64_t *__restrict
     }
 }
 
+// Loads and stores are coalesced (value i*256 + thread of the block); the
+// scan itself runs over ITEMS consecutive values per thread, regrouped in LDS.
+template <int ITEMS>
 __global__ void __launch_bounds__(SC_THREADS)
 scan_down_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
                  int32_t *__restrict__ out, int64_t count, const int64_t *__restrict__ bsum) {
+    constexpr int TILE = SC_THREADS * ITEMS;
+    __shared__ int32_t tile[TILE];
     const int64_t b = blockIdx.x;
-    // each thread owns SC_ITEMS consecutive values
-    const int64_t base = b * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
-    int32_t v[SC_ITEMS];
+    const int t = threadIdx.x;
+    const int64_t base = b * TILE;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = base + (int64_t)i * SC_THREADS + t;
+        tile[i * SC_THREADS + t] = idx < count ? scan_in(in, gather, idx) : 0;
+    }
+    __syncthreads();
+    int32_t v[ITEMS];
     int64_t s = 0;
 #pragma unroll
-    for (int i = 0; i < SC_ITEMS; ++i) {
-        v[i] = (base + i < count) ? scan_in(in, gather, base + i) : 0;
+    for (int i = 0; i < ITEMS; ++i) {
+        v[i] = tile[t * ITEMS + i];
         s += v[i];
     }
+    // every thread has read its values before the scan's barriers
     int64_t tot;
     int64_t run = bsum[b] + block_excl_scan(s, &tot);
 #pragma unroll
-    for (int i = 0; i < SC_ITEMS; ++i) {
-        if (base + i < count) out[base + i] = (int32_t)run;
+    for (int i = 0; i < ITEMS; ++i) {
+        tile[t * ITEMS + i] = (int32_t)run;
         run += v[i];
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = base + (int64_t)i * SC_THREADS + t;
+        if (idx < count) out[idx] = tile[i * SC_THREADS + t];
+    }
+}
+
+inline int sc_items(int64_t count) {
+    return count <= SC_SMALL_LIMIT ? SC_SMALL_ITEMS : SC_LARGE_ITEMS;
+}
+
+inline int64_t sc_blocks(int64_t count) {
+    const int64_t tile = (int64_t)SC_THREADS * sc_items(count);
+    return (count + tile - 1) / tile;
+}
+
+// the three launches of one scan (block sums, their scan with the optional
+// binning outputs, the down-sweep)
+int scan_launch(const int32_t *in, const uint32_t *gather, int32_t *out, int64_t count,
+                int64_t *total, int64_t *bsum, int64_t capacity, int64_t *n_pairs,
+                int32_t *overflow, hipStream_t st) {
+    const int64_t nb = sc_blocks(count);
+    if (sc_items(count) == SC_SMALL_ITEMS)
+        scan_reduce_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
+    else
+        scan_reduce_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
+    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, capacity, n_pairs, overflow);
+    if (sc_items(count) == SC_SMALL_ITEMS)
+        scan_down_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count, bsum);
+    else
+        scan_down_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count, bsum);
+    return GS4D_OK;
 }
 
 // ---------------------------------------------------------------- binning kernels
@@ -458,20 +508,19 @@ int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const
 }
 
 size_t scan_workspace_size(int64_t count) {
-    const int64_t nb = (count + SC_TILE - 1) / SC_TILE;
+    // enough block sums for any count up to this one
+    int64_t nb = sc_blocks(count);
+    const int64_t q = sc_blocks(count < SC_SMALL_LIMIT ? count : SC_SMALL_LIMIT);
+    nb = q > nb ? q : nb;
     return (size_t)(nb > 0 ? nb : 1) * sizeof(int64_t) + 256;
 }
 
 int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count, int64_t *total, void *ws,
                        hipStream_t st) {
-    const int64_t nb = (count + SC_TILE - 1) / SC_TILE;
-    int64_t *bsum = static_cast<int64_t *>(ws);
-    if (nb == 0) {
+    if (count <= 0) {
         return launch_fill<int64_t>(total, (int64_t)0, 1, st);
     }
-    scan_reduce_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, nullptr, count, bsum);
-    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, 0, nullptr, nullptr);
-    scan_down_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, nullptr, out, count, bsum);
+    scan_launch(in, nullptr, out, count, total, static_cast<int64_t *>(ws), 0, nullptr, nullptr, st);
     GS4D_LAUNCH_CHECK("exclusive_scan");
     return GS4D_OK;
 }
@@ -482,11 +531,8 @@ namespace {
 int pair_offsets(const int32_t *touched, const uint32_t *order, int32_t *offs, int64_t count,
                  int64_t *total, void *ws, int64_t capacity, int64_t *n_pairs, int32_t *overflow,
                  hipStream_t st) {
-    const int64_t nb = (count + SC_TILE - 1) / SC_TILE;
-    int64_t *bsum = static_cast<int64_t *>(ws);
-    scan_reduce_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(touched, order, count, bsum);
-    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, capacity, n_pairs, overflow);
-    scan_down_kernel<<<(unsigned)nb, SC_THREADS, 0, st>>>(touched, order, offs, count, bsum);
+    scan_launch(touched, order, offs, count, total, static_cast<int64_t *>(ws), capacity, n_pairs,
+                overflow, st);
     GS4D_LAUNCH_CHECK("pair_offsets");
     return GS4D_OK;
 }

@@ -731,11 +731,15 @@ namespace {
 // decreasing size class (empty tiles, class 0, last), by index within a
 // class -- a stable counting sort.  A pair count n >= 1 has class
 // 1 + 8 floor(log2 n) + its three bits below the leading one, i.e. eight
-// classes per octave (lengths within 12.5% share a class).  The whole block
-// counts the classes; wave 0 then walks the tiles in index order, 64 at a
-// time, ranking each lane among the lanes of the same class with ballots.
-// Also zeroes the work counters.
+// classes per octave (lengths within 12.5% share a class).  Each of the 16
+// waves owns a contiguous run of tiles: it counts its classes, one block
+// scan turns the counts into each (wave, class) start (classes largest
+// first, waves in index order inside a class), and each wave then places its
+// tiles 64 at a time, ranking a lane among the lanes of the same class with
+// ballots.  Also zeroes the work counters.
 constexpr int ORDER_CLASSES = 257;
+constexpr int ORDER_THREADS = 1024;
+constexpr int ORDER_WAVES = ORDER_THREADS / 64;
 
 __device__ __forceinline__ int tile_class(const int2 r) {
     const uint32_t len = (uint32_t)(r.y - r.x);
@@ -745,42 +749,62 @@ __device__ __forceinline__ int tile_class(const int2 r) {
     return 1 + 8 * e + (int)m;
 }
 
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(ORDER_THREADS)
 tile_order_kernel(const int2 *__restrict__ ranges, int64_t n_tiles, int32_t *__restrict__ order,
                   int32_t *__restrict__ queues, int n_queues) {
-    __shared__ uint32_t cnt[ORDER_CLASSES];
-    __shared__ uint32_t base[ORDER_CLASSES];
-    const int t = threadIdx.x;
-    for (int c = t; c < ORDER_CLASSES; c += blockDim.x) cnt[c] = 0;
+    __shared__ uint32_t cnt[ORDER_WAVES][ORDER_CLASSES];
+    __shared__ uint32_t wsum[ORDER_WAVES];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int i = t; i < ORDER_WAVES * ORDER_CLASSES; i += ORDER_THREADS) (&cnt[0][0])[i] = 0;
     if (t < n_queues) queues[t] = 0;
     __syncthreads();
-    for (int64_t i = t; i < n_tiles; i += blockDim.x) atomicAdd(&cnt[tile_class(ranges[i])], 1u);
+    // this wave's tiles [lo, hi), a whole number of 64-tile steps
+    const int64_t chunk = ((n_tiles + ORDER_WAVES - 1) / ORDER_WAVES + 63) / 64 * 64;
+    const int64_t lo = (int64_t)w * chunk;
+    const int64_t hi = lo + chunk < n_tiles ? lo + chunk : n_tiles;
+    for (int64_t i = lo + l; i < hi; i += 64) atomicAdd(&cnt[w][tile_class(ranges[i])], 1u);
     __syncthreads();
-    if (t == 0) {
-        uint32_t run = 0;
-        for (int c = ORDER_CLASSES - 1; c >= 0; --c) {
-            base[c] = run;
-            run += cnt[c];
+    // thread p < ORDER_CLASSES handles class ORDER_CLASSES - 1 - p (placement
+    // order): prefix over the waves, then a block scan of the class totals
+    const int c = ORDER_CLASSES - 1 - t;
+    uint32_t tot = 0;
+    if (t < ORDER_CLASSES) {
+        for (int k = 0; k < ORDER_WAVES; ++k) {
+            const uint32_t x = cnt[k][c];
+            cnt[k][c] = tot;
+            tot += x;
         }
     }
+    uint32_t incl = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (l >= off) incl += y;
+    }
+    if (l == 63) wsum[w] = incl;
     __syncthreads();
-    if (t >= 64) return;
-    const uint64_t lt_mask = (t == 0) ? 0ull : (~0ull >> (64 - t));
-    for (int64_t c0 = 0; c0 < n_tiles; c0 += 64) {
-        const int64_t i = c0 + t;
-        const bool valid = i < n_tiles;
-        const int c = valid ? tile_class(ranges[i]) : 0;
+    if (t < ORDER_CLASSES) {
+        uint32_t start = incl - tot;
+        for (int k = 0; k < w; ++k) start += wsum[k];
+        for (int k = 0; k < ORDER_WAVES; ++k) cnt[k][c] += start;
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    for (int64_t c0 = lo; c0 < hi; c0 += 64) {
+        const int64_t i = c0 + l;
+        const bool valid = i < hi;
+        const int cls = valid ? tile_class(ranges[i]) : 0;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 9; ++bit) {
-            const uint64_t m = __ballot((c >> bit) & 1);
-            peers &= ((c >> bit) & 1) ? m : ~m;
+            const uint64_t m = __ballot((cls >> bit) & 1);
+            peers &= ((cls >> bit) & 1) ? m : ~m;
         }
         const uint32_t before = __popcll(peers & lt_mask);
-        if (valid) order[base[c] + before] = (int32_t)i;
-        // all lanes have read base[c] before the class leader advances it
+        if (valid) order[cnt[w][cls] + before] = (int32_t)i;
+        // all lanes have read the start before the class leader advances it
         __builtin_amdgcn_wave_barrier();
-        if (valid && before == 0) base[c] += (uint32_t)__popcll(peers);
+        if (valid && before == 0) cnt[w][cls] += (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -802,7 +826,7 @@ extern "C" int gs4d_tile_order(const int32_t *ranges, int64_t n_tiles, int32_t *
     GS4D_REQUIRE(n_queues >= 0 && n_queues <= 64 && (n_queues == 0 || queues),
                  "gs4d_tile_order: bad queues (at most 64)");
     hipStream_t st = as_stream(stream);
-    tile_order_kernel<<<1, 1024, 0, st>>>(reinterpret_cast<const int2 *>(ranges), n_tiles, order,
+    tile_order_kernel<<<1, ORDER_THREADS, 0, st>>>(reinterpret_cast<const int2 *>(ranges), n_tiles, order,
                                           queues, n_queues);
     GS4D_LAUNCH_CHECK("gs4d_tile_order");
     return GS4D_OK;
