@@ -130,7 +130,9 @@ __device__ __forceinline__ void stage_batch(const float4 *__restrict__ recv,
     }
 }
 
-template <int BATCH>
+// COUNT: count evaluated and blended (pixel, entry) pairs into o.counters
+// (a separate instantiation, so the plain forward carries no counting).
+template <int BATCH, bool COUNT>
 __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__restrict__ rec,
                                                 int64_t n, const uint32_t *__restrict__ vals,
                                                 const int2 *__restrict__ ranges,
@@ -189,8 +191,10 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
             T = blend ? Tn : T;
             last = blend ? start + j : last;
             done = done || stop;
-            n_eval += live ? 1u : 0u;
-            n_blend += blend ? 1u : 0u;
+            if (COUNT) {
+                n_eval += live ? 1u : 0u;
+                n_blend += blend ? 1u : 0u;
+            }
         };
 #pragma unroll
         for (int k = 0; k < BATCH / 64; ++k) {
@@ -241,7 +245,7 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
         if (lane == 0 && s != 0.0f)
             atomicAdd(&o.loss_per_view[ti.v], s * (o.l1_weight / (float)(3 * HW)));
     }
-    if (o.counters) {
+    if (COUNT) {
         const uint32_t e = wave_sum_u32(n_eval);
         const uint32_t bl = wave_sum_u32(n_blend);
         if (lane == 0) {
@@ -251,7 +255,7 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
     }
 }
 
-template <int BATCH>
+template <int BATCH, bool COUNT>
 __global__ void __launch_bounds__(RT_THREADS)
 render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__restrict__ vals,
                   const int2 *__restrict__ ranges, ViewPack vp, gs4d_render_opts o,
@@ -262,8 +266,8 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
     __shared__ float4 sC[BATCH];
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * vp.n_views;
     if (!o.persistent) {
-        render_tile_fwd<BATCH>(blockIdx.x, rec, n, vals, ranges, vp, o, image, T_final, last, sA,
-                               sB, sC);
+        render_tile_fwd<BATCH, COUNT>(blockIdx.x, rec, n, vals, ranges, vp, o, image, T_final,
+                                      last, sA, sB, sC);
         return;
     }
     __shared__ int next;
@@ -274,8 +278,8 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
         const int k = next;
         if (k >= n_tiles) break;
         const int64_t tile = o.order ? o.order[k] : k;
-        render_tile_fwd<BATCH>(tile, rec, n, vals, ranges, vp, o, image, T_final, last, sA, sB,
-                               sC);
+        render_tile_fwd<BATCH, COUNT>(tile, rec, n, vals, ranges, vp, o, image, T_final, last, sA,
+                                      sB, sC);
     }
 }
 
@@ -628,15 +632,25 @@ extern "C" int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals
     }
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const int2 *rg = reinterpret_cast<const int2 *>(ranges);
+    const bool count = o.counters != nullptr;
     switch (o.batch) {
         case 64:
-            render_fwd_kernel<64><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
+            if (count)
+                render_fwd_kernel<64, true><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
+            else
+                render_fwd_kernel<64, false><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
             break;
         case 128:
-            render_fwd_kernel<128><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
+            if (count)
+                render_fwd_kernel<128, true><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
+            else
+                render_fwd_kernel<128, false><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
             break;
         default:
-            render_fwd_kernel<256><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
+            if (count)
+                render_fwd_kernel<256, true><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
+            else
+                render_fwd_kernel<256, false><<<grid, RT_THREADS, 0, st>>>(r4, n, vals, rg, vp, o, image, T_final, last);
             break;
     }
     GS4D_LAUNCH_CHECK("gs4d_render_fwd");

@@ -100,15 +100,37 @@ sse_kernel(const float *__restrict__ x, const float *__restrict__ y, int64_t cou
 
 // ---------------------------------------------------------------- SSIM
 constexpr int SS_R = 5;               // window radius (11 taps)
-constexpr int SS_T = 32;              // output tile edge (256 threads, 4 rows each)
+constexpr int SS_K = 2 * SS_R + 1;
+constexpr int SS_T = 32;              // output tile edge
 constexpr int SS_E = SS_T + 2 * SS_R; // staged edge (42)
-constexpr int SS_RPT = SS_T * SS_T / 256;   // output rows per thread
+constexpr int SS_EP = 44;             // staged row stride (float4-aligned rows)
+constexpr int SS_O = 4;               // adjacent outputs per thread in each pass
+constexpr int SS_W = SS_O + 2 * SS_R; // inputs one thread reads per pass (14)
 constexpr float SS_C1 = 0.01f * 0.01f;
 constexpr float SS_C2 = 0.03f * 0.03f;
+static_assert(SS_T * SS_T / SS_O == 256, "one vertical strip per thread");
 
 struct Win {
-    float g[2 * SS_R + 1];
+    float g[SS_K];
 };
+
+// Both passes are register-blocked: a thread filters SS_O adjacent outputs
+// from the SS_W inputs they share.  Horizontal pass: item (row r, column
+// group j) covers columns 4j..4j+3 of row r, read as four float4 from the
+// staged rows; vertical pass: thread (column c, row group) covers rows
+// 4g..4g+3 of column c.  Taps are summed in the same order as a plain
+// 11-tap loop.
+__device__ __forceinline__ void load_row14(const float *row, int c0, float v[16]) {
+    const float4 *p = reinterpret_cast<const float4 *>(row + c0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const float4 q = p[m];
+        v[4 * m] = q.x;
+        v[4 * m + 1] = q.y;
+        v[4 * m + 2] = q.z;
+        v[4 * m + 3] = q.w;
+    }
+}
 
 // Forward: per pixel SSIM and its partial derivatives with respect to the
 // windowed statistics mu_x, E[x^2], E[xy] (written to three maps).  Each
@@ -121,68 +143,82 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
                 float *__restrict__ P1, float *__restrict__ P2, float *__restrict__ P3,
                 float *__restrict__ part_ssim, float *__restrict__ part_l1, float l1_scale,
                 float *__restrict__ l1_grad) {
-    __shared__ float sx[SS_E][SS_E], sy[SS_E][SS_E];
-    __shared__ float hs[5][SS_E][SS_T];
+    __shared__ __align__(16) float sx[SS_E][SS_EP];
+    __shared__ __align__(16) float sy[SS_E][SS_EP];
+    __shared__ __align__(16) float hs[5][SS_E][SS_T];
     const int t = threadIdx.x;
     const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
     const int64_t plane = (int64_t)blockIdx.z * h * w;
-    for (int i = t; i < SS_E * SS_E; i += 256) {
-        const int r = i / SS_E, c = i - r * SS_E;
+    for (int i = t; i < SS_E * SS_EP; i += 256) {
+        const int r = i / SS_EP, c = i - r * SS_EP;
         const int gy = oy + r, gx = ox + c;
-        const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
+        const bool in = c < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
         sx[r][c] = in ? X[plane + (int64_t)gy * w + gx] : 0.0f;
         sy[r][c] = in ? Y[plane + (int64_t)gy * w + gx] : 0.0f;
     }
     __syncthreads();
-    for (int i = t; i < SS_E * SS_T; i += 256) {
-        const int r = i / SS_T, c = i - r * SS_T;
-        float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+    for (int i = t; i < SS_E * (SS_T / SS_O); i += 256) {
+        const int r = i / (SS_T / SS_O), c0 = (i - r * (SS_T / SS_O)) * SS_O;
+        float xv[16], yv[16];
+        load_row14(sx[r], c0, xv);
+        load_row14(sy[r], c0, yv);
+        float a[SS_O] = {}, b[SS_O] = {}, aa[SS_O] = {}, bb[SS_O] = {}, ab[SS_O] = {};
 #pragma unroll
-        for (int k = 0; k < 2 * SS_R + 1; ++k) {
-            const float xv = sx[r][c + k], yv = sy[r][c + k], g = win.g[k];
-            a += g * xv;
-            b += g * yv;
-            aa += g * xv * xv;
-            bb += g * yv * yv;
-            ab += g * xv * yv;
-        }
-        hs[0][r][c] = a;
-        hs[1][r][c] = b;
-        hs[2][r][c] = aa;
-        hs[3][r][c] = bb;
-        hs[4][r][c] = ab;
-    }
-    __syncthreads();
-    const int c = t % SS_T;
-    float sv = 0.0f, lv = 0.0f;
-#pragma unroll
-    for (int rr = 0; rr < SS_RPT; ++rr) {
-        const int r = t / SS_T + rr * (256 / SS_T);
-        float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < 2 * SS_R + 1; ++k) {
+        for (int k = 0; k < SS_K; ++k) {
             const float g = win.g[k];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) m[q] += g * hs[q][r + k][c];
+            for (int o = 0; o < SS_O; ++o) {
+                const float x = xv[o + k], y = yv[o + k];
+                a[o] += g * x;
+                b[o] += g * y;
+                aa[o] += g * x * x;
+                bb[o] += g * y * y;
+                ab[o] += g * x * y;
+            }
         }
-        const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
+        *reinterpret_cast<float4 *>(&hs[0][r][c0]) = make_float4(a[0], a[1], a[2], a[3]);
+        *reinterpret_cast<float4 *>(&hs[1][r][c0]) = make_float4(b[0], b[1], b[2], b[3]);
+        *reinterpret_cast<float4 *>(&hs[2][r][c0]) = make_float4(aa[0], aa[1], aa[2], aa[3]);
+        *reinterpret_cast<float4 *>(&hs[3][r][c0]) = make_float4(bb[0], bb[1], bb[2], bb[3]);
+        *reinterpret_cast<float4 *>(&hs[4][r][c0]) = make_float4(ab[0], ab[1], ab[2], ab[3]);
+    }
+    __syncthreads();
+    const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
+    float m[5][SS_O] = {};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        float v[SS_W];
+#pragma unroll
+        for (int k = 0; k < SS_W; ++k) v[k] = hs[q][r0 + k][c];
+#pragma unroll
+        for (int k = 0; k < SS_K; ++k) {
+            const float g = win.g[k];
+#pragma unroll
+            for (int o = 0; o < SS_O; ++o) m[q][o] += g * v[o + k];
+        }
+    }
+    float sv = 0.0f, lv = 0.0f;
+    const int gx = blockIdx.x * SS_T + c;
+#pragma unroll
+    for (int o = 0; o < SS_O; ++o) {
+        const int r = r0 + o, gy = blockIdx.y * SS_T + r;
         if (gx < w && gy < h) {
-            const float mx = m[0], my = m[1];
-            const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+            const float mx = m[0][o], my = m[1][o];
+            const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
             const float A1 = 2.f * mx * my + SS_C1, A2 = 2.f * sxy + SS_C2;
             const float B1 = mx * mx + my * my + SS_C1, B2 = sxx + syy + SS_C2;
             const float S = (A1 * A2) / (B1 * B2);
             sv += S;
-            const int64_t o = plane + (int64_t)gy * w + gx;
+            const int64_t po = plane + (int64_t)gy * w + gx;
             if (P1) {
-                P1[o] = S * (2.f * my / A1 - 2.f * mx / B1 - 2.f * my / A2 + 2.f * mx / B2);
-                P2[o] = -S / B2;
-                P3[o] = 2.f * S / A2;
+                P1[po] = S * (2.f * my / A1 - 2.f * mx / B1 - 2.f * my / A2 + 2.f * mx / B2);
+                P2[po] = -S / B2;
+                P3[po] = 2.f * S / A2;
             }
             if (part_l1) {
                 const float d = sx[r + SS_R][c + SS_R] - sy[r + SS_R][c + SS_R];
                 lv += fabsf(d);
-                if (l1_grad) l1_grad[o] = d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f);
+                if (l1_grad) l1_grad[po] = d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f);
             }
         }
     }
@@ -220,51 +256,59 @@ __global__ void __launch_bounds__(256)
 ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h, int w, Win win,
                 float scale, const float *__restrict__ P1, const float *__restrict__ P2,
                 const float *__restrict__ P3, float *__restrict__ dX) {
-    __shared__ float sp[3][SS_E][SS_E];
-    __shared__ float hs[3][SS_E][SS_T];
+    __shared__ __align__(16) float sp[3][SS_E][SS_EP];
+    __shared__ __align__(16) float hs[3][SS_E][SS_T];
     const int t = threadIdx.x;
     const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
     const int64_t plane = (int64_t)blockIdx.z * h * w;
-    for (int i = t; i < SS_E * SS_E; i += 256) {
-        const int r = i / SS_E, c = i - r * SS_E;
+    for (int i = t; i < SS_E * SS_EP; i += 256) {
+        const int r = i / SS_EP, c = i - r * SS_EP;
         const int gy = oy + r, gx = ox + c;
-        const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
+        const bool in = c < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
         const int64_t o = plane + (int64_t)gy * w + gx;
         sp[0][r][c] = in ? P1[o] : 0.0f;
         sp[1][r][c] = in ? P2[o] : 0.0f;
         sp[2][r][c] = in ? P3[o] : 0.0f;
     }
     __syncthreads();
-    for (int i = t; i < SS_E * SS_T; i += 256) {
-        const int r = i / SS_T, c = i - r * SS_T;
-        float a = 0.f, b = 0.f, d = 0.f;
+    for (int i = t; i < SS_E * (SS_T / SS_O); i += 256) {
+        const int r = i / (SS_T / SS_O), c0 = (i - r * (SS_T / SS_O)) * SS_O;
 #pragma unroll
-        for (int k = 0; k < 2 * SS_R + 1; ++k) {
-            const float g = win.g[k];
-            a += g * sp[0][r][c + k];
-            b += g * sp[1][r][c + k];
-            d += g * sp[2][r][c + k];
+        for (int j = 0; j < 3; ++j) {
+            float v[16];
+            load_row14(sp[j][r], c0, v);
+            float a[SS_O] = {};
+#pragma unroll
+            for (int k = 0; k < SS_K; ++k) {
+                const float g = win.g[k];
+#pragma unroll
+                for (int o = 0; o < SS_O; ++o) a[o] += g * v[o + k];
+            }
+            *reinterpret_cast<float4 *>(&hs[j][r][c0]) = make_float4(a[0], a[1], a[2], a[3]);
         }
-        hs[0][r][c] = a;
-        hs[1][r][c] = b;
-        hs[2][r][c] = d;
     }
     __syncthreads();
-    const int c = t % SS_T;
+    const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
+    float q[3][SS_O] = {};
 #pragma unroll
-    for (int rr = 0; rr < SS_RPT; ++rr) {
-        const int r = t / SS_T + rr * (256 / SS_T);
-        float q[3] = {0.f, 0.f, 0.f};
+    for (int j = 0; j < 3; ++j) {
+        float v[SS_W];
 #pragma unroll
-        for (int k = 0; k < 2 * SS_R + 1; ++k) {
+        for (int k = 0; k < SS_W; ++k) v[k] = hs[j][r0 + k][c];
+#pragma unroll
+        for (int k = 0; k < SS_K; ++k) {
             const float g = win.g[k];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) q[j] += g * hs[j][r + k][c];
+            for (int o = 0; o < SS_O; ++o) q[j][o] += g * v[o + k];
         }
-        const int gx = blockIdx.x * SS_T + c, gy = blockIdx.y * SS_T + r;
+    }
+    const int gx = blockIdx.x * SS_T + c;
+#pragma unroll
+    for (int o = 0; o < SS_O; ++o) {
+        const int gy = blockIdx.y * SS_T + r0 + o;
         if (gx < w && gy < h) {
-            const int64_t o = plane + (int64_t)gy * w + gx;
-            dX[o] += scale * (q[0] + 2.f * X[o] * q[1] + Y[o] * q[2]);
+            const int64_t po = plane + (int64_t)gy * w + gx;
+            dX[po] += scale * (q[0][o] + 2.f * X[po] * q[1][o] + Y[po] * q[2][o]);
         }
     }
 }
