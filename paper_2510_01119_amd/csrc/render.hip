@@ -24,8 +24,7 @@ constexpr int RT_WAVES = 4;
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float ALPHA_MAX = 0.99f;
 constexpr float T_EPS = 1e-4f;
-// backward stages 64 Gaussians per round: its per-wave, per-row partial sums
-// then take 36 KB of LDS and four tiles fit on a CU at once
+// backward stages 64 Gaussians per round (per-wave partial sums: 9 KB of LDS)
 constexpr int BWD_BATCH = 64;
 
 struct TileInfo {
@@ -284,9 +283,6 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
 }
 
 // ---------------------------------------------------------------- backward
-// Full wave64 sum with DPP: row_shr 1/2/4/8 leaves each 16-lane row's total
-// in its last lane, row_bcast:15 and row_bcast:31 fold the rows; the total
-// is valid in lane 63 only.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f(float x) {
     // bound_ctrl: a source lane outside the row reads 0, so `x + dpp_f(x)`
@@ -295,65 +291,61 @@ __device__ __forceinline__ float dpp_f(float x) {
         __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
 }
 
-// Sums N values over each 16-lane DPP row (row_shr 1/2/4/8, all N values per
-// stage so consecutive DPP operations are independent); each row's total is
-// valid in its last lane (15, 31, 47, 63).
-template <int N>
-__device__ __forceinline__ void row_totals(float (&x)[N]) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x111, 0xF>(x[q]);
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x112, 0xF>(x[q]);
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x114, 0xF>(x[q]);
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x118, 0xF>(x[q]);
+// Exchange of two registers between wave halves / 16-lane rows (gfx950):
+// swap32 gives x = [x lanes 0-31, y lanes 0-31], y = [x lanes 32-63,
+// y lanes 32-63]; swap16 gives x = [x row 0, y row 0, x row 2, y row 2],
+// y = [x row 1, y row 1, x row 3, y row 3].  x + y afterwards sums two
+// terms at once, each over half of the lanes.
+__device__ __forceinline__ void swap32(float &x, float &y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                    false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
 }
 
-// The nine-term case of row_totals.  After row_shr 1/2/4 lane 15 of a row
-// holds the sum of lanes 8..15 and lane 7 that of lanes 0..7, so the last
-// stage is x += row_ror:8(x): one fused DPP add per term with every lane
-// active (the compiler otherwise moves the add under the row-leader branch
-// and splits it into a DPP move and an add).  Register operands only; the
-// s_nop covers the two wait states a DPP read needs after a VALU write.
-__device__ __forceinline__ void row_totals9(float (&x)[9]) {
+__device__ __forceinline__ void swap16(float &x, float &y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                    false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+
+// Reduce-scatter of the nine gradient terms of one entry over the wave.
+// Terms are paired across the halves (5 swaps + adds, the ninth with zero),
+// then across rows (3 swaps + adds), leaving three registers whose 16-lane
+// row sums are wave totals: lane 15 of row r holds in x[m] the total of
+// term 4m + t(r), t = (0, 2, 1, 3); x[2] carries term 8 in row 0 and zero in
+// the others.  Row sums: after row_shr 1/2/4 (bound_ctrl: lanes shifted in
+// read 0) lane 15 of a row holds the sum of lanes 8..15 and lane 7 that of
+// lanes 0..7, so x += row_ror:8(x) completes it -- one fused DPP add per
+// register with every lane active (register operands only; the s_nop covers
+// the two wait states a DPP read needs after a VALU write).
+__device__ __forceinline__ void wave_scatter9(const float (&d)[9], float (&x)[3]) {
+    float a[5];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) x[q] += dpp_f<0x111, 0xF>(x[q]);
+    for (int k = 0; k < 5; ++k) {
+        float p = d[2 * k], q = k < 4 ? d[2 * k + 1] : 0.0f;
+        swap32(p, q);
+        a[k] = p + q;
+    }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) x[q] += dpp_f<0x112, 0xF>(x[q]);
+    for (int m = 0; m < 3; ++m) {
+        float p = a[2 * m], q = m < 2 ? a[2 * m + 1] : 0.0f;
+        swap16(p, q);
+        x[m] = p + q;
+    }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) x[q] += dpp_f<0x114, 0xF>(x[q]);
+    for (int m = 0; m < 3; ++m) x[m] += dpp_f<0x111, 0xF>(x[m]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) x[m] += dpp_f<0x112, 0xF>(x[m]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) x[m] += dpp_f<0x114, 0xF>(x[m]);
     asm volatile(
         "s_nop 1\n"
         "v_add_f32_dpp %0, %0, %0 row_ror:8 row_mask:0xf bank_mask:0xf\n"
         "v_add_f32_dpp %1, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xf\n"
         "v_add_f32_dpp %2, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        "v_add_f32_dpp %3, %3, %3 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        "v_add_f32_dpp %4, %4, %4 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        "v_add_f32_dpp %5, %5, %5 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        "v_add_f32_dpp %6, %6, %6 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        "v_add_f32_dpp %7, %7, %7 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        "v_add_f32_dpp %8, %8, %8 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
-          "+v"(x[7]), "+v"(x[8]));
-}
-
-// Reduces N independent values at once, one DPP stage at a time across all
-// of them, so consecutive DPP operations never depend on each other.
-template <int N>
-__device__ __forceinline__ void wave_total_lane63(float (&x)[N]) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x111, 0xF>(x[q]);   // row_shr:1
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x112, 0xF>(x[q]);   // row_shr:2
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x114, 0xF>(x[q]);   // row_shr:4
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x118, 0xF>(x[q]);   // row_shr:8
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x142, 0xA>(x[q]);   // row_bcast:15 -> rows 1, 3
-#pragma unroll
-    for (int q = 0; q < N; ++q) x[q] += dpp_f<0x143, 0xC>(x[q]);   // row_bcast:31 -> rows 2, 3
+        : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]));
 }
 
 // PPL = pixels per lane.  The workgroup has 256 / PPL threads; wave w owns
@@ -361,11 +353,11 @@ __device__ __forceinline__ void wave_total_lane63(float (&x)[N]) {
 // for PPL 4).  Each lane folds its PPL pixels' terms for an entry before the
 // cross-lane reduction.
 //
-// Reduction of the nine gradient terms of one entry over one wave: DPP sums
-// over each 16-lane row, then the four row-leader lanes store their row
-// totals into LDS slots part[wave][row][entry][term] (one store instruction
-// per term).  After the batch, each entry's slots are summed and added to
-// HBM with one atomic per term.  A wave skips every entry its block test
+// Reduction of the nine gradient terms of one entry over one wave: a
+// reduce-scatter in registers (wave_scatter9) leaves the wave totals in the
+// four row-leader lanes, which store them into LDS slots
+// part[wave][entry][term].  After the batch, each entry's slots are summed
+// over the waves and added to HBM with one atomic per term.  A wave skips every entry its block test
 // rejects and every entry no lane of it actually blends; the per-wave,
 // per-row "written" masks record which slots hold data.
 template <int BATCH, int PPL>
@@ -374,9 +366,8 @@ struct BwdShared {
     float4 sB[BATCH];
     float4 sC[BATCH];
     uint32_t sG[BATCH];
-    // [wave][row][entry * 9 + term]; each row padded by 4 floats so the four
-    // row leaders' simultaneous stores fall into different banks
-    float part[RT_THREADS / PPL / 64][4][BATCH * 9 + 4];
+    // [wave][entry * 9 + term]
+    float part[RT_THREADS / PPL / 64][BATCH * 9];
     uint64_t written[RT_THREADS / PPL / 64][BATCH / 64];
     int smax;
 };
@@ -454,6 +445,8 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
     float *gview = grad2d + (int64_t)ti.v * n * 9;
     const int drow = lane >> 4;
     const bool row_leader = (lane & 15) == 15;
+    // first term whose wave total this row's leader holds (see wave_scatter9)
+    const int trow = ((drow & 1) << 1) | (drow >> 1);
 
     for (int end = max_last + 1; end > rg.x; end -= BATCH) {
         const int start = max(rg.x, end - BATCH);
@@ -519,10 +512,13 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             }
             if (__ballot(any) == 0) return;   // no lane of this wave blends the entry
             wr[j >> 6] |= 1ull << (j & 63);
-            row_totals9(d);
+            float x[3];
+            wave_scatter9(d, x);
             if (row_leader) {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) part[w][drow][j * 9 + q] = d[q];
+                float *slot = &part[w][j * 9 + trow];
+                slot[0] = x[0];
+                slot[4] = x[1];
+                if (drow == 0) slot[8] = x[2];
             }
         };
 #pragma unroll
@@ -555,9 +551,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             float sum = 0.0f;
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
-                if (written[ww][e >> 6] & bit) {
-                    sum += part[ww][0][i] + part[ww][1][i] + part[ww][2][i] + part[ww][3][i];
-                }
+                if (written[ww][e >> 6] & bit) sum += part[ww][i];
             }
             if (sum != 0.0f) atomicAdd(gview + (int64_t)sG[e] * 9 + q, sum);
         }
