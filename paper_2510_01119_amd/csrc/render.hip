@@ -24,8 +24,8 @@ constexpr int RT_WAVES = 4;
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float ALPHA_MAX = 0.99f;
 constexpr float T_EPS = 1e-4f;
-// backward stages 64 Gaussians per round (per-wave partial sums: 9 KB of LDS)
-constexpr int BWD_BATCH = 64;
+// backward stages 128 Gaussians per round (per-wave partial sums: 18 KB of LDS)
+constexpr int BWD_BATCH = 128;
 
 struct TileInfo {
     int v, tx, ty;
