@@ -18,7 +18,7 @@ import torch
 
 from . import gs4d as G
 from .rasterizer import Rasterizer
-from .train import Trainer, adam_config
+from .train import Trainer, _capture, adam_config
 
 
 def split_frames(n_frames: int):
@@ -122,25 +122,16 @@ class GroupTrainer:
         self.stage_update(k)
 
     def capture(self, groups=None):
-        """Capture every group's step (the argument is accepted for symmetry
-        with Trainer.capture and ignored)."""
+        """Capture every group's step as one HIP graph (the argument is
+        accepted for symmetry with Trainer.capture and ignored)."""
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
-        self.graphs = []
-        for k in range(len(self.groups)):
-            gs = []
-            for stage in (self.stage_forward, self.stage_render_bwd, self.stage_update):
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g, stream=side):
-                    stage(k)
-                gs.append(g)
-            self.graphs.append(gs)
+        self.graphs = [_capture(lambda k=k: self.step(k), side) for k in range(len(self.groups))]
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
 
     def step_graph(self, k):
-        for g in self.graphs[k]:
-            g.replay()
+        self.graphs[k].replay()
 
 
 def run(trainer, schedule, evaluator, eval_every, budget, graph=True, target_psnr=None,

@@ -43,6 +43,14 @@ def adam_config(budget: int, lrs=None) -> G.gs4d_adam_cfg:
     return cfg
 
 
+def _capture(fn, stream):
+    """fn's launches on `stream`, captured as one HIP graph."""
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        fn()
+    return g
+
+
 class Trainer:
     """Single-view training on a fixed set of frames (views [F, 23],
     targets [F, 3, H, W] on the device)."""
@@ -114,34 +122,35 @@ class Trainer:
 
     # ------------------------------------------------------------ graphs
     def capture(self, frames):
-        """Capture each frame's step as three HIP graphs: [preprocess, bin/sort,
-        render, loss], [render backward], [preprocess backward, Adam].  The
-        split lets a caller time the render backward with events between
-        replays.  Every buffer is preallocated, so replays allocate nothing."""
+        """Capture each frame's step as one HIP graph, and again as three:
+        [preprocess, bin/sort, render, loss], [render backward], [preprocess
+        backward, Adam], so that a caller can time the render backward with
+        events between replays.  Every buffer is preallocated, so replays
+        allocate nothing."""
         self.graphs = {}
+        self.whole = {}
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         for f in frames:
-            gs = []
-            for stage in (self.stage_forward, self.stage_render_bwd, self.stage_update):
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g, stream=side):
-                    stage(f)
-                gs.append(g)
-            self.graphs[f] = gs
+            self.whole[f] = _capture(lambda: self.step(f), side)
+            self.graphs[f] = [_capture(lambda st=stage: st(f), side)
+                              for stage in (self.stage_forward, self.stage_render_bwd,
+                                            self.stage_update)]
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
 
     def step_graph(self, f: int, events=None):
         """Replay frame f's captured step; with events=(a, b), a and b are
-        recorded around the render-backward graph."""
+        recorded around the render backward (three graphs), else the step is
+        one graph."""
+        if events is None:
+            self.whole[f].replay()
+            return
         g0, g1, g2 = self.graphs[f]
         g0.replay()
-        if events is not None:
-            events[0].record()
+        events[0].record()
         g1.replay()
-        if events is not None:
-            events[1].record()
+        events[1].record()
         g2.replay()
 
     def loss_value(self) -> float:
@@ -223,28 +232,26 @@ class BatchedTrainer:
         self.stage_backward()
 
     def capture(self):
-        """The step as three HIP graphs ([forward + fused loss], [render
-        backward], [preprocess backward + Adam]) so that the render backward
-        can be timed with events between replays."""
+        """The step as one HIP graph, and again as three ([forward + fused
+        loss], [render backward], [preprocess backward + Adam]) so that the
+        render backward can be timed with events between replays."""
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
-        self.graphs = []
-        for stage in (self.stage_forward, self.stage_render_bwd, self.stage_update):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=side):
-                stage()
-            self.graphs.append(g)
+        self.whole = _capture(self.step, side)
+        self.graphs = [_capture(stage, side)
+                       for stage in (self.stage_forward, self.stage_render_bwd, self.stage_update)]
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
 
     def step_graph(self, events=None):
+        if events is None:
+            self.whole.replay()
+            return
         g0, g1, g2 = self.graphs
         g0.replay()
-        if events is not None:
-            events[0].record()
+        events[0].record()
         g1.replay()
-        if events is not None:
-            events[1].record()
+        events[1].record()
         g2.replay()
 
     def loss_per_view(self):
