@@ -269,16 +269,19 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
                                       last, sA, sB, sC);
         return;
     }
+    // Work list position k: a workgroup's first is its own index, the later
+    // ones come from the counter offset by the grid size, so the launch does
+    // not start with every workgroup hitting one counter (same-address
+    // atomics serialise).
     __shared__ int next;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) next = atomicAdd(o.queue, 1);
-        __syncthreads();
-        const int k = next;
-        if (k >= n_tiles) break;
+    for (int k = blockIdx.x; k < n_tiles;) {
         const int64_t tile = o.order ? o.order[k] : k;
         render_tile_fwd<BATCH, COUNT>(tile, rec, n, vals, ranges, vp, o, image, T_final, last, sA,
                                       sB, sC);
+        __syncthreads();
+        if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(o.queue, 1);
+        __syncthreads();
+        k = next;
     }
 }
 
@@ -571,18 +574,18 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
                                     grad2d, sh);
         return;
     }
-    // persistent: take tiles from the (largest-first) queue until it is empty
+    // persistent: take tiles from the (largest-first) work list until it is
+    // empty, the first one by workgroup index (as in the forward)
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * vp.n_views;
     __shared__ int next;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
-        __syncthreads();
-        const int k = next;
-        if (k >= n_tiles) break;
+    for (int k = blockIdx.x; k < n_tiles;) {
         const int64_t tile = order ? order[k] : k;
         render_tile_bwd<BATCH, PPL>(tile, rec, n, vals, ranges, vp, dL_dimage, T_final, last,
                                     grad2d, sh);
+        __syncthreads();
+        if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(queue, 1);
+        __syncthreads();
+        k = next;
     }
 }
 

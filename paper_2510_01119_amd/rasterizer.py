@@ -49,6 +49,7 @@ class Rasterizer:
         self.n_workgroups = n_workgroups
         self.order = torch.zeros(self.n_tiles, dtype=torch.int32, device=dev)
         self.queues = torch.zeros(2, dtype=torch.int32, device=dev)
+        self._bwd_queue_zeroed = False
         self.order_ws = torch.zeros(G.gs4d_tile_order_workspace_size(self.n_tiles), dtype=torch.uint8,
                                     device=dev)
         # fused per-view L1 (set_target)
@@ -111,7 +112,16 @@ class Rasterizer:
         return o
 
     def tile_order(self):
+        # also zeroes both work counters, so the next backward needs no reset
         G.gs4d_tile_order(self.ranges, self.order, self.queues, self.order_ws)
+        self._bwd_queue_zeroed = True
+
+    def _bwd_queue(self):
+        """A zero work counter for a persistent backward: left zero by the tile
+        ordering of the forward just before it, else reset here."""
+        if not self._bwd_queue_zeroed:
+            G.gs4d_fill_u32(self.queues[1:2], 0)
+        self._bwd_queue_zeroed = False
 
     def render(self, opts=None):
         if opts is None:
@@ -121,6 +131,7 @@ class Rasterizer:
                     self.tile_order()
                 else:
                     G.gs4d_fill_u32(self.queues, 0)
+                    self._bwd_queue_zeroed = True
         if self.counters is not None:
             G.gs4d_fill_u32(self.counters.view(torch.int32), 0)
             opts.counters = self.counters.data_ptr()
@@ -135,7 +146,7 @@ class Rasterizer:
 
     def render_bwd_2d(self, dL_dimage):
         if self.persistent:
-            G.gs4d_fill_u32(self.queues[1:2], 0)     # fresh work counter for this launch
+            self._bwd_queue()
         G.gs4d_render_bwd_2d(self.rec, self.n, self.vals, self.ranges, self.cviews, dL_dimage,
                              self.T_final, self.last, self.grad2d, self._opts(1))
 
@@ -148,7 +159,7 @@ class Rasterizer:
 
     def backward(self, params: torch.Tensor, dL_dimage: torch.Tensor):
         if self.persistent:
-            G.gs4d_fill_u32(self.queues[1:2], 0)
+            self._bwd_queue()
         G.gs4d_render_bwd(params, self.rec, self.touched, self.vals, self.ranges, self.cviews,
                           dL_dimage.contiguous(), self.T_final, self.last, self.dparams,
                           grad2d=self.grad2d, opts=self._opts(1))
