@@ -115,7 +115,10 @@ int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_t *touched,
 /* Render options.  Zero-initialise and set what is needed. */
 typedef struct gs4d_render_opts {
     int32_t batch;          /* Gaussians staged in LDS per round: 64, 128 or 256 (0 -> 256) */
-    int32_t persistent;     /* 1: persistent launch over a largest-first (view, tile) queue */
+    int32_t persistent;     /* 0: one workgroup per (view, tile); 1: persistent workgroups
+                               taking work-list positions from `queue`; 2: persistent with a
+                               static assignment (workgroup i takes positions i and
+                               2G-1-i of every 2G, G workgroups), no queue            */
     int32_t n_workgroups;   /* persistent launch size (0 -> 4 per CU)                       */
     int32_t reserved;
     const float *target;    /* optional [n_views][3][H][W]: fused per-view L1 loss          */
@@ -124,7 +127,7 @@ typedef struct gs4d_render_opts {
     float *dL_dimage;       /* out [n_views][3][H][W] dL1/dimage * l1_weight, needs target  */
     uint64_t *counters;     /* optional out [2], accumulated: evaluated entries, blends     */
     const int32_t *order;   /* optional [n_views*tiles_per_view] tile processing order (persistent) */
-    int32_t *queue;         /* device int32 work counter for persistent mode (caller zeroes) */
+    int32_t *queue;         /* device int32 work counter for persistent mode 1 (caller zeroes) */
 } gs4d_render_opts;
 
 /* ---------------------------------------------------------------------------

@@ -3,8 +3,8 @@
 Times the forward's LDS batch size (64 / 128 / 256 Gaussians per round),
 the backward's block shape (1 / 2 / 4 pixels per lane = 256 / 128 / 64
 threads) and the launch mode (one workgroup per tile, or persistent
-workgroups pulling tiles from a counter in index order or largest first) on
-the caller's live buffers with HIP events, keeps the fastest, and caches the
+workgroups pulling tiles from a counter in index order or largest first, or
+taking a fixed share of the largest-first order) on the caller's live buffers with HIP events, keeps the fastest, and caches the
 choice per (device, image size, view count, Gaussian-count bucket).  Every
 choice renders the same image (the forward bit for bit); only the speed
 differs.
@@ -62,14 +62,14 @@ def tune(r, params, dL_dimage, verbose=False):
         G.gs4d_set_bwd_variant(best_p)
         # launch mode: one workgroup per tile, or persistent workgroups taking
         # tiles from a counter in index order or largest first (the order costs
-        # a small sort per frame); timed as forward + backward
-        keep = (r.persistent, r.order_tiles)
+        # a small sort per frame), or largest first with a static assignment
+        # and no counter; timed as forward + backward
+        keep = (r.persistent, r.order_tiles, r.static_schedule)
         modes = {}
-        for name, pers, ordered in (("grid", False, True), ("persistent", True, False),
-                                    ("persistent_sorted", True, True)):
-            r.persistent, r.order_tiles = pers, ordered
+        for name in MODES:
+            _set_mode(r, name)
             modes[name] = _time(lambda: (r.render(), r.render_bwd_2d(dL_dimage)))
-        r.persistent, r.order_tiles = keep
+        r.persistent, r.order_tiles, r.static_schedule = keep
         best_m = min(modes, key=modes.get)
         choice = {"batch": best_b, "bwd_pixels_per_lane": best_p, "mode": best_m,
                   "fwd_ms": {str(k): round(v, 4) for k, v in fwd.items()},
@@ -80,6 +80,14 @@ def tune(r, params, dL_dimage, verbose=False):
             print(f"autotune {key}: {json.dumps(choice)}", flush=True)
     r.batch = choice["batch"]
     G.gs4d_set_bwd_variant(choice["bwd_pixels_per_lane"])
-    m = choice.get("mode", "grid")
-    r.persistent, r.order_tiles = m != "grid", m == "persistent_sorted"
+    _set_mode(r, choice.get("mode", "grid"))
     return choice
+
+
+MODES = ("grid", "persistent", "persistent_sorted", "persistent_static")
+
+
+def _set_mode(r, name):
+    r.persistent = name != "grid"
+    r.order_tiles = name in ("persistent_sorted", "persistent_static")
+    r.static_schedule = name == "persistent_static"

@@ -129,6 +129,15 @@ __device__ __forceinline__ void stage_batch(const float4 *__restrict__ recv,
     }
 }
 
+// Static schedule of a persistent launch (mode 2): round r hands the
+// workgroups the work-list positions base .. base + gridDim - 1, base =
+// r * gridDim, workgroup i taking the i-th of them in even rounds and the
+// (gridDim - 1 - i)-th in odd ones, so over a largest-first list each
+// workgroup's long and short tiles alternate.  No counter is touched.
+__device__ __forceinline__ int64_t static_position(int64_t r, int64_t base) {
+    return base + ((r & 1) ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x);
+}
+
 // COUNT: count evaluated and blended (pixel, entry) pairs into o.counters
 // (a separate instantiation, so the plain forward carries no counting).
 template <int BATCH, bool COUNT>
@@ -267,6 +276,18 @@ render_fwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
     if (!o.persistent) {
         render_tile_fwd<BATCH, COUNT>(blockIdx.x, rec, n, vals, ranges, vp, o, image, T_final,
                                       last, sA, sB, sC);
+        return;
+    }
+    if (o.persistent == 2) {
+        for (int64_t r = 0, base = 0; base < n_tiles; ++r, base += gridDim.x) {
+            const int64_t k = static_position(r, base);
+            if (k < n_tiles) {
+                const int64_t tile = o.order ? o.order[k] : k;
+                render_tile_fwd<BATCH, COUNT>(tile, rec, n, vals, ranges, vp, o, image, T_final,
+                                              last, sA, sB, sC);
+            }
+            __syncthreads();
+        }
         return;
     }
     // Work list position k: a workgroup's first is its own index, the later
@@ -574,9 +595,21 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
                                     grad2d, sh);
         return;
     }
+    const int64_t n_tiles = (int64_t)vp.tiles_per_view * vp.n_views;
+    if (persistent == 2) {
+        for (int64_t r = 0, base = 0; base < n_tiles; ++r, base += gridDim.x) {
+            const int64_t k = static_position(r, base);
+            if (k < n_tiles) {
+                const int64_t tile = order ? order[k] : k;
+                render_tile_bwd<BATCH, PPL>(tile, rec, n, vals, ranges, vp, dL_dimage, T_final,
+                                            last, grad2d, sh);
+            }
+            __syncthreads();
+        }
+        return;
+    }
     // persistent: take tiles from the (largest-first) work list until it is
     // empty, the first one by workgroup index (as in the forward)
-    const int64_t n_tiles = (int64_t)vp.tiles_per_view * vp.n_views;
     __shared__ int next;
     for (int k = blockIdx.x; k < n_tiles;) {
         const int64_t tile = order ? order[k] : k;
@@ -617,7 +650,8 @@ extern "C" int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals
                  "gs4d_render_fwd: batch must be 64, 128 or 256");
     GS4D_REQUIRE(!(o.loss_per_view || o.dL_dimage) || o.target,
                  "gs4d_render_fwd: loss outputs need a target");
-    GS4D_REQUIRE(!o.persistent || o.queue, "gs4d_render_fwd: persistent mode needs a queue counter");
+    GS4D_REQUIRE(o.persistent >= 0 && o.persistent <= 2, "gs4d_render_fwd: persistent must be 0, 1 or 2");
+    GS4D_REQUIRE(o.persistent != 1 || o.queue, "gs4d_render_fwd: persistent mode 1 needs a queue counter");
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
     hipStream_t st = as_stream(stream);
     unsigned grid = (unsigned)n_tiles;
@@ -683,7 +717,8 @@ extern "C" int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *v
     GS4D_REQUIRE(n == 0 || grad2d, "gs4d_render_bwd_2d: null grad2d");
     gs4d_render_opts o{};
     if (opts) o = *opts;
-    GS4D_REQUIRE(!o.persistent || o.queue, "gs4d_render_bwd_2d: persistent mode needs a queue counter");
+    GS4D_REQUIRE(o.persistent >= 0 && o.persistent <= 2, "gs4d_render_bwd_2d: persistent must be 0, 1 or 2");
+    GS4D_REQUIRE(o.persistent != 1 || o.queue, "gs4d_render_bwd_2d: persistent mode 1 needs a queue counter");
     if (n == 0) return GS4D_OK;
     hipStream_t st = as_stream(stream);
     GS4D_TRY(launch_fill<float>(grad2d, 0.0f, n * n_views * 9, st));
@@ -697,7 +732,7 @@ extern "C" int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *v
     }
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const int2 *rg = reinterpret_cast<const int2 *>(ranges);
-    const int ps = o.persistent ? 1 : 0;
+    const int ps = o.persistent;
     switch (g_bwd_ppl) {
         case 1:
             render_bwd_kernel<BWD_BATCH, 1><<<grid, RT_THREADS, 0, st>>>(

@@ -50,6 +50,9 @@ class Rasterizer:
         self.order = torch.zeros(self.n_tiles, dtype=torch.int32, device=dev)
         self.queues = torch.zeros(2, dtype=torch.int32, device=dev)
         self._bwd_queue_zeroed = False
+        # persistent launches: fixed assignment of work-list positions instead
+        # of a shared work counter
+        self.static_schedule = False
         self.order_ws = torch.zeros(G.gs4d_tile_order_workspace_size(self.n_tiles), dtype=torch.uint8,
                                     device=dev)
         # fused per-view L1 (set_target)
@@ -105,7 +108,7 @@ class Rasterizer:
         o = G.gs4d_render_opts()
         o.batch = self.batch
         if self.persistent:
-            o.persistent = 1
+            o.persistent = 2 if self.static_schedule else 1
             o.n_workgroups = self.n_workgroups
             o.order = self.order.data_ptr() if self.order_tiles else 0
             o.queue = self.queues.data_ptr() + 4 * queue_index

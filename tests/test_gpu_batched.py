@@ -2,7 +2,8 @@
 largest-first tile queue, the fused per-view L1 loss, and the batched
 training step captured as a HIP graph.
 
-* the persistent forward renders the same bits as one workgroup per tile,
+* the persistent forward (counter or fixed assignment) renders the same
+  bits as one workgroup per tile,
   for every LDS batch size, and matches the oracle's 8-view image;
 * the persistent backward matches the per-tile backward;
 * gs4d_tile_order yields the tiles by descending size class (eight per
@@ -34,8 +35,10 @@ def small_batch():
     return p, vs
 
 
-def _render(p, vs, persistent, batch=256, target=None):
+def _render(p, vs, persistent, batch=256, target=None, static=False):
     r = Rasterizer(p.shape[1], vs, persistent=persistent, batch=batch)
+    if static:
+        r.order_tiles, r.static_schedule = True, True
     P = torch.from_numpy(p).cuda()
     if target is not None:
         r.set_target(target)
@@ -47,11 +50,11 @@ def _render(p, vs, persistent, batch=256, target=None):
 def test_persistent_forward_bitwise(small_batch):
     p, vs = small_batch
     ref, _ = _render(p, vs, persistent=False)
-    for batch in (64, 128, 256):
-        r, _ = _render(p, vs, persistent=True, batch=batch)
-        assert torch.equal(r.image, ref.image), batch
-        assert torch.equal(r.T_final, ref.T_final), batch
-        assert torch.equal(r.last, ref.last), batch
+    for batch, static in ((64, False), (128, False), (256, False), (128, True), (256, True)):
+        r, _ = _render(p, vs, persistent=True, batch=batch, static=static)
+        assert torch.equal(r.image, ref.image), (batch, static)
+        assert torch.equal(r.T_final, ref.T_final), (batch, static)
+        assert torch.equal(r.last, ref.last), (batch, static)
     # against the oracle (8 views in one call)
     o = oracle.forward(p, vs, "f32")
     assert np.array_equal(ref.ranges.cpu().numpy(), o["ranges"])
@@ -106,9 +109,12 @@ def test_persistent_backward(small_batch):
     r, _ = _render(p, vs, persistent=True)
     d = r.backward(P, wt).cpu().numpy()
     d2 = r.backward(P, wt).cpu().numpy()      # queue counters are re-armed per call
+    rs, _ = _render(p, vs, persistent=True, static=True)
+    ds = rs.backward(P, wt).cpu().numpy()     # fixed assignment, no counter
     # same arithmetic, only the order of the per-Gaussian atomic sums differs
     _grad_bar(d, dref)
     _grad_bar(d2, dref)
+    _grad_bar(ds, dref)
     # and the oracle's FP64 gradient (Gaussians seen at threshold pixels exempted)
     o = oracle.forward(p, vs, "f32")
     g, _ = oracle.backward(p, vs, w.astype(np.float64), fwd=o)
