@@ -303,7 +303,9 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "launch": ("hip graphs" if use_graph else "eager") + f", {choice.get('mode', 'grid')} (autotuned)",
         "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"],
-                     "mode": choice.get("mode"), "mode_ms": choice.get("mode_ms")},
+                     "mode": choice.get("mode"), "mode_ms": choice.get("mode_ms"),
+                     "workgroups_per_cu": choice.get("workgroups_per_cu"),
+                     "wg_ms": choice.get("wg_ms")},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -440,7 +442,9 @@ def run_batched(args, dev):
         "pairs_per_step": pairs,
         "launch": f"hip graphs, {choice.get('mode', 'grid')} (autotuned)",
         "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"],
-                     "mode": choice.get("mode"), "mode_ms": choice.get("mode_ms")},
+                     "mode": choice.get("mode"), "mode_ms": choice.get("mode_ms"),
+                     "workgroups_per_cu": choice.get("workgroups_per_cu"),
+                     "wg_ms": choice.get("wg_ms")},
         "loss_per_view": [round(float(x), 5) for x in tr.loss_per_view()],
         "roofline": roof,
     }

@@ -69,22 +69,39 @@ def tune(r, params, dL_dimage, verbose=False):
         for name in MODES:
             _set_mode(r, name)
             modes[name] = _time(lambda: (r.render(), r.render_bwd_2d(dL_dimage)))
-        r.persistent, r.order_tiles, r.static_schedule = keep
         best_m = min(modes, key=modes.get)
+        # persistent modes: resident workgroups per compute unit
+        per_cu = {}
+        if best_m != "grid":
+            _set_mode(r, best_m)
+            cus = torch.cuda.get_device_properties(r.device).multi_processor_count
+            keep_wg = r.n_workgroups
+            for k in WG_PER_CU:
+                r.n_workgroups = k * cus
+                per_cu[k] = _time(lambda: (r.render(), r.render_bwd_2d(dL_dimage)))
+            r.n_workgroups = keep_wg
+        r.persistent, r.order_tiles, r.static_schedule = keep
+        best_wg = min(per_cu, key=per_cu.get) if per_cu else 0
         choice = {"batch": best_b, "bwd_pixels_per_lane": best_p, "mode": best_m,
+                  "workgroups_per_cu": best_wg,
                   "fwd_ms": {str(k): round(v, 4) for k, v in fwd.items()},
                   "bwd_ms": {str(k): round(v, 4) for k, v in bwd.items()},
-                  "mode_ms": {k: round(v, 4) for k, v in modes.items()}}
+                  "mode_ms": {k: round(v, 4) for k, v in modes.items()},
+                  "wg_ms": {str(k): round(v, 4) for k, v in per_cu.items()}}
         _CACHE[key] = choice
         if verbose:
             print(f"autotune {key}: {json.dumps(choice)}", flush=True)
     r.batch = choice["batch"]
     G.gs4d_set_bwd_variant(choice["bwd_pixels_per_lane"])
     _set_mode(r, choice.get("mode", "grid"))
+    if choice.get("workgroups_per_cu"):
+        r.n_workgroups = choice["workgroups_per_cu"] * torch.cuda.get_device_properties(
+            r.device).multi_processor_count
     return choice
 
 
 MODES = ("grid", "persistent", "persistent_sorted", "persistent_static")
+WG_PER_CU = (4, 6, 8)
 
 
 def _set_mode(r, name):
