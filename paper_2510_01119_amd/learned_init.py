@@ -313,13 +313,14 @@ def main(argv=None):
     t.add_argument("--batch", type=int, default=8192)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--seed", type=int, default=0)
+    from . import pipeline as P
     e = sub.add_parser("eval")
     e.add_argument("--seeds", required=True)
     e.add_argument("--model", default=MODEL_PATH)
     e.add_argument("--out", default=None)
-    e.add_argument("--budget", type=int, default=900)
-    e.add_argument("--lr-mult", type=float, default=4.0)
-    e.add_argument("--decay", type=float, default=0.1)
+    e.add_argument("--budget", type=int, default=P.BATCHED_BUDGET)
+    e.add_argument("--lr-mult", type=float, default=P.BATCHED_LR_MULT)
+    e.add_argument("--decay", type=float, default=P.BATCHED_DECAY)
     e.add_argument("--group", type=int, default=8)
     e.add_argument("--gain-only", action="store_true")
     args = ap.parse_args(argv)
