@@ -321,7 +321,7 @@ def main(argv=None):
     e.add_argument("--budget", type=int, default=P.BATCHED_BUDGET)
     e.add_argument("--lr-mult", type=float, default=P.BATCHED_LR_MULT)
     e.add_argument("--decay", type=float, default=P.BATCHED_DECAY)
-    e.add_argument("--group", type=int, default=8)
+    e.add_argument("--group", type=int, default=P.BATCHED_GROUP)
     e.add_argument("--gain-only", action="store_true")
     args = ap.parse_args(argv)
     {"gen": cmd_gen, "train": cmd_train, "eval": cmd_eval}[args.cmd](args)

@@ -206,15 +206,18 @@ def batched_run(params0, views, images, train_frames, evaluator, budget, lr_mult
     return hist, reached, tr
 
 
-# Batched-form schedule chosen on validation scenes 950-951 (neither training
-# scenes of the network nor test scenes) from multipliers 2-16, decays
-# 0.01-0.1 and budgets 600-900: rates x7, all decayed to 0.03x over at most
-# 900 steps (x16 diverges; shorter budgets miss the target).
-BATCHED_LR_MULT, BATCHED_DECAY, BATCHED_BUDGET = 7.0, 0.03, 900
+# Batched-form settings chosen on validation scenes 950-951 (neither training
+# scenes of the network nor test scenes) for the time to reach the plain
+# form's PSNR, over frames per step 2-16, rate multipliers 2-16, decays
+# 0.01-0.1 and budgets 600-2500: four frames per step, rates x6, all decayed
+# to 0.03x over at most 1,500 steps (larger groups need more frame-iterations,
+# x16 diverges, short budgets miss the target).
+BATCHED_GROUP, BATCHED_LR_MULT, BATCHED_DECAY, BATCHED_BUDGET = 4, 6.0, 0.03, 1500
 
 
 def time_to_psnr(sc, images, params0, pruned, model=None, plain_budget=5000,
-                 budget=BATCHED_BUDGET, lr_mult=BATCHED_LR_MULT, decay=BATCHED_DECAY, group=8,
+                 budget=BATCHED_BUDGET, lr_mult=BATCHED_LR_MULT, decay=BATCHED_DECAY,
+                 group=BATCHED_GROUP,
                  seed=0, log=None):
     """The plain single-view form (heuristic init, `plain_budget` steps) fixes
     the reference PSNR on the held-out frames; the batched form from the
