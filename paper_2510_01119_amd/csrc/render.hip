@@ -1,9 +1,13 @@
 // Per-tile alpha compositing, forward and backward (the Gaussian-splatting
 // renderer of Sec. 3.1; the backward of Table B-1 "Backward").
 //
-// One workgroup = one 16x16 tile = 256 threads = 4 wave64, one pixel per
-// thread.  The tile's sorted Gaussians are staged through LDS in batches of
-// up to 256 records; every thread then walks the batch with broadcast LDS
+// A workgroup renders one 16x16 tile at a time: one workgroup per tile, or
+// persistent workgroups walking the (view, tile) work list (from a shared
+// counter, or a fixed share of it).  Its four wave64 each own a pixel block
+// of the tile (8x8 at one pixel per lane; the backward's 2- and 4-pixel-per-
+// lane variants use 8x16 and 16x16 with 128 and 64 threads).  The tile's
+// sorted Gaussians are staged through LDS in batches; each wave walks the
+// entries whose alpha >= 1/255 ellipse meets its block, with broadcast LDS
 // reads.  Early termination: a pixel stops when its transmittance would fall
 // below 1e-4; the workgroup leaves the tile as soon as no pixel is active.
 //
