@@ -94,3 +94,25 @@ def test_workspace_queries(lib):
     assert lib.gs4d_render_bwd_workspace_size(1000, 2) >= 1000 * 2 * 9 * 4
     assert lib.gs4d_grid_prune_workspace_size(10 ** 6, 5) > 10 ** 6 * 24
     assert lib.gs4d_ssim_workspace_size(1, 3, 64, 64) >= 3 * 3 * 64 * 64 * 4
+
+
+def test_workspace_sizes_monotone(lib):
+    """Workspace sizes never shrink as the capacity grows, also across the
+    sizes where the radix sort and the scans switch to longer blocks (a
+    smaller input may use shorter blocks, hence more block counts)."""
+    caps = sorted({c + d for c in (1 << 10, 1 << 18, 1 << 20, 1 << 22, 1 << 24)
+                   for d in (-1, 0, 1)})
+    prev = 0
+    for cap in caps:
+        ws = lib.gs4d_bin_sort_workspace_size(1 << 17, 1, cap)
+        assert ws >= prev, cap
+        # the sort keeps one 256-count histogram per block of at most
+        # 4,096 keys, at least
+        assert ws >= cap * 12 + (cap // 4096) * 256 * 4, cap
+        prev = ws
+    for f in (lambda m: lib.gs4d_grid_prune_workspace_size(m, 3), lib.gs4d_knn8_workspace_size):
+        prev = 0
+        for m in caps:
+            ws = f(m)
+            assert ws >= prev, m
+            prev = ws
