@@ -339,41 +339,53 @@ __device__ __forceinline__ void swap16(float &x, float &y) {
 }
 
 // Reduce-scatter of the nine gradient terms of one entry over the wave.
-// Terms are paired across the halves (5 swaps + adds, the ninth with zero),
-// then across rows (3 swaps + adds), leaving three registers whose 16-lane
-// row sums are wave totals: lane 15 of row r holds in x[m] the total of
-// term 4m + t(r), t = (0, 2, 1, 3); x[2] carries term 8 in row 0 and zero in
-// the others.  Row sums: after row_shr 1/2/4 (bound_ctrl: lanes shifted in
-// read 0) lane 15 of a row holds the sum of lanes 8..15 and lane 7 that of
-// lanes 0..7, so x += row_ror:8(x) completes it -- one fused DPP add per
-// register with every lane active (register operands only; the s_nop covers
-// the two wait states a DPP read needs after a VALU write).
+// Terms 0-7 are paired across the halves (4 swaps + adds), then across rows
+// (2 swaps + adds), leaving two registers whose 16-lane row sums are wave
+// totals: lane 15 of row r holds in x[m] the total of term 4m + t(r),
+// t = (0, 2, 1, 3).  Row sums: after row_shr 1/2/4 (bound_ctrl: lanes
+// shifted in read 0) lane 15 of a row holds the sum of lanes 8..15 and lane
+// 7 that of lanes 0..7, so x += row_ror:8(x) completes it -- one fused DPP
+// add per register with every lane active (register operands only; the
+// s_nop covers the two wait states a DPP read needs after a VALU write).
+// Term 8 is summed on its own (row_shr 1/2/4/8, then row_bcast:15 into rows
+// 1 and 3 and row_bcast:31 into rows 2 and 3): its total ends in lane 63,
+// returned in x[2].
 __device__ __forceinline__ void wave_scatter9(const float (&d)[9], float (&x)[3]) {
-    float a[5];
+    float a[4];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        float p = d[2 * k], q = k < 4 ? d[2 * k + 1] : 0.0f;
+    for (int k = 0; k < 4; ++k) {
+        float p = d[2 * k], q = d[2 * k + 1];
         swap32(p, q);
         a[k] = p + q;
     }
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        float p = a[2 * m], q = m < 2 ? a[2 * m + 1] : 0.0f;
+    for (int m = 0; m < 2; ++m) {
+        float p = a[2 * m], q = a[2 * m + 1];
         swap16(p, q);
         x[m] = p + q;
     }
-#pragma unroll
-    for (int m = 0; m < 3; ++m) x[m] += dpp_f<0x111, 0xF>(x[m]);
-#pragma unroll
-    for (int m = 0; m < 3; ++m) x[m] += dpp_f<0x112, 0xF>(x[m]);
-#pragma unroll
-    for (int m = 0; m < 3; ++m) x[m] += dpp_f<0x114, 0xF>(x[m]);
+    float e = d[8];
+    x[0] += dpp_f<0x111, 0xF>(x[0]);
+    x[1] += dpp_f<0x111, 0xF>(x[1]);
+    e += dpp_f<0x111, 0xF>(e);
+    x[0] += dpp_f<0x112, 0xF>(x[0]);
+    x[1] += dpp_f<0x112, 0xF>(x[1]);
+    e += dpp_f<0x112, 0xF>(e);
+    x[0] += dpp_f<0x114, 0xF>(x[0]);
+    x[1] += dpp_f<0x114, 0xF>(x[1]);
+    e += dpp_f<0x114, 0xF>(e);
+    e += dpp_f<0x118, 0xF>(e);   // row_shr:8 -> lane 15 of each row: the row's sum
+    // rows outside a DPP row_mask are not written, so the broadcasts add
+    // into rows 1 and 3, then 2 and 3 only
     asm volatile(
         "s_nop 1\n"
         "v_add_f32_dpp %0, %0, %0 row_ror:8 row_mask:0xf bank_mask:0xf\n"
         "v_add_f32_dpp %1, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        "v_add_f32_dpp %2, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xf\n"
-        : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]));
+        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0xa bank_mask:0xf\n"
+        "s_nop 1\n"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:31 row_mask:0xc bank_mask:0xf\n"
+        : "+v"(x[0]), "+v"(x[1]), "+v"(e));
+    x[2] = e;
 }
 
 // PPL = pixels per lane.  The workgroup has 256 / PPL threads; wave w owns
@@ -546,7 +558,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
                 float *slot = &part[w][j * 9 + trow];
                 slot[0] = x[0];
                 slot[4] = x[1];
-                if (drow == 0) slot[8] = x[2];
+                if (drow == 3) part[w][j * 9 + 8] = x[2];   // lane 63
             }
         };
 #pragma unroll
