@@ -487,6 +487,10 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
     const bool row_leader = (lane & 15) == 15;
     // first term whose wave total this row's leader holds (see wave_scatter9)
     const int trow = ((drow & 1) << 1) | (drow >> 1);
+    // this wave's partial slots as an LDS pointer, so per-entry offsets are
+    // 32-bit adds
+    __attribute__((address_space(3))) float *wpart =
+        (__attribute__((address_space(3))) float *)&part[w][0];
 
     for (int end = max_last + 1; end > rg.x; end -= BATCH) {
         const int start = max(rg.x, end - BATCH);
@@ -555,10 +559,10 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             float x[3];
             wave_scatter9(d, x);
             if (row_leader) {
-                float *slot = &part[w][j * 9 + trow];
-                slot[0] = x[0];
-                slot[4] = x[1];
-                if (drow == 3) part[w][j * 9 + 8] = x[2];   // lane 63
+                const int o = j * 9 + trow;
+                wpart[o] = x[0];
+                wpart[o + 4] = x[1];
+                if (drow == 3) wpart[o + 5] = x[2];   // lane 63: term 8 (t(3) = 3)
             }
         };
 #pragma unroll
