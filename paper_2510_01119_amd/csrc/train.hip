@@ -234,9 +234,10 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
 // One block: out[0] += a * sum(pa) + b * sum(pb) + c (pb may be NULL); with
 // overwrite set the output is replaced instead of accumulated.  Partial
 // sums are added in a fixed order, so the result is deterministic.
-__global__ void __launch_bounds__(256)
-partial_sum_kernel(const float *__restrict__ pa, const float *__restrict__ pb, int count, float a,
-                   float b, float c, float *__restrict__ out, int overwrite) {
+__device__ __forceinline__ void sum_partials(const float *__restrict__ pa,
+                                             const float *__restrict__ pb, int count, float a,
+                                             float b, float c, float *__restrict__ out,
+                                             int overwrite) {
     float sa = 0.0f, sb = 0.0f;
     for (int i = threadIdx.x; i < count; i += 256) {
         sa += pa[i];
@@ -250,12 +251,30 @@ partial_sum_kernel(const float *__restrict__ pa, const float *__restrict__ pb, i
     }
 }
 
+__global__ void __launch_bounds__(256)
+partial_sum_kernel(const float *__restrict__ pa, const float *__restrict__ pb, int count, float a,
+                   float b, float c, float *__restrict__ out, int overwrite) {
+    sum_partials(pa, pb, count, a, b, c, out, overwrite);
+}
+
+// The final loss sum of partial_sum_kernel, done instead by the first block
+// of the SSIM backward before its own tile (the partials are complete once
+// the forward has finished; no block waits on another).
+struct LossSum {
+    const float *pa, *pb;
+    int count;
+    float a, b, c;
+    float *out;   // NULL: nothing to sum
+};
+
 // Backward: dSSIM/dx(q) = (G*P1)(q) + 2 x(q) (G*P2)(q) + y(q) (G*P3)(q),
 // the window being symmetric (its adjoint is itself).
 __global__ void __launch_bounds__(256)
 ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h, int w, Win win,
                 float scale, const float *__restrict__ P1, const float *__restrict__ P2,
-                const float *__restrict__ P3, float *__restrict__ dX) {
+                const float *__restrict__ P3, float *__restrict__ dX, LossSum ls) {
+    if (ls.out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
+        sum_partials(ls.pa, ls.pb, ls.count, ls.a, ls.b, ls.c, ls.out, 1);
     __shared__ __align__(16) float sp[3][SS_E][SS_EP];
     __shared__ __align__(16) float hs[3][SS_E][SS_T];
     const int t = threadIdx.x;
@@ -425,7 +444,7 @@ extern "C" int gs4d_ssim(const float *img, const float *target, int32_t b, int32
     }
     if (dL_dimg) {
         ssim_bwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, weight / (float)count, S.P1,
-                                                S.P2, S.P3, dL_dimg);
+                                                S.P2, S.P3, dL_dimg, LossSum{});
         GS4D_LAUNCH_CHECK("gs4d_ssim bwd");
     }
     return GS4D_OK;
@@ -451,14 +470,17 @@ extern "C" int gs4d_photometric_loss(const float *img, const float *target, int3
     ssim_fwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, S.P1, S.P2, S.P3, S.part_ssim,
                                             S.part_l1, w_l1 * inv, dL_dimg);
     GS4D_LAUNCH_CHECK("gs4d_photometric_loss fwd");
-    // loss = w_l1 mean|x - y| + w_ssim (1 - mean SSIM)
-    partial_sum_kernel<<<1, 256, 0, st>>>(S.part_l1, S.part_ssim, (int)(S.grid.x * S.grid.y * S.grid.z),
-                                          w_l1 * inv, -w_ssim * inv, w_ssim, loss, 1);
-    GS4D_LAUNCH_CHECK("gs4d_photometric_loss sum");
+    // loss = w_l1 mean|x - y| + w_ssim (1 - mean SSIM), summed by the first
+    // block of the backward (or its own launch when there is no backward)
+    const LossSum ls{S.part_l1, S.part_ssim, (int)(S.grid.x * S.grid.y * S.grid.z), w_l1 * inv,
+                     -w_ssim * inv, w_ssim, loss};
     if (w_ssim != 0.0f) {
         ssim_bwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, -w_ssim * inv, S.P1, S.P2,
-                                                S.P3, dL_dimg);
+                                                S.P3, dL_dimg, ls);
         GS4D_LAUNCH_CHECK("gs4d_photometric_loss bwd");
+    } else {
+        partial_sum_kernel<<<1, 256, 0, st>>>(ls.pa, ls.pb, ls.count, ls.a, ls.b, ls.c, loss, 1);
+        GS4D_LAUNCH_CHECK("gs4d_photometric_loss sum");
     }
     return GS4D_OK;
 }
