@@ -642,6 +642,17 @@ render_bwd_kernel(const float4 *__restrict__ rec, int64_t n, const uint32_t *__r
     }
 }
 
+// Workgroups of a persistent launch: the caller's count, else 4 per CU.
+unsigned persistent_grid(int32_t n_workgroups) {
+    if (n_workgroups > 0) return (unsigned)n_workgroups;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    return (unsigned)(4 * cus);
+}
+
 int check_render_args(const float *rec, int64_t n, const uint32_t *vals, const int32_t *ranges) {
     GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "render: n out of range");
     GS4D_REQUIRE(ranges != nullptr, "render: null ranges");
@@ -676,10 +687,7 @@ extern "C" int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals
     hipStream_t st = as_stream(stream);
     unsigned grid = (unsigned)n_tiles;
     if (o.persistent) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess)
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = (unsigned)(o.n_workgroups > 0 ? o.n_workgroups : 4 * cus);
+        grid = persistent_grid(o.n_workgroups);
     }
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const int2 *rg = reinterpret_cast<const int2 *>(ranges);
@@ -745,10 +753,7 @@ extern "C" int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *v
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
     unsigned grid = (unsigned)n_tiles;
     if (o.persistent) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess)
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = (unsigned)(o.n_workgroups > 0 ? o.n_workgroups : 4 * cus);
+        grid = persistent_grid(o.n_workgroups);
     }
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const int2 *rg = reinterpret_cast<const int2 *>(ranges);
