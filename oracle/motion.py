@@ -70,8 +70,11 @@ def jacobi_eigh(A, sweeps=60):
             for q in range(p + 1, n):
                 if A[p, q] == 0.0:
                     continue
-                theta = (A[q, q] - A[p, p]) / (2.0 * A[p, q])
-                t = np.sign(theta) / (abs(theta) + np.hypot(theta, 1.0)) if theta != 0 else 1.0
+                # a negligible A[p, q] makes theta overflow to inf, and t = 0:
+                # the identity rotation, the limit of the formula
+                with np.errstate(over="ignore"):
+                    theta = (A[q, q] - A[p, p]) / (2.0 * A[p, q])
+                    t = np.sign(theta) / (abs(theta) + np.hypot(theta, 1.0)) if theta != 0 else 1.0
                 c = 1.0 / np.sqrt(t * t + 1.0)
                 s = t * c
                 J = np.eye(n)
