@@ -245,7 +245,7 @@ preprocess_fwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp, float
 // point (no gradient through a clamped guard-band coordinate), camera ->
 // conditional mean, conditional -> (Sigma blocks, mu_t, opacity), Sigma =
 // M M^T -> (R, s), R -> (left, right) unit quaternions -> raw quaternions.
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(128, 3)
 preprocess_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
                       const int32_t *__restrict__ touched, const float *__restrict__ grad2d,
                       float *__restrict__ dP) {
