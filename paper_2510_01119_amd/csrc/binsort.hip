@@ -6,8 +6,9 @@
 //
 // Work plan (one GPU, no host synchronisation):
 //   1. item keys: the depth bits of each (view, Gaussian) record (culled ->
-//      0xFFFFFFFF), value = view * n + Gaussian.
-//   2. stable LSD radix sort of the items on the 32 depth bits.
+//      0xFFFFFFFF), value = view * n + Gaussian, built by the first
+//      histogram pass of
+//   2. a stable LSD radix sort of the items on the 32 depth bits.
 //   3. device-wide exclusive scan of tiles-touched read in that order -> each
 //      item's first pair slot, the pair count P and the capacity flag (on
 //      device).
@@ -73,6 +74,52 @@ rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t cou
     for (int i = 0; i < RS_ITEMS; ++i) {
         const int64_t idx = base + i * 64 + l;
         if (idx < n) atomicAdd(&cnt[w][digit_of(keys[idx], shift)], 1u);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) c += cnt[k][t];
+    hist[(int64_t)t * nb + b] = c;
+}
+
+// The depth sort's items as the source of its first pass: item o's key is
+// the bits of its FP32 depth (culled items, no tile touched: 0xFFFFFFFF, so
+// they sort last) and its value o.  The first histogram pass builds keys
+// and values itself (same block layout as rs_hist_kernel), and zeroes the
+// tile ranges in the same launch (a tile no pair reaches stays (0, 0)).
+struct ItemSource {
+    const float4 *rec;
+    const int32_t *touched;
+    int32_t *ranges;
+    int64_t n_range_ints;
+};
+
+template <int RS_ITEMS>
+__global__ void __launch_bounds__(RS_THREADS)
+rs_hist_items_kernel(ItemSource src, int64_t m, uint32_t *__restrict__ keys,
+                     uint32_t *__restrict__ vals, uint32_t *__restrict__ hist) {
+    constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int64_t i = (int64_t)blockIdx.x * RS_THREADS + t; i < src.n_range_ints;
+         i += (int64_t)gridDim.x * RS_THREADS)
+        src.ranges[i] = 0;
+    const int64_t nb = (m + RS_TILE - 1) / RS_TILE;
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    __shared__ uint32_t cnt[RS_WAVES][256];
+    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = b * RS_TILE + (int64_t)w * (RS_TILE / RS_WAVES);
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t o = base + i * 64 + l;
+        if (o < m) {
+            const uint32_t key =
+                src.touched[o] > 0 ? __float_as_uint(src.rec[3 * o + 1].z) : 0xFFFFFFFFu;
+            keys[o] = key;
+            vals[o] = (uint32_t)o;
+            atomicAdd(&cnt[w][key & 0xFFu], 1u);
+        }
     }
     __syncthreads();
     uint32_t c = 0;
@@ -363,20 +410,6 @@ int scan_launch(const int32_t *in, const uint32_t *gather, int32_t *out, int64_t
 }
 
 // ---------------------------------------------------------------- binning kernels
-// Item keys (depth bits, culled last) and, in the same pass, the zeroed
-// tile ranges (a tile no pair reaches stays (0, 0)).
-__global__ void item_keys_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
-                                 int64_t m, uint32_t *__restrict__ keys,
-                                 uint32_t *__restrict__ vals, int32_t *__restrict__ ranges,
-                                 int64_t n_range_ints) {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o < n_range_ints) ranges[o] = 0;
-    if (o >= m) return;
-    const float z = rec[3 * o + 1].z;
-    keys[o] = touched[o] > 0 ? __float_as_uint(z) : 0xFFFFFFFFu;
-    vals[o] = (uint32_t)o;
-}
-
 __global__ void emit_kernel(const uint32_t *__restrict__ dkeys, const uint32_t *__restrict__ order,
                             const int32_t *__restrict__ touched, const int32_t *__restrict__ offs,
                             const int4 *__restrict__ rect, int64_t m, int64_t n, int32_t tiles_x,
@@ -424,15 +457,25 @@ inline unsigned grid_for(int64_t count, int threads) {
 template <class K, int ITEMS>
 int radix_passes(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
                  int64_t count_host, int64_t capacity, int bit_lo, int passes, uint32_t *hist,
-                 uint32_t *totals, hipStream_t st) {
+                 uint32_t *totals, const ItemSource *items, hipStream_t st) {
     constexpr int TILE = RS_THREADS * ITEMS;
     const int64_t nb_max = (capacity + TILE - 1) / TILE;
     K *src = k0, *dst = k1;
     uint32_t *vsrc = v0, *vdst = v1;
     for (int p = 0; p < passes; ++p) {
         const int shift = bit_lo + 8 * p;
-        rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-            src, count_dev, count_host, capacity, shift, hist);
+        if constexpr (sizeof(K) == 4) {
+            if (p == 0 && items) {
+                rs_hist_items_kernel<ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+                    *items, count_host, src, vsrc, hist);
+            } else {
+                rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+                    src, count_dev, count_host, capacity, shift, hist);
+            }
+        } else {
+            rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+                src, count_dev, count_host, capacity, shift, hist);
+        }
         rs_scan_kernel<<<256, 64, 0, st>>>(hist, totals, count_dev, count_host, capacity, TILE);
         rs_scatter_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
             src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, hist, totals);
@@ -457,7 +500,7 @@ inline int64_t rs_blocks(int64_t capacity) {
 template <class K>
 int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
                     int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
-                    hipStream_t st, int *result_in_alt) {
+                    hipStream_t st, int *result_in_alt, const ItemSource *items = nullptr) {
     const int passes = (bit_hi - bit_lo + 7) / 8;
     *result_in_alt = passes & 1;
     if (passes <= 0 || capacity <= 0) return GS4D_OK;
@@ -467,13 +510,13 @@ int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *cou
     switch (rs_items(capacity)) {
     case RS_TINY_ITEMS:
         return radix_passes<K, RS_TINY_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                               bit_lo, passes, hist, totals, st);
+                                               bit_lo, passes, hist, totals, items, st);
     case RS_SMALL_ITEMS:
         return radix_passes<K, RS_SMALL_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, passes, hist, totals, st);
+                                                bit_lo, passes, hist, totals, items, st);
     default:
         return radix_passes<K, RS_LARGE_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, passes, hist, totals, st);
+                                                bit_lo, passes, hist, totals, items, st);
     }
 }
 
@@ -613,12 +656,12 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
         GS4D_TRY(launch_fill<int32_t>(overflow, 0, 1, st));
         return GS4D_OK;
     }
-    // 1-2: items sorted by depth bits (the same pass zeroes the ranges)
-    item_keys_kernel<<<grid_for(m > 2 * n_tiles ? m : 2 * n_tiles, 256), 256, 0, st>>>(
-        reinterpret_cast<const float4 *>(rec), touched, m, L.ik0, L.iv0, ranges, 2 * n_tiles);
-    GS4D_LAUNCH_CHECK("item_keys");
+    // 1-2: items sorted by depth bits; the first pass builds their keys and
+    // zeroes the ranges
+    const ItemSource items{reinterpret_cast<const float4 *>(rec), touched, ranges, 2 * n_tiles};
     int alt = 0;
-    GS4D_TRY(radix_sort_u32(L.ik0, L.iv0, L.ik1, L.iv1, nullptr, m, m, 0, 32, L.radix_ws, st, &alt));
+    GS4D_TRY(radix_sort_impl<uint32_t>(L.ik0, L.iv0, L.ik1, L.iv1, nullptr, m, m, 0, 32,
+                                       L.radix_ws, st, &alt, &items));
     const uint32_t *dkeys = alt ? L.ik1 : L.ik0;
     const uint32_t *order = alt ? L.iv1 : L.iv0;
     // 3: offsets in depth order, pair count and capacity flag
