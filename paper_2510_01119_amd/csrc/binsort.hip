@@ -342,12 +342,28 @@ scan_top_kernel(int64_t *__restrict__ bsum, int64_t nblocks, int64_t *__restrict
     }
 }
 
+// Scans of at most SC_FUSE_BLOCKS blocks skip scan_top_kernel: each
+// down-sweep block adds up the block sums before its own (at most a few
+// thousand values), and the last block writes the total (and, for the
+// binning, the pair count and capacity flag).
+constexpr int64_t SC_FUSE_BLOCKS = 2048;
+
+struct ScanTop {
+    int self_prefix;   // 1: bsum holds plain block sums; 0: scanned by scan_top_kernel
+    int64_t nblocks;
+    int64_t *total;
+    int64_t capacity;
+    int64_t *n_pairs;   // optional, with overflow
+    int32_t *overflow;
+};
+
 // Loads and stores are coalesced (value i*256 + thread of the block); the
 // scan itself runs over ITEMS consecutive values per thread, regrouped in LDS.
 template <int ITEMS>
 __global__ void __launch_bounds__(SC_THREADS)
 scan_down_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
-                 int32_t *__restrict__ out, int64_t count, const int64_t *__restrict__ bsum) {
+                 int32_t *__restrict__ out, int64_t count, const int64_t *__restrict__ bsum,
+                 ScanTop top) {
     constexpr int TILE = SC_THREADS * ITEMS;
     __shared__ int32_t tile[TILE];
     const int64_t b = blockIdx.x;
@@ -367,8 +383,24 @@ scan_down_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ ga
         s += v[i];
     }
     // every thread has read its values before the scan's barriers
+    int64_t prefix;
+    if (top.self_prefix) {
+        int64_t part = 0;
+        for (int64_t i = t; i < b; i += SC_THREADS) part += bsum[i];
+        block_excl_scan(part, &prefix);
+    } else {
+        prefix = bsum[b];
+    }
     int64_t tot;
-    int64_t run = bsum[b] + block_excl_scan(s, &tot);
+    int64_t run = prefix + block_excl_scan(s, &tot);
+    if (top.self_prefix && b == top.nblocks - 1 && t == 0) {
+        const int64_t all = prefix + tot;
+        *top.total = all;
+        if (top.n_pairs) {
+            *top.n_pairs = all;
+            *top.overflow = all > top.capacity ? 1 : 0;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         tile[t * ITEMS + i] = (int32_t)run;
@@ -391,21 +423,26 @@ inline int64_t sc_blocks(int64_t count) {
     return (count + tile - 1) / tile;
 }
 
-// the three launches of one scan (block sums, their scan with the optional
-// binning outputs, the down-sweep)
+// the launches of one scan: block sums, (for many blocks) their scan with
+// the optional binning outputs, the down-sweep
 int scan_launch(const int32_t *in, const uint32_t *gather, int32_t *out, int64_t count,
                 int64_t *total, int64_t *bsum, int64_t capacity, int64_t *n_pairs,
                 int32_t *overflow, hipStream_t st) {
     const int64_t nb = sc_blocks(count);
+    const bool fused = nb <= SC_FUSE_BLOCKS;
+    const ScanTop top{fused ? 1 : 0, nb, total, capacity, n_pairs, overflow};
     if (sc_items(count) == SC_SMALL_ITEMS)
         scan_reduce_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
     else
         scan_reduce_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
-    scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, capacity, n_pairs, overflow);
+    if (!fused)
+        scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, capacity, n_pairs, overflow);
     if (sc_items(count) == SC_SMALL_ITEMS)
-        scan_down_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count, bsum);
+        scan_down_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count,
+                                                                             bsum, top);
     else
-        scan_down_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count, bsum);
+        scan_down_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count,
+                                                                             bsum, top);
     return GS4D_OK;
 }
 

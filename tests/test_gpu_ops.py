@@ -88,8 +88,11 @@ def _points(m, seed):
     return xyz, attr, cls
 
 
+# 9M points: the point scans span more than 2048 blocks of 4096 and take
+# the three-kernel scan (block sums scanned by one block); smaller ones fuse it
 @pytest.mark.parametrize("m,vs,vd,min_count", [(20000, 0.02, 0.02, 1), (50000, 0.05, 0.01, 3),
-                                               (30000, 0.03, 0.0, 1), (7, 0.5, 0.5, 1)])
+                                               (30000, 0.03, 0.0, 1), (7, 0.5, 0.5, 1),
+                                               (9_000_000, 0.01, 0.005, 1)])
 def test_grid_prune_matches_oracle(m, vs, vd, min_count):
     need_gpu()
     xyz, attr, cls = _points(m, m)
