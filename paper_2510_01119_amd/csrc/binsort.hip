@@ -5,19 +5,17 @@
 // sorted ascending by (key, value).
 //
 // Work plan (one GPU, no host synchronisation):
-//   1. item keys: the depth bits of each (view, Gaussian) record (culled ->
-//      0xFFFFFFFF), value = view * n + Gaussian, built by the first
-//      histogram pass of
-//   2. a stable LSD radix sort of the items on the 32 depth bits.
-//   3. device-wide exclusive scan of tiles-touched read in that order -> each
-//      item's first pair slot, the pair count P and the capacity flag (on
-//      device).
-//   4. emit pairs in depth order; inside one tile they are then already
-//      ascending in (depth bits, Gaussian).
-//   5. stable LSD radix sort of the P pairs on the tile bits only, which
-//      yields exactly the ascending (key, value) order while moving the pairs
-//      through 1-2 digit passes instead of 5-6.
-//   6. tile ranges from adjacent key differences.
+//   1. device-wide exclusive scan of tiles-touched over the (view, Gaussian)
+//      items -> each item's first pair slot, the pair count P and the
+//      capacity flag (on device).
+//   2. emit pairs in item order (and zero the tile ranges).
+//   3. stable LSD radix sort of the P pairs on the tile bits only (1-2 digit
+//      passes); inside one tile the pairs stay in Gaussian order.
+//   4. tile ranges from adjacent key differences.
+//   5. one workgroup per tile sorts its pairs stably on the 32 depth bits,
+//      which yields exactly the ascending (key, value) order.  Tiles hold a
+//      few hundred to a few thousand pairs, so this runs in registers and
+//      LDS and replaces a device-wide sort of all items by depth.
 //
 // Radix sort: 8-bit digits; per pass a histogram kernel (per-block digit
 // counts), a scan kernel (one wave per digit over the blocks, giving each
@@ -74,52 +72,6 @@ rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t cou
     for (int i = 0; i < RS_ITEMS; ++i) {
         const int64_t idx = base + i * 64 + l;
         if (idx < n) atomicAdd(&cnt[w][digit_of(keys[idx], shift)], 1u);
-    }
-    __syncthreads();
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < RS_WAVES; ++k) c += cnt[k][t];
-    hist[(int64_t)t * nb + b] = c;
-}
-
-// The depth sort's items as the source of its first pass: item o's key is
-// the bits of its FP32 depth (culled items, no tile touched: 0xFFFFFFFF, so
-// they sort last) and its value o.  The first histogram pass builds keys
-// and values itself (same block layout as rs_hist_kernel), and zeroes the
-// tile ranges in the same launch (a tile no pair reaches stays (0, 0)).
-struct ItemSource {
-    const float4 *rec;
-    const int32_t *touched;
-    int32_t *ranges;
-    int64_t n_range_ints;
-};
-
-template <int RS_ITEMS>
-__global__ void __launch_bounds__(RS_THREADS)
-rs_hist_items_kernel(ItemSource src, int64_t m, uint32_t *__restrict__ keys,
-                     uint32_t *__restrict__ vals, uint32_t *__restrict__ hist) {
-    constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    for (int64_t i = (int64_t)blockIdx.x * RS_THREADS + t; i < src.n_range_ints;
-         i += (int64_t)gridDim.x * RS_THREADS)
-        src.ranges[i] = 0;
-    const int64_t nb = (m + RS_TILE - 1) / RS_TILE;
-    const int64_t b = blockIdx.x;
-    if (b >= nb) return;
-    __shared__ uint32_t cnt[RS_WAVES][256];
-    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0;
-    __syncthreads();
-    const int64_t base = b * RS_TILE + (int64_t)w * (RS_TILE / RS_WAVES);
-#pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) {
-        const int64_t o = base + i * 64 + l;
-        if (o < m) {
-            const uint32_t key =
-                src.touched[o] > 0 ? __float_as_uint(src.rec[3 * o + 1].z) : 0xFFFFFFFFu;
-            keys[o] = key;
-            vals[o] = (uint32_t)o;
-            atomicAdd(&cnt[w][key & 0xFFu], 1u);
-        }
     }
     __syncthreads();
     uint32_t c = 0;
@@ -296,23 +248,16 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *total) {
     return off + incl - x;
 }
 
-// value i of a scan input: in[i], or in[gather[i]] when a gather index is given
-__device__ __forceinline__ int32_t scan_in(const int32_t *__restrict__ in,
-                                           const uint32_t *__restrict__ gather, int64_t i) {
-    return gather ? in[gather[i]] : in[i];
-}
-
 template <int ITEMS>
 __global__ void __launch_bounds__(SC_THREADS)
-scan_reduce_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
-                   int64_t count, int64_t *__restrict__ bsum) {
+scan_reduce_kernel(const int32_t *__restrict__ in, int64_t count, int64_t *__restrict__ bsum) {
     const int64_t b = blockIdx.x;
     const int64_t base = b * (SC_THREADS * ITEMS);
     int64_t s = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
-        if (idx < count) s += scan_in(in, gather, idx);
+        if (idx < count) s += in[idx];
     }
     int64_t tot;
     block_excl_scan(s, &tot);
@@ -361,9 +306,8 @@ struct ScanTop {
 // scan itself runs over ITEMS consecutive values per thread, regrouped in LDS.
 template <int ITEMS>
 __global__ void __launch_bounds__(SC_THREADS)
-scan_down_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
-                 int32_t *__restrict__ out, int64_t count, const int64_t *__restrict__ bsum,
-                 ScanTop top) {
+scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t count,
+                 const int64_t *__restrict__ bsum, ScanTop top) {
     constexpr int TILE = SC_THREADS * ITEMS;
     __shared__ int32_t tile[TILE];
     const int64_t b = blockIdx.x;
@@ -372,7 +316,7 @@ scan_down_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ ga
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * SC_THREADS + t;
-        tile[i * SC_THREADS + t] = idx < count ? scan_in(in, gather, idx) : 0;
+        tile[i * SC_THREADS + t] = idx < count ? in[idx] : 0;
     }
     __syncthreads();
     int32_t v[ITEMS];
@@ -425,44 +369,49 @@ inline int64_t sc_blocks(int64_t count) {
 
 // the launches of one scan: block sums, (for many blocks) their scan with
 // the optional binning outputs, the down-sweep
-int scan_launch(const int32_t *in, const uint32_t *gather, int32_t *out, int64_t count,
+int scan_launch(const int32_t *in, int32_t *out, int64_t count,
                 int64_t *total, int64_t *bsum, int64_t capacity, int64_t *n_pairs,
                 int32_t *overflow, hipStream_t st) {
     const int64_t nb = sc_blocks(count);
     const bool fused = nb <= SC_FUSE_BLOCKS;
     const ScanTop top{fused ? 1 : 0, nb, total, capacity, n_pairs, overflow};
     if (sc_items(count) == SC_SMALL_ITEMS)
-        scan_reduce_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
+        scan_reduce_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, count, bsum);
     else
-        scan_reduce_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
+        scan_reduce_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, count, bsum);
     if (!fused)
         scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, capacity, n_pairs, overflow);
     if (sc_items(count) == SC_SMALL_ITEMS)
-        scan_down_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count,
-                                                                             bsum, top);
+        scan_down_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, out, count, bsum,
+                                                                             top);
     else
-        scan_down_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count,
-                                                                             bsum, top);
+        scan_down_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, out, count, bsum,
+                                                                             top);
     return GS4D_OK;
 }
 
 // ---------------------------------------------------------------- binning kernels
-__global__ void emit_kernel(const uint32_t *__restrict__ dkeys, const uint32_t *__restrict__ order,
-                            const int32_t *__restrict__ touched, const int32_t *__restrict__ offs,
-                            const int4 *__restrict__ rect, int64_t m, int64_t n, int32_t tiles_x,
-                            int32_t tiles_per_view, int64_t capacity, uint64_t *__restrict__ keys,
-                            uint32_t *__restrict__ vals) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    const uint32_t o = order[k];
+// Item o = view vi * n + Gaussian g writes its touched[o] pairs from offs[o]
+// on, its rectangle's tiles in row-major order, key (global tile << 32) |
+// bits(FP32 depth), value g.  The grid also zeroes the tile ranges (a tile
+// no pair reaches stays (0, 0)).
+__global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
+                            const int32_t *__restrict__ offs, const int4 *__restrict__ rect,
+                            int64_t m, int64_t n, int32_t tiles_x, int32_t tiles_per_view,
+                            int64_t capacity, uint64_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals, int32_t *__restrict__ ranges,
+                            int64_t n_range_ints) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = o; i < n_range_ints; i += (int64_t)gridDim.x * blockDim.x) ranges[i] = 0;
+    if (o >= m) return;
     const int32_t cnt = touched[o];
     if (cnt == 0) return;
-    const int64_t off = offs[k];
+    const int64_t off = offs[o];
     if (off < 0 || off + cnt > capacity) return;
-    const uint32_t vi = (uint32_t)(o / (uint64_t)n);
-    const uint32_t g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
+    const uint32_t vi = (uint32_t)(o / n);
+    const uint32_t g = (uint32_t)(o - (int64_t)vi * n);
     const int4 r = rect[o];
-    const uint64_t lo = dkeys[k];
+    const uint64_t lo = __float_as_uint(rec[3 * o + 1].z);
     const uint64_t tbase = (uint64_t)vi * (uint64_t)tiles_per_view;
     int64_t j = off;
     for (int ty = r.y; ty < r.w; ++ty)
@@ -486,6 +435,340 @@ __global__ void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *
     if (i == n - 1 || (keys[i + 1] >> 32) != tile) ranges[tile].y = (int32_t)(i + 1);
 }
 
+// ---------------------------------------------------------------- per-tile depth order
+// After the stable tile sort a tile's pairs sit in Gaussian order; one
+// workgroup per tile sorts them stably on the 32 depth bits (LSD, 8-bit
+// digits), giving the ascending (depth bits, Gaussian) order inside the
+// tile.  A tile of at most SEG_CAP pairs is sorted in registers and LDS; a
+// longer one passes through global memory SEG_CAP pairs at a time, with the
+// spare pair buffer as the other side of each pass.  A digit pass in which
+// every pair has the same digit leaves the order as it is and is skipped.
+//
+// Pair layout inside a chunk of R * 256 pairs: wave w owns pairs
+// [w*64*R, (w+1)*64*R); item i of lane l is pair (w*R + i)*64 + l.  A pair's
+// place in a pass: the start of its digit, plus the pairs of that digit in
+// earlier waves (and earlier chunks), plus its rank among the earlier pairs
+// of its wave with that digit (wave ballots).
+constexpr int SEG_THREADS = 256;
+constexpr int SEG_WAVES = SEG_THREADS / 64;
+constexpr int SEG_ITEMS = 8;
+constexpr int SEG_CAP = SEG_THREADS * SEG_ITEMS;
+
+struct SegShared {
+    uint32_t key[SEG_CAP];
+    uint32_t val[SEG_CAP];
+    uint32_t cnt[2][SEG_WAVES][256];   // per (wave, digit): counts, then starts
+    uint32_t base[256];                // long tiles: start of each digit's next run
+    uint32_t kmin[SEG_WAVES], kmax[SEG_WAVES];
+    int skip;
+};
+
+template <int CTRL, int ROW_MASK, bool MAX>
+__device__ __forceinline__ uint32_t dpp_extreme(uint32_t x) {
+    const uint32_t y =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROW_MASK, 0xF, false);
+    return MAX ? (x > y ? x : y) : (x < y ? x : y);
+}
+
+// minimum (or maximum) over the 64 lanes of a wave, in every lane
+template <bool MAX>
+__device__ __forceinline__ uint32_t wave_extreme(uint32_t x) {
+    x = dpp_extreme<0x111, 0xF, MAX>(x);   // row_shr:1
+    x = dpp_extreme<0x112, 0xF, MAX>(x);   // row_shr:2
+    x = dpp_extreme<0x114, 0xF, MAX>(x);   // row_shr:4
+    x = dpp_extreme<0x118, 0xF, MAX>(x);   // row_shr:8
+    x = dpp_extreme<0x142, 0xA, MAX>(x);   // row_bcast:15
+    x = dpp_extreme<0x143, 0xC, MAX>(x);   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// lanes of this wave that are valid and hold digit d (a digit of nbits bits)
+__device__ __forceinline__ uint64_t same_digit(uint32_t d, bool valid, int nbits) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        if (bit < nbits) {
+            const uint64_t m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+    }
+    return peers;
+}
+
+// Rank of each item of this thread among the earlier items of its wave with
+// the same digit; c[w][d] counts the wave's items of digit d (zero on entry).
+// Per round, the first lane of each digit's run adds the run's length with a
+// returning LDS atomic (a wave's LDS operations take effect in order, so the
+// rounds need not wait for each other) and its peers read the old count
+// from it.
+__device__ __forceinline__ void rank_items(const uint32_t (&k)[SEG_ITEMS],
+                                           uint32_t (&rank)[SEG_ITEMS], int R, int first,
+                                           int len, int shift, int nbits, uint32_t (*c)[256]) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    uint32_t old[SEG_ITEMS];
+    int lead[SEG_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SEG_ITEMS; ++i) {
+        if (i < R) {
+            const bool valid = first + (w * R + i) * 64 + l < len;
+            const uint32_t d = (k[i] >> shift) & 0xFFu;
+            const uint64_t peers = same_digit(d, valid, nbits);
+            const uint32_t before = (uint32_t)__popcll(peers & lt_mask);
+            uint32_t o = 0;
+            if (valid && before == 0) o = atomicAdd(&c[w][d], (uint32_t)__popcll(peers));
+            old[i] = o;
+            rank[i] = before;
+            lead[i] = valid ? (int)__builtin_ctzll(peers) : l;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < SEG_ITEMS; ++i)
+        if (i < R) rank[i] += (uint32_t)__shfl((int)old[i], lead[i], 64);
+}
+
+// inclusive prefix sum over the 64 lanes of a wave: shifts inside rows of
+// 16 lanes, then the row totals broadcast into the rows above (DPP)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
+// Wave 0: exclusive scan of the 256 digit totals tot(d) (lane l holds digits
+// l, l+64, l+128, l+192) into start(d); returns, in every lane, whether one
+// digit holds all `len` pairs.
+__device__ __forceinline__ bool wave_digit_scan(const uint32_t (&tot)[4], uint32_t (&start)[4],
+                                                int len) {
+    uint32_t carry = 0;
+    bool whole = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t incl = wave_incl_scan(tot[j]);
+        start[j] = carry + incl - tot[j];
+        carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        whole |= tot[j] == (uint32_t)len;
+    }
+    return __ballot(whole) != 0;
+}
+
+// pair j of the segment from the output arrays (at == 0) or the spare buffer
+__device__ __forceinline__ void seg_load(const uint64_t *keys, const uint32_t *vals,
+                                         const uint64_t *spill, bool in_spill, int64_t j,
+                                         uint32_t &k, uint32_t &v) {
+    if (in_spill) {
+        const uint64_t x = spill[j];
+        k = (uint32_t)x;
+        v = (uint32_t)(x >> 32);
+    } else {
+        k = (uint32_t)keys[j];
+        v = vals[j];
+    }
+}
+
+__device__ __forceinline__ void seg_store(uint64_t *keys, uint32_t *vals, uint64_t *spill,
+                                          bool to_spill, int64_t j, uint64_t tile_hi,
+                                          uint32_t k, uint32_t v) {
+    if (to_spill) {
+        spill[j] = (uint64_t)k | ((uint64_t)v << 32);
+    } else {
+        keys[j] = tile_hi | k;
+        vals[j] = v;
+    }
+}
+
+// a tile longer than SEG_CAP: four passes through global memory
+__device__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
+                               uint32_t *__restrict__ vals, uint64_t *__restrict__ spill,
+                               int64_t start, int len, uint64_t tile_hi) {
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    bool in_spill = false;
+    uint32_t k[SEG_ITEMS], v[SEG_ITEMS], rank[SEG_ITEMS];
+    for (int p = 0; p < 4; ++p) {
+        const int shift = 8 * p;
+        sh.base[t] = 0;
+        for (int i = t; i < 2 * SEG_WAVES * 256; i += SEG_THREADS) (&sh.cnt[0][0][0])[i] = 0;
+        __syncthreads();
+        for (int e = t; e < len; e += SEG_THREADS) {
+            uint32_t ke, ve;
+            seg_load(keys, vals, spill, in_spill, start + e, ke, ve);
+            atomicAdd(&sh.base[(ke >> shift) & 0xFFu], 1u);
+        }
+        __syncthreads();
+        if (w == 0) {
+            uint32_t tot[4], st[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tot[j] = sh.base[j * 64 + l];
+            const bool whole = wave_digit_scan(tot, st, len);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sh.base[j * 64 + l] = st[j];
+            if (l == 0) sh.skip = whole ? 1 : 0;
+        }
+        __syncthreads();
+        if (sh.skip) continue;
+        for (int c0 = 0, ci = 0; c0 < len; c0 += SEG_CAP, ++ci) {
+            uint32_t (*c)[256] = sh.cnt[ci & 1];
+#pragma unroll
+            for (int i = 0; i < SEG_ITEMS; ++i) {
+                const int e = c0 + (w * SEG_ITEMS + i) * 64 + l;
+                if (e < len) seg_load(keys, vals, spill, in_spill, start + e, k[i], v[i]);
+                else k[i] = 0;
+            }
+            rank_items(k, rank, SEG_ITEMS, c0, len, shift, 8, c);
+            __syncthreads();
+            // digit t: starts of its run in each wave of this chunk; the next
+            // chunk's counters are cleared
+            {
+                uint32_t run = sh.base[t];
+#pragma unroll
+                for (int ww = 0; ww < SEG_WAVES; ++ww) {
+                    const uint32_t x = c[ww][t];
+                    c[ww][t] = run;
+                    run += x;
+                }
+                sh.base[t] = run;
+#pragma unroll
+                for (int ww = 0; ww < SEG_WAVES; ++ww) sh.cnt[(ci + 1) & 1][ww][t] = 0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < SEG_ITEMS; ++i) {
+                const int e = c0 + (w * SEG_ITEMS + i) * 64 + l;
+                if (e < len) {
+                    const uint32_t pos = c[w][(k[i] >> shift) & 0xFFu] + rank[i];
+                    seg_store(keys, vals, spill, !in_spill, start + pos, tile_hi, k[i], v[i]);
+                }
+            }
+        }
+        // the pass's stores are complete before the next pass reads them
+        __syncthreads();
+        in_spill = !in_spill;
+    }
+    if (in_spill) {
+        for (int e = t; e < len; e += SEG_THREADS) {
+            uint32_t ke, ve;
+            seg_load(keys, vals, spill, true, start + e, ke, ve);
+            seg_store(keys, vals, spill, false, start + e, tile_hi, ke, ve);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(SEG_THREADS)
+tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                       const int2 *__restrict__ ranges, uint64_t *__restrict__ spill) {
+    __shared__ SegShared sh;
+    const int2 r = ranges[blockIdx.x];
+    const int len = r.y - r.x;
+    if (len <= 1) return;
+    const int64_t start = r.x;
+    const uint64_t tile_hi = (uint64_t)blockIdx.x << 32;
+    if (len > SEG_CAP) {
+        long_tile_sort(sh, keys, vals, spill, start, len, tile_hi);
+        return;
+    }
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int R = (len + SEG_THREADS - 1) / SEG_THREADS;   // items per lane, <= SEG_ITEMS
+    uint32_t k[SEG_ITEMS], v[SEG_ITEMS], rank[SEG_ITEMS];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0;
+#pragma unroll
+    for (int i = 0; i < SEG_ITEMS; ++i) {
+        const int e = (w * R + i) * 64 + l;
+        k[i] = 0;
+        v[i] = 0;
+        if (i < R && e < len) {
+            k[i] = (uint32_t)keys[start + e];
+            v[i] = vals[start + e];
+            lo = k[i] < lo ? k[i] : lo;
+            hi = k[i] > hi ? k[i] : hi;
+        }
+    }
+    // The tile's keys lie in [kmin, kmax]: sorting k - kmin on its
+    // bit_width(kmax - kmin) low bits gives the same order in fewer digit
+    // bits (depths inside one tile span a narrow range).
+    lo = wave_extreme<false>(lo);
+    hi = wave_extreme<true>(hi);
+    if (l == 0) {
+        sh.kmin[w] = lo;
+        sh.kmax[w] = hi;
+    }
+    for (int i = t; i < 2 * SEG_WAVES * 256; i += SEG_THREADS) (&sh.cnt[0][0][0])[i] = 0;
+    __syncthreads();
+    uint32_t kmin = sh.kmin[0], kmax = sh.kmax[0];
+#pragma unroll
+    for (int ww = 1; ww < SEG_WAVES; ++ww) {
+        kmin = sh.kmin[ww] < kmin ? sh.kmin[ww] : kmin;
+        kmax = sh.kmax[ww] > kmax ? sh.kmax[ww] : kmax;
+    }
+    const int bits = kmax == kmin ? 0 : 32 - __builtin_clz(kmax - kmin);
+#pragma unroll
+    for (int i = 0; i < SEG_ITEMS; ++i) k[i] -= kmin;
+    for (int p = 0; 8 * p < bits; ++p) {
+        const int shift = 8 * p;
+        const int nbits = bits - shift < 8 ? bits - shift : 8;
+        uint32_t (*c)[256] = sh.cnt[p & 1];
+        rank_items(k, rank, R, 0, len, shift, nbits, c);
+        __syncthreads();
+        // wave 0 turns the counts into starts; the next pass's counters are
+        // cleared meanwhile
+#pragma unroll
+        for (int ww = 0; ww < SEG_WAVES; ++ww) sh.cnt[(p + 1) & 1][ww][t] = 0;
+        if (w == 0) {
+            uint32_t tot[4], st[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int d = j * 64 + l;
+                tot[j] = 0;
+#pragma unroll
+                for (int ww = 0; ww < SEG_WAVES; ++ww) tot[j] += c[ww][d];
+            }
+            const bool whole = wave_digit_scan(tot, st, len);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int d = j * 64 + l;
+                uint32_t run = st[j];
+#pragma unroll
+                for (int ww = 0; ww < SEG_WAVES; ++ww) {
+                    const uint32_t x = c[ww][d];
+                    c[ww][d] = run;
+                    run += x;
+                }
+            }
+            if (l == 0) sh.skip = whole ? 1 : 0;
+        }
+        __syncthreads();
+        if (sh.skip) continue;
+#pragma unroll
+        for (int i = 0; i < SEG_ITEMS; ++i) {
+            if (i < R && (w * R + i) * 64 + l < len) {
+                const uint32_t pos = c[w][(k[i] >> shift) & 0xFFu] + rank[i];
+                sh.key[pos] = k[i];
+                sh.val[pos] = v[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SEG_ITEMS; ++i) {
+            const int e = (w * R + i) * 64 + l;
+            if (i < R && e < len) {
+                k[i] = sh.key[e];
+                v[i] = sh.val[e];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < SEG_ITEMS; ++i) {
+        const int e = (w * R + i) * 64 + l;
+        if (i < R && e < len) {
+            keys[start + e] = tile_hi | (k[i] + kmin);
+            vals[start + e] = v[i];
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t count, int threads) {
     int64_t b = (count + threads - 1) / threads;
     return (unsigned)(b > 0 ? b : 1);
@@ -494,25 +777,15 @@ inline unsigned grid_for(int64_t count, int threads) {
 template <class K, int ITEMS>
 int radix_passes(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
                  int64_t count_host, int64_t capacity, int bit_lo, int passes, uint32_t *hist,
-                 uint32_t *totals, const ItemSource *items, hipStream_t st) {
+                 uint32_t *totals, hipStream_t st) {
     constexpr int TILE = RS_THREADS * ITEMS;
     const int64_t nb_max = (capacity + TILE - 1) / TILE;
     K *src = k0, *dst = k1;
     uint32_t *vsrc = v0, *vdst = v1;
     for (int p = 0; p < passes; ++p) {
         const int shift = bit_lo + 8 * p;
-        if constexpr (sizeof(K) == 4) {
-            if (p == 0 && items) {
-                rs_hist_items_kernel<ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-                    *items, count_host, src, vsrc, hist);
-            } else {
-                rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-                    src, count_dev, count_host, capacity, shift, hist);
-            }
-        } else {
-            rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-                src, count_dev, count_host, capacity, shift, hist);
-        }
+        rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+            src, count_dev, count_host, capacity, shift, hist);
         rs_scan_kernel<<<256, 64, 0, st>>>(hist, totals, count_dev, count_host, capacity, TILE);
         rs_scatter_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
             src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, hist, totals);
@@ -537,7 +810,7 @@ inline int64_t rs_blocks(int64_t capacity) {
 template <class K>
 int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
                     int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
-                    hipStream_t st, int *result_in_alt, const ItemSource *items = nullptr) {
+                    hipStream_t st, int *result_in_alt) {
     const int passes = (bit_hi - bit_lo + 7) / 8;
     *result_in_alt = passes & 1;
     if (passes <= 0 || capacity <= 0) return GS4D_OK;
@@ -547,13 +820,13 @@ int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *cou
     switch (rs_items(capacity)) {
     case RS_TINY_ITEMS:
         return radix_passes<K, RS_TINY_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                               bit_lo, passes, hist, totals, items, st);
+                                               bit_lo, passes, hist, totals, st);
     case RS_SMALL_ITEMS:
         return radix_passes<K, RS_SMALL_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, passes, hist, totals, items, st);
+                                                bit_lo, passes, hist, totals, st);
     default:
         return radix_passes<K, RS_LARGE_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, passes, hist, totals, items, st);
+                                                bit_lo, passes, hist, totals, st);
     }
 }
 
@@ -580,13 +853,6 @@ int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const
                                      bit_hi, ws, st, result_in_alt);
 }
 
-int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *count_dev,
-                   int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
-                   hipStream_t st, int *result_in_alt) {
-    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, count_dev, count_host, capacity, bit_lo,
-                                     bit_hi, ws, st, result_in_alt);
-}
-
 size_t scan_workspace_size(int64_t count) {
     // enough block sums for any count up to this one
     int64_t nb = sc_blocks(count);
@@ -600,18 +866,17 @@ int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count, int64_t *
     if (count <= 0) {
         return launch_fill<int64_t>(total, (int64_t)0, 1, st);
     }
-    scan_launch(in, nullptr, out, count, total, static_cast<int64_t *>(ws), 0, nullptr, nullptr, st);
+    scan_launch(in, out, count, total, static_cast<int64_t *>(ws), 0, nullptr, nullptr, st);
     GS4D_LAUNCH_CHECK("exclusive_scan");
     return GS4D_OK;
 }
 
 namespace {
-// Pair offsets of the depth-ordered items: exclusive scan of touched[order[k]],
-// the pair count and the capacity flag, in three kernels (count >= 1).
-int pair_offsets(const int32_t *touched, const uint32_t *order, int32_t *offs, int64_t count,
-                 int64_t *total, void *ws, int64_t capacity, int64_t *n_pairs, int32_t *overflow,
-                 hipStream_t st) {
-    scan_launch(touched, order, offs, count, total, static_cast<int64_t *>(ws), capacity, n_pairs,
+// Pair offsets of the items: exclusive scan of touched, the pair count and
+// the capacity flag (count >= 1).
+int pair_offsets(const int32_t *touched, int32_t *offs, int64_t count, int64_t *total, void *ws,
+                 int64_t capacity, int64_t *n_pairs, int32_t *overflow, hipStream_t st) {
+    scan_launch(touched, offs, count, total, static_cast<int64_t *>(ws), capacity, n_pairs,
                 overflow, st);
     GS4D_LAUNCH_CHECK("pair_offsets");
     return GS4D_OK;
@@ -620,7 +885,6 @@ int pair_offsets(const int32_t *touched, const uint32_t *order, int32_t *offs, i
 
 namespace {
 struct BinLayout {
-    uint32_t *ik0, *iv0, *ik1, *iv1;   // item keys / values, two buffers
     int32_t *offs;
     void *scan_ws;
     int64_t *total;
@@ -633,16 +897,12 @@ BinLayout carve_bin(void *ws, int64_t m, int64_t cap, size_t *used) {
     Carve c(ws, ~size_t(0));
     BinLayout L;
     const size_t mm = (size_t)(m > 0 ? m : 1);
-    L.ik0 = c.take<uint32_t>(mm);
-    L.iv0 = c.take<uint32_t>(mm);
-    L.ik1 = c.take<uint32_t>(mm);
-    L.iv1 = c.take<uint32_t>(mm);
     L.offs = c.take<int32_t>(mm);
     L.scan_ws = c.take<char>(scan_workspace_size(m));
     L.total = c.take<int64_t>(1);
     L.pk = c.take<uint64_t>((size_t)(cap > 0 ? cap : 1));
     L.pv = c.take<uint32_t>((size_t)(cap > 0 ? cap : 1));
-    L.radix_ws = c.take<char>(radix_workspace_size(m > cap ? m : cap));
+    L.radix_ws = c.take<char>(radix_workspace_size(cap));
     *used = c.used;
     return L;
 }
@@ -693,35 +953,32 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
         GS4D_TRY(launch_fill<int32_t>(overflow, 0, 1, st));
         return GS4D_OK;
     }
-    // 1-2: items sorted by depth bits; the first pass builds their keys and
-    // zeroes the ranges
-    const ItemSource items{reinterpret_cast<const float4 *>(rec), touched, ranges, 2 * n_tiles};
-    int alt = 0;
-    GS4D_TRY(radix_sort_impl<uint32_t>(L.ik0, L.iv0, L.ik1, L.iv1, nullptr, m, m, 0, 32,
-                                       L.radix_ws, st, &alt, &items));
-    const uint32_t *dkeys = alt ? L.ik1 : L.ik0;
-    const uint32_t *order = alt ? L.iv1 : L.iv0;
-    // 3: offsets in depth order, pair count and capacity flag
-    GS4D_TRY(pair_offsets(touched, order, L.offs, m, L.total, L.scan_ws, pair_capacity, n_pairs,
-                          overflow, st));
-    if (pair_capacity == 0) return GS4D_OK;
-    // 4-5: emit in depth order, stable sort on tile bits only
+    // 1: pair offsets of the items, pair count and capacity flag
+    GS4D_TRY(pair_offsets(touched, L.offs, m, L.total, L.scan_ws, pair_capacity, n_pairs, overflow,
+                          st));
+    if (pair_capacity == 0) return launch_fill<int32_t>(ranges, 0, 2 * n_tiles, st);
+    // 2-3: emit in item order, stable sort on the tile bits only
     const int tbits = tile_bits_for(n_tiles);
     const int tpasses = (tbits + 7) / 8;
     uint64_t *ek = (tpasses & 1) ? L.pk : keys;
     uint32_t *ev = (tpasses & 1) ? L.pv : vals;
     uint64_t *ok = (tpasses & 1) ? keys : L.pk;
     uint32_t *ov = (tpasses & 1) ? vals : L.pv;
-    emit_kernel<<<grid_for(m, 128), 128, 0, st>>>(dkeys, order, touched, L.offs,
-                                                  reinterpret_cast<const int4 *>(rect), m, n,
-                                                  vp.tiles_x, vp.tiles_per_view, pair_capacity, ek,
-                                                  ev);
+    emit_kernel<<<grid_for(m, 128), 128, 0, st>>>(reinterpret_cast<const float4 *>(rec), touched,
+                                                  L.offs, reinterpret_cast<const int4 *>(rect), m,
+                                                  n, vp.tiles_x, vp.tiles_per_view, pair_capacity,
+                                                  ek, ev, ranges, 2 * n_tiles);
     GS4D_LAUNCH_CHECK("emit");
+    int alt = 0;
     GS4D_TRY(radix_sort_u64(ek, ev, ok, ov, n_pairs, 0, pair_capacity, 32, 32 + tbits, L.radix_ws,
                             st, &alt));
-    // 6: ranges
+    // 4: ranges
     ranges_kernel<<<grid_for(pair_capacity, 256), 256, 0, st>>>(keys, n_pairs, pair_capacity, n_tiles,
                                                                 reinterpret_cast<int2 *>(ranges));
     GS4D_LAUNCH_CHECK("ranges");
+    // 5: depth order inside each tile (the pair buffer L.pk is free again)
+    tile_depth_sort_kernel<<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
+        keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk);
+    GS4D_LAUNCH_CHECK("tile depth sort");
     return GS4D_OK;
 }

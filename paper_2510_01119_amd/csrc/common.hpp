@@ -126,8 +126,5 @@ size_t radix_workspace_size(int64_t capacity);
 int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, const int64_t *count_dev,
                    int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
                    hipStream_t st, int *result_in_alt);
-int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *count_dev,
-                   int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
-                   hipStream_t st, int *result_in_alt);
 
 }  // namespace gs4d
