@@ -482,17 +482,20 @@ __device__ __forceinline__ uint32_t wave_extreme(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// lanes of this wave that are valid and hold digit d (a digit of nbits bits)
-__device__ __forceinline__ uint64_t same_digit(uint32_t d, bool valid, int nbits) {
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-        if (bit < nbits) {
-            const uint64_t m = __ballot((d >> bit) & 1u);
-            peers &= ((d >> bit) & 1u) ? m : ~m;
-        }
+// lanes of this wave that are valid and hold the same digit, bits
+// [shift, shift + nbits) of k, as this lane: per bit, the lane's bit as an
+// all-ones / zero word, its ballot, and the lanes that agree with it
+// (xnor), in both halves of the mask
+__device__ __forceinline__ uint64_t same_digit(uint32_t k, int shift, bool valid, int nbits) {
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    for (int bit = 0; bit < nbits; ++bit) {
+        const uint32_t own = (uint32_t)__builtin_amdgcn_sbfe((int)k, shift + bit, 1);
+        const uint64_t m = __ballot(own != 0u);
+        lo &= ~((uint32_t)m ^ own);
+        hi &= ~((uint32_t)(m >> 32) ^ own);
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Rank of each item of this thread among the earlier items of its wave with
@@ -513,7 +516,7 @@ __device__ __forceinline__ void rank_items(const uint32_t (&k)[SEG_ITEMS],
         if (i < R) {
             const bool valid = first + (w * R + i) * 64 + l < len;
             const uint32_t d = (k[i] >> shift) & 0xFFu;
-            const uint64_t peers = same_digit(d, valid, nbits);
+            const uint64_t peers = same_digit(k[i], shift, valid, nbits);
             const uint32_t before = (uint32_t)__popcll(peers & lt_mask);
             uint32_t o = 0;
             if (valid && before == 0) o = atomicAdd(&c[w][d], (uint32_t)__popcll(peers));
