@@ -6,7 +6,10 @@ finite differences.
 * the maximum of 16 views in one call;
 * GS4DRasterize under torch.autograd matches gs4d_render_bwd;
 * gradients against central differences (h = 1e-3) of the oracle's FP64
-  forward on 64 random parameters.
+  forward on 64 random parameters;
+* the per-tile depth sort's corner cases against the oracle's binning, bit
+  for bit: equal depths (ties broken by Gaussian index), a tile of more than
+  2,048 pairs, tiles whose keys are all equal.
 """
 import numpy as np
 import pytest
@@ -148,3 +151,52 @@ def test_gradients_vs_central_differences():
         assert abs(d[k, g] - fd) <= 1e-3 * scale, (k, g, d[k, g], fd)
         checked += 1
     assert checked == 64, (checked, rejected)
+
+
+def _depth_sort_corner_set(seed=11):
+    """Gaussians for the per-tile depth sort's corner cases, seen by a
+    96x64 front view (6x4 tiles).  Every mean time equals the view time, so
+    the conditional mean is the spatial mean and equal z gives bit-equal
+    depths.
+    * 3,000 in a blob inside tile (2, 1), half at one shared z: more than
+      2,048 pairs in one tile (the passes through global memory), with ties
+      broken by Gaussian index;
+    * 1,500 over the whole frame at another shared z: the right half's
+      tiles hold only equal keys (no digit pass at all);
+    * 1,500 over the left half with z in [-2, 2] (depths 1 to 5, all four
+      digit passes), mixed with the shared-z ones."""
+    rng = np.random.default_rng(seed)
+    p = synth.small_set(6000, seed, log_s_xyz=(-4.0, 0.3))
+    p[3] = 0.5
+    blob, spread, deep = slice(0, 3000), slice(3000, 4500), slice(4500, 6000)
+    p[0, blob] = rng.normal(-0.375, 0.03, 3000)
+    p[1, blob] = rng.normal(-0.375, 0.03, 3000)
+    p[2, blob] = np.where(np.arange(3000) % 2 == 0, 0.0, rng.uniform(-0.5, 0.5, 3000))
+    p[0, spread] = rng.uniform(-2.0, 2.0, 1500)
+    p[1, spread] = rng.uniform(-1.4, 1.4, 1500)
+    p[2, spread] = 0.25
+    p[0, deep] = rng.uniform(-2.0, -0.1, 1500)
+    p[1, deep] = rng.uniform(-1.4, 1.4, 1500)
+    p[2, deep] = rng.uniform(-2.0, 2.0, 1500)
+    return p.astype(np.float32)
+
+
+def test_depth_sort_ties_long_and_equal_tiles():
+    need_gpu()
+    view = synth.front_view(96, 64, 64.0)
+    p = _depth_sort_corner_set()
+    rec, rect, touched = oracle.preprocess_f32(p, view)
+    keys, vals, ranges = oracle.bin_sort(rect, touched, oracle.depth_bits(rec), view)
+    lens = ranges[:, 1] - ranges[:, 0]
+    # the fixture reaches the cases it is for
+    assert lens.max() > 2048
+    same = (keys[1:] == keys[:-1])
+    assert same.sum() > 1000
+    all_equal = [b - a > 1 and keys[a] == keys[b - 1] for a, b in ranges]
+    assert sum(all_equal) >= 3
+    r, _ = gpu_forward(p, view, capacity=len(vals) + 64)
+    g = to_np(r)
+    assert g["n_pairs"] == len(vals)
+    assert np.array_equal(g["ranges"].reshape(-1, 2), ranges)
+    assert np.array_equal(g["keys"], keys)
+    assert np.array_equal(g["vals"], vals)
