@@ -45,9 +45,11 @@ __device__ __forceinline__ int64_t read_count(const int64_t *count_dev, int64_t 
     return n;
 }
 
+// the digit of a pass: key bits [shift, shift + nbits), nbits <= 8 (the
+// last pass of a sort on bits [lo, hi) takes only the bits below hi)
 template <class K>
-__device__ __forceinline__ uint32_t digit_of(K key, int shift) {
-    return (uint32_t)((key >> shift) & (K)0xFF);
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, int nbits) {
+    return (uint32_t)((key >> shift) & (K)((1u << nbits) - 1u));
 }
 
 // Block b covers keys [b*TILE, (b+1)*TILE), TILE = 256 * ITEMS.  Wave w owns
@@ -57,7 +59,7 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
 template <class K, int RS_ITEMS>
 __global__ void __launch_bounds__(RS_THREADS)
 rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t count_host,
-               int64_t capacity, int shift, uint32_t *__restrict__ hist) {
+               int64_t capacity, int shift, int nbits, uint32_t *__restrict__ hist) {
     constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
     const int64_t n = read_count(count_dev, count_host, capacity);
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
@@ -71,7 +73,7 @@ rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t cou
 #pragma unroll 4
     for (int i = 0; i < RS_ITEMS; ++i) {
         const int64_t idx = base + i * 64 + l;
-        if (idx < n) atomicAdd(&cnt[w][digit_of(keys[idx], shift)], 1u);
+        if (idx < n) atomicAdd(&cnt[w][digit_of(keys[idx], shift, nbits)], 1u);
     }
     __syncthreads();
     uint32_t c = 0;
@@ -119,7 +121,7 @@ template <class K, int RS_ITEMS>
 __global__ void __launch_bounds__(RS_THREADS)
 rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                   K *__restrict__ kout, uint32_t *__restrict__ vout, const int64_t *count_dev,
-                  int64_t count_host, int64_t capacity, int shift,
+                  int64_t count_host, int64_t capacity, int shift, int nbits,
                   const uint32_t *__restrict__ hist, const uint32_t *__restrict__ row_total) {
     constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
     const int64_t n = read_count(count_dev, count_host, capacity);
@@ -145,14 +147,19 @@ rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
         const bool valid = idx < n;
         key[i] = valid ? kin[idx] : (K)0;
         val[i] = valid ? vin[idx] : 0u;
-        const uint32_t d = digit_of(key[i], shift);
-        // lanes holding the same digit (ballot-based match)
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const uint64_t m = __ballot((d >> bit) & 1u);
-            peers &= ((d >> bit) & 1u) ? m : ~m;
+        const uint32_t d = digit_of(key[i], shift, nbits);
+        // lanes holding the same digit: per significant digit bit, the lane's
+        // bit as an all-ones / zero word, its ballot, and the lanes that agree
+        // (xnor) in both halves of the mask
+        const uint64_t vmask = __ballot(valid);
+        uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
+        for (int bit = 0; bit < nbits; ++bit) {
+            const uint32_t own = (uint32_t)__builtin_amdgcn_sbfe((int)d, bit, 1);
+            const uint64_t m = __ballot(own != 0u);
+            plo &= ~((uint32_t)m ^ own);
+            phi &= ~((uint32_t)(m >> 32) ^ own);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t before = __popcll(peers & lt_mask);
         uint32_t r = 0;
         if (valid) r = wcnt[w][d] + before;
@@ -198,7 +205,7 @@ rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) {
         if (rank[i] != 0xFFFFFFFFu) {
-            const uint32_t d = digit_of(key[i], shift);
+            const uint32_t d = digit_of(key[i], shift, nbits);
             const uint32_t pos = dstart[d] + wcnt[w][d] + rank[i];
             sk[pos] = key[i];
             sv[pos] = val[i];
@@ -211,7 +218,7 @@ rs_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
         const int idx = i * RS_THREADS + t;
         if (idx < nvalid) {
             const K k = sk[idx];
-            const uint32_t d = digit_of(k, shift);
+            const uint32_t d = digit_of(k, shift, nbits);
             const uint32_t dst = gbase[d] + (uint32_t)idx - dstart[d];
             kout[dst] = k;
             vout[dst] = sv[idx];
@@ -779,19 +786,19 @@ inline unsigned grid_for(int64_t count, int threads) {
 
 template <class K, int ITEMS>
 int radix_passes(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
-                 int64_t count_host, int64_t capacity, int bit_lo, int passes, uint32_t *hist,
+                 int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, uint32_t *hist,
                  uint32_t *totals, hipStream_t st) {
     constexpr int TILE = RS_THREADS * ITEMS;
     const int64_t nb_max = (capacity + TILE - 1) / TILE;
     K *src = k0, *dst = k1;
     uint32_t *vsrc = v0, *vdst = v1;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = bit_lo + 8 * p;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+        const int nbits = bit_hi - shift < 8 ? bit_hi - shift : 8;
         rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-            src, count_dev, count_host, capacity, shift, hist);
+            src, count_dev, count_host, capacity, shift, nbits, hist);
         rs_scan_kernel<<<256, 64, 0, st>>>(hist, totals, count_dev, count_host, capacity, TILE);
         rs_scatter_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-            src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, hist, totals);
+            src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, nbits, hist, totals);
         GS4D_LAUNCH_CHECK("radix pass");
         K *tk = src; src = dst; dst = tk;
         uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
@@ -823,13 +830,13 @@ int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *cou
     switch (rs_items(capacity)) {
     case RS_TINY_ITEMS:
         return radix_passes<K, RS_TINY_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                               bit_lo, passes, hist, totals, st);
+                                               bit_lo, bit_hi, hist, totals, st);
     case RS_SMALL_ITEMS:
         return radix_passes<K, RS_SMALL_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, passes, hist, totals, st);
+                                                bit_lo, bit_hi, hist, totals, st);
     default:
         return radix_passes<K, RS_LARGE_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, passes, hist, totals, st);
+                                                bit_lo, bit_hi, hist, totals, st);
     }
 }
 
