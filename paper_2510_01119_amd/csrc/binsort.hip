@@ -398,25 +398,26 @@ int scan_launch(const int32_t *in, int32_t *out, int64_t count,
 }
 
 // ---------------------------------------------------------------- binning kernels
-// Item o = view vi * n + Gaussian g writes its touched[o] pairs from offs[o]
-// on, its rectangle's tiles in row-major order, key (global tile << 32) |
-// bits(FP32 depth), value g.  The grid also zeroes the tile ranges (a tile
-// no pair reaches stays (0, 0)).
+// Item o = view vi * n + Gaussian g (grid: x over g, y over vi) writes its
+// touched[o] pairs from offs[o] on, its rectangle's tiles in row-major
+// order, key (global tile << 32) | bits(FP32 depth), value g.  The grid also
+// zeroes the tile ranges (a tile no pair reaches stays (0, 0)).
 __global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
                             const int32_t *__restrict__ offs, const int4 *__restrict__ rect,
-                            int64_t m, int64_t n, int32_t tiles_x, int32_t tiles_per_view,
-                            int64_t capacity, uint64_t *__restrict__ keys,
-                            uint32_t *__restrict__ vals, int32_t *__restrict__ ranges,
-                            int64_t n_range_ints) {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t i = o; i < n_range_ints; i += (int64_t)gridDim.x * blockDim.x) ranges[i] = 0;
-    if (o >= m) return;
+                            int64_t n, int32_t tiles_x, int32_t tiles_per_view, int64_t capacity,
+                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                            int32_t *__restrict__ ranges, int64_t n_range_ints) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t vi = blockIdx.y;
+    const int64_t stride = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+    for (int64_t i = g + (int64_t)vi * gridDim.x * blockDim.x; i < n_range_ints; i += stride)
+        ranges[i] = 0;
+    if (g >= n) return;
+    const int64_t o = (int64_t)vi * n + g;
     const int32_t cnt = touched[o];
     if (cnt == 0) return;
     const int64_t off = offs[o];
     if (off < 0 || off + cnt > capacity) return;
-    const uint32_t vi = (uint32_t)(o / n);
-    const uint32_t g = (uint32_t)(o - (int64_t)vi * n);
     const int4 r = rect[o];
     const uint64_t lo = __float_as_uint(rec[3 * o + 1].z);
     const uint64_t tbase = (uint64_t)vi * (uint64_t)tiles_per_view;
@@ -425,7 +426,7 @@ __global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__res
         for (int tx = r.x; tx < r.z; ++tx) {
             const uint64_t tile = tbase + (uint64_t)ty * tiles_x + tx;
             keys[j] = (tile << 32) | lo;
-            vals[j] = g;
+            vals[j] = (uint32_t)g;
             ++j;
         }
 }
@@ -434,12 +435,13 @@ __global__ void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *
                               int64_t capacity, int64_t n_tiles, int2 *__restrict__ ranges) {
     const int64_t n = *n_pairs;
     if (n > capacity) return;   // overflow: every tile stays empty (0, 0)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t tile = keys[i] >> 32;
-    if (tile >= (uint64_t)n_tiles) return;
-    if (i == 0 || (keys[i - 1] >> 32) != tile) ranges[tile].x = (int32_t)i;
-    if (i == n - 1 || (keys[i + 1] >> 32) != tile) ranges[tile].y = (int32_t)(i + 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t tile = keys[i] >> 32;
+        if (tile >= (uint64_t)n_tiles) continue;
+        if (i == 0 || (keys[i - 1] >> 32) != tile) ranges[tile].x = (int32_t)i;
+        if (i == n - 1 || (keys[i + 1] >> 32) != tile) ranges[tile].y = (int32_t)(i + 1);
+    }
 }
 
 // ---------------------------------------------------------------- per-tile depth order
@@ -974,17 +976,19 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
     uint32_t *ev = (tpasses & 1) ? L.pv : vals;
     uint64_t *ok = (tpasses & 1) ? keys : L.pk;
     uint32_t *ov = (tpasses & 1) ? vals : L.pv;
-    emit_kernel<<<grid_for(m, 128), 128, 0, st>>>(reinterpret_cast<const float4 *>(rec), touched,
-                                                  L.offs, reinterpret_cast<const int4 *>(rect), m,
-                                                  n, vp.tiles_x, vp.tiles_per_view, pair_capacity,
-                                                  ek, ev, ranges, 2 * n_tiles);
+    emit_kernel<<<dim3(grid_for(n, 128), (unsigned)n_views), 128, 0, st>>>(
+        reinterpret_cast<const float4 *>(rec), touched, L.offs, reinterpret_cast<const int4 *>(rect),
+        n, vp.tiles_x, vp.tiles_per_view, pair_capacity, ek, ev, ranges, 2 * n_tiles);
     GS4D_LAUNCH_CHECK("emit");
     int alt = 0;
     GS4D_TRY(radix_sort_u64(ek, ev, ok, ov, n_pairs, 0, pair_capacity, 32, 32 + tbits, L.radix_ws,
                             st, &alt));
     // 4: ranges
-    ranges_kernel<<<grid_for(pair_capacity, 256), 256, 0, st>>>(keys, n_pairs, pair_capacity, n_tiles,
-                                                                reinterpret_cast<int2 *>(ranges));
+    // the pair count is on the device: a grid of at most 2,048 blocks strides
+    // over it
+    const unsigned rgrid = grid_for(pair_capacity, 256) < 2048u ? grid_for(pair_capacity, 256) : 2048u;
+    ranges_kernel<<<rgrid, 256, 0, st>>>(keys, n_pairs, pair_capacity, n_tiles,
+                                         reinterpret_cast<int2 *>(ranges));
     GS4D_LAUNCH_CHECK("ranges");
     // 5: depth order inside each tile (the pair buffer L.pk is free again)
     tile_depth_sort_kernel<<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
