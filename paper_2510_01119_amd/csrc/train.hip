@@ -145,7 +145,9 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
                 float *__restrict__ l1_grad) {
     __shared__ __align__(16) float sx[SS_E][SS_EP];
     __shared__ __align__(16) float sy[SS_E][SS_EP];
-    __shared__ __align__(16) float hs[5][SS_E][SS_T];
+    // row-filtered statistics, three planes: (mu_x, mu_y, E[x^2]) first, then
+    // (E[y^2], E[xy]) -- 30.9 KB of LDS in all
+    __shared__ __align__(16) float hs[3][SS_E][SS_T];
     const int t = threadIdx.x;
     const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
     const int64_t plane = (int64_t)blockIdx.z * h * w;
@@ -157,44 +159,55 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
         sy[r][c] = in ? Y[plane + (int64_t)gy * w + gx] : 0.0f;
     }
     __syncthreads();
-    for (int i = t; i < SS_E * (SS_T / SS_O); i += 256) {
-        const int r = i / (SS_T / SS_O), c0 = (i - r * (SS_T / SS_O)) * SS_O;
-        float xv[16], yv[16];
-        load_row14(sx[r], c0, xv);
-        load_row14(sy[r], c0, yv);
-        float a[SS_O] = {}, b[SS_O] = {}, aa[SS_O] = {}, bb[SS_O] = {}, ab[SS_O] = {};
-#pragma unroll
-        for (int k = 0; k < SS_K; ++k) {
-            const float g = win.g[k];
-#pragma unroll
-            for (int o = 0; o < SS_O; ++o) {
-                const float x = xv[o + k], y = yv[o + k];
-                a[o] += g * x;
-                b[o] += g * y;
-                aa[o] += g * x * x;
-                bb[o] += g * y * y;
-                ab[o] += g * x * y;
-            }
-        }
-        *reinterpret_cast<float4 *>(&hs[0][r][c0]) = make_float4(a[0], a[1], a[2], a[3]);
-        *reinterpret_cast<float4 *>(&hs[1][r][c0]) = make_float4(b[0], b[1], b[2], b[3]);
-        *reinterpret_cast<float4 *>(&hs[2][r][c0]) = make_float4(aa[0], aa[1], aa[2], aa[3]);
-        *reinterpret_cast<float4 *>(&hs[3][r][c0]) = make_float4(bb[0], bb[1], bb[2], bb[3]);
-        *reinterpret_cast<float4 *>(&hs[4][r][c0]) = make_float4(ab[0], ab[1], ab[2], ab[3]);
-    }
-    __syncthreads();
     const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
     float m[5][SS_O] = {};
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        float v[SS_W];
+    for (int grp = 0; grp < 2; ++grp) {
+        if (grp > 0) __syncthreads();   // the first group's column pass has read hs
+        for (int i = t; i < SS_E * (SS_T / SS_O); i += 256) {
+            const int r = i / (SS_T / SS_O), c0 = (i - r * (SS_T / SS_O)) * SS_O;
+            float xv[16], yv[16];
+            load_row14(sx[r], c0, xv);
+            load_row14(sy[r], c0, yv);
+            float s0[SS_O] = {}, s1[SS_O] = {}, s2[SS_O] = {};
 #pragma unroll
-        for (int k = 0; k < SS_W; ++k) v[k] = hs[q][r0 + k][c];
+            for (int k = 0; k < SS_K; ++k) {
+                const float g = win.g[k];
 #pragma unroll
-        for (int k = 0; k < SS_K; ++k) {
-            const float g = win.g[k];
+                for (int o = 0; o < SS_O; ++o) {
+                    const float x = xv[o + k], y = yv[o + k];
+                    if (grp == 0) {
+                        s0[o] += g * x;
+                        s1[o] += g * y;
+                        s2[o] += g * x * x;
+                    } else {
+                        s0[o] += g * y * y;
+                        s1[o] += g * x * y;
+                    }
+                }
+            }
+            *reinterpret_cast<float4 *>(&hs[0][r][c0]) = make_float4(s0[0], s0[1], s0[2], s0[3]);
+            *reinterpret_cast<float4 *>(&hs[1][r][c0]) = make_float4(s1[0], s1[1], s1[2], s1[3]);
+            if (grp == 0)
+                *reinterpret_cast<float4 *>(&hs[2][r][c0]) =
+                    make_float4(s2[0], s2[1], s2[2], s2[3]);
+        }
+        __syncthreads();
 #pragma unroll
-            for (int o = 0; o < SS_O; ++o) m[q][o] += g * v[o + k];
+        for (int q = 0; q < 3; ++q) {
+            if (grp == 1 && q == 2) continue;
+            float v[SS_W];
+#pragma unroll
+            for (int k = 0; k < SS_W; ++k) v[k] = hs[q][r0 + k][c];
+            float acc[SS_O] = {};
+#pragma unroll
+            for (int k = 0; k < SS_K; ++k) {
+                const float g = win.g[k];
+#pragma unroll
+                for (int o = 0; o < SS_O; ++o) acc[o] += g * v[o + k];
+            }
+#pragma unroll
+            for (int o = 0; o < SS_O; ++o) m[grp == 0 ? q : 3 + q][o] = acc[o];
         }
     }
     float sv = 0.0f, lv = 0.0f;
@@ -275,27 +288,30 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
                 const float *__restrict__ P3, float *__restrict__ dX, LossSum ls) {
     if (ls.out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
         sum_partials(ls.pa, ls.pb, ls.count, ls.a, ls.b, ls.c, ls.out, 1);
-    __shared__ __align__(16) float sp[3][SS_E][SS_EP];
-    __shared__ __align__(16) float hs[3][SS_E][SS_T];
+    // one map at a time (staged, filtered along rows, then along columns into
+    // registers): 12.8 KB of LDS, so that more blocks share a CU
+    __shared__ __align__(16) float sp[SS_E][SS_EP];
+    __shared__ __align__(16) float hs[SS_E][SS_T];
     const int t = threadIdx.x;
     const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
     const int64_t plane = (int64_t)blockIdx.z * h * w;
-    for (int i = t; i < SS_E * SS_EP; i += 256) {
-        const int r = i / SS_EP, c = i - r * SS_EP;
-        const int gy = oy + r, gx = ox + c;
-        const bool in = c < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
-        const int64_t o = plane + (int64_t)gy * w + gx;
-        sp[0][r][c] = in ? P1[o] : 0.0f;
-        sp[1][r][c] = in ? P2[o] : 0.0f;
-        sp[2][r][c] = in ? P3[o] : 0.0f;
-    }
-    __syncthreads();
-    for (int i = t; i < SS_E * (SS_T / SS_O); i += 256) {
-        const int r = i / (SS_T / SS_O), c0 = (i - r * (SS_T / SS_O)) * SS_O;
+    const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
+    float q[3][SS_O] = {};
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < 3; ++j) {
+        const float *Pj = j == 0 ? P1 : (j == 1 ? P2 : P3);
+        if (j > 0) __syncthreads();   // the previous map's column pass has read hs
+        for (int i = t; i < SS_E * SS_EP; i += 256) {
+            const int r = i / SS_EP, cc = i - r * SS_EP;
+            const int gy = oy + r, gx = ox + cc;
+            const bool in = cc < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
+            sp[r][cc] = in ? Pj[plane + (int64_t)gy * w + gx] : 0.0f;
+        }
+        __syncthreads();
+        for (int i = t; i < SS_E * (SS_T / SS_O); i += 256) {
+            const int r = i / (SS_T / SS_O), c0 = (i - r * (SS_T / SS_O)) * SS_O;
             float v[16];
-            load_row14(sp[j][r], c0, v);
+            load_row14(sp[r], c0, v);
             float a[SS_O] = {};
 #pragma unroll
             for (int k = 0; k < SS_K; ++k) {
@@ -303,17 +319,12 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
 #pragma unroll
                 for (int o = 0; o < SS_O; ++o) a[o] += g * v[o + k];
             }
-            *reinterpret_cast<float4 *>(&hs[j][r][c0]) = make_float4(a[0], a[1], a[2], a[3]);
+            *reinterpret_cast<float4 *>(&hs[r][c0]) = make_float4(a[0], a[1], a[2], a[3]);
         }
-    }
-    __syncthreads();
-    const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
-    float q[3][SS_O] = {};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
+        __syncthreads();
         float v[SS_W];
 #pragma unroll
-        for (int k = 0; k < SS_W; ++k) v[k] = hs[j][r0 + k][c];
+        for (int k = 0; k < SS_W; ++k) v[k] = hs[r0 + k][c];
 #pragma unroll
         for (int k = 0; k < SS_K; ++k) {
             const float g = win.g[k];
