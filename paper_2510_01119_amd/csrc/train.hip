@@ -293,25 +293,39 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
     if (ls.out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
         sum_partials(ls.pa, ls.pb, ls.count, ls.a, ls.b, ls.c, ls.out, 1);
     // one map at a time (staged, filtered along rows, then along columns into
-    // registers): 12.8 KB of LDS, so that more blocks share a CU
+    // registers): 12.8 KB of LDS, so that more blocks share a CU; the next
+    // map's values are loaded into registers while the current one is
+    // filtered
+    constexpr int SS_PER = (SS_E * SS_EP + 255) / 256;
     __shared__ __align__(16) float sp[SS_E][SS_EP];
     __shared__ __align__(16) float hs[SS_E][SS_T];
     const int t = threadIdx.x;
     const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
     const int64_t plane = (int64_t)blockIdx.z * h * w;
     const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
+    auto fetch = [&](const float *Pj, float (&pre)[SS_PER]) {
+#pragma unroll
+        for (int u = 0; u < SS_PER; ++u) {
+            const int i = t + u * 256;
+            const int r = i / SS_EP, cc = i - r * SS_EP;
+            const int gy = oy + r, gx = ox + cc;
+            const bool in = i < SS_E * SS_EP && cc < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
+            pre[u] = in ? Pj[plane + (int64_t)gy * w + gx] : 0.0f;
+        }
+    };
+    float pre[SS_PER];
+    fetch(P1, pre);
     float q[3][SS_O] = {};
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        const float *Pj = j == 0 ? P1 : (j == 1 ? P2 : P3);
-        if (j > 0) __syncthreads();   // the previous map's column pass has read hs
-        for (int i = t; i < SS_E * SS_EP; i += 256) {
-            const int r = i / SS_EP, cc = i - r * SS_EP;
-            const int gy = oy + r, gx = ox + cc;
-            const bool in = cc < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
-            sp[r][cc] = in ? Pj[plane + (int64_t)gy * w + gx] : 0.0f;
+        // sp's last readers (the previous map's row pass) are behind a barrier
+#pragma unroll
+        for (int u = 0; u < SS_PER; ++u) {
+            const int i = t + u * 256;
+            if (i < SS_E * SS_EP) (&sp[0][0])[i] = pre[u];
         }
         __syncthreads();
+        if (j < 2) fetch(j == 0 ? P2 : P3, pre);
         for (int i = t; i < SS_E * (SS_T / SS_O); i += 256) {
             const int r = i / (SS_T / SS_O), c0 = (i - r * (SS_T / SS_O)) * SS_O;
             float v[16];
@@ -335,6 +349,8 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
 #pragma unroll
             for (int o = 0; o < SS_O; ++o) q[j][o] += g * v[o + k];
         }
+        // the next map's row pass writes hs only after the barrier that
+        // follows its staging, so this column pass needs none of its own
     }
     const int gx = blockIdx.x * SS_T + c;
 #pragma unroll
