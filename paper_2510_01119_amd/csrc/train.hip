@@ -289,7 +289,8 @@ struct LossSum {
 __global__ void __launch_bounds__(256)
 ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h, int w, Win win,
                 float scale, const float *__restrict__ P1, const float *__restrict__ P2,
-                const float *__restrict__ P3, float *__restrict__ dX, LossSum ls) {
+                const float *__restrict__ P3, float *__restrict__ dX, float l1_scale,
+                int overwrite, LossSum ls) {
     if (ls.out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
         sum_partials(ls.pa, ls.pb, ls.count, ls.a, ls.b, ls.c, ls.out, 1);
     // one map at a time (staged, filtered along rows, then along columns into
@@ -358,7 +359,12 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
         const int gy = blockIdx.y * SS_T + r0 + o;
         if (gx < w && gy < h) {
             const int64_t po = plane + (int64_t)gy * w + gx;
-            dX[po] += scale * (q[0][o] + 2.f * X[po] * q[1][o] + Y[po] * q[2][o]);
+            const float x = X[po], y = Y[po];
+            // overwrite: dX = l1_scale sign(x - y) + the SSIM term (the
+            // photometric loss), else the SSIM term is added to dX
+            const float base =
+                overwrite ? (x > y ? l1_scale : (x < y ? -l1_scale : 0.0f)) : dX[po];
+            dX[po] = base + scale * (q[0][o] + 2.f * x * q[1][o] + y * q[2][o]);
         }
     }
 }
@@ -475,7 +481,7 @@ extern "C" int gs4d_ssim(const float *img, const float *target, int32_t b, int32
     }
     if (dL_dimg) {
         ssim_bwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, weight / (float)count, S.P1,
-                                                S.P2, S.P3, dL_dimg, LossSum{});
+                                                S.P2, S.P3, dL_dimg, 0.0f, 0, LossSum{});
         GS4D_LAUNCH_CHECK("gs4d_ssim bwd");
     }
     return GS4D_OK;
@@ -498,8 +504,11 @@ extern "C" int gs4d_photometric_loss(const float *img, const float *target, int3
     const float inv = 1.0f / (float)count;
     SsimWs S = carve_ssim(ws, ws_bytes, b, c, h, w);
     const Win win = make_window();
+    // with an SSIM term the backward writes the L1 gradient together with its
+    // own, else the forward writes it
     ssim_fwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, S.P1, S.P2, S.P3, S.part_ssim,
-                                            S.part_l1, w_l1 * inv, dL_dimg);
+                                            S.part_l1, w_l1 * inv,
+                                            w_ssim != 0.0f ? nullptr : dL_dimg);
     GS4D_LAUNCH_CHECK("gs4d_photometric_loss fwd");
     // loss = w_l1 mean|x - y| + w_ssim (1 - mean SSIM), summed by the first
     // block of the backward (or its own launch when there is no backward)
@@ -507,7 +516,7 @@ extern "C" int gs4d_photometric_loss(const float *img, const float *target, int3
                      -w_ssim * inv, w_ssim, loss};
     if (w_ssim != 0.0f) {
         ssim_bwd_kernel<<<S.grid, 256, 0, st>>>(img, target, h, w, win, -w_ssim * inv, S.P1, S.P2,
-                                                S.P3, dL_dimg, ls);
+                                                S.P3, dL_dimg, w_l1 * inv, 1, ls);
         GS4D_LAUNCH_CHECK("gs4d_photometric_loss bwd");
     } else {
         partial_sum_kernel<<<1, 256, 0, st>>>(ls.pa, ls.pb, ls.count, ls.a, ls.b, ls.c, loss, 1);
