@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--workload", default="scene", choices=["scene", "small", "batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR leg")
+    ap.add_argument("--no-fps", action="store_true",
+                    help="skip the forward-only frame-rate leg at display sizes")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--calib-copy", action="store_true",
@@ -308,6 +310,8 @@ def main():
                      "wg_ms": choice.get("wg_ms")},
         "roofline": roof,
     }
+    if args.workload == "scene" and not args.no_fps:
+        line["render_fps"] = render_fps_leg(tr.params, views)
     if not args.no_cpu_baseline:
         from paper_2510_01119_amd import synth  # noqa: F401
         p_np = tr.params.detach().cpu().numpy()
@@ -324,6 +328,25 @@ def main():
     if args.workload == "scene" and not args.no_ttp and pruned is not None:
         line["time_to_psnr"] = time_to_psnr_leg(params, views, images, pruned)
     print(json.dumps(line), flush=True)
+
+
+def render_fps_leg(params, views, frames=200):
+    """Forward-only frame rate of the parameters as they stand after the
+    timed training steps, at display sizes: 16 of the scene's cameras (the
+    960x540 intrinsics rescaled), each frame one graph replay of preprocess,
+    binning, tile ordering and compositing."""
+    import torch
+    from paper_2510_01119_amd.realtime import DISPLAY_SIZES, FrameRenderer, rescale_view
+    sel = np.linspace(0, len(views) - 1, 16).round().astype(int)
+    out = {}
+    for W, H in DISPLAY_SIZES:
+        vs = np.stack([rescale_view(views[f], W, H) for f in sel])
+        fr = FrameRenderer(params, vs)
+        out[f"{W}x{H}"] = fr.frame_rate(frames=frames)
+        del fr
+        torch.cuda.empty_cache()
+    log(f"bench: forward-only frame rate {json.dumps(out)}")
+    return out
 
 
 def time_to_psnr_leg(params, views, images, pruned):

@@ -140,6 +140,8 @@ typedef struct gs4d_render_opts {
  *   T_final  out float [n_views][H][W]
  *   last     out int32 [n_views][H][W]: global pair index of the last blended
  *            entry, -1 if none
+ *            T_final and last may both be NULL: forward-only rendering, which
+ *            keeps no state for gs4d_render_bwd (the image is the same)
  *   opts     host, may be NULL
  * ------------------------------------------------------------------------- */
 int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals, const int32_t *ranges,

@@ -238,8 +238,10 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
         img[0] = out[0];
         img[HW] = out[1];
         img[2 * HW] = out[2];
-        T_final[(int64_t)ti.v * HW + pix] = T;
-        last_out[(int64_t)ti.v * HW + pix] = last;
+        if (T_final) {   // null in forward-only rendering (no state for a backward)
+            T_final[(int64_t)ti.v * HW + pix] = T;
+            last_out[(int64_t)ti.v * HW + pix] = last;
+        }
         if (o.target) {
             const float *tg = o.target + (int64_t)ti.v * 3 * HW + pix;
             const float scale = o.l1_weight / (float)(3 * HW);
@@ -673,7 +675,9 @@ extern "C" int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals
     ViewPack vp;
     GS4D_TRY(make_view_pack(views, n_views, &vp));
     GS4D_TRY(check_render_args(rec, n, vals, ranges));
-    GS4D_REQUIRE(image && T_final && last, "gs4d_render_fwd: null output");
+    GS4D_REQUIRE(image, "gs4d_render_fwd: null image");
+    GS4D_REQUIRE((T_final == nullptr) == (last == nullptr),
+                 "gs4d_render_fwd: T_final and last must both be given or both be null");
     gs4d_render_opts o{};
     if (opts) o = *opts;
     if (o.batch == 0) o.batch = 256;

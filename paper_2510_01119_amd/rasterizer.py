@@ -15,11 +15,14 @@ from . import gs4d as G
 
 
 class Rasterizer:
-    """Buffers for rendering ``n`` Gaussians into ``views`` (numpy [V, 23])."""
+    """Buffers for rendering ``n`` Gaussians into ``views`` (numpy [V, 23]).
+    With ``forward_only`` no per-pixel state or gradient buffer is kept (the
+    forward then writes the image only; backward calls raise)."""
 
     def __init__(self, n: int, views, device="cuda", pair_capacity: int | None = None,
                  batch: int = 256, count_blends: bool = False, persistent: bool = False,
-                 n_workgroups: int = 0):
+                 n_workgroups: int = 0, forward_only: bool = False):
+        self.forward_only = bool(forward_only)
         self.device = torch.device(device)
         self.views_np = np.atleast_2d(np.asarray(views, dtype=np.float64))
         self.cviews = G.make_views(self.views_np)
@@ -38,10 +41,14 @@ class Rasterizer:
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
         self.image = torch.zeros((V, 3, H, W), dtype=torch.float32, device=dev)
-        self.T_final = torch.zeros((V, H, W), dtype=torch.float32, device=dev)
-        self.last = torch.zeros((V, H, W), dtype=torch.int32, device=dev)
-        self.dparams = torch.zeros((G.N_FIELDS, max(n, 1)), dtype=torch.float32, device=dev)
-        self.grad2d = torch.zeros((V, max(n, 1), G.GRAD2D_FLOATS), dtype=torch.float32, device=dev)
+        if self.forward_only:
+            self.T_final = self.last = self.dparams = self.grad2d = None
+        else:
+            self.T_final = torch.zeros((V, H, W), dtype=torch.float32, device=dev)
+            self.last = torch.zeros((V, H, W), dtype=torch.int32, device=dev)
+            self.dparams = torch.zeros((G.N_FIELDS, max(n, 1)), dtype=torch.float32, device=dev)
+            self.grad2d = torch.zeros((V, max(n, 1), G.GRAD2D_FLOATS), dtype=torch.float32,
+                                      device=dev)
         self.counters = torch.zeros(2, dtype=torch.int64, device=dev) if count_blends else None
         # persistent launches: largest-first tile order + one work counter per kernel
         self.persistent = persistent
@@ -59,7 +66,8 @@ class Rasterizer:
         self.target = None
         self.l1_weight = 1.0
         self.loss_per_view = torch.zeros(V, dtype=torch.float32, device=dev)
-        self.dL_dimage = torch.zeros((V, 3, H, W), dtype=torch.float32, device=dev)
+        self.dL_dimage = (None if self.forward_only
+                          else torch.zeros((V, 3, H, W), dtype=torch.float32, device=dev))
         self._alloc_pairs(pair_capacity if pair_capacity else max(1 << 16, 8 * n * V))
 
     def set_views(self, views):
@@ -143,11 +151,13 @@ class Rasterizer:
             opts.target = self.target.data_ptr()
             opts.l1_weight = self.l1_weight
             opts.loss_per_view = self.loss_per_view.data_ptr()
-            opts.dL_dimage = self.dL_dimage.data_ptr()
+            opts.dL_dimage = self.dL_dimage.data_ptr() if self.dL_dimage is not None else 0
         G.gs4d_render_fwd(self.rec, self.n, self.vals, self.ranges, self.cviews, self.image,
                           self.T_final, self.last, opts)
 
     def render_bwd_2d(self, dL_dimage):
+        if self.forward_only:
+            raise RuntimeError("forward-only rasterizer: no state for a backward")
         if self.persistent:
             self._bwd_queue()
         G.gs4d_render_bwd_2d(self.rec, self.n, self.vals, self.ranges, self.cviews, dL_dimage,
@@ -161,6 +171,8 @@ class Rasterizer:
         return self.image
 
     def backward(self, params: torch.Tensor, dL_dimage: torch.Tensor):
+        if self.forward_only:
+            raise RuntimeError("forward-only rasterizer: no state for a backward")
         if self.persistent:
             self._bwd_queue()
         G.gs4d_render_bwd(params, self.rec, self.touched, self.vals, self.ranges, self.cviews,

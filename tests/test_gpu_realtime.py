@@ -1,0 +1,60 @@
+"""Forward-only rendering at display sizes (the frame-rate path).
+
+* a forward-only rasterizer (no T_final / last / gradient buffers) writes
+  the same image bits as the training forward, and refuses a backward;
+* FrameRenderer at 480x270 (a 960x540 camera rescaled): every frame's graph
+  replay equals its eager launches bit for bit, and the image matches the
+  oracle's compositing to 1e-4 except at pixels next to an alpha / clamp /
+  transmittance threshold.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_01119_amd import synth
+from paper_2510_01119_amd.rasterizer import Rasterizer
+from paper_2510_01119_amd.realtime import FrameRenderer, rescale_view
+
+from gpu_helpers import gpu_forward, near_threshold_pixels, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_forward_only_image_equals_training_forward():
+    need_gpu()
+    p = synth.small_set(2000, 0)
+    view = synth.front_view(64, 64, 64.0)
+    r1, P = gpu_forward(p, view)
+    r2 = Rasterizer(2000, view, forward_only=True)
+    r2.forward(P)
+    torch.cuda.synchronize()
+    assert r2.T_final is None and r2.last is None
+    assert torch.equal(r1.image, r2.image)
+    with pytest.raises(RuntimeError):
+        r2.render_bwd_2d(torch.zeros_like(r2.image))
+
+
+def test_frame_renderer_display_size():
+    need_gpu()
+    p = synth.small_set(6000, 5, log_s_xyz=(-3.5, 0.5))
+    base = [synth.front_view(960, 540, 800.0, 3.0, t) for t in (0.25, 0.5, 0.75)]
+    views = np.stack([rescale_view(v, 480, 270) for v in base])
+    P = torch.from_numpy(p).cuda()
+    fr = FrameRenderer(P, views)
+    fr.capture()
+    for f in range(len(views)):
+        fr.replay(f)
+        torch.cuda.synchronize()
+        img = fr.image.clone()
+        fr.render(f)
+        torch.cuda.synchronize()
+        assert torch.equal(img, fr.image)
+        o = oracle.forward(p, views[f], "f32")
+        near = near_threshold_pixels(o["rec"].astype(np.float64), views[f][None], o["vals"],
+                                     o["ranges"])
+        diff = np.abs(img.cpu().numpy() - o["image"]).max(axis=1)
+        assert not np.any((diff > 1e-4) & ~near), diff[~near].max()
+        assert near.mean() < 1e-2
+    rate = fr.frame_rate(frames=30, warmup=3)
+    assert rate["fps"] > 0 and rate["peak_pairs"] > 0
