@@ -33,6 +33,8 @@ _SIGS = {
     "or_logf_public": (_f32, [_f32]),
     "or_preprocess_f32": (None, [_p, _i64, _p, _i32, _p, _p, _p]),
     "or_preprocess_f64": (None, [_p, _i64, _p, _i32, _p, _p, _p]),
+    "or_preprocess_iso_f32": (None, [_p, _i64, _p, _i32, _p, _p, _p]),
+    "or_preprocess_iso_f64": (None, [_p, _i64, _p, _i32, _p, _p, _p]),
     "or_covariance_f64": (_i32, [_p, _i64, _i64, _p]),
     "or_conditional_f64": (_i32, [_p, _i64, _i64, _f64, _p, _p, _p]),
     "or_bin_sort": (_i64, [_p, _p, _p, _i64, _i32, _i32, _i32, _i64, _p, _p, _p]),
@@ -107,6 +109,38 @@ def preprocess_f64(params, views):
     rect = np.zeros((V, n, 4), np.int32)
     touched = np.zeros((V, n), np.int32)
     lib().or_preprocess_f64(_ptr(P), n, _ptr(v), V, _ptr(rec), _ptr(rect), _ptr(touched))
+    return rec, rect, touched
+
+
+ISO_FIELDS = 13   # isotropic, motion-aware parameters per Gaussian
+
+
+def preprocess_iso_f32(params, views):
+    """Preprocess of the isotropic, motion-aware parameterisation ([13][n]:
+    mean xyz t, log s, log s_t, velocity xyz, opacity logit, rgb) in the
+    kernel's precision; same outputs as preprocess_f32."""
+    P = np.ascontiguousarray(params, dtype=np.float32)
+    assert P.shape[0] == ISO_FIELDS
+    v = _views(views)
+    n = P.shape[1]
+    V = v.shape[0]
+    rec = np.zeros((V, n, REC), np.float32)
+    rect = np.zeros((V, n, 4), np.int32)
+    touched = np.zeros((V, n), np.int32)
+    lib().or_preprocess_iso_f32(_ptr(P), n, _ptr(v), V, _ptr(rec), _ptr(rect), _ptr(touched))
+    return rec, rect, touched
+
+
+def preprocess_iso_f64(params, views):
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    assert P.shape[0] == ISO_FIELDS
+    v = _views(views)
+    n = P.shape[1]
+    V = v.shape[0]
+    rec = np.zeros((V, n, REC), np.float64)
+    rect = np.zeros((V, n, 4), np.int32)
+    touched = np.zeros((V, n), np.int32)
+    lib().or_preprocess_iso_f64(_ptr(P), n, _ptr(v), V, _ptr(rec), _ptr(rect), _ptr(touched))
     return rec, rect, touched
 
 

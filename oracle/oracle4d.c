@@ -151,6 +151,29 @@ void or_preprocess_f64(const double *params, int64_t n, const double *views, int
         }
 }
 
+/* Isotropic, motion-aware parameterisation: params [13][n] planes. */
+void or_preprocess_iso_f32(const float *params, int64_t n, const double *views, int32_t n_views,
+                           float *rec, int32_t *rect, int32_t *touched)
+{
+    for (int32_t vi = 0; vi < n_views; ++vi)
+        for (int64_t g = 0; g < n; ++g) {
+            const int64_t o = (int64_t)vi * n + g;
+            preprocess_iso_one_f32(params, n, g, views + (int64_t)vi * OR_VIEW, rec + o * OR_REC,
+                                   rect + o * 4, touched + o);
+        }
+}
+
+void or_preprocess_iso_f64(const double *params, int64_t n, const double *views, int32_t n_views,
+                           double *rec, int32_t *rect, int32_t *touched)
+{
+    for (int32_t vi = 0; vi < n_views; ++vi)
+        for (int64_t g = 0; g < n; ++g) {
+            const int64_t o = (int64_t)vi * n + g;
+            preprocess_iso_one_f64(params, n, g, views + (int64_t)vi * OR_VIEW, rec + o * OR_REC,
+                                   rect + o * 4, touched + o);
+        }
+}
+
 /* Self-check helpers (FP64): Sigma (row-major 4x4) of Gaussian g, and its
  * conditional at time t: mu[3], Sc (row-major 3x3), o_t.  Return 0 if
  * degenerate. */
