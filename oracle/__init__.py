@@ -43,6 +43,7 @@ _SIGS = {
     "or_render_brute": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "or_render_bwd": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "or_preprocess_bwd": (None, [_p, _i64, _p, _i32, _p, _p]),
+    "or_preprocess_iso_bwd": (None, [_p, _i64, _p, _i32, _p, _p]),
     "or_grid_prune": (_i64, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p]),
 }
 
@@ -248,6 +249,19 @@ def preprocess_bwd(params, views, grad_rec):
     d = np.zeros((20, n))
     lib().or_preprocess_bwd(_ptr(P), n, _ptr(v), v.shape[0],
                             _ptr(np.ascontiguousarray(grad_rec, np.float64)), _ptr(d))
+    return d
+
+
+def preprocess_iso_bwd(params, views, grad_rec):
+    """Chain rule of the isotropic, motion-aware preprocess (FP64): grad_rec
+    [V, n, 9] = d(mean2D, conic, o_t, rgb) -> d params [13, n]."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    assert P.shape[0] == ISO_FIELDS
+    v = _views(views)
+    n = P.shape[1]
+    d = np.zeros((ISO_FIELDS, n))
+    lib().or_preprocess_iso_bwd(_ptr(P), n, _ptr(v), v.shape[0],
+                                _ptr(np.ascontiguousarray(grad_rec, np.float64)), _ptr(d))
     return d
 
 

@@ -481,6 +481,91 @@ void or_render_bwd(const double *rec, int64_t n, const double *views, int32_t n_
     }
 }
 
+/* Backward of the projection (FP64) for one record: d(mean2D, conic) in
+ * G[0..4] -> d(conditional mean) Gmu and d(conditional covariance) GSc,
+ * through Sigma2D = T Sc T^T + 0.3 I, T = J W, the guard-banded Jacobian and
+ * the camera point (no gradient through a clamped coordinate). */
+static void proj_bwd_f64(const double *vw, const double mu[3], double Sc[3][3], const double *G,
+                         double Gmu[3], double GSc[3][3])
+{
+    int i, j, k;
+    double Wm[3][3];
+    for (i = 0; i < 3; ++i)
+        for (j = 0; j < 3; ++j) Wm[i][j] = vw[4 * i + j];
+    const double fx = vw[12], fy = vw[13];
+    const int Wd = (int)vw[16], Hd = (int)vw[17];
+    double xc[3];
+    for (i = 0; i < 3; ++i) xc[i] = Wm[i][0] * mu[0] + Wm[i][1] * mu[1] + Wm[i][2] * mu[2] + vw[4 * i + 3];
+    const double z = xc[2];
+    const double limx = 1.3 * (0.5 * Wd / fx), limy = 1.3 * (0.5 * Hd / fy);
+    const double ux0 = xc[0] / z, uy0 = xc[1] / z;
+    const int clx = (ux0 < -limx) || (ux0 > limx), cly = (uy0 < -limy) || (uy0 > limy);
+    const double ux = fmin(fmax(ux0, -limx), limx), uy = fmin(fmax(uy0, -limy), limy);
+    double J[2][3] = { { fx / z, 0.0, -fx * ux / z }, { 0.0, fy / z, -fy * uy / z } };
+    double T[2][3];
+    for (i = 0; i < 2; ++i)
+        for (j = 0; j < 3; ++j) {
+            T[i][j] = 0.0;
+            for (k = 0; k < 3; ++k) T[i][j] += J[i][k] * Wm[k][j];
+        }
+    double S2[2][2];
+    for (i = 0; i < 2; ++i)
+        for (j = 0; j < 2; ++j) {
+            double acc = 0.0;
+            for (k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) acc += T[i][k] * Sc[k][l] * T[j][l];
+            S2[i][j] = acc + (i == j ? 0.3 : 0.0);
+        }
+    const double det = S2[0][0] * S2[1][1] - S2[0][1] * S2[0][1];
+    double Qc[2][2] = { { S2[1][1] / det, -S2[0][1] / det }, { -S2[0][1] / det, S2[0][0] / det } };
+
+    /* ---- backward ---- */
+    /* conic -> Sigma2D : dL/dS2 = -Q Gq Q, Gq symmetric */
+    double Gq[2][2] = { { G[2], 0.5 * G[3] }, { 0.5 * G[3], G[4] } };
+    double tmp[2][2], GS2[2][2];
+    for (i = 0; i < 2; ++i)
+        for (j = 0; j < 2; ++j) tmp[i][j] = Gq[i][0] * Qc[0][j] + Gq[i][1] * Qc[1][j];
+    for (i = 0; i < 2; ++i)
+        for (j = 0; j < 2; ++j) GS2[i][j] = -(Qc[i][0] * tmp[0][j] + Qc[i][1] * tmp[1][j]);
+    /* Sigma2D = T Sc T^T : dL/dSc = T^T GS2 T ; dL/dT = 2 GS2 T Sc */
+    double GT[2][3];
+    for (i = 0; i < 3; ++i)
+        for (j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l) acc += T[k][i] * GS2[k][l] * T[l][j];
+            GSc[i][j] = acc;
+        }
+    for (i = 0; i < 2; ++i)
+        for (j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (k = 0; k < 2; ++k)
+                for (int l = 0; l < 3; ++l) acc += GS2[i][k] * T[k][l] * Sc[l][j];
+            GT[i][j] = 2.0 * acc;
+        }
+    /* T = J W : dL/dJ = GT W^T */
+    double GJ[2][3];
+    for (i = 0; i < 2; ++i)
+        for (j = 0; j < 3; ++j) {
+            GJ[i][j] = 0.0;
+            for (k = 0; k < 3; ++k) GJ[i][j] += GT[i][k] * Wm[j][k];
+        }
+    /* J entries -> camera-space point */
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    gz += GJ[0][0] * (-fx / (z * z)) + GJ[1][1] * (-fy / (z * z));
+    /* J02 = -fx ux / z with ux = x/z unless clamped */
+    if (clx) gz += GJ[0][2] * (fx * ux / (z * z));
+    else { gx += GJ[0][2] * (-fx / (z * z)); gz += GJ[0][2] * (2.0 * fx * xc[0] / (z * z * z)); }
+    if (cly) gz += GJ[1][2] * (fy * uy / (z * z));
+    else { gy += GJ[1][2] * (-fy / (z * z)); gz += GJ[1][2] * (2.0 * fy * xc[1] / (z * z * z)); }
+    /* mean2D = (fx x/z + cx, fy y/z + cy) */
+    gx += G[0] * fx / z;
+    gy += G[1] * fy / z;
+    gz += -G[0] * fx * xc[0] / (z * z) - G[1] * fy * xc[1] / (z * z);
+    /* camera -> conditional mean */
+    for (j = 0; j < 3; ++j) Gmu[j] = Wm[0][j] * gx + Wm[1][j] * gy + Wm[2][j] * gz;
+}
+
 /* ------------------------------------------------------------------------- *
  * Preprocess backward (FP64): chain rule from d(mean2D, conic, o_t, rgb) per
  * (view, Gaussian) to the 20 raw parameters, summed over views.
@@ -500,11 +585,7 @@ void or_preprocess_bwd(const double *params, int64_t n, const double *views, int
             double v[20];
             int i, j, k;
             for (k = 0; k < 20; ++k) v[k] = params[(int64_t)k * n + g];
-            double Wm[3][3];
-            for (i = 0; i < 3; ++i)
-                for (j = 0; j < 3; ++j) Wm[i][j] = vw[4 * i + j];
-            const double fx = vw[12], fy = vw[13], t = vw[18];
-            const int Wd = (int)vw[16], Hd = (int)vw[17];
+            const double t = vw[18];
 
             /* ---- recompute forward intermediates ---- */
             double s[4];
@@ -540,77 +621,8 @@ void or_preprocess_bwd(const double *params, int64_t n, const double *views, int
                 for (j = 0; j < 3; ++j) Sc[i][j] = Sg[i][j] - a3[i] * a3[j] / c;
             const double ef = exp(-0.5 * dt * dt / c);
             const double ot = o * ef;
-            double xc[3];
-            for (i = 0; i < 3; ++i) xc[i] = Wm[i][0] * mu[0] + Wm[i][1] * mu[1] + Wm[i][2] * mu[2] + vw[4 * i + 3];
-            const double z = xc[2];
-            const double limx = 1.3 * (0.5 * Wd / fx), limy = 1.3 * (0.5 * Hd / fy);
-            const double ux0 = xc[0] / z, uy0 = xc[1] / z;
-            const int clx = (ux0 < -limx) || (ux0 > limx), cly = (uy0 < -limy) || (uy0 > limy);
-            const double ux = fmin(fmax(ux0, -limx), limx), uy = fmin(fmax(uy0, -limy), limy);
-            double J[2][3] = { { fx / z, 0.0, -fx * ux / z }, { 0.0, fy / z, -fy * uy / z } };
-            double T[2][3];
-            for (i = 0; i < 2; ++i)
-                for (j = 0; j < 3; ++j) {
-                    T[i][j] = 0.0;
-                    for (k = 0; k < 3; ++k) T[i][j] += J[i][k] * Wm[k][j];
-                }
-            double S2[2][2];
-            for (i = 0; i < 2; ++i)
-                for (j = 0; j < 2; ++j) {
-                    double acc = 0.0;
-                    for (k = 0; k < 3; ++k)
-                        for (int l = 0; l < 3; ++l) acc += T[i][k] * Sc[k][l] * T[j][l];
-                    S2[i][j] = acc + (i == j ? 0.3 : 0.0);
-                }
-            const double det = S2[0][0] * S2[1][1] - S2[0][1] * S2[0][1];
-            double Qc[2][2] = { { S2[1][1] / det, -S2[0][1] / det }, { -S2[0][1] / det, S2[0][0] / det } };
-
-            /* ---- backward ---- */
-            /* conic -> Sigma2D : dL/dS2 = -Q Gq Q, Gq symmetric */
-            double Gq[2][2] = { { G[2], 0.5 * G[3] }, { 0.5 * G[3], G[4] } };
-            double tmp[2][2], GS2[2][2];
-            for (i = 0; i < 2; ++i)
-                for (j = 0; j < 2; ++j) tmp[i][j] = Gq[i][0] * Qc[0][j] + Gq[i][1] * Qc[1][j];
-            for (i = 0; i < 2; ++i)
-                for (j = 0; j < 2; ++j) GS2[i][j] = -(Qc[i][0] * tmp[0][j] + Qc[i][1] * tmp[1][j]);
-            /* Sigma2D = T Sc T^T : dL/dSc = T^T GS2 T ; dL/dT = 2 GS2 T Sc */
-            double GSc[3][3], GT[2][3];
-            for (i = 0; i < 3; ++i)
-                for (j = 0; j < 3; ++j) {
-                    double acc = 0.0;
-                    for (k = 0; k < 2; ++k)
-                        for (int l = 0; l < 2; ++l) acc += T[k][i] * GS2[k][l] * T[l][j];
-                    GSc[i][j] = acc;
-                }
-            for (i = 0; i < 2; ++i)
-                for (j = 0; j < 3; ++j) {
-                    double acc = 0.0;
-                    for (k = 0; k < 2; ++k)
-                        for (int l = 0; l < 3; ++l) acc += GS2[i][k] * T[k][l] * Sc[l][j];
-                    GT[i][j] = 2.0 * acc;
-                }
-            /* T = J W : dL/dJ = GT W^T */
-            double GJ[2][3];
-            for (i = 0; i < 2; ++i)
-                for (j = 0; j < 3; ++j) {
-                    GJ[i][j] = 0.0;
-                    for (k = 0; k < 3; ++k) GJ[i][j] += GT[i][k] * Wm[j][k];
-                }
-            /* J entries -> camera-space point */
-            double gx = 0.0, gy = 0.0, gz = 0.0;
-            gz += GJ[0][0] * (-fx / (z * z)) + GJ[1][1] * (-fy / (z * z));
-            /* J02 = -fx ux / z with ux = x/z unless clamped */
-            if (clx) gz += GJ[0][2] * (fx * ux / (z * z));
-            else { gx += GJ[0][2] * (-fx / (z * z)); gz += GJ[0][2] * (2.0 * fx * xc[0] / (z * z * z)); }
-            if (cly) gz += GJ[1][2] * (fy * uy / (z * z));
-            else { gy += GJ[1][2] * (-fy / (z * z)); gz += GJ[1][2] * (2.0 * fy * xc[1] / (z * z * z)); }
-            /* mean2D = (fx x/z + cx, fy y/z + cy) */
-            gx += G[0] * fx / z;
-            gy += G[1] * fy / z;
-            gz += -G[0] * fx * xc[0] / (z * z) - G[1] * fy * xc[1] / (z * z);
-            /* camera -> conditional mean */
-            double Gmu[3];
-            for (j = 0; j < 3; ++j) Gmu[j] = Wm[0][j] * gx + Wm[1][j] * gy + Wm[2][j] * gz;
+            double Gmu[3], GSc[3][3];
+            proj_bwd_f64(vw, mu, Sc, G, Gmu, GSc);
             /* conditional -> Sigma blocks, mean, opacity */
             const double go = G[5];
             double Gmua = Gmu[0] * a3[0] + Gmu[1] * a3[1] + Gmu[2] * a3[2];
@@ -675,6 +687,56 @@ void or_preprocess_bwd(const double *params, int64_t n, const double *views, int
             }
             dp[(int64_t)16 * n + g] += Gdo * o * (1.0 - o);
             for (k = 0; k < 3; ++k) dp[(int64_t)(17 + k) * n + g] += G[6 + k];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- *
+ * Preprocess backward of the isotropic, motion-aware form (FP64), summed
+ * over views; dparams [13][n] overwritten.  With dt = t - mu_t and
+ * c = s_t^2:
+ *   mu_c = mu + v dt    -> d mu += Gmu, d v += Gmu dt, d mu_t -= v . Gmu;
+ *   Sc = s^2 I          -> d log s = 2 s^2 trace(GSc);
+ *   o_t = o exp(-dt^2 / (2c)) -> d mu_t += go o_t dt / c,
+ *                          d log s_t = go o_t dt^2 / c,
+ *                          d logit = go exp(-dt^2 / (2c)) o (1 - o).
+ * ------------------------------------------------------------------------- */
+void or_preprocess_iso_bwd(const double *params, int64_t n, const double *views, int32_t n_views,
+                           const double *grad_rec, double *dparams)
+{
+    memset(dparams, 0, sizeof(double) * 13 * (size_t)n);
+    for (int32_t vi = 0; vi < n_views; ++vi) {
+        const double *vw = views + (int64_t)vi * OR_VIEW;
+        for (int64_t g = 0; g < n; ++g) {
+            double rec[OR_REC];
+            int32_t rect[4], touched;
+            if (!preprocess_iso_one_f64(params, n, g, vw, rec, rect, &touched)) continue;
+            const double *G = grad_rec + ((int64_t)vi * n + g) * 9;
+            double v[13], d[13];
+            int i, k;
+            for (k = 0; k < 13; ++k) { v[k] = params[(int64_t)k * n + g]; d[k] = 0.0; }
+            const double t = vw[18];
+            const double s = exp(v[4]), st = exp(v[5]);
+            const double o = 1.0 / (1.0 + exp(-v[9]));
+            const double c = st * st, dt = t - v[3];
+            double mu[3], Sc[3][3] = { { s * s, 0.0, 0.0 }, { 0.0, s * s, 0.0 }, { 0.0, 0.0, s * s } };
+            for (i = 0; i < 3; ++i) mu[i] = v[i] + v[6 + i] * dt;
+            const double ef = exp(-0.5 * dt * dt / c), ot = o * ef;
+            double Gmu[3], GSc[3][3];
+            proj_bwd_f64(vw, mu, Sc, G, Gmu, GSc);
+            const double go = G[5];
+            double vG = 0.0;
+            for (i = 0; i < 3; ++i) {
+                d[i] += Gmu[i];
+                d[6 + i] += Gmu[i] * dt;
+                vG += v[6 + i] * Gmu[i];
+            }
+            d[3] += -vG + go * ot * dt / c;
+            d[4] += 2.0 * s * s * (GSc[0][0] + GSc[1][1] + GSc[2][2]);
+            d[5] += go * ot * dt * dt / c;
+            d[9] += go * ef * o * (1.0 - o);
+            for (k = 0; k < 3; ++k) d[10 + k] += G[6 + k];
+            for (k = 0; k < 13; ++k) dparams[(int64_t)k * n + g] += d[k];
         }
     }
 }

@@ -11,6 +11,7 @@ rotor-form path it is a special case of.
   through the general conditional of Eq. "4dgs", to 1e-9 in FP64.
 """
 import numpy as np
+import pytest
 
 import oracle
 from oracle import motion
@@ -68,3 +69,76 @@ def test_velocity_matches_rotor_form_of_same_covariance():
         d = np.abs(ra[both] - rb[both])
         scale = np.maximum(np.abs(rb[both]), 1.0)
         assert (d / scale).max() < 1e-9
+
+
+def _loss_and_sig(p, vs, w):
+    rec, rect, touched = oracle.preprocess_iso_f64(p, vs)
+    keys, vals, ranges = oracle.bin_sort(rect, touched, oracle.depth_bits(rec), vs)
+    out = oracle.render_fwd(rec, vs, vals, ranges, signature=True)
+    return float((w * out["image"]).sum()), out["sig"], (rec, vals, ranges)
+
+
+@pytest.mark.parametrize("seed,n_views", [(31, 1), (32, 2)])
+def test_iso_backward_vs_central_differences(seed, n_views):
+    """The FP64 chain rule (render backward, then the isotropic preprocess
+    backward) against central differences (h = 1e-6) of the FP64 forward of a
+    random linear loss; entries whose +-h step changes a blend decision (the
+    per-pixel signature) are skipped."""
+    n = 120
+    rng = np.random.default_rng(seed)
+    p = np.zeros((oracle.ISO_FIELDS, n))
+    p[0:3] = rng.uniform(-1.0, 1.0, (3, n))
+    p[3] = rng.uniform(0.35, 0.65, n)
+    p[4] = rng.normal(-2.0, 0.4, n)
+    p[5] = rng.normal(-1.0, 0.3, n)
+    p[6:9] = rng.normal(0.0, 0.3, (3, n))
+    p[9] = rng.normal(0.0, 1.0, n)
+    p[10:13] = rng.uniform(0.0, 1.0, (3, n))
+    vs = np.stack([synth.front_view(48, 40, f=48.0, dist=3.0, t=0.45 + 0.1 * i)
+                   for i in range(n_views)])
+    w = synth.linear_loss_weights(n_views, 40, 48, seed=seed).astype(np.float64)
+    L0, sig0, (rec, vals, ranges) = _loss_and_sig(p, vs, w)
+    grec = oracle.render_bwd(rec, vs, vals, ranges, w)
+    grad = oracle.preprocess_iso_bwd(p, vs, grec)
+    _, _, touched = oracle.preprocess_iso_f64(p, vs)
+    vis = np.nonzero(touched.sum(axis=0) > 0)[0]
+    h = 1e-6
+    checked, rejected = 0, 0
+    per_class = np.zeros(oracle.ISO_FIELDS, int)
+    for k in range(oracle.ISO_FIELDS):
+        for g in rng.choice(vis, size=6, replace=False):
+            pp = p.copy()
+            pp[k, g] += h
+            Lp, sp, _ = _loss_and_sig(pp, vs, w)
+            pp[k, g] -= 2 * h
+            Lm, sm, _ = _loss_and_sig(pp, vs, w)
+            if not (np.array_equal(sp, sig0) and np.array_equal(sm, sig0)):
+                rejected += 1
+                continue
+            fd = (Lp - Lm) / (2 * h)
+            scale = max(abs(fd), 1e-3 * np.abs(grad[k]).max(), 1e-9)
+            assert abs(grad[k, g] - fd) <= 1e-5 * scale, (k, g, grad[k, g], fd)
+            checked += 1
+            per_class[k] += 1
+    assert rejected <= 0.1 * (checked + rejected)
+    assert np.all(per_class >= 3), per_class
+
+
+def test_zero_velocity_gradient_is_identity_rotor_gradient():
+    """With v = 0 the isotropic form is the rotor form with identity
+    quaternions and tied scales, so its gradients are sums of the rotor
+    form's: d log s = d log s_x + d log s_y + d log s_z, d log s_t = the
+    rotor's, the rest equal (FP64)."""
+    p = _iso_set(300, 3, zero_velocity=True)
+    base = _rotor_base(p)
+    view = synth.front_view(64, 48, 64.0, 3.0, 0.5)
+    rec, _, touched = oracle.preprocess_iso_f64(p, view)
+    rng = np.random.default_rng(4)
+    grec = rng.normal(0.0, 1.0, (1, p.shape[1], 9)) * (touched[..., None] > 0)
+    gi = oracle.preprocess_iso_bwd(p, view, grec)
+    gr = oracle.preprocess_bwd(base, view, grec)
+    assert np.abs(gi).sum() > 0
+    pairs = [(gi[0:4], gr[0:4]), (gi[4], gr[4] + gr[5] + gr[6]), (gi[5], gr[7]), (gi[9], gr[16]),
+             (gi[10:13], gr[17:20])]
+    for a, b in pairs:
+        assert np.allclose(a, b, rtol=1e-9, atol=1e-12 * np.abs(b).max())
