@@ -53,6 +53,7 @@ typedef enum {
 } gs4d_status;
 
 #define GS4D_N_FIELDS 20     /* floats per Gaussian in params / dparams     */
+#define GS4D_ISO_FIELDS 13   /* floats per Gaussian, isotropic motion-aware form */
 #define GS4D_REC_FLOATS 12   /* floats per (view, Gaussian) projected record */
 #define GS4D_GRAD2D_FLOATS 9 /* floats per (view, Gaussian) 2D gradient      */
 #define GS4D_TILE 16         /* tile edge in pixels                          */
@@ -89,6 +90,26 @@ typedef struct gs4d_view {
  * ------------------------------------------------------------------------- */
 int gs4d_preprocess(const float *params, int64_t n, const gs4d_view *views, int32_t n_views,
                     float *rec, int32_t *rect, int32_t *touched, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * gs4d_preprocess_iso -- gs4d_preprocess for the paper's isotropic,
+ *   motion-aware parameterisation (Sec. 3.3 "Motion-Aware Gaussian" and the
+ *   isotropic variant: one spatial scale, a temporal scale and a velocity).
+ *   params   float [13][n]: 0-2 mean xyz, 3 mean t, 4 log s, 5 log s_t,
+ *            6-8 velocity v (d mean / d t), 9 opacity logit, 10-12 rgb.
+ *   The 4D covariance [[s^2 I + s_t^2 v v^T, s_t^2 v], [s_t^2 v^T, s_t^2]]
+ *   sliced at the view's t gives mean + v (t - mean_t), covariance s^2 I
+ *   and o_t = o exp(-(t - mean_t)^2 / (2 s_t^2)); projection, culls,
+ *   record layout, rect and touched are those of gs4d_preprocess, so
+ *   gs4d_bin_sort and the renderers take the output unchanged.
+ * gs4d_preprocess_iso_bwd -- its chain rule from grad2d [n_views][n][9]
+ *   to dparams [13][n] (overwritten, summed over views).
+ * ------------------------------------------------------------------------- */
+int gs4d_preprocess_iso(const float *params, int64_t n, const gs4d_view *views, int32_t n_views,
+                        float *rec, int32_t *rect, int32_t *touched, void *stream);
+int gs4d_preprocess_iso_bwd(const float *params, int64_t n, const gs4d_view *views,
+                            int32_t n_views, const int32_t *touched, const float *grad2d,
+                            float *dparams, void *stream);
 
 /* ---------------------------------------------------------------------------
  * gs4d_bin_sort -- duplicate each visible (view, Gaussian) once per touched

@@ -84,6 +84,8 @@ struct Slice {
     float hx, hy;             // footprint half-widths
 };
 
+__device__ __forceinline__ int project_slice(const gs4d_view &V, Slice &S, int4 *rect_out);
+
 // Returns 1 if the Gaussian is visible; `touched`/`rect` filled when asked.
 __device__ __forceinline__ int slice_project(const float (&p)[20], const gs4d_view &V, Slice &S,
                                              int4 *rect_out) {
@@ -148,6 +150,39 @@ __device__ __forceinline__ int slice_project(const float (&p)[20], const gs4d_vi
     const float qd = (S.dt * S.dt) / c;
     S.ef = fixed_exp(-0.5f * qd);
     S.ot = S.o * S.ef;
+    return project_slice(V, S, rect_out);
+}
+
+// Isotropic, motion-aware parameters (13 per Gaussian: mean xyz t, log s,
+// log s_t, velocity v, opacity logit, rgb), Sec. 3.3: the 4D covariance
+// [[s^2 I + s_t^2 v v^T, s_t^2 v], [s_t^2 v^T, s_t^2]] has, at time t, the
+// conditional mean mu + v (t - mu_t), covariance s^2 I and o_t = o exp(-(t -
+// mu_t)^2 / (2 s_t^2)).  S.s[0] = s, S.s[3] = s_t.
+__device__ __forceinline__ int slice_project_iso(const float (&p)[GS4D_ISO_FIELDS],
+                                                 const gs4d_view &V, Slice &S, int4 *rect_out) {
+    for (int k = 0; k < GS4D_ISO_FIELDS; ++k)
+        if (!isfinite(p[k])) return 0;
+    S.s[0] = fixed_exp(p[4]);
+    S.s[3] = fixed_exp(p[5]);
+    S.o = 1.0f / (1.0f + fixed_exp(-p[9]));
+    const float c = S.s[3] * S.s[3];
+    if (!(c > 0.0f)) return 0;
+    S.dt = V.t - p[3];
+    for (int i = 0; i < 3; ++i) S.mu[i] = p[i] + p[6 + i] * S.dt;
+    const float s2 = S.s[0] * S.s[0];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S.Sc[i][j] = i == j ? s2 : 0.0f;
+    const float qd = (S.dt * S.dt) / c;
+    S.ef = fixed_exp(-0.5f * qd);
+    S.ot = S.o * S.ef;
+    return project_slice(V, S, rect_out);
+}
+
+// ---------------------------------------------------------------- projection
+// From the conditional 3D Gaussian (S.mu, S.Sc, S.ot) to the record: the
+// temporal cull, camera space, the guard-banded EWA Jacobian, Sigma2D and
+// its conic, the exact footprint and its tile rectangle.
+__device__ __forceinline__ int project_slice(const gs4d_view &V, Slice &S, int4 *rect_out) {
     if (!(255.0f * S.ot >= 1.0f)) return 0;
 
     // camera space
@@ -239,6 +274,64 @@ preprocess_fwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp, float
     touched[o] = tt;
 }
 
+// Backward of project_slice for one record: d(mean2D, conic) -> d(conditional
+// mean) Gmu and d(conditional covariance) GSc (chain rule term by term: conic
+// -> Sigma2D (dS = -Q dQ Q), Sigma2D -> (T, Sc), T = J W -> J -> camera point,
+// no gradient through a clamped guard-band coordinate).
+__device__ __forceinline__ void project_bwd(const gs4d_view &V, const Slice &S, const float (&G)[9],
+                                            float (&Gmu)[3], float (&GSc)[3][3]) {
+    const float *Rt = V.Rt;
+    const float z = S.xc[2];
+    // conic -> Sigma2D:  G_S = -Q Gq Q, Gq = [[ga, gb/2], [gb/2, gc]]
+    const float q00 = S.ca, q01 = S.cb, q11 = S.cc;
+    const float g00 = G[2], g01 = 0.5f * G[3], g11 = G[4];
+    const float t00 = g00 * q00 + g01 * q01, t01 = g00 * q01 + g01 * q11;
+    const float t10 = g01 * q00 + g11 * q01, t11 = g01 * q01 + g11 * q11;
+    const float S00 = -(q00 * t00 + q01 * t10);
+    const float S01 = -(q00 * t01 + q01 * t11);
+    const float S11 = -(q01 * t01 + q11 * t11);
+    const float GS2[2][2] = {{S00, S01}, {S01, S11}};
+
+    // Sigma2D = T Sc T^T: dSc = T^T GS2 T; dT = 2 GS2 U  (U = T Sc)
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            float accv = 0.0f;
+            for (int k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l) accv += S.T[k][i] * GS2[k][l] * S.T[l][j];
+            GSc[i][j] = accv;
+        }
+    float GT[2][3];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            GT[i][j] = 2.0f * (GS2[i][0] * S.U[0][j] + GS2[i][1] * S.U[1][j]);
+    // T = J W: dJ = dT W^T (only the non-constant entries of J)
+    const float GJ00 = GT[0][0] * Rt[0] + GT[0][1] * Rt[1] + GT[0][2] * Rt[2];
+    const float GJ02 = GT[0][0] * Rt[8] + GT[0][1] * Rt[9] + GT[0][2] * Rt[10];
+    const float GJ11 = GT[1][0] * Rt[4] + GT[1][1] * Rt[5] + GT[1][2] * Rt[6];
+    const float GJ12 = GT[1][0] * Rt[8] + GT[1][1] * Rt[9] + GT[1][2] * Rt[10];
+    const float iz = 1.0f / z, iz2 = iz * iz;
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    gz += -(GJ00 * V.fx + GJ11 * V.fy) * iz2;
+    if (S.clx) {
+        gz += GJ02 * V.fx * S.ux * iz2;
+    } else {
+        gx += -GJ02 * V.fx * iz2;
+        gz += GJ02 * 2.0f * V.fx * S.xc[0] * iz2 * iz;
+    }
+    if (S.cly) {
+        gz += GJ12 * V.fy * S.uy * iz2;
+    } else {
+        gy += -GJ12 * V.fy * iz2;
+        gz += GJ12 * 2.0f * V.fy * S.xc[1] * iz2 * iz;
+    }
+    // mean2D = (fx x/z + cx, fy y/z + cy)
+    gx += G[0] * V.fx * iz;
+    gy += G[1] * V.fy * iz;
+    gz += -(G[0] * V.fx * S.xc[0] + G[1] * V.fy * S.xc[1]) * iz2;
+    // camera point -> conditional mean
+    for (int j = 0; j < 3; ++j) Gmu[j] = Rt[j] * gx + Rt[4 + j] * gy + Rt[8 + j] * gz;
+}
+
 // Backward: d(mean2D, conic, o_t, rgb) per (view, Gaussian) -> d(raw params),
 // summed over views.  Follows the forward above term by term (chain rule):
 // conic -> Sigma2D (dS = -Q dQ Q), Sigma2D -> (T, Sc), T = J W -> J -> camera
@@ -267,59 +360,8 @@ preprocess_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
         float G[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) G[k] = grad2d[o * 9 + k];
-        const float *Rt = V.Rt;
-        const float z = S.xc[2];
-
-        // conic -> Sigma2D:  G_S = -Q Gq Q, Gq = [[ga, gb/2], [gb/2, gc]]
-        const float q00 = S.ca, q01 = S.cb, q11 = S.cc;
-        const float g00 = G[2], g01 = 0.5f * G[3], g11 = G[4];
-        const float t00 = g00 * q00 + g01 * q01, t01 = g00 * q01 + g01 * q11;
-        const float t10 = g01 * q00 + g11 * q01, t11 = g01 * q01 + g11 * q11;
-        const float S00 = -(q00 * t00 + q01 * t10);
-        const float S01 = -(q00 * t01 + q01 * t11);
-        const float S11 = -(q01 * t01 + q11 * t11);
-        const float GS2[2][2] = {{S00, S01}, {S01, S11}};
-
-        // Sigma2D = T Sc T^T: dSc = T^T GS2 T; dT = 2 GS2 U  (U = T Sc)
-        float GSc[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                float accv = 0.0f;
-                for (int k = 0; k < 2; ++k)
-                    for (int l = 0; l < 2; ++l) accv += S.T[k][i] * GS2[k][l] * S.T[l][j];
-                GSc[i][j] = accv;
-            }
-        float GT[2][3];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j)
-                GT[i][j] = 2.0f * (GS2[i][0] * S.U[0][j] + GS2[i][1] * S.U[1][j]);
-        // T = J W: dJ = dT W^T (only the non-constant entries of J)
-        const float GJ00 = GT[0][0] * Rt[0] + GT[0][1] * Rt[1] + GT[0][2] * Rt[2];
-        const float GJ02 = GT[0][0] * Rt[8] + GT[0][1] * Rt[9] + GT[0][2] * Rt[10];
-        const float GJ11 = GT[1][0] * Rt[4] + GT[1][1] * Rt[5] + GT[1][2] * Rt[6];
-        const float GJ12 = GT[1][0] * Rt[8] + GT[1][1] * Rt[9] + GT[1][2] * Rt[10];
-        const float iz = 1.0f / z, iz2 = iz * iz;
-        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-        gz += -(GJ00 * V.fx + GJ11 * V.fy) * iz2;
-        if (S.clx) {
-            gz += GJ02 * V.fx * S.ux * iz2;
-        } else {
-            gx += -GJ02 * V.fx * iz2;
-            gz += GJ02 * 2.0f * V.fx * S.xc[0] * iz2 * iz;
-        }
-        if (S.cly) {
-            gz += GJ12 * V.fy * S.uy * iz2;
-        } else {
-            gy += -GJ12 * V.fy * iz2;
-            gz += GJ12 * 2.0f * V.fy * S.xc[1] * iz2 * iz;
-        }
-        // mean2D = (fx x/z + cx, fy y/z + cy)
-        gx += G[0] * V.fx * iz;
-        gy += G[1] * V.fy * iz;
-        gz += -(G[0] * V.fx * S.xc[0] + G[1] * V.fy * S.xc[1]) * iz2;
-        // camera point -> conditional mean
-        float Gmu[3];
-        for (int j = 0; j < 3; ++j) Gmu[j] = Rt[j] * gx + Rt[4 + j] * gy + Rt[8 + j] * gz;
+        float Gmu[3], GSc[3][3];
+        project_bwd(V, S, G, Gmu, GSc);
 
         // conditional -> Sigma blocks (Sb, a, c), mu, opacity
         const float c = S.Sg[3][3], ic = 1.0f / c;
@@ -399,6 +441,90 @@ preprocess_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
     for (int k = 0; k < 20; ++k) dP[(int64_t)k * n + g] = acc[k];
 }
 
+// Forward of the isotropic, motion-aware parameters [13][n]; the records,
+// rectangles and counts have the layout of preprocess_fwd_kernel's.
+__global__ void __launch_bounds__(256)
+preprocess_iso_fwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
+                          float4 *__restrict__ rec, int4 *__restrict__ rect,
+                          int32_t *__restrict__ touched) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int vi = blockIdx.y;
+    if (g >= n) return;
+    float p[GS4D_ISO_FIELDS];
+#pragma unroll
+    for (int k = 0; k < GS4D_ISO_FIELDS; ++k) p[k] = P[(int64_t)k * n + g];
+    Slice S;
+    int4 rc = make_int4(0, 0, 0, 0);
+    const int vis = slice_project_iso(p, vp.v[vi], S, &rc);
+    const int64_t o = (int64_t)vi * n + g;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    int tt = 0;
+    if (vis) {
+        r0 = make_float4(S.mx, S.my, S.ca, S.cb);
+        r1 = make_float4(S.cc, S.ot, S.xc[2], S.hx);
+        r2 = make_float4(p[10], p[11], p[12], S.hy);
+        tt = (rc.z - rc.x) * (rc.w - rc.y);
+    } else {
+        rc = make_int4(0, 0, 0, 0);
+    }
+    rec[3 * o + 0] = r0;
+    rec[3 * o + 1] = r1;
+    rec[3 * o + 2] = r2;
+    rect[o] = rc;
+    touched[o] = tt;
+}
+
+// Backward of the isotropic, motion-aware form, summed over views:
+//   mu_c = mu + v dt (dt = t - mu_t): d mu += Gmu, d v += Gmu dt,
+//     d mu_t -= v . Gmu;
+//   Sc = s^2 I: d log s = 2 s^2 trace(GSc);
+//   o_t = o exp(-dt^2 / (2 s_t^2)): d mu_t += go o_t dt / s_t^2,
+//     d log s_t = go o_t dt^2 / s_t^2, d logit = go exp(.) o (1 - o).
+__global__ void __launch_bounds__(128)
+preprocess_iso_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
+                          const int32_t *__restrict__ touched, const float *__restrict__ grad2d,
+                          float *__restrict__ dP) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    float p[GS4D_ISO_FIELDS];
+#pragma unroll
+    for (int k = 0; k < GS4D_ISO_FIELDS; ++k) p[k] = P[(int64_t)k * n + g];
+    float acc[GS4D_ISO_FIELDS];
+#pragma unroll
+    for (int k = 0; k < GS4D_ISO_FIELDS; ++k) acc[k] = 0.0f;
+
+    for (int vi = 0; vi < vp.n_views; ++vi) {
+        const int64_t o = (int64_t)vi * n + g;
+        if (touched[o] == 0) continue;
+        const gs4d_view &V = vp.v[vi];
+        Slice S;
+        if (!slice_project_iso(p, V, S, nullptr)) continue;
+        float G[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) G[k] = grad2d[o * 9 + k];
+        float Gmu[3], GSc[3][3];
+        project_bwd(V, S, G, Gmu, GSc);
+        const float go = G[5];
+        const float ic = 1.0f / (S.s[3] * S.s[3]);
+        const float dt = S.dt;
+        float vG = 0.0f;
+        for (int i = 0; i < 3; ++i) {
+            acc[i] += Gmu[i];
+            acc[6 + i] += Gmu[i] * dt;
+            vG += p[6 + i] * Gmu[i];
+        }
+        acc[3] += -vG + go * S.ot * dt * ic;
+        acc[4] += 2.0f * S.s[0] * S.s[0] * (GSc[0][0] + GSc[1][1] + GSc[2][2]);
+        acc[5] += go * S.ot * dt * dt * ic;
+        acc[9] += go * S.ef * S.o * (1.0f - S.o);
+        acc[10] += G[6];
+        acc[11] += G[7];
+        acc[12] += G[8];
+    }
+#pragma unroll
+    for (int k = 0; k < GS4D_ISO_FIELDS; ++k) dP[(int64_t)k * n + g] = acc[k];
+}
+
 }  // namespace
 
 }  // namespace gs4d
@@ -433,5 +559,36 @@ extern "C" int gs4d_preprocess_bwd(const float *params, int64_t n, const gs4d_vi
     preprocess_bwd_kernel<<<blocks, 128, 0, as_stream(stream)>>>(params, n, vp, touched, grad2d,
                                                                  dparams);
     GS4D_LAUNCH_CHECK("gs4d_preprocess_bwd");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_preprocess_iso(const float *params, int64_t n, const gs4d_view *views,
+                                   int32_t n_views, float *rec, int32_t *rect, int32_t *touched,
+                                   void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_REQUIRE(n >= 0, "gs4d_preprocess_iso: n < 0");
+    GS4D_REQUIRE(n <= (int64_t)0x7fffffff, "gs4d_preprocess_iso: n >= 2^31");
+    if (n == 0) return GS4D_OK;
+    GS4D_REQUIRE(params && rec && rect && touched, "gs4d_preprocess_iso: null pointer");
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
+    preprocess_iso_fwd_kernel<<<grid, 256, 0, as_stream(stream)>>>(
+        params, n, vp, reinterpret_cast<float4 *>(rec), reinterpret_cast<int4 *>(rect), touched);
+    GS4D_LAUNCH_CHECK("gs4d_preprocess_iso");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_preprocess_iso_bwd(const float *params, int64_t n, const gs4d_view *views,
+                                       int32_t n_views, const int32_t *touched,
+                                       const float *grad2d, float *dparams, void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "gs4d_preprocess_iso_bwd: n out of range");
+    if (n == 0) return GS4D_OK;
+    GS4D_REQUIRE(params && touched && grad2d && dparams, "gs4d_preprocess_iso_bwd: null pointer");
+    const unsigned blocks = (unsigned)((n + 127) / 128);
+    preprocess_iso_bwd_kernel<<<blocks, 128, 0, as_stream(stream)>>>(params, n, vp, touched,
+                                                                     grad2d, dparams);
+    GS4D_LAUNCH_CHECK("gs4d_preprocess_iso_bwd");
     return GS4D_OK;
 }

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgs4d.so")
 
 N_FIELDS = 20
+ISO_FIELDS = 13   # isotropic, motion-aware parameterisation (gs4d_preprocess_iso)
 REC_FLOATS = 12
 GRAD2D_FLOATS = 9
 TILE = 16
@@ -69,6 +70,8 @@ _SIGS = {
     "gs4d_tile_order_workspace_size": (_sz, [_i64]),
     "gs4d_tile_order": (_i32, [_p, _i64, _p, _p, _i32, _p, _sz, _p]),
     "gs4d_preprocess_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
+    "gs4d_preprocess_iso": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
+    "gs4d_preprocess_iso_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "gs4d_set_bwd_variant": (_i32, [_i32]),
     "gs4d_grid_prune_workspace_size": (_sz, [_i64, _i32]),
     "gs4d_grid_prune": (_i32, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p, _p,
@@ -220,6 +223,24 @@ def gs4d_preprocess_bwd(params, touched, grad2d, views, dparams, stream=None):
     _check(lib().gs4d_preprocess_bwd(_ptr(params), params.shape[1], va, len(va), _ptr(touched),
                                      _ptr(grad2d), _ptr(dparams), _stream(stream)),
            "gs4d_preprocess_bwd")
+
+
+def gs4d_preprocess_iso(params, views, rec, rect, touched, stream=None):
+    """Preprocess of the isotropic, motion-aware parameters [13][n]."""
+    assert params.shape[0] == ISO_FIELDS
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_preprocess_iso(_ptr(params), params.shape[1], va, len(va), _ptr(rec),
+                                     _ptr(rect), _ptr(touched), _stream(stream)),
+           "gs4d_preprocess_iso")
+
+
+def gs4d_preprocess_iso_bwd(params, touched, grad2d, views, dparams, stream=None):
+    assert params.shape[0] == ISO_FIELDS
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_preprocess_iso_bwd(_ptr(params), params.shape[1], va, len(va),
+                                         _ptr(touched), _ptr(grad2d), _ptr(dparams),
+                                         _stream(stream)),
+           "gs4d_preprocess_iso_bwd")
 
 
 def gs4d_tile_order_workspace_size(n_tiles):
