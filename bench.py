@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR leg")
     ap.add_argument("--no-fps", action="store_true",
                     help="skip the forward-only frame-rate leg at display sizes")
+    ap.add_argument("--no-iso", action="store_true",
+                    help="skip the isotropic, motion-aware form's leg (throughput and ablation)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--calib-copy", action="store_true",
@@ -312,6 +314,7 @@ def main():
     }
     if args.workload == "scene" and not args.no_fps:
         line["render_fps"] = render_fps_leg(tr.params, views)
+
     if not args.no_cpu_baseline:
         from paper_2510_01119_amd import synth  # noqa: F401
         p_np = tr.params.detach().cpu().numpy()
@@ -327,7 +330,67 @@ def main():
                                           f"thread"}
     if args.workload == "scene" and not args.no_ttp and pruned is not None:
         line["time_to_psnr"] = time_to_psnr_leg(params, views, images, pruned)
+    if args.workload == "scene" and not args.no_iso:
+        line["iso_form"] = iso_leg(params, views, images, args.seed)
     print(json.dumps(line), flush=True)
+
+
+def iso_leg(params, views, images, seed, steps=200, warmup=20, budget=1500):
+    """The paper's isotropic, motion-aware parameterisation (13 floats per
+    Gaussian) on the same scene, from the same heuristic initialisation:
+    training iterations/s (whole steps replayed from graphs, render launches
+    autotuned as for the rotor form), and a synthetic analogue of the
+    paper's ablation at a fixed budget of `budget` single-frame steps:
+    PSNR on held-out frames (every 10th) of the rotor form ("w/o
+    isotropic"), the isotropic form with its velocity trained, and with the
+    velocity frozen at zero ("w/o motion-aware")."""
+    import torch
+    from paper_2510_01119_amd import autotune
+    from paper_2510_01119_amd.train import Trainer, to_iso
+    F = len(views)
+    rng = np.random.default_rng(seed + 7)
+    sample = range(0, F, max(1, F // 20))
+    tr = Trainer(to_iso(params.clone()), views, images, budget=5000)
+    tr.size_pairs(sample, margin=2.0)
+    seq = rng.integers(0, F, warmup + steps)
+    for i in range(warmup):
+        tr.step(int(seq[i]))
+    tr.forward_loss(int(seq[0]))
+    autotune.tune(tr.rast, tr.params, tr.dimg)
+    tr.capture(sorted(set(int(f) for f in seq[warmup:])))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        tr.step_graph(int(seq[warmup + i]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if int(tr.overflow_seen.item()) != 0:
+        raise RuntimeError("pair capacity overflowed in the isotropic form's timed steps")
+    out = {"iters_per_s": round(steps / dt, 1), "ms_per_step": round(1e3 * dt / steps, 4),
+           "floats_per_gaussian": 13}
+    del tr
+    torch.cuda.empty_cache()
+    held = list(range(5, F, 10))
+    train = [f for f in range(F) if f % 10 != 5]
+    order = rng.choice(train, size=budget)
+    variants = {
+        "rotor (w/o isotropic)": (params, None),
+        "isotropic + velocity": (to_iso(params), None),
+        "isotropic, velocity frozen (w/o motion-aware)": (to_iso(params), {"velocity": (0.0, 0.0)}),
+    }
+    psnr = {}
+    for name, (p0, lrs) in variants.items():
+        t = Trainer(p0.clone(), views, images, budget=budget, lrs=lrs)
+        t.size_pairs(sample, margin=2.0)
+        for f in order:
+            t.step(int(f))
+        psnr[name] = (round(t.psnr(held), 3)
+                      if int(t.overflow_seen.item()) == 0 else None)
+        del t
+        torch.cuda.empty_cache()
+    out["ablation"] = {"steps": budget, "heldout_frames": len(held), "psnr_db": psnr}
+    log(f"bench: isotropic form {json.dumps(out)}")
+    return out
 
 
 def render_fps_leg(params, views, frames=200):

@@ -91,7 +91,12 @@ class Rasterizer:
 
     # ------------------------------------------------------------------ stages
     def preprocess(self, params: torch.Tensor):
-        G.gs4d_preprocess(params, self.cviews, self.rec, self.rect, self.touched)
+        """Rotor-form parameters [20, n], or the isotropic, motion-aware form
+        [13, n] (gs4d_preprocess_iso); the outputs are the same."""
+        if params.shape[0] == G.ISO_FIELDS:
+            G.gs4d_preprocess_iso(params, self.cviews, self.rec, self.rect, self.touched)
+        else:
+            G.gs4d_preprocess(params, self.cviews, self.rec, self.rect, self.touched)
 
     def bin_sort(self, check: bool = True):
         """Sort into tiles.  With ``check`` the host reads the pair count and
@@ -164,7 +169,8 @@ class Rasterizer:
                              self.T_final, self.last, self.grad2d, self._opts(1))
 
     def forward(self, params: torch.Tensor, check: bool = True, opts=None):
-        assert params.shape == (G.N_FIELDS, self.n) and params.dtype == torch.float32
+        assert params.shape in ((G.N_FIELDS, self.n), (G.ISO_FIELDS, self.n))
+        assert params.dtype == torch.float32
         self.preprocess(params)
         self.bin_sort(check)
         self.render(opts)
@@ -173,6 +179,9 @@ class Rasterizer:
     def backward(self, params: torch.Tensor, dL_dimage: torch.Tensor):
         if self.forward_only:
             raise RuntimeError("forward-only rasterizer: no state for a backward")
+        if params.shape[0] != G.N_FIELDS:
+            raise ValueError("backward() takes rotor-form parameters; for the isotropic form "
+                             "use render_bwd_2d and gs4d_preprocess_iso_bwd")
         if self.persistent:
             self._bwd_queue()
         G.gs4d_render_bwd(params, self.rec, self.touched, self.vals, self.ranges, self.cviews,

@@ -28,17 +28,33 @@ LR_DEFAULTS = {
     "rotors": (1e-3, 1e-3),
     "opacity": (5e-2, 5e-2),
     "rgb": (2.5e-3, 2.5e-3),
+    # isotropic, motion-aware form only: the velocity (world units per unit
+    # of normalised time)
+    "velocity": (1e-3, 1e-5),
 }
 
-
-def adam_config(budget: int, lrs=None) -> G.gs4d_adam_cfg:
-    lrs = dict(LR_DEFAULTS, **(lrs or {}))
-    rows = (["mean_xyz"] * 3 + ["mean_t"] + ["log_scale"] * 4 + ["rotors"] * 8 + ["opacity"]
+ROTOR_ROWS = (["mean_xyz"] * 3 + ["mean_t"] + ["log_scale"] * 4 + ["rotors"] * 8 + ["opacity"]
+              + ["rgb"] * 3)
+ISO_ROWS = (["mean_xyz"] * 3 + ["mean_t"] + ["log_scale"] * 2 + ["velocity"] * 3 + ["opacity"]
             + ["rgb"] * 3)
+
+
+def to_iso(params: torch.Tensor) -> torch.Tensor:
+    """Isotropic, motion-aware parameters [13, n] from rotor-form ones with
+    identity rotors and one spatial scale (the heuristic initialisation):
+    the same model, at zero velocity."""
+    p = params
+    return torch.cat([p[0:4], p[4:5], p[7:8], torch.zeros_like(p[0:3]), p[16:17], p[17:20]],
+                     dim=0).contiguous()
+
+
+def adam_config(budget: int, lrs=None, iso: bool = False) -> G.gs4d_adam_cfg:
+    lrs = dict(LR_DEFAULTS, **(lrs or {}))
+    rows = ISO_ROWS if iso else ROTOR_ROWS
     cfg = G.gs4d_adam_cfg()
     for k, name in enumerate(rows):
         cfg.lr0[k], cfg.lr1[k] = lrs[name]
-    cfg.budget, cfg.rows = int(budget), 20
+    cfg.budget, cfg.rows = int(budget), len(rows)
     cfg.beta1, cfg.beta2, cfg.eps = 0.9, 0.999, 1e-15
     return cfg
 
@@ -53,7 +69,8 @@ def _capture(fn, stream):
 
 class Trainer:
     """Single-view training on a fixed set of frames (views [F, 23],
-    targets [F, 3, H, W] on the device)."""
+    targets [F, 3, H, W] on the device).  Parameters in rotor form [20, N] or
+    in the isotropic, motion-aware form [13, N] (chosen by their rows)."""
 
     def __init__(self, params: torch.Tensor, views, targets: torch.Tensor, budget: int = 5000,
                  ssim_weight: float = 0.2, pair_capacity: int | None = None, lrs=None,
@@ -70,7 +87,10 @@ class Trainer:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.cfg = adam_config(budget, lrs)
+        self.iso = self.params.shape[0] == G.ISO_FIELDS
+        self.cfg = adam_config(budget, lrs, iso=self.iso)
+        # parameter gradients (the rasterizer's buffer holds the rotor form's)
+        self.dparams = torch.zeros_like(self.params) if self.iso else self.rast.dparams
         self.ssim_w = float(ssim_weight)
         H, W = self.rast.H, self.rast.W
         self.dimg = torch.zeros((1, 3, H, W), device=dev)
@@ -112,8 +132,9 @@ class Trainer:
 
     def stage_update(self, f: int):
         r = self.rast
-        G.gs4d_preprocess_bwd(self.params, r.touched, r.grad2d, self.cviews[f], r.dparams)
-        G.gs4d_adam_step(self.params, r.dparams, self.m, self.v, self.cfg, self.step_dev)
+        bwd = G.gs4d_preprocess_iso_bwd if self.iso else G.gs4d_preprocess_bwd
+        bwd(self.params, r.touched, r.grad2d, self.cviews[f], self.dparams)
+        G.gs4d_adam_step(self.params, self.dparams, self.m, self.v, self.cfg, self.step_dev)
 
     def step(self, f: int):
         self.stage_forward(f)

@@ -98,3 +98,45 @@ def test_iso_gradients(iso_case):
         worst = np.argmax(np.where(ok, err / tol, 0))
         assert not np.any(bad), (k, err[worst], tol[worst], ref[k][worst])
         assert np.all(err[tainted] <= 0.05 * np.maximum(np.abs(ref[k][tainted]), 10 * floor)), k
+
+
+def test_iso_trainer_starts_as_rotor_and_trains():
+    """Trainer on isotropic parameters converted from an identity-rotor,
+    tied-scale set: the first forward equals the rotor form's bit for bit
+    (the same model at zero velocity); twenty steps lower the loss and keep
+    the parameters finite."""
+    need_gpu()
+    from paper_2510_01119_amd.train import Trainer, to_iso
+    rng = np.random.default_rng(3)
+    n = 3000
+    p = np.zeros((G.N_FIELDS, n), np.float32)
+    p[0:3] = rng.uniform(-1, 1, (3, n))
+    p[3] = rng.uniform(0, 1, n)
+    p[4:7] = rng.normal(-3.0, 0.3, n)
+    p[7] = rng.normal(-1.0, 0.3, n)
+    p[8] = 1.0
+    p[12] = 1.0
+    p[16] = rng.normal(0, 1, n)
+    p[17:20] = rng.uniform(0, 1, (3, n))
+    views = np.stack([synth.front_view(64, 48, 60.0, 3.0, t) for t in (0.3, 0.6)])
+    P = torch.from_numpy(p).cuda()
+    tgt_p = P.clone()
+    tgt_p[0:3] += 0.02
+    r = Rasterizer(n, views)
+    r.forward(tgt_p)
+    targets = r.image.clone()
+    rot = Trainer(P.clone(), views, targets, budget=100)
+    iso = Trainer(to_iso(P), views, targets, budget=100)
+    assert iso.params.shape == (G.ISO_FIELDS, n) and iso.cfg.rows == G.ISO_FIELDS
+    rot.forward_loss(0)
+    iso.forward_loss(0)
+    torch.cuda.synchronize()
+    assert torch.equal(rot.rast.image, iso.rast.image)
+    first = iso.loss_value()
+    for k in range(20):
+        iso.step(k % 2)
+    iso.forward_loss(0)
+    torch.cuda.synchronize()
+    assert iso.loss_value() < first
+    assert torch.isfinite(iso.params).all()
+    assert float(iso.params[6:9].abs().max()) > 0.0   # the velocity is trained
