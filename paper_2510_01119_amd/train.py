@@ -29,8 +29,9 @@ LR_DEFAULTS = {
     "opacity": (5e-2, 5e-2),
     "rgb": (2.5e-3, 2.5e-3),
     # isotropic, motion-aware form only: the velocity (world units per unit
-    # of normalised time)
-    "velocity": (1e-3, 1e-5),
+    # of normalised time); 1e-2 beat 3e-3 and 1e-3 on held-out PSNR after
+    # 1,500 scene steps
+    "velocity": (1e-2, 1e-4),
 }
 
 ROTOR_ROWS = (["mean_xyz"] * 3 + ["mean_t"] + ["log_scale"] * 4 + ["rotors"] * 8 + ["opacity"]
