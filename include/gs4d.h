@@ -401,6 +401,24 @@ int gs4d_motion_init(float *params, const float *pred, int64_t n, void *stream);
  *   optimiser converged).  Non-finite or degenerate parameters give NaN. */
 int gs4d_motion_of(const float *params, int64_t n, float *out, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * gs4d_otsu_mask -- static / dynamic split of a motion-probability map by
+ *   Otsu's threshold (Sec. 3.2; Otsu 1979).
+ *   prob       float [count], count <= 4,000,000 (one map); values clamped to
+ *              [0, 1], NaN read as 0; 256 uniform bins, bin(x) =
+ *              min(255, floor(256 x))
+ *   threshold  out device float or NULL: k* / 256, where k* in 1..255 is the
+ *              first split maximising the between-class variance (256 when
+ *              every value falls in one bin)
+ *   mask       out uint8 [count] or NULL: 1 (dynamic) where bin(x) >= k*
+ *   ws         >= gs4d_otsu_workspace_size() bytes
+ *   The split is decided on integer class sums with one fixed FP64
+ *   evaluation per candidate, so it is reproducible bit for bit.
+ * ------------------------------------------------------------------------- */
+size_t gs4d_otsu_workspace_size(void);
+int gs4d_otsu_mask(const float *prob, int64_t count, float *threshold, uint8_t *mask, void *ws,
+                   size_t ws_bytes, void *stream);
+
 /* Fill count floats with value (graph-capturable replacement of memset). */
 int gs4d_fill_f32(float *dst, float value, int64_t count, void *stream);
 int gs4d_fill_u32(uint32_t *dst, uint32_t value, int64_t count, void *stream);

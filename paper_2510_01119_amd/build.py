@@ -25,6 +25,7 @@ SOURCES = {
     "render.hip": [],
     "train.hip": [],
     "prune.hip": [],
+    "segment.hip": ["-ffp-contract=off"],
     # the network's layers are fully unrolled so activations stay in registers
     "learned.hip": ["-mllvm", "-pragma-unroll-threshold=2000000"],
 }

@@ -72,6 +72,8 @@ _SIGS = {
     "gs4d_preprocess_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "gs4d_preprocess_iso": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "gs4d_preprocess_iso_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
+    "gs4d_otsu_workspace_size": (_sz, []),
+    "gs4d_otsu_mask": (_i32, [_p, _i64, _p, _p, _p, _sz, _p]),
     "gs4d_set_bwd_variant": (_i32, [_i32]),
     "gs4d_grid_prune_workspace_size": (_sz, [_i64, _i32]),
     "gs4d_grid_prune": (_i32, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p, _p,
@@ -241,6 +243,17 @@ def gs4d_preprocess_iso_bwd(params, touched, grad2d, views, dparams, stream=None
                                          _ptr(touched), _ptr(grad2d), _ptr(dparams),
                                          _stream(stream)),
            "gs4d_preprocess_iso_bwd")
+
+
+def gs4d_otsu_workspace_size():
+    return int(lib().gs4d_otsu_workspace_size())
+
+
+def gs4d_otsu_mask(prob, threshold, mask, ws, stream=None):
+    """Otsu split of one motion-probability map (float32 device tensor):
+    threshold (device float [1] or None), mask (uint8 like prob, or None)."""
+    _check(lib().gs4d_otsu_mask(_ptr(prob), prob.numel(), _ptr(threshold), _ptr(mask), _ptr(ws),
+                                ws.numel(), _stream(stream)), "gs4d_otsu_mask")
 
 
 def gs4d_tile_order_workspace_size(n_tiles):

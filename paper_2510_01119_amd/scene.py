@@ -18,6 +18,14 @@ recovery are not available here).  Recipe:
   its depth, optical-flow magnitude and scene flow (further passes render
   each ground-truth Gaussian's pixel and world displacement to the next
   frame), the inputs of the learned initialisation;
+* the motion class of a point is either the ground-truth mask or (motion =
+  "otsu") the paper's segmentation: a low-resolution motion-probability
+  map (here the ground-truth dynamic fraction averaged over 8x8 pixels plus
+  seeded noise, standing in for the SLAM's H/8 x W/8 map), bilinearly
+  upsampled and split by Otsu's threshold (gs4d_otsu_mask);
+* the voxel edge is fixed, or (voxel = "adaptive") S_v = lambda (1/N) sum
+  D_i / f over the back-projected pixels (Sec. 3.2), with one lambda for
+  static and one for dynamic points;
 * gs4d_grid_prune merges the points per voxel (Sec. 3.2, grid pruning);
 * the heuristic initialisation (Sec. 4.1): centroid position, mean
   timestamp and colour, temporal scale 2 / frames for dynamic points (two
@@ -198,11 +206,22 @@ class Scene:
             mus.append(mu)
         return torch.linalg.norm(px[1] - px[0], dim=0), mus[1] - mus[0]
 
-    def render_ground_truth(self, verbose=False):
+    def render_ground_truth(self, verbose=False, motion="gt", motion_noise=0.1):
         """Renders every frame; returns (images [F,3,H,W] on device, point
         cloud (xyz [3,M], attr [9,M] = rgb, t, depth, optical-flow
-        magnitude, scene flow xyz; cls [M]) on device)."""
+        magnitude, scene flow xyz; cls [M]) on device).  Also records
+        self.depth_over_f (the mean of D / f over the back-projected pixels)
+        and, with motion="otsu", self.mask_iou (mean over frames of the
+        Otsu mask's intersection over union with the ground-truth mask, on
+        the back-projected pixels)."""
+        import torch.nn.functional as F
         dev = self.device
+        d_over_f, n_back, ious = 0.0, 0, []
+        if motion == "otsu":
+            otsu_ws = torch.zeros(G.gs4d_otsu_workspace_size(), dtype=torch.uint8, device=dev)
+            otsu_mask = torch.zeros(self.H * self.W, dtype=torch.uint8, device=dev)
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(1000 + self.seed)
         n = self.static.shape[1] + self.obj_local.shape[1]
         r = Rasterizer(n, self.cams[0], device=dev, pair_capacity=1 << 24)
         dyn_flag = torch.zeros(n, device=dev)
@@ -246,15 +265,33 @@ class Scene:
             col = images[f][:, keep]
             attrs.append(torch.cat([col, torch.full((1, col.shape[1]), float(view[18]), device=dev),
                                     depth[None], flow, sfz[None]]))
-            clss.append((aux[2][keep] / cov[keep] > 0.5).to(torch.uint8))
+            d_over_f += float((depth / float(view[12])).sum().item())
+            n_back += int(depth.numel())
+            gt_dyn = aux[2][keep] / cov[keep] > 0.5
+            if motion == "otsu":
+                frac = torch.where(cov > 0, aux[2] / cov.clamp_min(1e-6), torch.zeros_like(cov))
+                low = F.avg_pool2d(frac[None, None], 8, ceil_mode=True)
+                low = (low + motion_noise * torch.randn(low.shape, generator=gen, device=dev))
+                prob = F.interpolate(low.clamp(0.0, 1.0), size=(self.H, self.W), mode="bilinear",
+                                     align_corners=False)[0, 0].contiguous()
+                G.gs4d_otsu_mask(prob, None, otsu_mask, otsu_ws)
+                dyn = otsu_mask.view(self.H, self.W)[keep].bool()
+                inter = float((dyn & gt_dyn).sum().item())
+                union = float((dyn | gt_dyn).sum().item())
+                ious.append(inter / union if union > 0 else 1.0)
+            else:
+                dyn = gt_dyn
+            clss.append(dyn.to(torch.uint8))
             if verbose and f % 50 == 0:
                 print(f"scene: frame {f}/{self.frames} pairs={int(r.n_pairs.item())}", flush=True)
         xyz = torch.cat(pts, dim=1).contiguous()
         attr = torch.cat(attrs, dim=1).contiguous()
         cls = torch.cat(clss).contiguous()
+        self.depth_over_f = d_over_f / max(n_back, 1)
+        self.mask_iou = float(np.mean(ious)) if ious else None
         return images, (xyz, attr, cls)
 
-    def prune(self, cloud, voxel=0.01, min_count=1):
+    def prune(self, cloud, voxel=0.01, min_count=1, voxel_dynamic=None):
         xyz, attr, cls = cloud
         dev = self.device
         m = xyz.shape[1]
@@ -267,7 +304,8 @@ class Scene:
         status = torch.zeros(1, dtype=torch.int32, device=dev)
         ws = torch.empty(G.gs4d_grid_prune_workspace_size(m, attr.shape[0]), dtype=torch.uint8,
                          device=dev)
-        G.gs4d_grid_prune(xyz, attr, cls, voxel, voxel, min_count, cap, out_xyz, out_attr,
+        vd = voxel if voxel_dynamic is None else voxel_dynamic
+        G.gs4d_grid_prune(xyz, attr, cls, voxel, vd, min_count, cap, out_xyz, out_attr,
                           out_count, out_key, n_out, status, ws)
         st, k = int(status.item()), int(n_out.item())
         if st != 0:
@@ -276,13 +314,15 @@ class Scene:
         dyn = (out_key[:k] < 0)          # class bit 63 set -> negative as int64
         return out_xyz[:, :k], out_attr[:, :k], dyn, out_count[:k]
 
-    def heuristic_init(self, pruned, voxel=0.01):
+    def heuristic_init(self, pruned, voxel=0.01, voxel_dynamic=None):
         xyz, attr, dyn, _ = pruned
         k = xyz.shape[1]
+        vd = voxel if voxel_dynamic is None else voxel_dynamic
         p = torch.zeros((20, k), device=self.device)
         p[0:3] = xyz
         p[3] = attr[3]
-        p[4:7] = math.log(voxel)
+        p[4:7] = torch.where(dyn, torch.full_like(attr[3], math.log(vd)),
+                             torch.full_like(attr[3], math.log(voxel)))
         p[7] = torch.where(dyn, torch.full_like(attr[3], math.log(2.0 / self.frames)),
                            torch.zeros_like(attr[3]))
         p[8] = 1.0
@@ -293,18 +333,26 @@ class Scene:
 
 
 def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel=0.01,
-                device="cuda", verbose=False, keep_pruned=False):
+                device="cuda", verbose=False, keep_pruned=False, motion="gt",
+                lambda_static=4.0, lambda_dynamic=4.0):
     """Ground-truth frames and the pruned, heuristically initialised set
     (with keep_pruned, also the pruned cloud: xyz, attr, dynamic flag,
-    count)."""
+    count).  voxel: an edge length, or "adaptive" for S_v = lambda mean(D / f)
+    with lambda_static / lambda_dynamic (the paper's Lite setting is 4 and
+    4); motion: "gt" (ground-truth mask) or "otsu" (the paper's split)."""
     sc = Scene(seed, n_gt, frames, width, height, device=device)
-    images, cloud = sc.render_ground_truth(verbose)
+    images, cloud = sc.render_ground_truth(verbose, motion=motion)
     n_raw = cloud[0].shape[1]
-    pruned = sc.prune(cloud, voxel)
+    if voxel == "adaptive":
+        vs, vd = lambda_static * sc.depth_over_f, lambda_dynamic * sc.depth_over_f
+    else:
+        vs = vd = float(voxel)
+    pruned = sc.prune(cloud, vs, voxel_dynamic=vd)
     del cloud
-    params = sc.heuristic_init(pruned, voxel)
+    params = sc.heuristic_init(pruned, vs, vd)
     info = dict(n_raw_points=n_raw, n_gaussians=params.shape[1],
-                n_dynamic=int(pruned[2].sum().item()))
+                n_dynamic=int(pruned[2].sum().item()), voxel_static=vs, voxel_dynamic=vd,
+                depth_over_f=sc.depth_over_f, motion=motion, mask_iou=sc.mask_iou)
     if keep_pruned:
         return sc, images, params, info, pruned
     return sc, images, params, info
