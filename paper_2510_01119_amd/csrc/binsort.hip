@@ -669,7 +669,9 @@ __device__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
     }
 }
 
-__global__ void __launch_bounds__(SEG_THREADS)
+// six waves per SIMD (80 VGPRs, a few spilled in the long-tile path): the
+// batched set's 16k tiles run in fewer rounds of workgroups
+__global__ void __launch_bounds__(SEG_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
 tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                        const int2 *__restrict__ ranges, uint64_t *__restrict__ spill) {
     __shared__ SegShared sh;
