@@ -33,7 +33,7 @@ constexpr int RS_WAVES = RS_THREADS / 64;
 // still spread over all 256 compute units; long ones for tens of millions
 constexpr int RS_TINY_ITEMS = 2;
 constexpr int RS_SMALL_ITEMS = 4;
-constexpr int RS_LARGE_ITEMS = 16;
+constexpr int RS_LARGE_ITEMS = 8;
 constexpr int64_t RS_TINY_LIMIT = 1 << 18;
 constexpr int64_t RS_SMALL_LIMIT = 1 << 22;
 
