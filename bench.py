@@ -439,18 +439,21 @@ def scene_prep_leg(params_gt, views, images_gt, seed, steps=1500):
 def render_fps_leg(params, views, frames=200):
     """Forward-only frame rate of the parameters as they stand after the
     timed training steps, at display sizes: 16 of the scene's cameras (the
-    960x540 intrinsics rescaled), each frame one graph replay of preprocess,
-    binning, tile ordering and compositing."""
+    960x540 intrinsics rescaled), each launch one graph replay of preprocess,
+    binning, tile ordering and compositing -- one frame per launch (the
+    latency mode), and 8 consecutive frames per launch ("_x8", playback
+    throughput)."""
     import torch
     from paper_2510_01119_amd.realtime import DISPLAY_SIZES, FrameRenderer, rescale_view
     sel = np.linspace(0, len(views) - 1, 16).round().astype(int)
     out = {}
     for W, H in DISPLAY_SIZES:
         vs = np.stack([rescale_view(views[f], W, H) for f in sel])
-        fr = FrameRenderer(params, vs)
-        out[f"{W}x{H}"] = fr.frame_rate(frames=frames)
-        del fr
-        torch.cuda.empty_cache()
+        for B in (1, 8):
+            fr = FrameRenderer(params, vs, frames_per_launch=B)
+            out[f"{W}x{H}" + ("" if B == 1 else f"_x{B}")] = fr.frame_rate(frames=frames)
+            del fr
+            torch.cuda.empty_cache()
     log(f"bench: forward-only frame rate {json.dumps(out)}")
     return out
 

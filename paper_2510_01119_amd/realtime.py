@@ -34,14 +34,22 @@ def rescale_view(view, width: int, height: int) -> np.ndarray:
 
 
 class FrameRenderer:
-    """Renders frame f = one view (numpy [F, 23] views, one image size) of
-    fixed parameters, forward only, on persistent largest-first launches."""
+    """Renders the frames of ``views`` (numpy [F, 23], one image size) of
+    fixed parameters, forward only, on persistent largest-first launches.
+    ``frames_per_launch`` consecutive frames share one launch of each kernel
+    (the multi-view path: one preprocess, one sort over view-major tiles, one
+    compositing launch), which fills the GPU at small image sizes at the
+    cost of latency; F must be a multiple of it."""
 
-    def __init__(self, params: torch.Tensor, views, margin: float = 1.3, batch: int = 256):
+    def __init__(self, params: torch.Tensor, views, margin: float = 1.3, batch: int = 256,
+                 frames_per_launch: int = 1):
         self.params = params.contiguous()
         self.views = np.atleast_2d(views)
-        self.cviews = [G.make_views(v) for v in self.views]
-        self.rast = Rasterizer(self.params.shape[1], self.views[0], device=self.params.device,
+        B = int(frames_per_launch)
+        assert B >= 1 and len(self.views) % B == 0
+        self.B = B
+        self.cviews = [G.make_views(self.views[i:i + B]) for i in range(0, len(self.views), B)]
+        self.rast = Rasterizer(self.params.shape[1], self.views[0:B], device=self.params.device,
                                batch=batch, persistent=True, forward_only=True)
         # The parameters do not change, so each frame's pair count is fixed:
         # buffers sized from the measured peak cannot overflow on replay.
@@ -59,10 +67,12 @@ class FrameRenderer:
 
     @property
     def image(self) -> torch.Tensor:
+        """[frames_per_launch, 3, H, W]: the last launch's frames."""
         return self.rast.image
 
     def render(self, f: int) -> torch.Tensor:
-        """Frame f's launches (eager); the image lands in ``self.image``."""
+        """Launch f's frames (f * frames_per_launch ...), eager; the images
+        land in ``self.image``."""
         r = self.rast
         r.set_views(self.cviews[f])
         r.preprocess(self.params)
@@ -81,18 +91,21 @@ class FrameRenderer:
         self.graphs[f].replay()
 
     def frame_rate(self, frames: int = 200, warmup: int = 20) -> dict:
-        """Frames per second over ``frames`` graph replays cycling through the
-        views, bracketed by device synchronisations."""
+        """Frames per second over ``frames`` frames (graph replays cycling
+        through the launches), bracketed by device synchronisations."""
         if self.graphs is None:
             self.capture()
         F = len(self.graphs)
+        launches = max(1, frames // self.B)
         for k in range(warmup):
             self.replay(k % F)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(frames):
+        for k in range(launches):
             self.replay(k % F)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        return {"fps": round(frames / dt, 1), "ms_per_frame": round(1e3 * dt / frames, 4),
-                "frames": frames, "views": F, "peak_pairs": self.peak_pairs}
+        n = launches * self.B
+        return {"fps": round(n / dt, 1), "ms_per_frame": round(1e3 * dt / n, 4),
+                "frames": n, "views": F * self.B, "frames_per_launch": self.B,
+                "peak_pairs": self.peak_pairs}

@@ -5,7 +5,7 @@
 * FrameRenderer at 480x270 (a 960x540 camera rescaled): every frame's graph
   replay equals its eager launches bit for bit, and the image matches the
   oracle's compositing to 1e-4 except at pixels next to an alpha / clamp /
-  transmittance threshold.
+  transmittance threshold; three frames per launch give the same bits.
 """
 import numpy as np
 import pytest
@@ -58,3 +58,12 @@ def test_frame_renderer_display_size():
         assert near.mean() < 1e-2
     rate = fr.frame_rate(frames=30, warmup=3)
     assert rate["fps"] > 0 and rate["peak_pairs"] > 0
+    # three frames per launch: the same image bits as one frame per launch
+    fr3 = FrameRenderer(P, views, frames_per_launch=3)
+    fr3.capture()
+    fr3.replay(0)
+    torch.cuda.synchronize()
+    for f in range(len(views)):
+        fr.render(f)
+        torch.cuda.synchronize()
+        assert torch.equal(fr3.image[f], fr.image[0])
