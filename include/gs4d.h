@@ -133,6 +133,21 @@ int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_t *touched,
                   uint32_t *vals, int32_t *ranges, int64_t *n_pairs, int32_t *overflow, void *ws,
                   size_t ws_bytes, void *stream);
 
+/* Binning strategy of gs4d_bin_sort (process-wide; the output is the same):
+ *   GS4D_BIN_PER_TILE  emit pairs in item order, sort on the tile bits, then
+ *                      one workgroup per tile sorts its pairs by depth in LDS
+ *                      (fewest launches; suits tiles of up to a few thousand
+ *                      pairs)
+ *   GS4D_BIN_PRESORT   sort the items by depth on the device first, emit in
+ *                      that order, then sort on the tile bits (suits tiles of
+ *                      tens of thousands of pairs)
+ *   GS4D_BIN_AUTO      per tile while pair_capacity <= 4096 * tiles, else
+ *                      presort (the default) */
+#define GS4D_BIN_AUTO 0
+#define GS4D_BIN_PER_TILE 1
+#define GS4D_BIN_PRESORT 2
+int gs4d_set_bin_strategy(int32_t strategy);
+
 /* Render options.  Zero-initialise and set what is needed. */
 typedef struct gs4d_render_opts {
     int32_t batch;          /* Gaussians staged in LDS per round: 64, 128 or 256 (0 -> 256) */

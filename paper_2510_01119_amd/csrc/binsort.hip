@@ -4,7 +4,8 @@
 // tile, as (key, value) = ((global tile << 32) | bits(FP32 depth), Gaussian)
 // sorted ascending by (key, value).
 //
-// Work plan (one GPU, no host synchronisation):
+// Work plan (one GPU, no host synchronisation), per tile (the default while
+// tiles hold up to a few thousand pairs):
 //   1. device-wide exclusive scan of tiles-touched over the (view, Gaussian)
 //      items -> each item's first pair slot, the pair count P and the
 //      capacity flag (on device).
@@ -13,9 +14,11 @@
 //      passes); inside one tile the pairs stay in Gaussian order.
 //   4. tile ranges from adjacent key differences.
 //   5. one workgroup per tile sorts its pairs stably on the 32 depth bits,
-//      which yields exactly the ascending (key, value) order.  Tiles hold a
-//      few hundred to a few thousand pairs, so this runs in registers and
-//      LDS and replaces a device-wide sort of all items by depth.
+//      which yields exactly the ascending (key, value) order.
+// Presort (for tiles of tens of thousands of pairs): a stable radix sort of
+// the items on their depth bits (the first histogram pass builds the keys
+// and zeroes the ranges), the scan of step 1 read in that order, emission in
+// depth order, then steps 3 and 4; the pairs are then in order already.
 //
 // Radix sort: 8-bit digits; per pass a histogram kernel (per-block digit
 // counts), a scan kernel (one wave per digit over the blocks, giving each
@@ -74,6 +77,53 @@ rs_hist_kernel(const K *__restrict__ keys, const int64_t *count_dev, int64_t cou
     for (int i = 0; i < RS_ITEMS; ++i) {
         const int64_t idx = base + i * 64 + l;
         if (idx < n) atomicAdd(&cnt[w][digit_of(keys[idx], shift, nbits)], 1u);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) c += cnt[k][t];
+    hist[(int64_t)t * nb + b] = c;
+}
+
+// Presort strategy: the items (view, Gaussian) as the source of the depth
+// sort's first pass: item o's key is
+// the bits of its FP32 depth (culled items, no tile touched: 0xFFFFFFFF, so
+// they sort last) and its value o.  The first histogram pass builds keys
+// and values itself (same block layout as rs_hist_kernel), and zeroes the
+// tile ranges in the same launch (a tile no pair reaches stays (0, 0)).
+struct ItemSource {
+    const float4 *rec;
+    const int32_t *touched;
+    int32_t *ranges;
+    int64_t n_range_ints;
+};
+
+template <int RS_ITEMS>
+__global__ void __launch_bounds__(RS_THREADS)
+rs_hist_items_kernel(ItemSource src, int64_t m, uint32_t *__restrict__ keys,
+                     uint32_t *__restrict__ vals, uint32_t *__restrict__ hist) {
+    constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int64_t i = (int64_t)blockIdx.x * RS_THREADS + t; i < src.n_range_ints;
+         i += (int64_t)gridDim.x * RS_THREADS)
+        src.ranges[i] = 0;
+    const int64_t nb = (m + RS_TILE - 1) / RS_TILE;
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    __shared__ uint32_t cnt[RS_WAVES][256];
+    for (int i = t; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = b * RS_TILE + (int64_t)w * (RS_TILE / RS_WAVES);
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t o = base + i * 64 + l;
+        if (o < m) {
+            const uint32_t key =
+                src.touched[o] > 0 ? __float_as_uint(src.rec[3 * o + 1].z) : 0xFFFFFFFFu;
+            keys[o] = key;
+            vals[o] = (uint32_t)o;
+            atomicAdd(&cnt[w][key & 0xFFu], 1u);
+        }
     }
     __syncthreads();
     uint32_t c = 0;
@@ -255,16 +305,23 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *total) {
     return off + incl - x;
 }
 
+// value i of a scan input: in[i], or in[gather[i]] when a gather index is given
+__device__ __forceinline__ int32_t scan_in(const int32_t *__restrict__ in,
+                                           const uint32_t *__restrict__ gather, int64_t i) {
+    return gather ? in[gather[i]] : in[i];
+}
+
 template <int ITEMS>
 __global__ void __launch_bounds__(SC_THREADS)
-scan_reduce_kernel(const int32_t *__restrict__ in, int64_t count, int64_t *__restrict__ bsum) {
+scan_reduce_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
+                   int64_t count, int64_t *__restrict__ bsum) {
     const int64_t b = blockIdx.x;
     const int64_t base = b * (SC_THREADS * ITEMS);
     int64_t s = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
-        if (idx < count) s += in[idx];
+        if (idx < count) s += scan_in(in, gather, idx);
     }
     int64_t tot;
     block_excl_scan(s, &tot);
@@ -313,8 +370,9 @@ struct ScanTop {
 // scan itself runs over ITEMS consecutive values per thread, regrouped in LDS.
 template <int ITEMS>
 __global__ void __launch_bounds__(SC_THREADS)
-scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t count,
-                 const int64_t *__restrict__ bsum, ScanTop top) {
+scan_down_kernel(const int32_t *__restrict__ in, const uint32_t *__restrict__ gather,
+                 int32_t *__restrict__ out, int64_t count, const int64_t *__restrict__ bsum,
+                 ScanTop top) {
     constexpr int TILE = SC_THREADS * ITEMS;
     __shared__ int32_t tile[TILE];
     const int64_t b = blockIdx.x;
@@ -323,7 +381,7 @@ scan_down_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out, int6
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = base + (int64_t)i * SC_THREADS + t;
-        tile[i * SC_THREADS + t] = idx < count ? in[idx] : 0;
+        tile[i * SC_THREADS + t] = idx < count ? scan_in(in, gather, idx) : 0;
     }
     __syncthreads();
     int32_t v[ITEMS];
@@ -376,24 +434,24 @@ inline int64_t sc_blocks(int64_t count) {
 
 // the launches of one scan: block sums, (for many blocks) their scan with
 // the optional binning outputs, the down-sweep
-int scan_launch(const int32_t *in, int32_t *out, int64_t count,
+int scan_launch(const int32_t *in, const uint32_t *gather, int32_t *out, int64_t count,
                 int64_t *total, int64_t *bsum, int64_t capacity, int64_t *n_pairs,
                 int32_t *overflow, hipStream_t st) {
     const int64_t nb = sc_blocks(count);
     const bool fused = nb <= SC_FUSE_BLOCKS;
     const ScanTop top{fused ? 1 : 0, nb, total, capacity, n_pairs, overflow};
     if (sc_items(count) == SC_SMALL_ITEMS)
-        scan_reduce_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, count, bsum);
+        scan_reduce_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
     else
-        scan_reduce_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, count, bsum);
+        scan_reduce_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, count, bsum);
     if (!fused)
         scan_top_kernel<<<1, SC_THREADS, 0, st>>>(bsum, nb, total, capacity, n_pairs, overflow);
     if (sc_items(count) == SC_SMALL_ITEMS)
-        scan_down_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, out, count, bsum,
-                                                                             top);
+        scan_down_kernel<SC_SMALL_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count,
+                                                                             bsum, top);
     else
-        scan_down_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, out, count, bsum,
-                                                                             top);
+        scan_down_kernel<SC_LARGE_ITEMS><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, gather, out, count,
+                                                                             bsum, top);
     return GS4D_OK;
 }
 
@@ -427,6 +485,37 @@ __global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__res
             const uint64_t tile = tbase + (uint64_t)ty * tiles_x + tx;
             keys[j] = (tile << 32) | lo;
             vals[j] = (uint32_t)g;
+            ++j;
+        }
+}
+
+// Presort strategy: items in depth order k (order[k] = item o) write their
+// pairs from offs[k] on; inside one tile they are then ascending in (depth
+// bits, Gaussian) already.
+__global__ void emit_depth_order_kernel(const uint32_t *__restrict__ dkeys,
+                                        const uint32_t *__restrict__ order,
+                            const int32_t *__restrict__ touched, const int32_t *__restrict__ offs,
+                            const int4 *__restrict__ rect, int64_t m, int64_t n, int32_t tiles_x,
+                            int32_t tiles_per_view, int64_t capacity, uint64_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const uint32_t o = order[k];
+    const int32_t cnt = touched[o];
+    if (cnt == 0) return;
+    const int64_t off = offs[k];
+    if (off < 0 || off + cnt > capacity) return;
+    const uint32_t vi = (uint32_t)(o / (uint64_t)n);
+    const uint32_t g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
+    const int4 r = rect[o];
+    const uint64_t lo = dkeys[k];
+    const uint64_t tbase = (uint64_t)vi * (uint64_t)tiles_per_view;
+    int64_t j = off;
+    for (int ty = r.y; ty < r.w; ++ty)
+        for (int tx = r.x; tx < r.z; ++tx) {
+            const uint64_t tile = tbase + (uint64_t)ty * tiles_x + tx;
+            keys[j] = (tile << 32) | lo;
+            vals[j] = g;
             ++j;
         }
 }
@@ -791,15 +880,25 @@ inline unsigned grid_for(int64_t count, int threads) {
 template <class K, int ITEMS>
 int radix_passes(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
                  int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, uint32_t *hist,
-                 uint32_t *totals, hipStream_t st) {
+                 uint32_t *totals, const ItemSource *items, hipStream_t st) {
     constexpr int TILE = RS_THREADS * ITEMS;
     const int64_t nb_max = (capacity + TILE - 1) / TILE;
     K *src = k0, *dst = k1;
     uint32_t *vsrc = v0, *vdst = v1;
     for (int shift = bit_lo; shift < bit_hi; shift += 8) {
         const int nbits = bit_hi - shift < 8 ? bit_hi - shift : 8;
-        rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
-            src, count_dev, count_host, capacity, shift, nbits, hist);
+        if constexpr (sizeof(K) == 4) {
+            if (shift == bit_lo && items) {
+                rs_hist_items_kernel<ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+                    *items, count_host, src, vsrc, hist);
+            } else {
+                rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+                    src, count_dev, count_host, capacity, shift, nbits, hist);
+            }
+        } else {
+            rs_hist_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
+                src, count_dev, count_host, capacity, shift, nbits, hist);
+        }
         rs_scan_kernel<<<256, 64, 0, st>>>(hist, totals, count_dev, count_host, capacity, TILE);
         rs_scatter_kernel<K, ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
             src, vsrc, dst, vdst, count_dev, count_host, capacity, shift, nbits, hist, totals);
@@ -824,7 +923,7 @@ inline int64_t rs_blocks(int64_t capacity) {
 template <class K>
 int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_dev,
                     int64_t count_host, int64_t capacity, int bit_lo, int bit_hi, void *ws,
-                    hipStream_t st, int *result_in_alt) {
+                    hipStream_t st, int *result_in_alt, const ItemSource *items = nullptr) {
     const int passes = (bit_hi - bit_lo + 7) / 8;
     *result_in_alt = passes & 1;
     if (passes <= 0 || capacity <= 0) return GS4D_OK;
@@ -834,13 +933,13 @@ int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *cou
     switch (rs_items(capacity)) {
     case RS_TINY_ITEMS:
         return radix_passes<K, RS_TINY_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                               bit_lo, bit_hi, hist, totals, st);
+                                               bit_lo, bit_hi, hist, totals, items, st);
     case RS_SMALL_ITEMS:
         return radix_passes<K, RS_SMALL_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, bit_hi, hist, totals, st);
+                                                bit_lo, bit_hi, hist, totals, items, st);
     default:
         return radix_passes<K, RS_LARGE_ITEMS>(k0, v0, k1, v1, count_dev, count_host, capacity,
-                                                bit_lo, bit_hi, hist, totals, st);
+                                                bit_lo, bit_hi, hist, totals, items, st);
     }
 }
 
@@ -880,17 +979,18 @@ int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t count, int64_t *
     if (count <= 0) {
         return launch_fill<int64_t>(total, (int64_t)0, 1, st);
     }
-    scan_launch(in, out, count, total, static_cast<int64_t *>(ws), 0, nullptr, nullptr, st);
+    scan_launch(in, nullptr, out, count, total, static_cast<int64_t *>(ws), 0, nullptr, nullptr, st);
     GS4D_LAUNCH_CHECK("exclusive_scan");
     return GS4D_OK;
 }
 
 namespace {
-// Pair offsets of the items: exclusive scan of touched, the pair count and
-// the capacity flag (count >= 1).
-int pair_offsets(const int32_t *touched, int32_t *offs, int64_t count, int64_t *total, void *ws,
-                 int64_t capacity, int64_t *n_pairs, int32_t *overflow, hipStream_t st) {
-    scan_launch(touched, offs, count, total, static_cast<int64_t *>(ws), capacity, n_pairs,
+// Pair offsets of the items (taken in `order` when given): exclusive scan of
+// touched, the pair count and the capacity flag (count >= 1).
+int pair_offsets(const int32_t *touched, const uint32_t *order, int32_t *offs, int64_t count,
+                 int64_t *total, void *ws, int64_t capacity, int64_t *n_pairs, int32_t *overflow,
+                 hipStream_t st) {
+    scan_launch(touched, order, offs, count, total, static_cast<int64_t *>(ws), capacity, n_pairs,
                 overflow, st);
     GS4D_LAUNCH_CHECK("pair_offsets");
     return GS4D_OK;
@@ -899,6 +999,7 @@ int pair_offsets(const int32_t *touched, int32_t *offs, int64_t count, int64_t *
 
 namespace {
 struct BinLayout {
+    uint32_t *ik0, *iv0, *ik1, *iv1;   // presort: item keys / values, two buffers
     int32_t *offs;
     void *scan_ws;
     int64_t *total;
@@ -911,15 +1012,24 @@ BinLayout carve_bin(void *ws, int64_t m, int64_t cap, size_t *used) {
     Carve c(ws, ~size_t(0));
     BinLayout L;
     const size_t mm = (size_t)(m > 0 ? m : 1);
+    L.ik0 = c.take<uint32_t>(mm);
+    L.iv0 = c.take<uint32_t>(mm);
+    L.ik1 = c.take<uint32_t>(mm);
+    L.iv1 = c.take<uint32_t>(mm);
     L.offs = c.take<int32_t>(mm);
     L.scan_ws = c.take<char>(scan_workspace_size(m));
     L.total = c.take<int64_t>(1);
     L.pk = c.take<uint64_t>((size_t)(cap > 0 ? cap : 1));
     L.pv = c.take<uint32_t>((size_t)(cap > 0 ? cap : 1));
-    L.radix_ws = c.take<char>(radix_workspace_size(cap));
+    L.radix_ws = c.take<char>(radix_workspace_size(m > cap ? m : cap));
     *used = c.used;
     return L;
 }
+
+// binning strategy (gs4d_set_bin_strategy); automatic: per tile while the
+// pair capacity averages at most BIN_PER_TILE_MAX_MEAN pairs per tile
+int g_bin_strategy = GS4D_BIN_AUTO;
+constexpr int64_t BIN_PER_TILE_MAX_MEAN = 4096;
 
 int tile_bits_for(int64_t n_tiles) {
     int b = 1;
@@ -931,6 +1041,14 @@ int tile_bits_for(int64_t n_tiles) {
 }  // namespace gs4d
 
 using namespace gs4d;
+
+extern "C" int gs4d_set_bin_strategy(int32_t strategy) {
+    GS4D_REQUIRE(strategy == GS4D_BIN_AUTO || strategy == GS4D_BIN_PER_TILE ||
+                     strategy == GS4D_BIN_PRESORT,
+                 "gs4d_set_bin_strategy: strategy must be 0, 1 or 2");
+    g_bin_strategy = strategy;
+    return GS4D_OK;
+}
 
 extern "C" size_t gs4d_bin_sort_workspace_size(int64_t n, int32_t n_views, int64_t pair_capacity) {
     size_t used = 0;
@@ -967,34 +1085,65 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
         GS4D_TRY(launch_fill<int32_t>(overflow, 0, 1, st));
         return GS4D_OK;
     }
-    // 1: pair offsets of the items, pair count and capacity flag
-    GS4D_TRY(pair_offsets(touched, L.offs, m, L.total, L.scan_ws, pair_capacity, n_pairs, overflow,
-                          st));
-    if (pair_capacity == 0) return launch_fill<int32_t>(ranges, 0, 2 * n_tiles, st);
-    // 2-3: emit in item order, stable sort on the tile bits only
     const int tbits = tile_bits_for(n_tiles);
     const int tpasses = (tbits + 7) / 8;
     uint64_t *ek = (tpasses & 1) ? L.pk : keys;
     uint32_t *ev = (tpasses & 1) ? L.pv : vals;
     uint64_t *ok = (tpasses & 1) ? keys : L.pk;
     uint32_t *ov = (tpasses & 1) ? vals : L.pv;
-    emit_kernel<<<dim3(grid_for(n, 128), (unsigned)n_views), 128, 0, st>>>(
-        reinterpret_cast<const float4 *>(rec), touched, L.offs, reinterpret_cast<const int4 *>(rect),
-        n, vp.tiles_x, vp.tiles_per_view, pair_capacity, ek, ev, ranges, 2 * n_tiles);
-    GS4D_LAUNCH_CHECK("emit");
+    // Both strategies give the same pairs in the same order.  Per tile: fewer
+    // launches, and cheap while tiles hold up to a few thousand pairs.
+    // Presort: one device-wide sort of the items by depth, which wins when
+    // tiles hold tens of thousands of pairs (then the per-tile sorts pass
+    // through global memory).  Automatic choice from the pair capacity per
+    // tile, known on the host.
+    const bool per_tile = g_bin_strategy == GS4D_BIN_PER_TILE ||
+                          (g_bin_strategy == GS4D_BIN_AUTO &&
+                           pair_capacity <= (int64_t)BIN_PER_TILE_MAX_MEAN * n_tiles);
     int alt = 0;
+    if (per_tile) {
+        // pair offsets of the items, pair count and capacity flag
+        GS4D_TRY(pair_offsets(touched, nullptr, L.offs, m, L.total, L.scan_ws, pair_capacity,
+                              n_pairs, overflow, st));
+        if (pair_capacity == 0) return launch_fill<int32_t>(ranges, 0, 2 * n_tiles, st);
+        // emit in item order (zeroing the ranges), stable sort on the tile bits only
+        emit_kernel<<<dim3(grid_for(n, 128), (unsigned)n_views), 128, 0, st>>>(
+            reinterpret_cast<const float4 *>(rec), touched, L.offs,
+            reinterpret_cast<const int4 *>(rect), n, vp.tiles_x, vp.tiles_per_view, pair_capacity,
+            ek, ev, ranges, 2 * n_tiles);
+        GS4D_LAUNCH_CHECK("emit");
+    } else {
+        // items sorted by depth bits; the first pass builds their keys and
+        // zeroes the ranges
+        const ItemSource items{reinterpret_cast<const float4 *>(rec), touched, ranges,
+                               2 * n_tiles};
+        GS4D_TRY(radix_sort_impl<uint32_t>(L.ik0, L.iv0, L.ik1, L.iv1, nullptr, m, m, 0, 32,
+                                           L.radix_ws, st, &alt, &items));
+        const uint32_t *dkeys = alt ? L.ik1 : L.ik0;
+        const uint32_t *order = alt ? L.iv1 : L.iv0;
+        // offsets in depth order, pair count and capacity flag
+        GS4D_TRY(pair_offsets(touched, order, L.offs, m, L.total, L.scan_ws, pair_capacity,
+                              n_pairs, overflow, st));
+        if (pair_capacity == 0) return GS4D_OK;
+        // emit in depth order: inside a tile the pairs are then in (depth, Gaussian) order
+        emit_depth_order_kernel<<<grid_for(m, 128), 128, 0, st>>>(
+            dkeys, order, touched, L.offs, reinterpret_cast<const int4 *>(rect), m, n,
+            vp.tiles_x, vp.tiles_per_view, pair_capacity, ek, ev);
+        GS4D_LAUNCH_CHECK("emit (depth order)");
+    }
     GS4D_TRY(radix_sort_u64(ek, ev, ok, ov, n_pairs, 0, pair_capacity, 32, 32 + tbits, L.radix_ws,
                             st, &alt));
-    // 4: ranges
-    // the pair count is on the device: a grid of at most 2,048 blocks strides
-    // over it
+    // tile ranges; the pair count is on the device: a grid of at most 2,048
+    // blocks strides over it
     const unsigned rgrid = grid_for(pair_capacity, 256) < 2048u ? grid_for(pair_capacity, 256) : 2048u;
     ranges_kernel<<<rgrid, 256, 0, st>>>(keys, n_pairs, pair_capacity, n_tiles,
                                          reinterpret_cast<int2 *>(ranges));
     GS4D_LAUNCH_CHECK("ranges");
-    // 5: depth order inside each tile (the pair buffer L.pk is free again)
-    tile_depth_sort_kernel<<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
-        keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk);
-    GS4D_LAUNCH_CHECK("tile depth sort");
+    if (per_tile) {
+        // depth order inside each tile (the pair buffer L.pk is free again)
+        tile_depth_sort_kernel<<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
+            keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk);
+        GS4D_LAUNCH_CHECK("tile depth sort");
+    }
     return GS4D_OK;
 }

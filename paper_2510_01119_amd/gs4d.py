@@ -75,6 +75,7 @@ _SIGS = {
     "gs4d_otsu_workspace_size": (_sz, []),
     "gs4d_otsu_mask": (_i32, [_p, _i64, _p, _p, _p, _sz, _p]),
     "gs4d_set_bwd_variant": (_i32, [_i32]),
+    "gs4d_set_bin_strategy": (_i32, [_i32]),
     "gs4d_grid_prune_workspace_size": (_sz, [_i64, _i32]),
     "gs4d_grid_prune": (_i32, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p, _p,
                                _p, _p, _sz, _p]),
@@ -254,6 +255,15 @@ def gs4d_otsu_mask(prob, threshold, mask, ws, stream=None):
     threshold (device float [1] or None), mask (uint8 like prob, or None)."""
     _check(lib().gs4d_otsu_mask(_ptr(prob), prob.numel(), _ptr(threshold), _ptr(mask), _ptr(ws),
                                 ws.numel(), _stream(stream)), "gs4d_otsu_mask")
+
+
+BIN_AUTO, BIN_PER_TILE, BIN_PRESORT = 0, 1, 2
+
+
+def gs4d_set_bin_strategy(strategy):
+    """Binning strategy of gs4d_bin_sort (process-wide): BIN_AUTO,
+    BIN_PER_TILE or BIN_PRESORT; the output is the same."""
+    _check(lib().gs4d_set_bin_strategy(int(strategy)), "gs4d_set_bin_strategy")
 
 
 def gs4d_tile_order_workspace_size(n_tiles):

@@ -7,9 +7,10 @@ finite differences.
 * GS4DRasterize under torch.autograd matches gs4d_render_bwd;
 * gradients against central differences (h = 1e-3) of the oracle's FP64
   forward on 64 random parameters;
-* the per-tile depth sort's corner cases against the oracle's binning, bit
-  for bit: equal depths (ties broken by Gaussian index), a tile of more than
-  2,048 pairs, tiles whose keys are all equal.
+* the binning's corner cases against the oracle's, bit for bit, under both
+  strategies (per-tile depth sort, device-wide depth presort): equal depths
+  (ties broken by Gaussian index), a tile of more than 2,048 pairs, tiles
+  whose keys are all equal.
 """
 import numpy as np
 import pytest
@@ -181,8 +182,17 @@ def _depth_sort_corner_set(seed=11):
     return p.astype(np.float32)
 
 
-def test_depth_sort_ties_long_and_equal_tiles():
+@pytest.mark.parametrize("strategy", [G.BIN_AUTO, G.BIN_PER_TILE, G.BIN_PRESORT])
+def test_depth_sort_ties_long_and_equal_tiles(strategy):
     need_gpu()
+    G.gs4d_set_bin_strategy(strategy)
+    try:
+        _depth_sort_case()
+    finally:
+        G.gs4d_set_bin_strategy(G.BIN_AUTO)
+
+
+def _depth_sort_case():
     view = synth.front_view(96, 64, 64.0)
     p = _depth_sort_corner_set()
     rec, rect, touched = oracle.preprocess_f32(p, view)
