@@ -456,10 +456,55 @@ int scan_launch(const int32_t *in, const uint32_t *gather, int32_t *out, int64_t
 }
 
 // ---------------------------------------------------------------- binning kernels
+// The pairs of one item: its rectangle's tiles in row-major order from slot
+// off on, key (global tile << 32) | depth bits, value g.  An item of at
+// least EMIT_WIDE pairs is written by the whole wave (64 consecutive pairs
+// per store); a smaller one by its own lane.  Every lane of the wave calls
+// this (has = the lane holds an item to write).
+constexpr int EMIT_WIDE = 32;
+
+__device__ __forceinline__ void emit_item_pairs(bool has, int64_t off, int32_t cnt, int4 r,
+                                                uint32_t lo, uint32_t g, uint32_t tbase,
+                                                int32_t tiles_x, uint64_t *__restrict__ keys,
+                                                uint32_t *__restrict__ vals) {
+    const bool wide = has && cnt >= EMIT_WIDE;
+    if (has && !wide) {
+        int64_t j = off;
+        for (int ty = r.y; ty < r.w; ++ty)
+            for (int tx = r.x; tx < r.z; ++tx) {
+                const uint64_t tile = (uint64_t)tbase + (uint64_t)ty * tiles_x + tx;
+                keys[j] = (tile << 32) | lo;
+                vals[j] = g;
+                ++j;
+            }
+    }
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(wide);
+    while (pending) {
+        const int src = __builtin_ctzll(pending);
+        pending &= pending - 1;
+        const int64_t boff =
+            (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)off, src) |
+            ((int64_t)__builtin_amdgcn_readlane((int)(off >> 32), src) << 32);
+        const int bcnt = __builtin_amdgcn_readlane(cnt, src);
+        const int x0 = __builtin_amdgcn_readlane(r.x, src);
+        const int y0 = __builtin_amdgcn_readlane(r.y, src);
+        const int w = __builtin_amdgcn_readlane(r.z, src) - x0;
+        const uint32_t blo = (uint32_t)__builtin_amdgcn_readlane((int)lo, src);
+        const uint32_t bg = (uint32_t)__builtin_amdgcn_readlane((int)g, src);
+        const uint32_t btb = (uint32_t)__builtin_amdgcn_readlane((int)tbase, src);
+        for (int j = lane; j < bcnt; j += 64) {
+            const int ty = j / w, tx = j - ty * w;
+            const uint64_t tile = (uint64_t)btb + (uint64_t)(y0 + ty) * tiles_x + (x0 + tx);
+            keys[boff + j] = (tile << 32) | blo;
+            vals[boff + j] = bg;
+        }
+    }
+}
+
 // Item o = view vi * n + Gaussian g (grid: x over g, y over vi) writes its
-// touched[o] pairs from offs[o] on, its rectangle's tiles in row-major
-// order, key (global tile << 32) | bits(FP32 depth), value g.  The grid also
-// zeroes the tile ranges (a tile no pair reaches stays (0, 0)).
+// touched[o] pairs from offs[o] on.  The grid also zeroes the tile ranges (a
+// tile no pair reaches stays (0, 0)).
 __global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
                             const int32_t *__restrict__ offs, const int4 *__restrict__ rect,
                             int64_t n, int32_t tiles_x, int32_t tiles_per_view, int64_t capacity,
@@ -470,23 +515,25 @@ __global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__res
     const int64_t stride = (int64_t)gridDim.x * gridDim.y * blockDim.x;
     for (int64_t i = g + (int64_t)vi * gridDim.x * blockDim.x; i < n_range_ints; i += stride)
         ranges[i] = 0;
-    if (g >= n) return;
-    const int64_t o = (int64_t)vi * n + g;
-    const int32_t cnt = touched[o];
-    if (cnt == 0) return;
-    const int64_t off = offs[o];
-    if (off < 0 || off + cnt > capacity) return;
-    const int4 r = rect[o];
-    const uint64_t lo = __float_as_uint(rec[3 * o + 1].z);
-    const uint64_t tbase = (uint64_t)vi * (uint64_t)tiles_per_view;
-    int64_t j = off;
-    for (int ty = r.y; ty < r.w; ++ty)
-        for (int tx = r.x; tx < r.z; ++tx) {
-            const uint64_t tile = tbase + (uint64_t)ty * tiles_x + tx;
-            keys[j] = (tile << 32) | lo;
-            vals[j] = (uint32_t)g;
-            ++j;
+    bool has = false;
+    int32_t cnt = 0;
+    int64_t off = 0;
+    int4 r = make_int4(0, 0, 0, 0);
+    uint32_t lo = 0;
+    if (g < n) {
+        const int64_t o = (int64_t)vi * n + g;
+        cnt = touched[o];
+        if (cnt > 0) {
+            off = offs[o];
+            has = off >= 0 && off + cnt <= capacity;
+            if (has) {
+                r = rect[o];
+                lo = __float_as_uint(rec[3 * o + 1].z);
+            }
         }
+    }
+    emit_item_pairs(has, off, cnt, r, lo, (uint32_t)g, vi * (uint32_t)tiles_per_view, tiles_x,
+                    keys, vals);
 }
 
 // Presort strategy: items in depth order k (order[k] = item o) write their
@@ -494,42 +541,56 @@ __global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__res
 // bits, Gaussian) already.
 __global__ void emit_depth_order_kernel(const uint32_t *__restrict__ dkeys,
                                         const uint32_t *__restrict__ order,
-                            const int32_t *__restrict__ touched, const int32_t *__restrict__ offs,
-                            const int4 *__restrict__ rect, int64_t m, int64_t n, int32_t tiles_x,
-                            int32_t tiles_per_view, int64_t capacity, uint64_t *__restrict__ keys,
-                            uint32_t *__restrict__ vals) {
+                                        const int32_t *__restrict__ touched,
+                                        const int32_t *__restrict__ offs,
+                                        const int4 *__restrict__ rect, int64_t m, int64_t n,
+                                        int32_t tiles_x, int32_t tiles_per_view, int64_t capacity,
+                                        uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    const uint32_t o = order[k];
-    const int32_t cnt = touched[o];
-    if (cnt == 0) return;
-    const int64_t off = offs[k];
-    if (off < 0 || off + cnt > capacity) return;
-    const uint32_t vi = (uint32_t)(o / (uint64_t)n);
-    const uint32_t g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
-    const int4 r = rect[o];
-    const uint64_t lo = dkeys[k];
-    const uint64_t tbase = (uint64_t)vi * (uint64_t)tiles_per_view;
-    int64_t j = off;
-    for (int ty = r.y; ty < r.w; ++ty)
-        for (int tx = r.x; tx < r.z; ++tx) {
-            const uint64_t tile = tbase + (uint64_t)ty * tiles_x + tx;
-            keys[j] = (tile << 32) | lo;
-            vals[j] = g;
-            ++j;
+    bool has = false;
+    int32_t cnt = 0;
+    int64_t off = 0;
+    int4 r = make_int4(0, 0, 0, 0);
+    uint32_t lo = 0, g = 0, tbase = 0;
+    if (k < m) {
+        const uint32_t o = order[k];
+        cnt = touched[o];
+        if (cnt > 0) {
+            off = offs[k];
+            has = off >= 0 && off + cnt <= capacity;
+            if (has) {
+                const uint32_t vi = (uint32_t)(o / (uint64_t)n);
+                g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
+                r = rect[o];
+                lo = dkeys[k];
+                tbase = vi * (uint32_t)tiles_per_view;
+            }
         }
+    }
+    emit_item_pairs(has, off, cnt, r, lo, g, tbase, tiles_x, keys, vals);
 }
 
+// Tile ranges from adjacent key differences; each thread takes four
+// consecutive keys (a grid-stride loop over the device pair count).
 __global__ void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *__restrict__ n_pairs,
                               int64_t capacity, int64_t n_tiles, int2 *__restrict__ ranges) {
     const int64_t n = *n_pairs;
     if (n > capacity) return;   // overflow: every tile stays empty (0, 0)
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t tile = keys[i] >> 32;
-        if (tile >= (uint64_t)n_tiles) continue;
-        if (i == 0 || (keys[i - 1] >> 32) != tile) ranges[tile].x = (int32_t)i;
-        if (i == n - 1 || (keys[i + 1] >> 32) != tile) ranges[tile].y = (int32_t)(i + 1);
+    for (int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i0 < n;
+         i0 += 4 * (int64_t)gridDim.x * blockDim.x) {
+        uint64_t prev = i0 > 0 ? keys[i0 - 1] >> 32 : ~0ull;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u;
+            if (i >= n) break;
+            const uint64_t tile = keys[i] >> 32;
+            const uint64_t next = i + 1 < n ? keys[i + 1] >> 32 : ~0ull;
+            if (tile < (uint64_t)n_tiles) {
+                if (prev != tile) ranges[tile].x = (int32_t)i;
+                if (next != tile) ranges[tile].y = (int32_t)(i + 1);
+            }
+            prev = tile;
+        }
     }
 }
 
@@ -1135,7 +1196,8 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
                             st, &alt));
     // tile ranges; the pair count is on the device: a grid of at most 2,048
     // blocks strides over it
-    const unsigned rgrid = grid_for(pair_capacity, 256) < 2048u ? grid_for(pair_capacity, 256) : 2048u;
+    const unsigned rblocks = grid_for((pair_capacity + 3) / 4, 256);
+    const unsigned rgrid = rblocks < 8192u ? rblocks : 8192u;
     ranges_kernel<<<rgrid, 256, 0, st>>>(keys, n_pairs, pair_capacity, n_tiles,
                                          reinterpret_cast<int2 *>(ranges));
     GS4D_LAUNCH_CHECK("ranges");
