@@ -570,26 +570,37 @@ __global__ void emit_depth_order_kernel(const uint32_t *__restrict__ dkeys,
     emit_item_pairs(has, off, cnt, r, lo, g, tbase, tiles_x, keys, vals);
 }
 
-// Tile ranges from adjacent key differences; each thread takes four
-// consecutive keys (a grid-stride loop over the device pair count).
+// Tile ranges from adjacent key differences: where the tile changes between
+// pairs i - 1 and i, the earlier tile ends and the later one starts at i; the
+// last pair closes its tile.  Each thread takes RG_UNROLL pairs one grid
+// stride apart, so a wave's loads stay coalesced and several are in flight
+// (the kernel is bound by load latency otherwise; the key at i - 1 is read
+// from cache).
+constexpr int RG_UNROLL = 4;
+
 __global__ void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *__restrict__ n_pairs,
                               int64_t capacity, int64_t n_tiles, int2 *__restrict__ ranges) {
     const int64_t n = *n_pairs;
     if (n > capacity) return;   // overflow: every tile stays empty (0, 0)
-    for (int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i0 < n;
-         i0 += 4 * (int64_t)gridDim.x * blockDim.x) {
-        uint64_t prev = i0 > 0 ? keys[i0 - 1] >> 32 : ~0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += RG_UNROLL * stride) {
+        uint64_t cur[RG_UNROLL], prv[RG_UNROLL];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t i = i0 + u;
+        for (int u = 0; u < RG_UNROLL; ++u) {
+            const int64_t i = b + u * stride;
+            cur[u] = i < n ? keys[i] >> 32 : ~0ull;
+            prv[u] = (i < n && i > 0) ? keys[i - 1] >> 32 : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < RG_UNROLL; ++u) {
+            const int64_t i = b + u * stride;
             if (i >= n) break;
-            const uint64_t tile = keys[i] >> 32;
-            const uint64_t next = i + 1 < n ? keys[i + 1] >> 32 : ~0ull;
-            if (tile < (uint64_t)n_tiles) {
-                if (prev != tile) ranges[tile].x = (int32_t)i;
-                if (next != tile) ranges[tile].y = (int32_t)(i + 1);
+            const uint64_t tile = cur[u], prev = prv[u];
+            if (tile != prev) {
+                if (tile < (uint64_t)n_tiles) ranges[tile].x = (int32_t)i;
+                if (prev < (uint64_t)n_tiles) ranges[prev].y = (int32_t)i;
             }
-            prev = tile;
+            if (i == n - 1 && tile < (uint64_t)n_tiles) ranges[tile].y = (int32_t)n;
         }
     }
 }
@@ -1196,8 +1207,8 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
                             st, &alt));
     // tile ranges; the pair count is on the device: a grid of at most 2,048
     // blocks strides over it
-    const unsigned rblocks = grid_for((pair_capacity + 3) / 4, 256);
-    const unsigned rgrid = rblocks < 8192u ? rblocks : 8192u;
+    const unsigned rblocks = grid_for((pair_capacity + RG_UNROLL - 1) / RG_UNROLL, 256);
+    const unsigned rgrid = rblocks < 65536u ? rblocks : 65536u;
     ranges_kernel<<<rgrid, 256, 0, st>>>(keys, n_pairs, pair_capacity, n_tiles,
                                          reinterpret_cast<int2 *>(ranges));
     GS4D_LAUNCH_CHECK("ranges");
