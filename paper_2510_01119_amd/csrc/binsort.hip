@@ -456,118 +456,133 @@ int scan_launch(const int32_t *in, const uint32_t *gather, int32_t *out, int64_t
 }
 
 // ---------------------------------------------------------------- binning kernels
-// The pairs of one item: its rectangle's tiles in row-major order from slot
-// off on, key (global tile << 32) | depth bits, value g.  An item of at
-// least EMIT_WIDE pairs is written by the whole wave (64 consecutive pairs
-// per store); a smaller one by its own lane.  Every lane of the wave calls
-// this (has = the lane holds an item to write).
-constexpr int EMIT_WIDE = 32;
+// The pairs of one wave's items.  An item's pairs are its rectangle's tiles
+// in row-major order from slot off on: key (global tile << 32) | depth bits,
+// value g.  The lanes hold items that are consecutive in the pair-offset
+// scan, so their pairs fill one contiguous slot range [S, S + total); the
+// wave writes it 64 slots per step (coalesced stores), lane j taking slot
+// C + j.  The item owning a slot is the highest lane whose first slot is at
+// or before it: the lanes whose item starts inside the step mark their start
+// in the wave's 64 LDS slots, a prefix maximum over the lanes spreads each
+// mark to the slots after it, and the lane whose item started before the step
+// covers the slots ahead of the first mark.  Every lane of the wave calls
+// this; `mark` holds -1 in all 64 slots on entry and again on return.  Slots
+// outside [0, capacity) are not written.
+constexpr int EMIT_THREADS = 128;
 
-__device__ __forceinline__ void emit_item_pairs(bool has, int64_t off, int32_t cnt, int4 r,
+__device__ __forceinline__ void emit_wave_pairs(bool valid, int32_t off, int32_t cnt, int4 r,
                                                 uint32_t lo, uint32_t g, uint32_t tbase,
-                                                int32_t tiles_x, uint64_t *__restrict__ keys,
+                                                int32_t tiles_x, int64_t capacity, int32_t *mark,
+                                                uint64_t *__restrict__ keys,
                                                 uint32_t *__restrict__ vals) {
-    const bool wide = has && cnt >= EMIT_WIDE;
-    if (has && !wide) {
-        int64_t j = off;
-        for (int ty = r.y; ty < r.w; ++ty)
-            for (int tx = r.x; tx < r.z; ++tx) {
-                const uint64_t tile = (uint64_t)tbase + (uint64_t)ty * tiles_x + tx;
-                keys[j] = (tile << 32) | lo;
-                vals[j] = g;
-                ++j;
-            }
-    }
     const int lane = threadIdx.x & 63;
-    uint64_t pending = __ballot(wide);
-    while (pending) {
-        const int src = __builtin_ctzll(pending);
-        pending &= pending - 1;
-        const int64_t boff =
-            (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)off, src) |
-            ((int64_t)__builtin_amdgcn_readlane((int)(off >> 32), src) << 32);
-        const int bcnt = __builtin_amdgcn_readlane(cnt, src);
-        const int x0 = __builtin_amdgcn_readlane(r.x, src);
-        const int y0 = __builtin_amdgcn_readlane(r.y, src);
-        const int w = __builtin_amdgcn_readlane(r.z, src) - x0;
-        const uint32_t blo = (uint32_t)__builtin_amdgcn_readlane((int)lo, src);
-        const uint32_t bg = (uint32_t)__builtin_amdgcn_readlane((int)g, src);
-        const uint32_t btb = (uint32_t)__builtin_amdgcn_readlane((int)tbase, src);
-        for (int j = lane; j < bcnt; j += 64) {
-            const int ty = j / w, tx = j - ty * w;
-            const uint64_t tile = (uint64_t)btb + (uint64_t)(y0 + ty) * tiles_x + (x0 + tx);
-            keys[boff + j] = (tile << 32) | blo;
-            vals[boff + j] = bg;
+    valid = valid && cnt > 0;
+    const uint64_t vm = __ballot(valid);
+    if (vm == 0) return;
+    const int64_t S = __builtin_amdgcn_readlane(off, __builtin_ctzll(vm));
+    int32_t total = valid ? cnt : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) total += __shfl_xor(total, d, 64);
+    for (int64_t C = S; C < S + total; C += 64) {
+        const int64_t rel = (int64_t)off - C;
+        if (valid && rel >= 0 && rel < 64) mark[rel] = lane;
+        __builtin_amdgcn_wave_barrier();
+        int own = mark[lane];
+        __builtin_amdgcn_wave_barrier();
+        mark[lane] = -1;
+        const uint64_t before = __ballot(valid && rel < 0);
+        const int carry = before ? 63 - __builtin_clzll(before) : -1;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(own, d, 64);
+            if (lane >= d) own = max(own, y);
         }
+        own = max(own, carry);
+        const int src = own < 0 ? 0 : own;
+        const int32_t ooff = __shfl(off, src, 64);
+        const int x0 = __shfl(r.x, src, 64), y0 = __shfl(r.y, src, 64);
+        const int w = __shfl(r.z, src, 64) - x0;
+        const uint32_t olo = (uint32_t)__shfl((int)lo, src, 64);
+        const uint32_t og = (uint32_t)__shfl((int)g, src, 64);
+        const uint32_t otb = (uint32_t)__shfl((int)tbase, src, 64);
+        const int64_t slot = C + lane;
+        if (own >= 0 && w > 0 && slot < S + total && slot >= 0 && slot < capacity) {
+            const int local = (int)(slot - ooff);
+            const int ty = local / w, tx = local - ty * w;
+            const uint64_t tile = (uint64_t)otb + (uint64_t)(y0 + ty) * tiles_x + (x0 + tx);
+            keys[slot] = (tile << 32) | olo;
+            vals[slot] = og;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 // Item o = view vi * n + Gaussian g (grid: x over g, y over vi) writes its
 // touched[o] pairs from offs[o] on.  The grid also zeroes the tile ranges (a
 // tile no pair reaches stays (0, 0)).
-__global__ void emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
-                            const int32_t *__restrict__ offs, const int4 *__restrict__ rect,
-                            int64_t n, int32_t tiles_x, int32_t tiles_per_view, int64_t capacity,
-                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                            int32_t *__restrict__ ranges, int64_t n_range_ints) {
+__global__ void __launch_bounds__(EMIT_THREADS)
+emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
+            const int32_t *__restrict__ offs, const int4 *__restrict__ rect, int64_t n,
+            int32_t tiles_x, int32_t tiles_per_view, int64_t capacity, uint64_t *__restrict__ keys,
+            uint32_t *__restrict__ vals, int32_t *__restrict__ ranges, int64_t n_range_ints) {
+    __shared__ int32_t mark[EMIT_THREADS / 64][64];
+    mark[threadIdx.x >> 6][threadIdx.x & 63] = -1;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t vi = blockIdx.y;
     const int64_t stride = (int64_t)gridDim.x * gridDim.y * blockDim.x;
     for (int64_t i = g + (int64_t)vi * gridDim.x * blockDim.x; i < n_range_ints; i += stride)
         ranges[i] = 0;
-    bool has = false;
-    int32_t cnt = 0;
-    int64_t off = 0;
+    bool valid = false;
+    int32_t cnt = 0, off = 0;
     int4 r = make_int4(0, 0, 0, 0);
     uint32_t lo = 0;
     if (g < n) {
         const int64_t o = (int64_t)vi * n + g;
         cnt = touched[o];
         if (cnt > 0) {
+            valid = true;
             off = offs[o];
-            has = off >= 0 && off + cnt <= capacity;
-            if (has) {
-                r = rect[o];
-                lo = __float_as_uint(rec[3 * o + 1].z);
-            }
+            r = rect[o];
+            lo = __float_as_uint(rec[3 * o + 1].z);
         }
     }
-    emit_item_pairs(has, off, cnt, r, lo, (uint32_t)g, vi * (uint32_t)tiles_per_view, tiles_x,
-                    keys, vals);
+    __builtin_amdgcn_wave_barrier();
+    emit_wave_pairs(valid, off, cnt, r, lo, (uint32_t)g, vi * (uint32_t)tiles_per_view, tiles_x,
+                    capacity, mark[threadIdx.x >> 6], keys, vals);
 }
 
 // Presort strategy: items in depth order k (order[k] = item o) write their
 // pairs from offs[k] on; inside one tile they are then ascending in (depth
 // bits, Gaussian) already.
-__global__ void emit_depth_order_kernel(const uint32_t *__restrict__ dkeys,
-                                        const uint32_t *__restrict__ order,
-                                        const int32_t *__restrict__ touched,
-                                        const int32_t *__restrict__ offs,
-                                        const int4 *__restrict__ rect, int64_t m, int64_t n,
-                                        int32_t tiles_x, int32_t tiles_per_view, int64_t capacity,
-                                        uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+__global__ void __launch_bounds__(EMIT_THREADS)
+emit_depth_order_kernel(const uint32_t *__restrict__ dkeys, const uint32_t *__restrict__ order,
+                        const int32_t *__restrict__ touched, const int32_t *__restrict__ offs,
+                        const int4 *__restrict__ rect, int64_t m, int64_t n, int32_t tiles_x,
+                        int32_t tiles_per_view, int64_t capacity, uint64_t *__restrict__ keys,
+                        uint32_t *__restrict__ vals) {
+    __shared__ int32_t mark[EMIT_THREADS / 64][64];
+    mark[threadIdx.x >> 6][threadIdx.x & 63] = -1;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool has = false;
-    int32_t cnt = 0;
-    int64_t off = 0;
+    bool valid = false;
+    int32_t cnt = 0, off = 0;
     int4 r = make_int4(0, 0, 0, 0);
     uint32_t lo = 0, g = 0, tbase = 0;
     if (k < m) {
         const uint32_t o = order[k];
         cnt = touched[o];
         if (cnt > 0) {
+            valid = true;
             off = offs[k];
-            has = off >= 0 && off + cnt <= capacity;
-            if (has) {
-                const uint32_t vi = (uint32_t)(o / (uint64_t)n);
-                g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
-                r = rect[o];
-                lo = dkeys[k];
-                tbase = vi * (uint32_t)tiles_per_view;
-            }
+            const uint32_t vi = (uint32_t)(o / (uint64_t)n);
+            g = (uint32_t)(o - (uint64_t)vi * (uint64_t)n);
+            r = rect[o];
+            lo = dkeys[k];
+            tbase = vi * (uint32_t)tiles_per_view;
         }
     }
-    emit_item_pairs(has, off, cnt, r, lo, g, tbase, tiles_x, keys, vals);
+    __builtin_amdgcn_wave_barrier();
+    emit_wave_pairs(valid, off, cnt, r, lo, g, tbase, tiles_x, capacity, mark[threadIdx.x >> 6],
+                    keys, vals);
 }
 
 // Tile ranges from adjacent key differences: where the tile changes between
@@ -1179,7 +1194,7 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
                               n_pairs, overflow, st));
         if (pair_capacity == 0) return launch_fill<int32_t>(ranges, 0, 2 * n_tiles, st);
         // emit in item order (zeroing the ranges), stable sort on the tile bits only
-        emit_kernel<<<dim3(grid_for(n, 128), (unsigned)n_views), 128, 0, st>>>(
+        emit_kernel<<<dim3(grid_for(n, EMIT_THREADS), (unsigned)n_views), EMIT_THREADS, 0, st>>>(
             reinterpret_cast<const float4 *>(rec), touched, L.offs,
             reinterpret_cast<const int4 *>(rect), n, vp.tiles_x, vp.tiles_per_view, pair_capacity,
             ek, ev, ranges, 2 * n_tiles);
@@ -1198,7 +1213,7 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
                               n_pairs, overflow, st));
         if (pair_capacity == 0) return GS4D_OK;
         // emit in depth order: inside a tile the pairs are then in (depth, Gaussian) order
-        emit_depth_order_kernel<<<grid_for(m, 128), 128, 0, st>>>(
+        emit_depth_order_kernel<<<grid_for(m, EMIT_THREADS), EMIT_THREADS, 0, st>>>(
             dkeys, order, touched, L.offs, reinterpret_cast<const int4 *>(rect), m, n,
             vp.tiles_x, vp.tiles_per_view, pair_capacity, ek, ev);
         GS4D_LAUNCH_CHECK("emit (depth order)");
