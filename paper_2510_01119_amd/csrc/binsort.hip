@@ -135,6 +135,8 @@ rs_hist_items_kernel(ItemSource src, int64_t m, uint32_t *__restrict__ keys,
 // One wave per digit: exclusive prefix of hist[d][0..nb) in place and the
 // digit's total count in row_total[d] (the offsets between digits are left to
 // the scatter blocks, so no kernel needs device-wide atomics).
+constexpr int RS_SCAN_LOADS = 16;
+
 __global__ void __launch_bounds__(64)
 rs_scan_kernel(uint32_t *__restrict__ hist, uint32_t *__restrict__ row_total,
                const int64_t *count_dev, int64_t count_host, int64_t capacity, int RS_TILE) {
@@ -144,15 +146,17 @@ rs_scan_kernel(uint32_t *__restrict__ hist, uint32_t *__restrict__ row_total,
     const int d = blockIdx.x, l = threadIdx.x;
     uint32_t running = 0;
     uint32_t *row = hist + (int64_t)d * nb;
-    for (int64_t c0 = 0; c0 < nb; c0 += 256) {
-        uint32_t x[4];
+    // RS_SCAN_LOADS loads per lane in flight per step: the loop is bound by
+    // load latency, not by the wave scans
+    for (int64_t c0 = 0; c0 < nb; c0 += 64 * RS_SCAN_LOADS) {
+        uint32_t x[RS_SCAN_LOADS];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < RS_SCAN_LOADS; ++i) {
             const int64_t idx = c0 + i * 64 + l;
             x[i] = idx < nb ? row[idx] : 0u;
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < RS_SCAN_LOADS; ++i) {
             uint32_t incl = x[i];
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
