@@ -14,39 +14,63 @@ from gpu_helpers import need_gpu
 pytestmark = pytest.mark.gpu
 
 
-def test_adam_matches_oracle():
+def _dev(a, offset):
+    """a on the device, starting `offset` floats into its allocation (offset 1
+    leaves the data 4-byte but not 16-byte aligned)."""
+    t = torch.zeros(a.size + offset, dtype=torch.float32, device="cuda")
+    v = t[offset:].view(a.shape)
+    v.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+    return v
+
+
+@pytest.mark.parametrize("n,rows,frozen,offset", [
+    (5000, 20, None, 0),
+    # row boundaries inside groups of four elements, a ragged tail of
+    # rows * n % 4 = 1 elements, and a frozen row (rate 0)
+    (5001, 13, 3, 0),
+    # arrays not 16-byte aligned (the one-element-per-thread kernel)
+    (5001, 13, 3, 1),
+])
+def test_adam_matches_oracle(n, rows, frozen, offset):
     """Five Adam steps with a decaying per-row learning rate.  Parameters
-    start at 0 so that FP32 resolves the ~lr-sized displacements."""
+    start at 0 so that FP32 resolves the ~lr-sized displacements.  A row
+    whose rate is 0 is left untouched, moments included."""
     need_gpu()
     rng = np.random.default_rng(0)
-    n = 5000
-    p = np.zeros((20, n), np.float32)
+    p = np.zeros((rows, n), np.float32)
     cfg = G.gs4d_adam_cfg()
-    lr0 = np.array([1e-5] * 4 + [5e-3] * 4 + [1e-3] * 8 + [5e-2] + [2.5e-3] * 3, np.float32)
+    lr0 = np.array([1e-5] * 4 + [5e-3] * 4 + [1e-3] * 8 + [5e-2] + [2.5e-3] * 3, np.float32)[:rows]
+    if frozen is not None:
+        lr0[frozen] = 0.0
     lr1 = lr0 * 0.01
-    for k in range(20):
+    for k in range(rows):
         cfg.lr0[k] = float(lr0[k])
         cfg.lr1[k] = float(lr1[k])
-    cfg.budget, cfg.rows, cfg.beta1, cfg.beta2, cfg.eps = 100, 20, 0.9, 0.999, 1e-15
-    P = torch.from_numpy(p).cuda()
-    M = torch.zeros_like(P)
-    V = torch.zeros_like(P)
+    cfg.budget, cfg.rows, cfg.beta1, cfg.beta2, cfg.eps = 100, rows, 0.9, 0.999, 1e-15
+    P = _dev(p, offset)
+    M = _dev(np.zeros_like(p), offset)
+    V = _dev(np.zeros_like(p), offset)
     step = torch.zeros(1, dtype=torch.int32, device="cuda")
-    rp, rm, rv = p.astype(np.float64), np.zeros((20, n)), np.zeros((20, n))
+    rp, rm, rv = p.astype(np.float64), np.zeros((rows, n)), np.zeros((rows, n))
+    live = [k for k in range(rows) if k != frozen]
     for s in range(1, 6):
-        g = rng.normal(0, 1, (20, n)).astype(np.float32)
-        G.gs4d_adam_step(P, torch.from_numpy(g).cuda(), M, V, cfg, step)
-        lrs = [oadam.lr_schedule(s, float(lr0[k]), float(lr1[k]), 100) for k in range(20)]
+        g = rng.normal(0, 1, (rows, n)).astype(np.float32)
+        G.gs4d_adam_step(P, _dev(g, offset), M, V, cfg, step)
+        lrs = [oadam.lr_schedule(s, float(lr0[k]), float(lr1[k]), 100) if k != frozen else 0.0
+               for k in range(rows)]
         rp, rm, rv = oadam.adam_step(rp, g, rm, rv, s, lrs, eps=1e-15)
     torch.cuda.synchronize()
     assert int(step.item()) == 5
-    assert np.allclose(M.cpu().numpy(), rm, rtol=1e-5, atol=1e-7)
+    gm, gv = M.cpu().numpy(), V.cpu().numpy()
+    assert np.allclose(gm[live], rm[live], rtol=1e-5, atol=1e-7)
     # beta2 = 0.999 is not representable in FP32: 1 - fl32(0.999) differs
     # from 0.001 by 1.3e-5 relative, which the second moment inherits
-    assert np.allclose(V.cpu().numpy(), rv, rtol=5e-5, atol=1e-9)
+    assert np.allclose(gv[live], rv[live], rtol=5e-5, atol=1e-9)
     got = P.cpu().numpy().astype(np.float64)
-    for k in range(20):
+    for k in live:
         assert np.allclose(got[k], rp[k], rtol=1e-4, atol=1e-5 * lr0[k])
+    if frozen is not None:
+        assert not got[frozen].any() and not gm[frozen].any() and not gv[frozen].any()
 
 
 @pytest.mark.parametrize("shape", [(1, 3, 64, 64), (2, 3, 37, 50)])
