@@ -976,8 +976,20 @@ int radix_passes(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const int64_t *count_
     const int64_t nb_max = (capacity + TILE - 1) / TILE;
     K *src = k0, *dst = k1;
     uint32_t *vsrc = v0, *vdst = v1;
-    for (int shift = bit_lo; shift < bit_hi; shift += 8) {
-        const int nbits = bit_hi - shift < 8 ? bit_hi - shift : 8;
+    // ceil(bits / 8) passes.  64-bit (tile) keys split their bits evenly over
+    // the passes (e.g. 7 + 7 for 14 tile bits rather than 8 + 6): a pass with
+    // fewer buckets writes longer runs per block, and the widest pass sets the
+    // cost.  32-bit keys take 8-bit digits from bit_lo up.
+    const int bits = bit_hi - bit_lo, passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        int shift, nbits;
+        if constexpr (sizeof(K) == 8) {
+            shift = bit_lo + p * bits / passes;
+            nbits = bit_lo + (p + 1) * bits / passes - shift;
+        } else {
+            shift = bit_lo + 8 * p;
+            nbits = bit_hi - shift < 8 ? bit_hi - shift : 8;
+        }
         if constexpr (sizeof(K) == 4) {
             if (shift == bit_lo && items) {
                 rs_hist_items_kernel<ITEMS><<<(unsigned)nb_max, RS_THREADS, 0, st>>>(
