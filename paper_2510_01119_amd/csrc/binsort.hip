@@ -593,28 +593,37 @@ emit_depth_order_kernel(const uint32_t *__restrict__ dkeys, const uint32_t *__re
 // pairs i - 1 and i, the earlier tile ends and the later one starts at i; the
 // last pair closes its tile.  Each thread takes RG_UNROLL pairs one grid
 // stride apart, so a wave's loads stay coalesced and several are in flight
-// (the kernel is bound by load latency otherwise; the key at i - 1 is read
-// from cache).
+// (the kernel is bound by load latency otherwise).  Only a key's upper word
+// (the tile) is read; the tile of pair i - 1 comes from the next lower lane,
+// lane 0 reads it.
 constexpr int RG_UNROLL = 4;
 
 __global__ void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *__restrict__ n_pairs,
                               int64_t capacity, int64_t n_tiles, int2 *__restrict__ ranges) {
     const int64_t n = *n_pairs;
     if (n > capacity) return;   // overflow: every tile stays empty (0, 0)
+    const uint32_t *hi = reinterpret_cast<const uint32_t *>(keys) + 1;   // word 2 i + 1
+    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += RG_UNROLL * stride) {
-        uint64_t cur[RG_UNROLL], prv[RG_UNROLL];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b - lane < n;
+         b += RG_UNROLL * stride) {
+        uint32_t cur[RG_UNROLL], prv[RG_UNROLL];
 #pragma unroll
         for (int u = 0; u < RG_UNROLL; ++u) {
             const int64_t i = b + u * stride;
-            cur[u] = i < n ? keys[i] >> 32 : ~0ull;
-            prv[u] = (i < n && i > 0) ? keys[i - 1] >> 32 : ~0ull;
+            cur[u] = i < n ? hi[2 * i] : ~0u;
+            prv[u] = (lane == 0 && i > 0 && i <= n) ? hi[2 * (i - 1)] : ~0u;
+        }
+#pragma unroll
+        for (int u = 0; u < RG_UNROLL; ++u) {
+            const uint32_t up = __shfl_up(cur[u], 1, 64);
+            if (lane > 0) prv[u] = up;
         }
 #pragma unroll
         for (int u = 0; u < RG_UNROLL; ++u) {
             const int64_t i = b + u * stride;
             if (i >= n) break;
-            const uint64_t tile = cur[u], prev = prv[u];
+            const uint32_t tile = cur[u], prev = prv[u];
             if (tile != prev) {
                 if (tile < (uint64_t)n_tiles) ranges[tile].x = (int32_t)i;
                 if (prev < (uint64_t)n_tiles) ranges[prev].y = (int32_t)i;
