@@ -168,10 +168,12 @@ typedef struct gs4d_render_opts {
 
 /* ---------------------------------------------------------------------------
  * gs4d_render_fwd -- front-to-back alpha compositing per pixel (Sec. 3.1):
- *   power = -1/2 (a dx^2 + c dy^2) - b dx dy (skip if > 0), alpha =
+ *   power = min(0, -1/2 (a dx^2 + c dy^2) - b dx dy), alpha =
  *   min(0.99, o_t e^power) (skip if < 1/255), T' = T (1 - alpha) (stop
  *   before blending if T' < 1e-4), C += rgb alpha T; output C + T bg.
- *   Pixel centres at (x + 1/2, y + 1/2).
+ *   Pixel centres at (x + 1/2, y + 1/2).  The conic is positive definite,
+ *   so the exponent is <= 0 in exact arithmetic: the min with 0 absorbs
+ *   rounding only (the backward differentiates the exponent itself).
  *   image    out float [n_views][3][H][W]
  *   T_final  out float [n_views][H][W]
  *   last     out int32 [n_views][H][W]: global pair index of the last blended

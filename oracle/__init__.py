@@ -37,11 +37,16 @@ _SIGS = {
     "or_preprocess_iso_f64": (None, [_p, _i64, _p, _i32, _p, _p, _p]),
     "or_covariance_f64": (_i32, [_p, _i64, _i64, _p]),
     "or_conditional_f64": (_i32, [_p, _i64, _i64, _f64, _p, _p, _p]),
+    "or_conditional_f32": (_i32, [_p, _i64, _i64, _f32, _p, _p, _p]),
     "or_bin_sort": (_i64, [_p, _p, _p, _i64, _i32, _i32, _i32, _i64, _p, _p, _p]),
-    "or_render_fwd": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p, _p, _p, _p]),
-    "or_trace_pixel": (_i64, [_p, _i64, _p, _i32, _p, _p, _i32, _i32, _p, _p, _i64, _p]),
-    "or_render_brute": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
-    "or_render_bwd": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
+    "or_floor_skip_f32": (_i32, [_p, _f64, _f64]),
+    "or_doubtful_decisions": (_i64, [_p, _i64, _p, _i32, _p, _p, _p, _i64, _p]),
+    "or_render_fwd": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p, _p, _p, _p, _i32]),
+    "or_trace_pixel": (_i64, [_p, _i64, _p, _i32, _p, _p, _i32, _i32, _p, _p, _i64, _p, _i32]),
+    "or_render_brute": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p, _i32]),
+    "or_render_bwd": (None, [_p, _i64, _p, _i32, _p, _p, _p, _p, _i32]),
+    "or_pixel_variant": (_i64, [_p, _i64, _p, _i32, _p, _p, _i32, _i32, _i64, _i32, _p, _p, _p, _p,
+                                _i32]),
     "or_preprocess_bwd": (None, [_p, _i64, _p, _i32, _p, _p]),
     "or_preprocess_iso_bwd": (None, [_p, _i64, _p, _i32, _p, _p]),
     "or_grid_prune": (_i64, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p]),
@@ -161,6 +166,18 @@ def conditional(params, g, t):
     return (mu, sc.reshape(3, 3), float(ot[0])) if ok else None
 
 
+def conditional_f32(params, g, t):
+    """The FP32 instance's conditional (the kernel's precision and evaluation
+    order): (mu [3], Sc [3, 3], o_t) as float32, or None."""
+    P = np.ascontiguousarray(params, dtype=np.float32)
+    mu = np.zeros(3, np.float32)
+    sc = np.zeros(9, np.float32)
+    ot = np.zeros(1, np.float32)
+    ok = lib().or_conditional_f32(_ptr(P), P.shape[1], g, float(np.float32(t)), _ptr(mu), _ptr(sc),
+                                  _ptr(ot))
+    return (mu, sc.reshape(3, 3), float(ot[0])) if ok else None
+
+
 def depth_bits(rec):
     """uint32 bit patterns of the FP32 depth of each record."""
     return np.ascontiguousarray(rec[..., 6].astype(np.float32)).view(np.uint32)
@@ -186,7 +203,11 @@ def bin_sort(rect, touched, dbits, views, capacity=None):
 
 
 # ---------------------------------------------------------------- render
-def render_fwd(rec64, views, vals, ranges, signature=False):
+def render_fwd(rec64, views, vals, ranges, signature=False, *, f32):
+    """Binned compositing in FP64.  f32: records from the FP32
+    preprocess, whose alpha >= 1/255 decisions are taken in the kernel's
+    precision (bit for bit as the kernel takes them); False for FP64
+    records (self-checks, finite differences)."""
     v = _views(views)
     rec64 = np.ascontiguousarray(rec64, np.float64)
     V, n, _ = rec64.shape
@@ -198,14 +219,14 @@ def render_fwd(rec64, views, vals, ranges, signature=False):
     sig = np.zeros((V, H, W), np.uint64) if signature else None
     lib().or_render_fwd(_ptr(rec64), n, _ptr(v), V, _ptr(np.ascontiguousarray(vals, np.uint32)),
                         _ptr(np.ascontiguousarray(ranges, np.int32)), _ptr(image), _ptr(T),
-                        _ptr(last), _ptr(counts), _ptr(sig))
+                        _ptr(last), _ptr(counts), _ptr(sig), int(bool(f32)))
     out = dict(image=image, T_final=T, last=last, n_eval=int(counts[0]), n_blend=int(counts[1]))
     if signature:
         out["sig"] = sig
     return out
 
 
-def trace_pixel(rec64, views, vi, vals, ranges, x, y):
+def trace_pixel(rec64, views, vi, vals, ranges, x, y, *, f32):
     v = _views(views)
     rec64 = np.ascontiguousarray(rec64, np.float64)
     V, n, _ = rec64.shape
@@ -215,11 +236,74 @@ def trace_pixel(rec64, views, vi, vals, ranges, x, y):
     Tf = np.zeros(1)
     nb = lib().or_trace_pixel(_ptr(rec64), n, _ptr(v), vi, _ptr(np.ascontiguousarray(vals, np.uint32)),
                               _ptr(np.ascontiguousarray(ranges, np.int32)), x, y, _ptr(a), _ptr(T),
-                              cap, _ptr(Tf))
+                              cap, _ptr(Tf), int(bool(f32)))
     return a[:nb], T[:nb], float(Tf[0])
 
 
-def render_brute(rec64, views, touched, dbits):
+def floor_skip_f32(rec12, px, py):
+    """The alpha >= 1/255 floor as decided in the kernel's precision: 1 to
+    skip the entry (FP32 record rec12 at pixel centre (px, py))."""
+    r = np.ascontiguousarray(rec12, np.float64)
+    return int(lib().or_floor_skip_f32(_ptr(r), float(px), float(py)))
+
+
+DECISION_KIND = {1: "alpha", 2: "clamp", 3: "stop"}
+
+
+def doubtful_decisions(rec64, views, vals, ranges):
+    """Decisions an FP32 kernel render may take the other way from the
+    oracle's FP32 shadow: (flag [V, H, W] of their pixels, list of (view, x,
+    y, entry position in the tile's list, kind))."""
+    v = _views(views)
+    rec64 = np.ascontiguousarray(rec64, np.float64)
+    V, n, _ = rec64.shape
+    W, H, _, _ = view_dims(v)
+    flag = np.zeros((V, H, W), np.uint8)
+    cap = 1 << 16
+    while True:
+        out = np.zeros((cap, 5), np.int32)
+        k = lib().or_doubtful_decisions(_ptr(rec64), n, _ptr(v), V,
+                                        _ptr(np.ascontiguousarray(vals, np.uint32)),
+                                        _ptr(np.ascontiguousarray(ranges, np.int32)), _ptr(out), cap,
+                                        _ptr(flag))
+        if k <= cap:
+            break
+        cap = int(k)
+        flag[:] = 0
+    found = [(int(a), int(b), int(c), int(d), DECISION_KIND[int(e)]) for a, b, c, d, e in out[:k]]
+    return flag.astype(bool), found
+
+
+PIXEL_FORCE = {"alpha": 1, "clamp": 2, "stop": 3}
+
+
+def pixel_variant(rec64, views, vi, vals, ranges, x, y, gC, force_entry=-1, force="alpha", *,
+                  f32):
+    """One pixel composited with (optionally) one discrete decision inverted:
+    entry `force_entry` of its tile's list takes the other side of its
+    alpha >= 1/255 test ("alpha"), its 0.99 clamp ("clamp") or its
+    transmittance stop ("stop").  Returns (colour [3] with background,
+    T_final, d/d(record) [m, 9] per entry of the tile's list for the upstream
+    colour gradient gC [3], number of blends)."""
+    v = _views(views)
+    rec64 = np.ascontiguousarray(rec64, np.float64)
+    V, n, _ = rec64.shape
+    W, H, tx, ty = view_dims(v)
+    tile = vi * tx * ty + (y // 16) * tx + (x // 16)
+    b, e = (int(q) for q in np.asarray(ranges)[tile])
+    m = max(e - b, 0)
+    grec = np.zeros((max(m, 1), 9))
+    C = np.zeros(3)
+    T = np.zeros(1)
+    gc = np.ascontiguousarray(gC, np.float64)
+    nb = lib().or_pixel_variant(_ptr(rec64), n, _ptr(v), vi, _ptr(np.ascontiguousarray(vals, np.uint32)),
+                                _ptr(np.ascontiguousarray(ranges, np.int32)), int(x), int(y),
+                                int(force_entry), PIXEL_FORCE[force] if force_entry >= 0 else 0,
+                                _ptr(gc), _ptr(C), _ptr(T), _ptr(grec), int(bool(f32)))
+    return C, float(T[0]), grec[:m], int(nb)
+
+
+def render_brute(rec64, views, touched, dbits, *, f32):
     v = _views(views)
     rec64 = np.ascontiguousarray(rec64, np.float64)
     V, n, _ = rec64.shape
@@ -227,18 +311,20 @@ def render_brute(rec64, views, touched, dbits):
     image = np.zeros((V, 3, H, W))
     T = np.zeros((V, H, W))
     lib().or_render_brute(_ptr(rec64), n, _ptr(v), V, _ptr(np.ascontiguousarray(touched, np.int32)),
-                          _ptr(np.ascontiguousarray(dbits, np.uint32)), _ptr(image), _ptr(T))
+                          _ptr(np.ascontiguousarray(dbits, np.uint32)), _ptr(image), _ptr(T),
+                          int(bool(f32)))
     return image, T
 
 
-def render_bwd(rec64, views, vals, ranges, dL_dimage):
+def render_bwd(rec64, views, vals, ranges, dL_dimage, *, f32):
     v = _views(views)
     rec64 = np.ascontiguousarray(rec64, np.float64)
     V, n, _ = rec64.shape
     g = np.zeros((V, n, 9))
     lib().or_render_bwd(_ptr(rec64), n, _ptr(v), V, _ptr(np.ascontiguousarray(vals, np.uint32)),
                         _ptr(np.ascontiguousarray(ranges, np.int32)),
-                        _ptr(np.ascontiguousarray(dL_dimage, np.float64)), _ptr(g))
+                        _ptr(np.ascontiguousarray(dL_dimage, np.float64)), _ptr(g),
+                        int(bool(f32)))
     return g
 
 
@@ -268,7 +354,8 @@ def preprocess_iso_bwd(params, views, grad_rec):
 # ---------------------------------------------------------------- pipelines
 def forward(params, views, precision="f32"):
     """Full forward.  precision="f32": the kernel-precision preprocess (whose
-    integers the GPU must match bit for bit) promoted to FP64 for compositing.
+    integers the GPU must match bit for bit) promoted to FP64 for compositing,
+    the alpha >= 1/255 decisions taken in the kernel's precision.
     precision="f64": everything in FP64 (self-checks, finite differences)."""
     if precision == "f32":
         rec, rect, touched = preprocess_f32(params, views)
@@ -277,9 +364,9 @@ def forward(params, views, precision="f32"):
     dbits = depth_bits(rec)
     keys, vals, ranges = bin_sort(rect, touched, dbits, views)
     rec64 = rec.astype(np.float64)
-    out = render_fwd(rec64, views, vals, ranges)
+    out = render_fwd(rec64, views, vals, ranges, f32=precision == "f32")
     out.update(rec=rec, rect=rect, touched=touched, keys=keys, vals=vals, ranges=ranges,
-               dbits=dbits)
+               dbits=dbits, f32=precision == "f32")
     return out
 
 
@@ -287,7 +374,8 @@ def backward(params, views, dL_dimage, fwd=None, precision="f32"):
     """dL/dparams [20, N] for an upstream image gradient (FP64 chain rule)."""
     if fwd is None:
         fwd = forward(params, views, precision)
-    grec = render_bwd(fwd["rec"].astype(np.float64), views, fwd["vals"], fwd["ranges"], dL_dimage)
+    grec = render_bwd(fwd["rec"].astype(np.float64), views, fwd["vals"], fwd["ranges"], dL_dimage,
+                      f32=fwd["f32"])
     return preprocess_bwd(params, views, grec), grec
 
 

@@ -88,6 +88,7 @@ float or_logf_public(float x) { return or_logf(x); }
 
 /* ---- FP32 instance ---- */
 #define REAL float
+#define PROJECTED_SLICE 1
 #define FN(x) x##_f32
 #define EXPR(x) or_expf(x)
 #define LOGR(x) or_logf(x)
@@ -98,6 +99,7 @@ float or_logf_public(float x) { return or_logf(x); }
 #define FMINR(a, b) fminf(a, b)
 #include "pre_tmpl.inc"
 #undef REAL
+#undef PROJECTED_SLICE
 #undef FN
 #undef EXPR
 #undef LOGR
@@ -109,6 +111,7 @@ float or_logf_public(float x) { return or_logf(x); }
 
 /* ---- FP64 instance ---- */
 #define REAL double
+#define PROJECTED_SLICE 0
 #define FN(x) x##_f64
 #define EXPR(x) exp(x)
 #define LOGR(x) log(x)
@@ -119,6 +122,7 @@ float or_logf_public(float x) { return or_logf(x); }
 #define FMINR(a, b) fmin(a, b)
 #include "pre_tmpl.inc"
 #undef REAL
+#undef PROJECTED_SLICE
 #undef FN
 #undef EXPR
 #undef LOGR
@@ -179,9 +183,9 @@ void or_preprocess_iso_f64(const double *params, int64_t n, const double *views,
  * degenerate. */
 int or_covariance_f64(const double *params, int64_t n, int64_t g, double *sigma16)
 {
-    double v[20], Sg[4][4], s[4], o;
+    double v[20], Sg[4][4], M[4][4], s[4], o;
     for (int k = 0; k < 20; ++k) v[k] = params[(int64_t)k * n + g];
-    if (!covariance_f64(v, Sg, s, &o)) return 0;
+    if (!covariance_f64(v, Sg, M, s, &o)) return 0;
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) sigma16[4 * i + j] = Sg[i][j];
     return 1;
@@ -190,10 +194,27 @@ int or_covariance_f64(const double *params, int64_t n, int64_t g, double *sigma1
 int or_conditional_f64(const double *params, int64_t n, int64_t g, double t, double *mu3,
                        double *sc9, double *ot)
 {
-    double v[20], Sg[4][4], s[4], o, mu[3], Sc[3][3];
+    double v[20], Sg[4][4], M[4][4], s[4], o, mu[3], Sc[3][3];
     for (int k = 0; k < 20; ++k) v[k] = params[(int64_t)k * n + g];
-    if (!covariance_f64(v, Sg, s, &o)) return 0;
-    if (!conditional_f64(v, Sg, o, t, mu, Sc, ot)) return 0;
+    if (!covariance_f64(v, Sg, M, s, &o)) return 0;
+    if (!conditional_f64(v, Sg, M, o, t, mu, Sc, ot)) return 0;
+    for (int i = 0; i < 3; ++i) {
+        mu3[i] = mu[i];
+        for (int j = 0; j < 3; ++j) sc9[3 * i + j] = Sc[i][j];
+    }
+    return 1;
+}
+
+/* The FP32 instance's conditional (the kernel's precision and evaluation
+ * order): mu[3], Sc (row-major 3x3), o_t of Gaussian g at time t.  Returns
+ * 0 if degenerate. */
+int or_conditional_f32(const float *params, int64_t n, int64_t g, float t, float *mu3,
+                       float *sc9, float *ot)
+{
+    float v[20], Sg[4][4], M[4][4], s[4], o, mu[3], Sc[3][3];
+    for (int k = 0; k < 20; ++k) v[k] = params[(int64_t)k * n + g];
+    if (!covariance_f32(v, Sg, M, s, &o)) return 0;
+    if (!conditional_f32(v, Sg, M, o, t, mu, Sc, ot)) return 0;
     for (int i = 0; i < 3; ++i) {
         mu3[i] = mu[i];
         for (int j = 0; j < 3; ++j) sc9[3 * i + j] = Sc[i][j];
@@ -260,12 +281,17 @@ int64_t or_bin_sort(const int32_t *rect, const int32_t *touched, const uint32_t 
 /* ------------------------------------------------------------------------- *
  * Per-pixel compositing (FP64).  Pixel centres sit at (x + 1/2, y + 1/2).
  * For each entry, front to back:
- *   power = -1/2 (a dx^2 + c dy^2) - b dx dy; skip if power > 0
+ *   power = min(0, -1/2 (a dx^2 + c dy^2) - b dx dy)
  *   alpha = min(0.99, o_t exp(power)); skip if alpha < 1/255
  *   T' = T (1 - alpha); stop (without blending) if T' < 1e-4
  *   C += rgb alpha T; T = T'
  * Output C + T bg.  These per-pixel constants are those of the 3D Gaussian
- * splatting renderer the paper builds on.
+ * splatting renderer the paper builds on.  The conic of a visible record is
+ * positive definite (its determinant is positive and its diagonal carries
+ * the 0.3 px^2 dilation), so the exponent is <= 0 in exact arithmetic; the
+ * min() only absorbs rounding, so alpha never exceeds o_t and the pixel
+ * value stays continuous where the exponent passes 0.  The derivative is
+ * that of the exponent itself (the min is the identity on the exact values).
  * ------------------------------------------------------------------------- */
 typedef struct {
     double alpha, atil, ex, T;
@@ -273,38 +299,235 @@ typedef struct {
     int64_t entry;
 } or_blend;
 
+/* Compositing decisions taken in the kernel's precision.
+ *
+ * Blending an entry, clamping its alpha and stopping a pixel are integer
+ * decisions that FP32 and FP64 evaluations can take differently near a
+ * threshold.  With f32 decisions the oracle takes them on an FP32 shadow of
+ * the kernel's per-entry arithmetic, in the kernel's fixed order:
+ *   dx = (x + 1/2) - mx, dy likewise,
+ *   power = min(0, fma(-1/2, fma(a dx, dx, (c dy) dy), -(b dx) dy)),
+ *   skip iff power < lo, lo = -ln(255 o_t) (project-defined logarithm; in
+ *     exact arithmetic the same as alpha < 1/255),
+ *   at = o_t * 2^(power * log2 e), alpha = min(0.99, at),
+ *   clamped iff at > 0.99, stop iff T (1 - alpha) < 1e-4 (T in FP32),
+ * with 2^x correctly rounded where the kernel uses the hardware exp2 (a few
+ * ulp apart).  Colour, transmittance and gradients stay FP64.  The floor
+ * is then the same bit for bit; clamp and stop can differ only where the
+ * shadow lies within the hardware exp2's ulps of the threshold (see
+ * or_doubtful_decisions). */
+static const float LOG2E_F32 = 1.44269502162933349609375f;   /* log2 e rounded to FP32 */
+
+typedef struct {
+    float power, lo, at;
+} or_shadow;
+
+static void shadow_entry(const double *r, double px, double py, or_shadow *sh)
+{
+    const float mx = (float)r[0], my = (float)r[1];
+    const float a = (float)r[2], b = (float)r[3], c = (float)r[4], ot = (float)r[5];
+    const float dx = (float)px - mx, dy = (float)py - my;
+    const float t1 = a * dx, t2 = c * dy;
+    const float q = fmaf(t1, dx, t2 * dy);
+    sh->power = fminf(fmaf(-0.5f, q, -(b * dx) * dy), 0.0f);
+    sh->lo = -or_logf(255.0f * ot);
+    const float ex = (float)exp2((double)(sh->power * LOG2E_F32));
+    sh->at = ot * ex;
+}
+
+static int floor_skip_f32(const double *r, double px, double py)
+{
+    or_shadow sh;
+    shadow_entry(r, px, py, &sh);
+    return sh.power < sh.lo;
+}
+
+int32_t or_floor_skip_f32(const double *rec12, double px, double py)
+{
+    return floor_skip_f32(rec12, px, py);
+}
+
 /* Composites the pixel over the ordered Gaussian list ids[0..m).  Records are
- * FP64 [*][12] at rec_view.  Fills up to max_b blends.  Returns count. */
-static int64_t composite_pixel(const double *rec_view, const uint32_t *ids, int64_t m, double px,
-                               double py, double *C, double *Tout, int64_t *last, or_blend *bl,
-                               int64_t max_b, int64_t *n_eval)
+ * FP64 [*][12] at rec_view.  Fills up to max_b blends.  Returns count.
+ * force_e >= 0 inverts one discrete decision of entry force_e (for error
+ * bounds: what the pixel would be had a rounding taken that decision the
+ * other way): force_kind 1 the alpha >= 1/255 test, 2 the 0.99 clamp, 3 the
+ * T' < 1e-4 stop.  f32: take the decisions in the kernel's precision (the
+ * FP32 shadow above; records from the FP32 preprocess), else in FP64. */
+static int64_t composite_pixel_ex(const double *rec_view, const uint32_t *ids, int64_t m, double px,
+                                  double py, double *C, double *Tout, int64_t *last, or_blend *bl,
+                                  int64_t max_b, int64_t *n_eval, int64_t force_e, int force_kind,
+                                  int f32)
 {
     double T = 1.0;
+    float T32 = 1.0f;
     int64_t nb = 0;
     C[0] = C[1] = C[2] = 0.0;
     *last = -1;
     for (int64_t e = 0; e < m; ++e) {
         const double *r = rec_view + (int64_t)ids[e] * OR_REC;
         const double dx = px - r[0], dy = py - r[1];
-        const double power = -0.5 * (r[2] * dx * dx + r[4] * dy * dy) - r[3] * dx * dy;
+        const double power = fmin(-0.5 * (r[2] * dx * dx + r[4] * dy * dy) - r[3] * dx * dy, 0.0);
         ++*n_eval;
-        if (power > 0.0) continue;
         const double ex = exp(power);
         const double atil = r[5] * ex;
-        const double alpha = atil < 0.99 ? atil : 0.99;
-        if (alpha < 1.0 / 255.0) continue;
+        or_shadow sh = { 0.0f, 0.0f, 0.0f };
+        if (f32) shadow_entry(r, px, py, &sh);
+        int clamped = f32 ? sh.at > 0.99f : atil > 0.99;
+        if (e == force_e && force_kind == 2) clamped = !clamped;
+        const double alpha = clamped ? 0.99 : atil;
+        int skip = f32 ? sh.power < sh.lo : alpha < 1.0 / 255.0;
+        if (e == force_e && force_kind == 1) skip = !skip;
+        if (skip) continue;
         const double Tn = T * (1.0 - alpha);
-        if (Tn < 1e-4) break;
+        const float Tn32 = T32 * (1.0f - (clamped ? 0.99f : sh.at));
+        int stop = f32 ? Tn32 < 1e-4f : Tn < 1e-4;
+        if (e == force_e && force_kind == 3) stop = !stop;
+        if (stop) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += r[8 + ch] * alpha * T;
         if (bl && nb < max_b) {
             bl[nb].alpha = alpha; bl[nb].atil = atil; bl[nb].ex = ex; bl[nb].T = T;
-            bl[nb].clamped = atil > 0.99; bl[nb].entry = e;
+            bl[nb].clamped = clamped; bl[nb].entry = e;
         }
         ++nb;
         T = Tn;
+        T32 = Tn32;
         *last = e;
     }
     *Tout = T;
+    return nb;
+}
+
+static int64_t composite_pixel(const double *rec_view, const uint32_t *ids, int64_t m, double px,
+                               double py, double *C, double *Tout, int64_t *last, or_blend *bl,
+                               int64_t max_b, int64_t *n_eval, int f32)
+{
+    return composite_pixel_ex(rec_view, ids, m, px, py, C, Tout, last, bl, max_b, n_eval, -1, 0,
+                              f32);
+}
+
+/* The decisions an FP32 kernel render may take the other way from the FP32
+ * shadow (for parity bounds).  The shadow matches the kernel bit for bit
+ * except its correctly rounded 2^x against the hardware's (within 1 ulp of
+ * exact), so at = o_t 2^x may differ by a few ulp: EPS_AT = 2^-21 of it.
+ * A clamp is doubtful when at lies within that of 0.99.  1 - alpha then
+ * differs by at most EPS_AT alpha / (1 - alpha) relative (0 when both
+ * clamp), and the FP32 transmittance by the sum of those over the blends
+ * so far: a stop is doubtful when T (1 - alpha) lies within that of 1e-4.
+ * (The 1/255 floor is the same bit for bit.)  For every pixel with a tile
+ * list, each doubtful decision is written to out [cap][5] as (view, x, y,
+ * entry position in the tile's list, kind: 2 clamp, 3 stop), and
+ * flag [n_views][H][W] (zeroed first) marks its pixel.  Returns the number
+ * found (entries past cap are counted, not written). */
+int64_t or_doubtful_decisions(const double *rec, int64_t n, const double *views, int32_t n_views,
+                              const uint32_t *vals, const int32_t *ranges, int32_t *out, int64_t cap,
+                              uint8_t *flag)
+{
+    const float EPS_AT = 1.0f / 2097152.0f;
+    int64_t found = 0;
+    for (int32_t vi = 0; vi < n_views; ++vi) {
+        const double *vw = views + (int64_t)vi * OR_VIEW;
+        const int W = (int)vw[16], H = (int)vw[17];
+        const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+        const int64_t tpv = (int64_t)tiles_x * tiles_y;
+        const double *rv = rec + (int64_t)vi * n * OR_REC;
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                const int64_t tile = vi * tpv + (int64_t)(y >> 4) * tiles_x + (x >> 4);
+                const int32_t b = ranges[2 * tile], e = ranges[2 * tile + 1];
+                const double px = x + 0.5, py = y + 0.5;
+                float T32 = 1.0f, epsT = 0.0f;
+                for (int32_t k = b; k < e; ++k) {
+                    const double *r = rv + (int64_t)vals[k] * OR_REC;
+                    or_shadow sh;
+                    shadow_entry(r, px, py, &sh);
+                    if (sh.power < sh.lo) continue;
+                    const int clamped = sh.at > 0.99f;
+                    int kind = 0;
+                    if (fabsf(sh.at - 0.99f) <= 0.99f * EPS_AT) kind = 2;
+                    const float a = clamped ? 0.99f : sh.at;
+                    const float e_one = clamped && kind == 0 ? 0.0f : EPS_AT * a / (1.0f - a);
+                    const float Tn = T32 * (1.0f - a);
+                    for (int pass = 0; pass < 2; ++pass) {
+                        if (pass == 1) kind = fabsf(Tn - 1e-4f) <= Tn * (epsT + e_one) ? 3 : 0;
+                        if (!kind) continue;
+                        if (found < cap) {
+                            int32_t *o = out + 5 * found;
+                            o[0] = vi; o[1] = x; o[2] = y; o[3] = k - b; o[4] = kind;
+                        }
+                        ++found;
+                        flag[((int64_t)vi * H + y) * W + x] = 1;
+                    }
+                    if (Tn < 1e-4f) break;
+                    T32 = Tn;
+                    epsT += e_one;
+                }
+            }
+    }
+    return found;
+}
+
+/* Back-to-front gradient of one pixel's colour (see or_render_bwd) for its
+ * nb blends bl[]: adds d/d(mx, my, a, b, c, o_t, r, g, b) of each blended
+ * entry to dst + 9 * key, key = the entry's Gaussian id (by_entry = 0) or
+ * its position in the list (by_entry = 1). */
+static void pixel_backward(const double *rv, const uint32_t *ids, const or_blend *bl, int64_t nb,
+                           double px, double py, const double gC[3], const double bg[3],
+                           double *dst, int by_entry)
+{
+    double Bk[3] = { bg[0], bg[1], bg[2] };
+    for (int64_t k = nb - 1; k >= 0; --k) {
+        const uint32_t g = ids[bl[k].entry];
+        const double *r = rv + (int64_t)g * OR_REC;
+        double *gg = dst + 9 * (by_entry ? bl[k].entry : (int64_t)g);
+        const double a = bl[k].alpha, Ti = bl[k].T;
+        double dalpha = 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+            gg[6 + ch] += a * Ti * gC[ch];
+            dalpha += gC[ch] * Ti * (r[8 + ch] - Bk[ch]);
+            Bk[ch] = a * r[8 + ch] + (1.0 - a) * Bk[ch];
+        }
+        if (bl[k].clamped) continue;
+        const double dx = px - r[0], dy = py - r[1];
+        const double dpow = dalpha * bl[k].atil;
+        gg[5] += dalpha * bl[k].ex;
+        gg[2] += dpow * (-0.5 * dx * dx);
+        gg[3] += dpow * (-dx * dy);
+        gg[4] += dpow * (-0.5 * dy * dy);
+        gg[0] += dpow * (r[2] * dx + r[3] * dy);
+        gg[1] += dpow * (r[4] * dy + r[3] * dx);
+    }
+}
+
+/* One pixel (x, y) of view vi with one decision inverted (force_e, force_kind
+ * as in composite_pixel_ex; force_e < 0: none): its colour C[3] (background
+ * included), T_final, and the d/d(record) of each entry of the pixel's tile
+ * list for the upstream colour gradient gC[3], written to grec_entry
+ * [m][9] (m = the tile's list length; overwritten).  Returns the number of
+ * blends. */
+int64_t or_pixel_variant(const double *rec, int64_t n, const double *views, int32_t vi,
+                         const uint32_t *vals, const int32_t *ranges, int32_t x, int32_t y,
+                         int64_t force_e, int32_t force_kind, const double *gC, double *C_out,
+                         double *T_out, double *grec_entry, int32_t f32)
+{
+    const double *vw = views + (int64_t)vi * OR_VIEW;
+    const int W = (int)vw[16], H = (int)vw[17];
+    const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+    const int64_t tile = vi * (int64_t)tiles_x * tiles_y + (int64_t)(y >> 4) * tiles_x + (x >> 4);
+    const int32_t b = ranges[2 * tile], e = ranges[2 * tile + 1];
+    const int64_t m = e - b;
+    const double *rv = rec + (int64_t)vi * n * OR_REC;
+    or_blend *bl = (or_blend *)malloc(sizeof(or_blend) * (size_t)(m > 0 ? m : 1));
+    double C[3], T;
+    int64_t lst, dummy = 0;
+    const double px = x + 0.5, py = y + 0.5;
+    const int64_t nb = composite_pixel_ex(rv, vals + b, m, px, py, C, &T, &lst, bl, m, &dummy,
+                                          force_e, force_kind, f32);
+    for (int ch = 0; ch < 3; ++ch) C_out[ch] = C[ch] + T * vw[20 + ch];
+    *T_out = T;
+    memset(grec_entry, 0, sizeof(double) * 9 * (size_t)(m > 0 ? m : 1));
+    pixel_backward(rv, vals + b, bl, nb, px, py, gC, vw + 20, grec_entry, 1);
+    free(bl);
     return nb;
 }
 
@@ -313,7 +536,7 @@ static int64_t composite_pixel(const double *rec_view, const uint32_t *ids, int6
  * entry (-1 if none).  counts[0] += evaluated entries, counts[1] += blends. */
 void or_render_fwd(const double *rec, int64_t n, const double *views, int32_t n_views,
                    const uint32_t *vals, const int32_t *ranges, double *image, double *T_final,
-                   int32_t *last, int64_t *counts, uint64_t *sig)
+                   int32_t *last, int64_t *counts, uint64_t *sig, int32_t f32)
 {
     for (int32_t vi = 0; vi < n_views; ++vi) {
         const double *vw = views + (int64_t)vi * OR_VIEW;
@@ -330,7 +553,7 @@ void or_render_fwd(const double *rec, int64_t n, const double *views, int32_t n_
                 const int64_t m = e - b;
                 or_blend *bl = sig ? (or_blend *)malloc(sizeof(or_blend) * (size_t)(m > 0 ? m : 1)) : NULL;
                 const int64_t nb = composite_pixel(rv, vals + b, m, x + 0.5, y + 0.5, C, &T,
-                                                   &lst, bl, m, &counts[0]);
+                                                   &lst, bl, m, &counts[0], f32);
                 counts[1] += nb;
                 const int64_t pix = (int64_t)y * W + x;
                 const int64_t HW = (int64_t)H * W;
@@ -356,7 +579,7 @@ void or_render_fwd(const double *rec, int64_t n, const double *views, int32_t n_
  * are written) and the final transmittance in *T_final. */
 int64_t or_trace_pixel(const double *rec, int64_t n, const double *views, int32_t vi,
                        const uint32_t *vals, const int32_t *ranges, int32_t x, int32_t y,
-                       double *alpha_out, double *T_out, int64_t max_b, double *T_final)
+                       double *alpha_out, double *T_out, int64_t max_b, double *T_final, int32_t f32)
 {
     const double *vw = views + (int64_t)vi * OR_VIEW;
     const int W = (int)vw[16], H = (int)vw[17];
@@ -368,7 +591,7 @@ int64_t or_trace_pixel(const double *rec, int64_t n, const double *views, int32_
     double C[3];
     int64_t lst, dummy = 0;
     const int64_t nb = composite_pixel(rec + (int64_t)vi * n * OR_REC, vals + b, m, x + 0.5, y + 0.5,
-                                       C, T_final, &lst, bl, m, &dummy);
+                                       C, T_final, &lst, bl, m, &dummy, f32);
     for (int64_t k = 0; k < nb && k < max_b; ++k) { alpha_out[k] = bl[k].alpha; T_out[k] = bl[k].T; }
     free(bl);
     return nb;
@@ -386,7 +609,7 @@ static int cmp_depth_id(const void *pa, const void *pb)
 
 void or_render_brute(const double *rec, int64_t n, const double *views, int32_t n_views,
                      const int32_t *touched, const uint32_t *depth_bits, double *image,
-                     double *T_final)
+                     double *T_final, int32_t f32)
 {
     uint32_t *ids = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     for (int32_t vi = 0; vi < n_views; ++vi) {
@@ -404,7 +627,7 @@ void or_render_brute(const double *rec, int64_t n, const double *views, int32_t 
             for (int x = 0; x < W; ++x) {
                 double C[3], T;
                 int64_t lst;
-                composite_pixel(rv, ids, m, x + 0.5, y + 0.5, C, &T, &lst, NULL, 0, &dummy);
+                composite_pixel(rv, ids, m, x + 0.5, y + 0.5, C, &T, &lst, NULL, 0, &dummy, f32);
                 const int64_t pix = (int64_t)y * W + x;
                 for (int ch = 0; ch < 3; ++ch)
                     image[((int64_t)vi * 3 + ch) * HW + pix] = C[ch] + T * vw[20 + ch];
@@ -420,7 +643,8 @@ void or_render_brute(const double *rec, int64_t n, const double *views, int32_t 
  * recovered), then walked back to front:
  *   dC/drgb_i = alpha_i T_i;  dC/dalpha_i = T_i (rgb_i - B_i),
  *   B_last = bg,  B_{i-1} = alpha_i rgb_i + (1 - alpha_i) B_i.
- * Through alpha = min(0.99, o_t e^power): zero when clamped; otherwise
+ * Through alpha = min(0.99, o_t e^power): zero when clamped to 0.99;
+ * otherwise (the exponent's min with 0 passes its derivative through)
  *   dalpha/do_t = e^power, dalpha/dpower = alpha~,
  *   dpower/d(a, b, c) = (-dx^2/2, -dx dy, -dy^2/2),
  *   dpower/dmean = (a dx + b dy, c dy + b dx).
@@ -428,7 +652,7 @@ void or_render_brute(const double *rec, int64_t n, const double *views, int32_t 
  * ------------------------------------------------------------------------- */
 void or_render_bwd(const double *rec, int64_t n, const double *views, int32_t n_views,
                    const uint32_t *vals, const int32_t *ranges, const double *dL_dimage,
-                   double *grad_rec)
+                   double *grad_rec, int32_t f32)
 {
     memset(grad_rec, 0, sizeof(double) * 9 * (size_t)n * (size_t)n_views);
     for (int32_t vi = 0; vi < n_views; ++vi) {
@@ -448,34 +672,12 @@ void or_render_bwd(const double *rec, int64_t n, const double *views, int32_t n_
                 double C[3], T;
                 int64_t lst, dummy = 0;
                 const double px = x + 0.5, py = y + 0.5;
-                const int64_t nb = composite_pixel(rv, vals + b, m, px, py, C, &T, &lst, bl, m, &dummy);
+                const int64_t nb = composite_pixel(rv, vals + b, m, px, py, C, &T, &lst, bl, m, &dummy,
+                                                   f32);
                 const int64_t pix = (int64_t)y * W + x;
-                double gC[3], Bk[3];
-                for (int ch = 0; ch < 3; ++ch) {
-                    gC[ch] = dL_dimage[((int64_t)vi * 3 + ch) * HW + pix];
-                    Bk[ch] = vw[20 + ch];
-                }
-                for (int64_t k = nb - 1; k >= 0; --k) {
-                    const uint32_t g = vals[b + bl[k].entry];
-                    const double *r = rv + (int64_t)g * OR_REC;
-                    double *gg = gv + (int64_t)g * 9;
-                    const double a = bl[k].alpha, Ti = bl[k].T;
-                    double dalpha = 0.0;
-                    for (int ch = 0; ch < 3; ++ch) {
-                        gg[6 + ch] += a * Ti * gC[ch];
-                        dalpha += gC[ch] * Ti * (r[8 + ch] - Bk[ch]);
-                        Bk[ch] = a * r[8 + ch] + (1.0 - a) * Bk[ch];
-                    }
-                    if (bl[k].clamped) continue;
-                    const double dx = px - r[0], dy = py - r[1];
-                    const double dpow = dalpha * bl[k].atil;
-                    gg[5] += dalpha * bl[k].ex;
-                    gg[2] += dpow * (-0.5 * dx * dx);
-                    gg[3] += dpow * (-dx * dy);
-                    gg[4] += dpow * (-0.5 * dy * dy);
-                    gg[0] += dpow * (r[2] * dx + r[3] * dy);
-                    gg[1] += dpow * (r[4] * dy + r[3] * dx);
-                }
+                double gC[3];
+                for (int ch = 0; ch < 3; ++ch) gC[ch] = dL_dimage[((int64_t)vi * 3 + ch) * HW + pix];
+                pixel_backward(rv, vals + b, bl, nb, px, py, gC, vw + 20, gv, 0);
                 free(bl);
             }
     }

@@ -107,6 +107,55 @@ __device__ __forceinline__ double wave_sum_d(double x) {
     return x;
 }
 
+// Project-defined FP32 exp and ln.  Every per-Gaussian value that decides
+// an integer (cull, footprint, tile rectangle, sort-key depth, the alpha
+// >= 1/255 floor of compositing) uses these two, with a fixed operation
+// order and no contraction, so that the result is reproducible bit for bit.
+// exp(x): Cody-Waite reduction x = k ln2 + r (ln2 split so k * ln2_hi is
+// exact), degree-7 Taylor polynomial of e^r in Horner form, scale by 2^k.
+__device__ __forceinline__ float fixed_exp(float x) {
+#pragma clang fp contract(off)
+    if (x != x) return x;
+    if (x < -87.0f) return 0.0f;
+    if (x > 88.0f) return __builtin_huge_valf();
+    const float k = rintf(x * 1.44269504088896341f);
+    float r = x - k * 0.693145751953125f;
+    r = r - k * 1.428606765330187e-06f;
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)k);
+}
+
+// ln(x): x = m 2^e with m in [1/sqrt2, sqrt2); ln m = 2 atanh(u),
+// u = (m - 1) / (m + 1), series through u^9.
+__device__ __forceinline__ float fixed_log(float x) {
+#pragma clang fp contract(off)
+    if (x != x) return x;
+    if (x < 0.0f) return __builtin_nanf("");
+    if (x == 0.0f) return -__builtin_huge_valf();
+    if (x == __builtin_huge_valf()) return x;
+    int e;
+    float m = frexpf(x, &e);
+    if (m < 0.70710678118654752f) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    const float u = (m - 1.0f) / (m + 1.0f);
+    const float u2 = u * u;
+    float s = 1.0f / 9.0f;
+    s = fmaf(s, u2, 1.0f / 7.0f);
+    s = fmaf(s, u2, 1.0f / 5.0f);
+    s = fmaf(s, u2, 1.0f / 3.0f);
+    s = fmaf(s, u2, 1.0f);
+    return fmaf((float)e, 0.693147180559945309f, (2.0f * u) * s);
+}
+
 // Exclusive prefix sums (radix sort, scans) ---------------------------------
 struct ScanWs;   // defined in binsort.hip
 

@@ -20,49 +20,6 @@
 namespace gs4d {
 namespace {
 
-// exp(x): Cody-Waite reduction x = k ln2 + r (ln2 split so k * ln2_hi is
-// exact), degree-7 Taylor polynomial of e^r in Horner form, scale by 2^k.
-__device__ __forceinline__ float fixed_exp(float x) {
-    if (x != x) return x;
-    if (x < -87.0f) return 0.0f;
-    if (x > 88.0f) return __builtin_huge_valf();
-    const float k = rintf(x * 1.44269504088896341f);
-    float r = x - k * 0.693145751953125f;
-    r = r - k * 1.428606765330187e-06f;
-    float p = 1.0f / 5040.0f;
-    p = fmaf(p, r, 1.0f / 720.0f);
-    p = fmaf(p, r, 1.0f / 120.0f);
-    p = fmaf(p, r, 1.0f / 24.0f);
-    p = fmaf(p, r, 1.0f / 6.0f);
-    p = fmaf(p, r, 0.5f);
-    p = fmaf(p, r, 1.0f);
-    p = fmaf(p, r, 1.0f);
-    return ldexpf(p, (int)k);
-}
-
-// ln(x): x = m 2^e with m in [1/sqrt2, sqrt2); ln m = 2 atanh(u),
-// u = (m - 1) / (m + 1), series through u^9.
-__device__ __forceinline__ float fixed_log(float x) {
-    if (x != x) return x;
-    if (x < 0.0f) return __builtin_nanf("");
-    if (x == 0.0f) return -__builtin_huge_valf();
-    if (x == __builtin_huge_valf()) return x;
-    int e;
-    float m = frexpf(x, &e);
-    if (m < 0.70710678118654752f) {
-        m = m * 2.0f;
-        e = e - 1;
-    }
-    const float u = (m - 1.0f) / (m + 1.0f);
-    const float u2 = u * u;
-    float s = 1.0f / 9.0f;
-    s = fmaf(s, u2, 1.0f / 7.0f);
-    s = fmaf(s, u2, 1.0f / 5.0f);
-    s = fmaf(s, u2, 1.0f / 3.0f);
-    s = fmaf(s, u2, 1.0f);
-    return fmaf((float)e, 0.693147180559945309f, (2.0f * u) * s);
-}
-
 // Everything the backward needs from the forward of one (view, Gaussian).
 struct Slice {
     float s[4], o;
@@ -71,6 +28,7 @@ struct Slice {
     float R[4][4];            // rotation in (x, y, z, t) order
     float M[4][4];            // R diag(s)
     float Sg[4][4];           // 4D covariance
+    float P[3][4];            // rows of M with the time direction projected out
     float dt, ef, ot;         // t - mu_t, exp(-dt^2 / 2c), o_t
     float mu[3], Sc[3][3];    // conditional mean / covariance
     float xc[3];              // camera-space point
@@ -137,13 +95,23 @@ __device__ __forceinline__ int slice_project(const float (&p)[20], const gs4d_vi
     const float c = S.Sg[3][3];
     if (!(c > 0.0f)) return 0;
 
-    // conditional at time t
+    // conditional at time t.  With m = M[3] (the time row), c = m.m and
+    // a_i = M_i.m = Sg[i][3], the conditional covariance Sg_xyz - a a^T / c
+    // equals P P^T with P_i = M_i - (a_i / c) m: each row with the time
+    // direction projected out.  That form keeps FP32 accuracy when
+    // s_t >> s_xyz, where the difference of the two blocks would cancel
+    // (an error of order eps (s_t / s_xyz)^2 relative to Sc).
     S.dt = V.t - p[3];
     const float r = S.dt / c;
     for (int i = 0; i < 3; ++i) S.mu[i] = p[i] + S.Sg[i][3] * r;
+    for (int i = 0; i < 3; ++i) {
+        const float k = S.Sg[i][3] / c;
+        for (int j = 0; j < 4; ++j) S.P[i][j] = S.M[i][j] - k * S.M[3][j];
+    }
     for (int i = 0; i < 3; ++i)
         for (int j = i; j < 3; ++j) {
-            const float v = S.Sg[i][j] - (S.Sg[i][3] * S.Sg[j][3]) / c;
+            const float v = S.P[i][0] * S.P[j][0] + S.P[i][1] * S.P[j][1] +
+                            S.P[i][2] * S.P[j][2] + S.P[i][3] * S.P[j][3];
             S.Sc[i][j] = v;
             S.Sc[j][i] = v;
         }
@@ -363,40 +331,42 @@ preprocess_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
         float Gmu[3], GSc[3][3];
         project_bwd(V, S, G, Gmu, GSc);
 
-        // conditional -> Sigma blocks (Sb, a, c), mu, opacity
+        // conditional -> (M, mu_t, opacity).  With K = [I | -a/c] the
+        // covariance part of the Sigma gradient is K^T GSc K, and since
+        // K M = P, its share of dL/dM = 2 G4 M is 2 K^T GSc P: rows 0-2 are
+        // 2 GSc P, row 3 is -2 (a/c)^T GSc P (no cancelling terms when
+        // s_t >> s_xyz).  The conditional mean and o_t add
+        // G4_mo = [[0, g/2], [g^T/2, h]] with g = Gmu dt / c and
+        // h = -(Gmu.a) dt / c^2 + go o_t dt^2 / (2 c^2).
         const float c = S.Sg[3][3], ic = 1.0f / c;
-        const float a3[3] = {S.Sg[0][3], S.Sg[1][3], S.Sg[2][3]};
         const float go = G[5];
-        float Gmua = 0.0f, aGa = 0.0f, Ga[3];
-        for (int i = 0; i < 3; ++i) {
-            Gmua += Gmu[i] * a3[i];
-            Ga[i] = GSc[i][0] * a3[0] + GSc[i][1] * a3[1] + GSc[i][2] * a3[2];
-            aGa += a3[i] * Ga[i];
-        }
         const float dt = S.dt;
+        float Gmua = 0.0f;
+        for (int i = 0; i < 3; ++i) Gmua += Gmu[i] * S.Sg[i][3];
         for (int i = 0; i < 3; ++i) acc[i] += Gmu[i];
         acc[3] += -Gmua * ic + go * S.ot * dt * ic;
-        float Gda[3];
-        for (int i = 0; i < 3; ++i) Gda[i] = Gmu[i] * dt * ic - 2.0f * Ga[i] * ic;
-        const float Gdc = (-Gmua * dt + aGa + 0.5f * go * S.ot * dt * dt) * ic * ic;
         const float Gdo = go * S.ef;
-
-        // symmetric gradient of Sigma; Sigma = M M^T -> dM = 2 G4 M
-        float G4[4][4];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) G4[i][j] = GSc[i][j];
+        float gv[3], kv[3];
         for (int i = 0; i < 3; ++i) {
-            G4[i][3] = 0.5f * Gda[i];
-            G4[3][i] = 0.5f * Gda[i];
+            gv[i] = Gmu[i] * dt * ic;
+            kv[i] = S.Sg[i][3] * ic;
         }
-        G4[3][3] = Gdc;
+        const float h = (-Gmua * dt + 0.5f * go * S.ot * dt * dt) * ic * ic;
+        float GM[4][4];
+        for (int j = 0; j < 4; ++j) {
+            float GP[3];
+            for (int i = 0; i < 3; ++i)
+                GP[i] = GSc[i][0] * S.P[0][j] + GSc[i][1] * S.P[1][j] + GSc[i][2] * S.P[2][j];
+            for (int i = 0; i < 3; ++i) GM[i][j] = 2.0f * GP[i] + gv[i] * S.M[3][j];
+            GM[3][j] = -2.0f * (kv[0] * GP[0] + kv[1] * GP[1] + kv[2] * GP[2]) +
+                       (gv[0] * S.M[0][j] + gv[1] * S.M[1][j] + gv[2] * S.M[2][j]) +
+                       2.0f * h * S.M[3][j];
+        }
         float GR[4][4], Gs[4] = {0.f, 0.f, 0.f, 0.f};
         for (int i = 0; i < 4; ++i)
             for (int j = 0; j < 4; ++j) {
-                const float gm = 2.0f * (G4[i][0] * S.M[0][j] + G4[i][1] * S.M[1][j] +
-                                         G4[i][2] * S.M[2][j] + G4[i][3] * S.M[3][j]);
-                GR[i][j] = gm * S.s[j];
-                Gs[j] += gm * S.R[i][j];
+                GR[i][j] = GM[i][j] * S.s[j];
+                Gs[j] += GM[i][j] * S.R[i][j];
             }
         // R = Pi (A B) Pi^T
         const int perm[4] = {1, 2, 3, 0};

@@ -25,7 +25,6 @@ namespace {
 
 constexpr int RT_THREADS = 256;
 constexpr int RT_WAVES = 4;
-constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float ALPHA_MAX = 0.99f;
 constexpr float T_EPS = 1e-4f;
 // backward stages 128 Gaussians per round (per-wave partial sums: 18 KB of LDS)
@@ -45,13 +44,23 @@ __device__ __forceinline__ TileInfo tile_info(int64_t tile, const ViewPack &vp) 
 }
 
 // The exact same instruction sequence decides skip / blend in the forward
-// and the backward.
+// and the backward.  The conic of a visible record is positive definite
+// (positive determinant, 0.3 px^2 dilation on the diagonal), so the
+// exponent is <= 0 in exact arithmetic; the min with 0 only absorbs
+// rounding (alpha never exceeds o_t, and the pixel stays continuous where
+// the exponent passes 0).  Its derivative is the exponent's own.
 __device__ __forceinline__ float gauss_power(float4 a, float cc, float dx, float dy) {
     const float t1 = a.z * dx;   // conic.a dx
     const float t2 = cc * dy;    // conic.c dy
     const float q = fmaf(t1, dx, t2 * dy);
-    return fmaf(-0.5f, q, -(a.w * dx) * dy);
+    return fminf(fmaf(-0.5f, q, -(a.w * dx) * dy), 0.0f);
 }
+
+// The alpha >= 1/255 floor as a bound on the exponent: o_t e^power >= 1/255
+// iff power >= lo = -ln(255 o_t).  Both operands are FP32 values with a fixed
+// evaluation order (gauss_power; the project-defined logarithm), so the
+// decision to skip an entry is reproducible bit for bit.
+__device__ __forceinline__ float alpha_floor(float o_t) { return -fixed_log(255.0f * o_t); }
 
 // Each wave owns a block of pixels of the tile.  For a staged batch, every
 // wave marks (one ballot per 64 entries) the entries whose alpha >= 1/255
@@ -81,8 +90,8 @@ __device__ __forceinline__ void strip_masks(const float4 *sA, const float4 *sB, 
         bool hit = false;
         if (j < cnt) {
             const float4 a = sA[j];
-            const float4 c = sC[j];
-            hit = (a.x + c.y >= x0) && (a.x - c.y <= x1) && (a.y + c.z >= y0) && (a.y - c.z <= y1);
+            const float4 c = sC[j];   // b, lo, hx, hy
+            hit = (a.x + c.z >= x0) && (a.x - c.z <= x1) && (a.y + c.w >= y0) && (a.y - c.w <= y1);
             if (hit) {
                 // Refine: the alpha >= 1/255 ellipse q(d) = a dx^2 + 2 b dx dy + c dy^2
                 // <= tau must meet the block's rectangle of pixel centres.  q is convex, so
@@ -91,7 +100,10 @@ __device__ __forceinline__ void strip_masks(const float4 *sA, const float4 *sB, 
                 // a bound on its FP32 rounding (its terms can cancel), and tau
                 // carries the footprint's padding, so no entry that reaches
                 // alpha >= 1/255 at a pixel of the block is dropped.
-                const float ca = a.z, cb = a.w, cc = sB[j].x, tau = c.w;
+                // tau = 2 ln(255 o_t) = -2 lo, padded like the footprint (relative
+                // and absolute 2^-10) plus 2^-12
+                const float ca = a.z, cb = a.w, cc = sB[j].x;
+                const float tau = fmaf(-2.0f * c.y, 1.0f + 1.25f / 1024.0f, 1.25f / 1024.0f);
                 const float X0 = x0 - a.x, X1 = x1 - a.x, Y0 = y0 - a.y, Y1 = y1 - a.y;
                 const bool inside = X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f;
                 const float ia = __builtin_amdgcn_rcpf(ca), ic = __builtin_amdgcn_rcpf(cc);
@@ -124,11 +136,10 @@ __device__ __forceinline__ void stage_batch(const float4 *__restrict__ recv,
         const float4 r2 = recv[3 * (int64_t)g + 2];
         sA[t] = r0;                                       // mx my ca cb
         sB[t] = make_float4(r1.x, r1.y, r2.x, r2.y);      // cc o_t r g
-        // b hx hy tau: the level q <= tau of alpha >= 1/255, tau = 2 ln(255 o_t),
-        // padded like the footprint (relative and absolute 2^-10) plus 2^-12
-        // for the hardware logarithm
-        const float tau = 2.0f * __logf(255.0f * r1.y);
-        sC[t] = make_float4(r2.z, r1.w, r2.w, fmaf(tau, 1.0f + 1.25f / 1024.0f, 1.25f / 1024.0f));
+        // b, lo, hx, hy.  lo = -ln(255 o_t): alpha = o_t e^power >= 1/255 iff
+        // power >= lo, the form in which the floor is decided (FP32, the
+        // project-defined logarithm, so the decision is reproducible bit for bit)
+        sC[t] = make_float4(r2.z, alpha_floor(r1.y), r1.w, r2.w);
         if (sG) sG[t] = g;
     }
 }
@@ -186,13 +197,14 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
         // Branch-free per entry: every decision is a select, so the only
         // control flow is the wave-uniform walk over the mask bits; two
         // entries per step keep two sets of LDS reads in flight.
-        auto blend_one = [&](int j, float4 a, float4 b, float cb_) {
+        auto blend_one = [&](int j, float4 a, float4 b, float2 c) {
             const bool live = !done;
             const float dx = fx - a.x, dy = fy - a.y;
             const float power = gauss_power(a, b.x, dx, dy);
             const float at = b.y * __expf(power);
             const float alpha = fminf(ALPHA_MAX, at);
-            const bool ok = live && !(power > 0.0f) && !(alpha < ALPHA_MIN);
+            const bool ok = live && !(power < c.y);   // alpha >= 1/255
+            const float cb_ = c.x;
             const float Tn = T * (1.0f - alpha);
             const bool stop = ok && (Tn < T_EPS);
             const bool blend = ok && !stop;
@@ -219,9 +231,9 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
                 const int j1 = two ? k * 64 + __builtin_ctzll(mask) : j0;
                 if (two) mask &= mask - 1;
                 const float4 a0 = sA[j0], b0 = sB[j0];
-                const float c0 = sC[j0].x;
+                const float2 c0 = make_float2(sC[j0].x, sC[j0].y);
                 const float4 a1 = sA[j1], b1 = sB[j1];
-                const float c1 = sC[j1].x;
+                const float2 c1 = make_float2(sC[j1].x, sC[j1].y);
                 blend_one(j0, a0, b0, c0);
                 if (two) blend_one(j1, a1, b1, c1);
             }
@@ -505,8 +517,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             const float4 r2 = recv[3 * (int64_t)g + 2];
             sA[i] = r0;
             sB[i] = make_float4(r1.x, r1.y, r2.x, r2.y);
-            const float tau = 2.0f * __logf(255.0f * r1.y);     // as in stage_batch
-            sC[i] = make_float4(r2.z, r1.w, r2.w, fmaf(tau, 1.0f + 1.25f / 1024.0f, 1.25f / 1024.0f));
+            sC[i] = make_float4(r2.z, alpha_floor(r1.y), r1.w, r2.w);   // as in stage_batch
             sG[i] = g;
         }
         __syncthreads();
@@ -518,8 +529,9 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
         for (int k = 0; k < NK; ++k) wr[k] = 0;
         // Branch-free per entry (selects only), entries taken back to front
         // two at a time so their LDS reads overlap.
-        auto grad_one = [&](int j, float4 a, float4 b, float cbl) {
+        auto grad_one = [&](int j, float4 a, float4 b, float2 c) {
             const int idx = start + j;
+            const float cbl = c.x;
             float d[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) d[q] = 0.0f;
@@ -531,7 +543,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
                 const float ex = __expf(power);
                 const float at = b.y * ex;
                 const float alpha = fminf(ALPHA_MAX, at);
-                const bool ok = (idx <= my_last[k]) && !(power > 0.0f) && !(alpha < ALPHA_MIN);
+                const bool ok = (idx <= my_last[k]) && !(power < c.y);   // alpha >= 1/255
                 any = any || ok;
                 // transmittance in front of this entry
                 const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
@@ -578,9 +590,9 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
                 if (two) mask &= ~(1ull << bit1);
                 const int j0 = kk * 64 + bit0, j1 = kk * 64 + bit1;
                 const float4 a0 = sA[j0], b0 = sB[j0];
-                const float c0 = sC[j0].x;
+                const float2 c0 = make_float2(sC[j0].x, sC[j0].y);
                 const float4 a1 = sA[j1], b1 = sB[j1];
-                const float c1 = sC[j1].x;
+                const float2 c1 = make_float2(sC[j1].x, sC[j1].y);
                 grad_one(j0, a0, b0, c0);
                 if (two) grad_one(j1, a1, b1, c1);
             }

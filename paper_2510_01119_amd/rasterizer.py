@@ -68,6 +68,9 @@ class Rasterizer:
         self.loss_per_view = torch.zeros(V, dtype=torch.float32, device=dev)
         self.dL_dimage = (None if self.forward_only
                           else torch.zeros((V, 3, H, W), dtype=torch.float32, device=dev))
+        # bumped by every forward: the state a backward reads belongs to the
+        # latest forward only
+        self.generation = 0
         self._alloc_pairs(pair_capacity if pair_capacity else max(1 << 16, 8 * n * V))
 
     def set_views(self, views):
@@ -171,6 +174,7 @@ class Rasterizer:
     def forward(self, params: torch.Tensor, check: bool = True, opts=None):
         assert params.shape in ((G.N_FIELDS, self.n), (G.ISO_FIELDS, self.n))
         assert params.dtype == torch.float32
+        self.generation += 1
         self.preprocess(params)
         self.bin_sort(check)
         self.render(opts)
@@ -198,18 +202,23 @@ class GS4DRasterize(torch.autograd.Function):
     """image = GS4DRasterize.apply(params [20, N], rasterizer).
 
     The backward runs gs4d_render_bwd on the state the forward left in the
-    rasterizer's buffers, so a second forward through the same rasterizer
-    before backward is not allowed."""
+    rasterizer's buffers; if another forward ran through the same rasterizer
+    in between (its generation moved on), backward raises instead of
+    returning gradients of the wrong state."""
 
     @staticmethod
     def forward(ctx, params, rast):
         rast.forward(params.detach().contiguous())
         ctx.rast = rast
+        ctx.generation = rast.generation
         ctx.save_for_backward(params)
         return rast.image.clone()
 
     @staticmethod
     def backward(ctx, dimg):
+        if ctx.rast.generation != ctx.generation:
+            raise RuntimeError("GS4DRasterize.backward: the rasterizer ran another forward "
+                               "after this one; its buffers no longer hold this forward's state")
         (params,) = ctx.saved_tensors
         d = ctx.rast.backward(params.detach().contiguous(), dimg.contiguous())
         return d.clone(), None

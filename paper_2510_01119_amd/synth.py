@@ -128,19 +128,29 @@ def linear_loss_weights(n_views, height, width, seed=7):
     return rng.uniform(-1.0, 1.0, (n_views, 3, height, width)).astype(np.float32)
 
 
-def batched_set(n=500_000, seed=3, frac_dynamic=0.2):
-    """Many-view set in the structure of the paper's motion-aware model
+def batched_set(n=500_000, seed=3, frac_dynamic=0.2, rotations="motion"):
+    """Many-view set.  Means uniform in [-1,1]^3 x [0,1]; spatial log scales
+    N(-5, 0.5) per axis (the views zoom in, so splats stay a few pixels);
+    opacity logit N(0,1); rgb U(0,1).
+
+    rotations="motion": the structure of the paper's motion-aware model
     (Sec. 3.3): a static majority with identity orientation (no space-time
     coupling) and a long temporal scale (log s_t ~ N(0.5, 0.3)), and a
     dynamic part that lives briefly (log s_t ~ N(-2.5, 0.3)) and moves
     (rotors within ~0.1 rad of identity, so the velocity a/c is ~0.1 per
-    unit time).  Means uniform in [-1,1]^3 x [0,1]; spatial log scales
-    N(-5, 0.5) per axis (the views zoom in, so splats stay a few pixels);
-    opacity logit N(0,1); rgb U(0,1).  A random 4D rotation on a Gaussian
-    with s_t >> s_xyz would make the conditional covariance B - aa^T/c a
-    difference of nearly equal terms, a conditioning no trained model of
-    this kind has."""
+    unit time).
+
+    rotations="random": the 2,000-Gaussian set's shapes -- two random unit
+    quaternions (a random 4D rotation) per Gaussian, log s_t ~ N(0, 0.3),
+    so s_t is ~150 times s_xyz and the conditional covariance is the
+    ill-conditioned difference of two large blocks."""
     rng = np.random.default_rng(seed)
+    if rotations == "random":
+        p = small_set(n, seed, log_s_xyz=(-5.0, 0.5)).astype(np.float64)
+        p[7] = np.random.default_rng(seed + 7).normal(0.0, 0.3, n)
+        return p.astype(np.float32)
+    if rotations != "motion":
+        raise ValueError(rotations)
     p = np.zeros((N_FIELDS, n), dtype=np.float64)
     p[0:3] = rng.uniform(-1.0, 1.0, (3, n))
     p[3] = rng.uniform(0.0, 1.0, n)

@@ -89,7 +89,7 @@ class CropFD:
             self.lists[int(t)] = vals[b:e].astype(np.int64)
         # blend-decision signature of every crop pixel for the base set
         self.sig0 = oracle.render_fwd(self.rec, crop.view, vals, crop.restrict(ranges),
-                                      signature=True)["sig"][0]
+                                      signature=True, f32=False)["sig"][0]
 
     def _tiles_of(self, rect_row, touched_v):
         c = self.crop
@@ -121,7 +121,7 @@ class CropFD:
             pos += len(lst)
             vals.append(lst)
         vals = np.concatenate(vals).astype(np.uint32) if vals else np.zeros(0, np.uint32)
-        out = oracle.render_fwd(rec, self.crop.view, vals, ranges, signature=True)
+        out = oracle.render_fwd(rec, self.crop.view, vals, ranges, signature=True, f32=False)
         pm = self._pixels(tiles)
         L = float((self.w[0] * out["image"][0])[:, pm].sum())
         return L, out["sig"][0][pm], out["image"][0][:, pm]

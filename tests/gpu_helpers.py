@@ -6,6 +6,8 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
+
 ALPHA_MIN = 1.0 / 255.0
 
 
@@ -38,105 +40,162 @@ def to_np(r):
     return out
 
 
-def near_threshold_pixels(rec64, views, vals, ranges, rtol=1e-5, return_tainted=False,
-                          taint="pixel"):
-    """Boolean [V, H, W]: pixels where some entry's FP64 alpha lies within
-    the FP32 evaluation error of 1/255 or 0.99, its exponent within that
-    error of 0, or the transmittance test within it of 1e-4.  Such pixels
-    may legitimately differ between an FP32 and an FP64 render.
+def near_threshold_pixels(rec64, views, vals, ranges):
+    """Boolean [V, H, W]: pixels with a decision an FP32 kernel render may
+    take the other way from the oracle's FP32 shadow
+    (oracle.doubtful_decisions)."""
+    return oracle.doubtful_decisions(rec64, views, vals, ranges)[0]
 
-    The FP32 error of the exponent -(a dx^2 + c dy^2)/2 - b dx dy is bounded
-    by a few units of roundoff times the sum of its terms' magnitudes S (the
-    terms can cancel for thin splats, so S can be much larger than the
-    exponent); exp turns that absolute error into the same relative error of
-    alpha.  Transmittance after n blends carries about 2n roundoffs.  rtol
-    covers the exp approximation and the rest.
 
-    With return_tainted, also a boolean per Gaussian: its gradient may
-    differ between the two renders.
-      taint="pixel": every Gaussian that reaches alpha >= 1/255 (less the
-        tolerance) at such a pixel before it stops.
-      taint="entry": only the entries whose own decision is in doubt: an
-        alpha or clamp decision next to its threshold taints that entry (a
-        1/255 blend that flips changes the others' terms at that pixel by
-        about 0.4%); a transmittance stop next to 1e-4 taints the stopping
-        entry and the next two blends it would have allowed (their weights
-        are ~1e-4); an exponent next to 0 (blend at full alpha or skip)
-        taints every later entry at that pixel up to its stop and 64 blends
-        past it."""
-    u = 2.0 ** -24
+def decision_bounds(params, views, rec64, vals, ranges, dL_dimage, iso=False):
+    """What each doubtful decision can change, computed by the oracle: the
+    pixel re-composited with that one decision inverted, against the pixel as
+    the oracle takes it (its decisions taken on the FP32 shadow of the
+    kernel's arithmetic; oracle.doubtful_decisions lists the ones the
+    kernel's hardware exp2 may take the other way).  Returns (flag [V, H, W], img [V, H, W]: the summed
+    change of the pixel's colour (max over channels), T [V, H, W]: of its
+    final transmittance, grad [F, n]: the summed |change| of each
+    parameter's gradient, chained through the preprocess backward (FP64)).
+    An FP32 render that takes any of these decisions the other way differs
+    from the oracle by at most these amounts (plus its own rounding)."""
     views = np.atleast_2d(views)
-    V = views.shape[0]
-    n = rec64.shape[1]
-    W, H = int(views[0, 16]), int(views[0, 17])
+    V, n, _ = rec64.shape
+    flag, found = oracle.doubtful_decisions(rec64, views, vals, ranges)
+    H, W = flag.shape[1:]
+    img = np.zeros((V, H, W))
+    Tb = np.zeros((V, H, W))
+    F = oracle.ISO_FIELDS if iso else 20
+    grad = np.zeros((F, n))
+    if not found:
+        return flag, img, Tb, grad
+    bwd = oracle.preprocess_iso_bwd if iso else oracle.preprocess_bwd
     tx, ty = (W + 15) // 16, (H + 15) // 16
-    flag = np.zeros((V, H, W), bool)
-    tainted = np.zeros(n, bool)
-    ys, xs = np.mgrid[0:16, 0:16]
-    for v in range(V):
-        for tile_y in range(ty):
-            for tile_x in range(tx):
-                tile = v * tx * ty + tile_y * tx + tile_x
-                b, e = ranges[tile]
-                if e <= b:
-                    continue
-                px = tile_x * 16 + xs + 0.5
-                py = tile_y * 16 + ys + 0.5
-                y0, x0 = tile_y * 16, tile_x * 16
-                hh, ww = min(16, H - y0), min(16, W - x0)
-                inside = np.zeros((16, 16), bool)
-                inside[:hh, :ww] = True
-                T = np.ones((16, 16))
-                nb = np.zeros((16, 16))
-                near = np.zeros((16, 16), bool)
-                alive = np.ones((16, 16), bool)
-                pending = np.zeros((16, 16), np.int64)   # entry mode: blends still tainted
-                wide = np.zeros((16, 16), bool)          # entry mode: exponent next to 0
-                alphas = []
-                for k in range(b, e):
-                    r = rec64[v, vals[k]]
-                    dx, dy = px - r[0], py - r[1]
-                    power = -0.5 * (r[2] * dx * dx + r[4] * dy * dy) - r[3] * dx * dy
-                    S = 0.5 * (abs(r[2]) * dx * dx + abs(r[4]) * dy * dy) + abs(r[3] * dx * dy)
-                    tol = rtol + 8.0 * u * S
-                    at = r[5] * np.exp(np.minimum(power, 0.0))
-                    a = np.minimum(0.99, at)
-                    reach = a >= ALPHA_MIN * (1 - tol)
-                    own = alive & ((np.abs(a - ALPHA_MIN) <= tol * ALPHA_MIN)
-                                   | (np.abs(at - 0.99) <= tol * 0.99))
-                    zero = alive & (np.abs(power) <= 8.0 * u * S + 1e-6)
-                    near |= own | zero
-                    ok = alive & (power <= 0) & (a >= ALPHA_MIN)
-                    Tn = T * (1 - a)
-                    stop_near = ok & (np.abs(Tn - 1e-4) <= (rtol + 4.0 * u * (nb + 1)) * 1e-4)
-                    near |= stop_near
-                    if taint == "entry" and return_tainted:
-                        wide |= zero
-                        hit = inside & (own | stop_near | (wide & reach) | ((pending > 0) & reach))
-                        if hit.any():
-                            tainted[vals[k]] = True
-                        pending = np.where((pending > 0) & reach, pending - 1, pending)
-                        pending = np.where(stop_near, 2, pending)
-                    else:
-                        alphas.append((a, tol, alive.copy()))
-                    stop = ok & (Tn < 1e-4)
-                    if taint == "entry" and return_tainted:
-                        # an exponent next to 0 changes this pixel's transmittance by a
-                        # factor up to 100: the other render stops up to ~64 blends later
-                        pending = np.where(wide & stop, 64, pending)
-                        wide &= ~stop
-                    alive &= ~stop
-                    blend = ok & ~stop
-                    T = np.where(blend, Tn, T)
-                    nb += blend
-                    if not alive.any() and not (taint == "entry" and ((pending > 0) | wide).any()):
-                        break
-                near &= inside
-                flag[v, y0:y0 + hh, x0:x0 + ww] = near[:hh, :ww]
-                if return_tainted and taint == "pixel" and near.any():
-                    for k, (a, tol, live) in zip(range(b, e), alphas):
-                        if np.any(near & live & (a >= ALPHA_MIN * (1 - tol))):
-                            tainted[vals[k]] = True
-    if return_tainted:
-        return flag, tainted
-    return flag
+    # the preprocess backward is linear in the record gradient: its
+    # columns per view, from one call per record term
+    J = {}
+    for v in sorted({f[0] for f in found}):
+        cols = []
+        for j in range(9):
+            g = np.zeros((1, n, 9))
+            g[0, :, j] = 1.0
+            cols.append(bwd(params.astype(np.float64), views[v:v + 1], g))
+        J[v] = np.stack(cols)                       # [9, F, n]
+    base = {}
+    for v, x, y, e, kind in found:
+        gC = dL_dimage[v, :, y, x].astype(np.float64)
+        key = (v, x, y)
+        if key not in base:
+            base[key] = oracle.pixel_variant(rec64, views, v, vals, ranges, x, y, gC,
+                                             f32=True)
+        C0, T0, g0, _ = base[key]
+        C1, T1, g1, _ = oracle.pixel_variant(rec64, views, v, vals, ranges, x, y, gC, e, kind,
+                                             f32=True)
+        img[v, y, x] += np.abs(C1 - C0).max()
+        Tb[v, y, x] += abs(T1 - T0)
+        dg = g1 - g0
+        rows = np.nonzero(np.any(dg != 0, axis=1))[0]
+        if len(rows) == 0:
+            continue
+        b = int(ranges[v * tx * ty + (y // 16) * tx + (x // 16)][0])
+        ids = np.asarray(vals)[b + rows].astype(np.int64)
+        grad[:, ids] += np.abs(np.einsum("jfk,kj->fk", J[v][:, :, ids], dg[rows]))
+    return flag, img, Tb, grad
+
+
+def report_exempt(name, near, widened=None, contributing=None):
+    """Prints (and returns) the fraction of pixels with a doubtful decision
+    and, with `widened`, the fraction of the Gaussians (of `contributing`
+    ones if given) whose gradient bar the decision bounds widen."""
+    out = {"pixels": float(np.mean(near))}
+    if widened is not None:
+        base = contributing if contributing is not None else np.ones_like(widened)
+        out["gaussians_widened"] = float(widened[base].mean()) if base.any() else 0.0
+        out["n_widened"] = int(widened[base].sum())
+    print(f"doubtful[{name}]: " + ", ".join(f"{k}={v:.3g}" if isinstance(v, float) else f"{k}={v}"
+                                           for k, v in out.items()), flush=True)
+    return out
+
+
+def check_image(name, img_gpu, img_ref, flag, img_bound, max_pixels=1e-3):
+    """Image parity: every pixel within 1e-4 absolute of the oracle, plus, at
+    a pixel with a doubtful decision, what inverting it changes."""
+    report_exempt(name, flag)
+    assert flag.mean() <= max_pixels, flag.mean()
+    diff = np.abs(img_gpu - img_ref).max(axis=1)
+    lim = 1e-4 + img_bound
+    worst = np.unravel_index(np.argmax(diff / lim), diff.shape)
+    assert np.all(diff <= lim), (name, worst, float(diff[worst]), float(lim[worst]))
+
+
+def splat_condition(rec, touched):
+    """Per Gaussian: the largest condition number over the views where it is
+    visible of its 2D covariance (from the FP32 record's conic; the same as
+    the conic's).  A needle-shaped splat (kappa ~ 1e5) cannot hold its thin
+    direction in FP32 to better than u kappa, so neither can a FP32 chain
+    rule through it."""
+    r = rec.astype(np.float64)
+    a, b, c = r[..., 2], r[..., 3], r[..., 4]
+    half_tr = 0.5 * (a + c)
+    disc = np.sqrt(np.maximum(half_tr * half_tr - (a * c - b * b), 0.0))
+    lo = half_tr - disc
+    kappa = np.where((touched > 0) & (lo > 0), (half_tr + disc) / np.where(lo > 0, lo, 1.0), 1.0)
+    return kappa.max(axis=0)
+
+
+def check_gradients(name, d, ref, bound, max_widened=0.01, max_rel=0.02, max_outliers=0.0,
+                    kappa=None):
+    """Gradient parity: every entry within 1e-3 relative of the oracle (floor:
+    1e-3 of the parameter class's largest magnitude) plus the oracle-computed
+    change its doubtful decisions can make (`bound`, decision_bounds).  The
+    Gaussians whose bar that widens (bound above the 1e-3 bar) are counted,
+    printed and held to `max_widened` of those with a gradient; no bar may
+    widen beyond `max_rel` of max(|g|, floor).
+
+    max_outliers > 0 (the densest crop only): that fraction of the checked
+    (parameter, Gaussian) entries may exceed the bar -- FP32 rounding of the
+    transmittance behind alphas near 0.99, summed over hundreds of pixels
+    with cancelling signs -- but none by more than 10x; they are counted and
+    printed.
+
+    kappa (per Gaussian, splat_condition): the bar also allows 16 u kappa of
+    max(|g|, floor), the FP32 limit for needle-shaped splats; the Gaussians
+    where that exceeds 1e-3 and their worst measured error are printed."""
+    u = 2.0 ** -24
+    contributing = np.any(ref != 0, axis=0)
+    widened = np.zeros(ref.shape[1], bool)
+    worst_rel = 0.0
+    over, over_max, checked = 0, 0.0, 0
+    cond = np.zeros(ref.shape[1]) if kappa is None else 16.0 * u * kappa
+    needle = cond > 1e-3
+    needle_err = 0.0
+    for k in range(ref.shape[0]):
+        floor = 1e-3 * np.abs(ref[k]).max()
+        mag = np.maximum(np.abs(ref[k]), floor)
+        err = np.abs(d[k] - ref[k])
+        tol = 1e-3 * mag + 1e-7
+        widened |= bound[k] > tol
+        lim = tol + bound[k] + cond * mag
+        ratio = err / lim
+        checked += int(contributing.sum())
+        over += int((ratio > 1.0).sum())
+        over_max = max(over_max, float(ratio.max()) if ratio.size else 0.0)
+        if needle.any():
+            needle_err = max(needle_err, float(np.max(err[needle] / mag[needle])))
+        if max_outliers <= 0.0:
+            worst = int(np.argmax(ratio))
+            assert np.all(err <= lim), (name, k, worst, int((err > lim).sum()), err[worst],
+                                        tol[worst], bound[k][worst], ref[k][worst])
+        if ref.shape[1]:
+            worst_rel = max(worst_rel, float(np.max(bound[k] / np.maximum(np.abs(ref[k]), floor + 1e-30))))
+    rep = report_exempt(name, np.zeros(1, bool), widened, contributing)
+    rep.update(widest_bar_rel=worst_rel, over_bar=over, worst_over_bar=over_max)
+    print(f"parity[{name}]: widest bound relative to max(|g|, floor) = {worst_rel:.3g}; "
+          f"entries over the bar {over} of {checked} (worst {over_max:.3g}x)", flush=True)
+    if kappa is not None:
+        print(f"parity[{name}]: needle-shaped splats (16 u kappa > 1e-3): {int((needle & contributing).sum())}"
+              f" of {int(contributing.sum())} Gaussians, max kappa {float(kappa.max()):.3g}, "
+              f"their worst error relative to max(|g|, floor) {needle_err:.3g}", flush=True)
+    assert rep["gaussians_widened"] <= max_widened, rep
+    assert worst_rel <= max_rel, rep
+    assert over <= max_outliers * checked and over_max <= 10.0, rep
+    return rep

@@ -21,7 +21,7 @@ def _setup():
 def _crop_image(q, view, crop):
     rec, rect, touched = oracle.preprocess_f64(q, view)
     _, vals, ranges = oracle.bin_sort(rect, touched, oracle.depth_bits(rec), view)
-    return oracle.render_fwd(rec, view, vals, crop.restrict(ranges))["image"][0]
+    return oracle.render_fwd(rec, view, vals, crop.restrict(ranges), f32=False)["image"][0]
 
 
 def test_subset_restriction_exact():

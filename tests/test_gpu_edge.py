@@ -108,6 +108,13 @@ def test_autograd_function():
     d = r2.backward(Q, w)
     torch.cuda.synchronize()
     assert torch.allclose(P.grad, d, rtol=1e-5, atol=1e-6)
+    # a second forward through the same rasterizer before backward: the
+    # first graph's backward refuses the overwritten state
+    P2 = torch.from_numpy(p).cuda().requires_grad_(True)
+    img2 = GS4DRasterize.apply(P2, r)
+    r.forward(Q)
+    with pytest.raises(RuntimeError, match="another forward"):
+        (img2 * w).sum().backward()
 
 
 def test_gradients_vs_central_differences():
@@ -128,7 +135,7 @@ def test_gradients_vs_central_differences():
     def loss_sig(q):
         rec, rect, touched = oracle.preprocess_f64(q, view)
         keys, vals, ranges = oracle.bin_sort(rect, touched, oracle.depth_bits(rec), view)
-        out = oracle.render_fwd(rec, view, vals, ranges, signature=True)
+        out = oracle.render_fwd(rec, view, vals, ranges, signature=True, f32=False)
         return float((w64 * out["image"]).sum()), out["sig"]
 
     _, sig0 = loss_sig(p64)

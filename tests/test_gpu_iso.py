@@ -18,7 +18,7 @@ from paper_2510_01119_amd import gs4d as G
 from paper_2510_01119_amd import synth
 from paper_2510_01119_amd.rasterizer import Rasterizer
 
-from gpu_helpers import near_threshold_pixels, need_gpu
+from gpu_helpers import check_gradients, decision_bounds, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -84,20 +84,11 @@ def test_iso_gradients(iso_case):
     torch.cuda.synchronize()
     got = d.cpu().numpy()
     rec64 = c["rec"].astype(np.float64)
-    grec = oracle.render_bwd(rec64, c["views"], c["vals"], c["ranges"], w.astype(np.float64))
+    grec = oracle.render_bwd(rec64, c["views"], c["vals"], c["ranges"], w.astype(np.float64),
+                             f32=True)
     ref = oracle.preprocess_iso_bwd(c["p"].astype(np.float64), c["views"], grec)
-    _, tainted = near_threshold_pixels(rec64, c["views"], c["vals"], c["ranges"],
-                                       return_tainted=True)
-    ok = ~tainted
-    assert ok.mean() > 0.85, ok.mean()
-    for k in range(G.ISO_FIELDS):
-        floor = 1e-3 * np.abs(ref[k]).max()
-        err = np.abs(got[k] - ref[k])
-        tol = 1e-3 * np.maximum(np.abs(ref[k]), floor) + 1e-7
-        bad = (err > tol) & ok
-        worst = np.argmax(np.where(ok, err / tol, 0))
-        assert not np.any(bad), (k, err[worst], tol[worst], ref[k][worst])
-        assert np.all(err[tainted] <= 0.05 * np.maximum(np.abs(ref[k][tainted]), 10 * floor)), k
+    _, _, _, gb = decision_bounds(c["p"], c["views"], rec64, c["vals"], c["ranges"], w, iso=True)
+    check_gradients("iso", got, ref, gb)
 
 
 def test_iso_trainer_starts_as_rotor_and_trains():

@@ -1,10 +1,14 @@
 """GPU parity of the HIP path against the CPU oracle (through the C ABI).
 
 Bars: preprocess records, rectangles and tile counts, sort keys, values and
-tile ranges bit-exact; image within 1e-4 absolute (pixels next to an alpha /
-transmittance threshold exempted and counted); gradients within 1e-3
+tile ranges bit-exact; image within 1e-4 absolute and gradients within 1e-3
 relative of the oracle's FP64 chain rule (floor 1e-3 of the parameter
-class's largest magnitude).
+class's largest magnitude).  The oracle takes the alpha >= 1/255 floor in
+the kernel's precision (the same FP32 values, so the same decisions); where
+a 0.99 clamp or a transmittance stop lies within the FP32 render's error of
+its threshold, the oracle re-composites the pixel with that decision
+inverted and the difference widens that pixel's and those Gaussians' bars
+(counted and printed; no Gaussian is exempt).
 """
 import numpy as np
 import pytest
@@ -13,7 +17,7 @@ import torch
 import oracle
 from paper_2510_01119_amd import synth
 
-from gpu_helpers import gpu_forward, near_threshold_pixels, need_gpu, to_np
+from gpu_helpers import check_gradients, check_image, decision_bounds, gpu_forward, need_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +42,12 @@ def case(request):
     r, p = gpu_forward(params, views, count_blends=True)
     gpu = to_np(r)
     ref = oracle.forward(params, views, "f32")
-    return dict(name=request.param, params=params, views=views, gpu=gpu, ref=ref, rast=r, p=p)
+    w = synth.linear_loss_weights(r.V, r.H, r.W, seed=11)
+    # what each decision an FP32 render may take the other way can change
+    flag, img_b, T_b, grad_b = decision_bounds(params, views, ref["rec"].astype(np.float64),
+                                               ref["vals"], ref["ranges"], w)
+    return dict(name=request.param, params=params, views=views, gpu=gpu, ref=ref, rast=r, p=p,
+                w=w, flag=flag, img_b=img_b, T_b=T_b, grad_b=grad_b)
 
 
 def test_preprocess_bitexact(case):
@@ -76,16 +85,12 @@ def test_render_fwd_batches_identical(case, batch):
 
 def test_render_fwd_image(case):
     g, o = case["gpu"], case["ref"]
-    near = near_threshold_pixels(o["rec"].astype(np.float64), case["views"], o["vals"], o["ranges"])
-    diff = np.abs(g["image"] - o["image"]).max(axis=1)
-    bad = diff > 1e-4
-    assert not np.any(bad & ~near), (diff[~near].max(), int((bad & ~near).sum()))
-    assert near.mean() < 1e-2
+    check_image(case["name"], g["image"], o["image"], case["flag"], case["img_b"])
     tdiff = np.abs(g["T_final"] - o["T_final"])
-    assert np.all((tdiff <= 1e-4) | near)
+    assert np.all(tdiff <= 1e-4 + case["T_b"])
     lmis = g["last"] != o["last"]
-    assert not np.any(lmis & ~near)
-    # blend counters agree with the oracle's up to the exempted pixels
+    assert not np.any(lmis & ~case["flag"])
+    # blend counters agree with the oracle's up to the doubtful decisions
     assert abs(g["n_blend"] - o["n_blend"]) <= max(10, 0.001 * o["n_blend"])
 
 
@@ -94,29 +99,11 @@ def test_render_bwd_gradients(case, ppl):
     need_gpu()
     from paper_2510_01119_amd import gs4d as G
     params, views, r, p = case["params"], case["views"], case["rast"], case["p"]
-    V, H, W = r.V, r.H, r.W
-    w = synth.linear_loss_weights(V, H, W, seed=11)
+    w = case["w"]
     G.gs4d_set_bwd_variant(ppl)
     try:
         dparams = r.backward(p, torch.from_numpy(w).cuda()).cpu().numpy()
     finally:
         G.gs4d_set_bwd_variant(1)      # the library's default
     ref, _ = oracle.backward(params, views, w.astype(np.float64), fwd=case["ref"])
-    # Gaussians visible at a pixel next to a threshold are exempted (counted)
-    _, tainted = near_threshold_pixels(case["ref"]["rec"].astype(np.float64), views,
-                                       case["ref"]["vals"], case["ref"]["ranges"],
-                                       return_tainted=True)
-    ok = ~tainted
-    # at most a few pixels sit next to a threshold, but overlapping splats
-    # spread their effect over the Gaussians seen there
-    assert ok.mean() > 0.85, ok.mean()
-    for k in range(20):
-        floor = 1e-3 * np.abs(ref[k]).max()
-        err = np.abs(dparams[k] - ref[k])
-        tol = 1e-3 * np.maximum(np.abs(ref[k]), floor) + 1e-7
-        bad = err > tol
-        worst = np.argmax(np.where(ok, err / tol, 0))
-        assert not np.any(bad & ok), (case["name"], k, err[worst], tol[worst], ref[k][worst])
-        # exempted Gaussians: a flipped decision moves a gradient by at most a
-        # few pixels' worth
-        assert np.all(err[tainted] <= 0.05 * np.maximum(np.abs(ref[k][tainted]), 10 * floor)), k
+    check_gradients(f"{case['name']} ppl={ppl}", dparams, ref, case["grad_b"])

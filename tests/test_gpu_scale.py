@@ -7,9 +7,12 @@ through the slice, projection, sort and compositing.
   the oracle bit for bit;
 * on the densest 128x128 tile-aligned crop the image matches the oracle to
   1e-4 and the gradients of a random linear loss over the crop match the
-  oracle's FP64 chain rule to 1e-3 relative (Gaussians seen at a pixel
-  next to a threshold exempted); every Gaussian that misses the crop gets
-  an exactly zero gradient;
+  oracle's FP64 chain rule to 1e-3 relative (the oracle takes the
+  compositing decisions on an FP32 shadow of the kernel's arithmetic; the
+  few it may take differently -- its exp2 is correctly rounded, the
+  hardware's within an ulp -- widen their pixels' and Gaussians' bars by
+  what inverting them changes, counted and printed); every Gaussian that
+  misses the crop gets an exactly zero gradient;
 * 64 random (Gaussian, parameter) entries of Gaussians that blend in the
   crop match central differences (h = 1e-3) of the oracle's FP64 forward;
   entries whose +-h step changes a blend decision are redrawn.
@@ -22,7 +25,7 @@ import oracle
 from paper_2510_01119_amd import synth
 
 from crop_oracle import CropFD, densest_crop
-from gpu_helpers import gpu_forward, near_threshold_pixels, need_gpu
+from gpu_helpers import check_gradients, check_image, decision_bounds, gpu_forward, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -78,13 +81,12 @@ def crop_ref(scale):
     _, vs, rg = oracle.bin_sort(o["rect"][:, sub], o["touched"][:, sub], oracle.depth_bits(rs), view)
     crg = crop.restrict(rg)
     rs64 = rs.astype(np.float64)
-    out = oracle.render_fwd(rs64, view, vs, crg)
-    grec = oracle.render_bwd(rs64, view, vs, crg, w.astype(np.float64))
+    out = oracle.render_fwd(rs64, view, vs, crg, f32=True)
+    grec = oracle.render_bwd(rs64, view, vs, crg, w.astype(np.float64), f32=True)
     dsub = oracle.preprocess_bwd(p[:, sub], view, grec)
-    near, tainted = near_threshold_pixels(rs64, view, vs, crg, return_tainted=True,
-                                         taint="entry")
+    flag, img_b, _, grad_b = decision_bounds(p[:, sub], view, rs64, vs, crg, w)
     return dict(sub=sub, vals=vs, ranges=crg, image=out["image"], T_final=out["T_final"],
-                d=dsub, near=near, tainted=tainted)
+                d=dsub, flag=flag, img_b=img_b, grad_b=grad_b)
 
 
 def test_crop_image_and_lists(scale, crop_ref):
@@ -96,10 +98,8 @@ def test_crop_image_and_lists(scale, crop_ref):
         b2, e2 = c["ranges"][t]
         assert np.array_equal(g["vals"][b:e], sub[c["vals"][b2:e2]]), t
     m = crop.pixel_mask()
-    diff = np.abs(g["image"][0][:, m] - c["image"][0][:, m]).max(axis=0)
-    near = c["near"][0][m]
-    assert not np.any((diff > 1e-4) & ~near), float(diff[~near].max())
-    assert near.mean() < 1e-2
+    check_image("1M crop", g["image"][0][:, m][None], c["image"][0][:, m][None], c["flag"][0][m][None],
+                c["img_b"][0][m][None], max_pixels=1e-2)
     assert np.abs(c["image"][0][:, m]).max() > 0.1
 
 
@@ -111,19 +111,14 @@ def test_crop_gradients(scale, crop_ref):
     assert np.all(g["d"][:, outside] == 0.0)
     d = g["d"][:, sub]
     ref = c["d"]
-    ok = ~c["tainted"]
     contributing = np.abs(ref[17]) > 0
     assert contributing.sum() > 500
-    # in a crop this dense an exponent next to 0 at one pixel exempts the few
-    # hundred Gaussians blended there after it
-    assert ok[contributing].mean() > 0.7, ok[contributing].mean()
-    for k in range(20):
-        floor = 1e-3 * np.abs(ref[k]).max()
-        err = np.abs(d[k] - ref[k])
-        tol = 1e-3 * np.maximum(np.abs(ref[k]), floor) + 1e-7
-        bad = (err > tol) & ok
-        worst = int(np.argmax(np.where(ok, err / tol, 0)))
-        assert not np.any(bad), (k, int(bad.sum()), err[worst], tol[worst], ref[k][worst])
+    # this crop composites ~35,000 entries per tile.  Behind alphas near
+    # 0.99 the FP32 transmittance carries ~1e-4 relative error, which a
+    # gradient summed with cancelling signs over hundreds of pixels can lift
+    # past 1e-3: at most 0.1% of the entries may exceed the bar, none by
+    # more than 10x (counted and printed)
+    check_gradients("1M crop", d, ref, c["grad_b"], max_outliers=1e-3)
 
 
 def test_central_differences(scale, crop_ref):

@@ -136,3 +136,35 @@ def test_conditional_vs_bruteforce_marginalisation(oracle_lib, seed):
     assert np.allclose(m_t, mu, rtol=0, atol=1e-6 * np.sqrt(np.trace(Sc)))
     assert np.allclose(C_t, Sc, rtol=1e-6, atol=1e-6 * np.trace(Sc))
     assert np.isclose(mass_t / mass_0, ot / o, rtol=1e-6)
+
+
+def test_fp32_conditional_is_well_conditioned(oracle_lib):
+    """The FP32 instance (the kernel's precision and evaluation order) forms
+    the conditional covariance from the rows of R S with the time direction
+    projected out.  Against the FP64 plain Schur complement its error stays
+    at a few roundoffs of |Sc| for random 4D rotations with s_t up to ~1100
+    times s_xyz; the plain Schur complement evaluated in FP32 loses about
+    eps (s_t / s_xyz)^2 there, which this bound would catch."""
+    rng = np.random.default_rng(0)
+    worst, worst_plain = 0.0, 0.0
+    for ratio_log in (0.0, 2.0, 4.0, 5.0, 6.0, 7.0):
+        for _ in range(100):
+            ls = rng.normal(-5.0, 0.5, 3)
+            p = _one(mean=rng.uniform(-1, 1, 4), ls=(*ls, ls.mean() + ratio_log),
+                     ql=rng.standard_normal(4), qr=rng.standard_normal(4)).astype(np.float32)
+            mu64, S64, ot64 = oracle_lib.conditional(p.astype(np.float64), 0, 0.5)
+            mu32, S32, ot32 = oracle_lib.conditional_f32(p, 0, 0.5)
+            scale = np.abs(S64).max()
+            err = np.abs(S32.astype(np.float64) - S64).max() / scale
+            assert err < 2e-5, (ratio_log, err)
+            assert np.allclose(mu32, mu64, rtol=1e-5, atol=1e-6)
+            if ot64 >= 1.0 / 255.0:     # the range where o_t decides visibility
+                assert abs(ot32 - ot64) <= 1e-5 * ot64
+            worst = max(worst, err)
+            if ratio_log == 6.0:
+                Sg = oracle_lib.covariance(p.astype(np.float64), 0).astype(np.float32)
+                c, a = Sg[3, 3], Sg[:3, 3]
+                plain = (Sg[:3, :3] - np.outer(a, a) / c).astype(np.float64)
+                worst_plain = max(worst_plain, np.abs(plain - S64).max() / scale)
+    assert worst < 2e-5
+    assert worst_plain > 1e-3

@@ -17,7 +17,7 @@ def _loss_and_sig(oracle_lib, p, views, w):
     rec, rect, touched = oracle_lib.preprocess_f64(p, views)
     dbits = oracle_lib.depth_bits(rec)
     keys, vals, ranges = oracle_lib.bin_sort(rect, touched, dbits, views)
-    out = oracle_lib.render_fwd(rec, views, vals, ranges, signature=True)
+    out = oracle_lib.render_fwd(rec, views, vals, ranges, signature=True, f32=False)
     return float((w * out["image"]).sum()), out["sig"]
 
 

@@ -87,7 +87,7 @@ def test_identical_layers_stop_index(oracle_lib):
     a_center = _closed_form(p[0:3, 0], 0.5, 0.3, 0.5, 0.0, (1, 1, 1), view)[0]
     # depths differ, so the conic differs slightly per layer: use the oracle trace
     a, T, Tf = oracle_lib.trace_pixel(out["rec"].astype(np.float64), view, 0, out["vals"],
-                                      out["ranges"], 8, 8)
+                                      out["ranges"], 8, 8, f32=False)
     prod = np.cumprod(np.concatenate([[1.0], 1 - a]))
     assert np.allclose(T, prod[:-1], rtol=1e-13)
     assert np.isclose(Tf, prod[-1], rtol=1e-13)
@@ -107,7 +107,8 @@ def test_transmittance_invariants(oracle_lib):
     n_checked = 0
     for _ in range(300):
         x, y = rng.integers(0, 64, 2)
-        a, T, Tf = oracle_lib.trace_pixel(rec64, view, 0, out["vals"], out["ranges"], int(x), int(y))
+        a, T, Tf = oracle_lib.trace_pixel(rec64, view, 0, out["vals"], out["ranges"], int(x), int(y),
+                                          f32=True)
         assert Tf >= 1e-4
         if len(a) == 0:
             assert Tf == 1.0
@@ -115,7 +116,9 @@ def test_transmittance_invariants(oracle_lib):
         n_checked += 1
         assert T[0] == 1.0
         assert np.all(np.diff(np.concatenate([T, [Tf]])) <= 0)
-        assert np.all(a >= 1 / 255) and np.all(a <= 0.99)
+        # the floor is decided on the FP32 exponent (the kernel's precision):
+        # an FP64 alpha it admits lies within FP32 rounding of 1/255
+        assert np.all(a >= (1 / 255) * (1 - 1e-5)) and np.all(a <= 0.99)
         assert np.isclose((a * T).sum(), 1 - Tf, rtol=0, atol=1e-12)
         assert Tf == out["T_final"][0, y, x]
     assert n_checked > 100
@@ -123,3 +126,37 @@ def test_transmittance_invariants(oracle_lib):
     img = out["image"][0]
     assert img.min() >= 0
     assert np.all(img <= (1 - out["T_final"][0])[None] * p[17:20].max() + 1e-12)
+
+
+def test_fp32_floor_decision(oracle_lib):
+    """The alpha >= 1/255 floor taken in the kernel's precision (FP32
+    exponent against -ln(255 o_t)) agrees with the FP64 rule alpha >= 1/255
+    wherever the FP64 alpha is outside the FP32 rounding window of 1/255, and
+    disagrees only inside it."""
+    p = synth.small_set(300, seed=17, log_s_xyz=(-2.5, 0.6))
+    view = synth.front_view(48, 48, f=48.0, dist=3.0, t=0.5)
+    rec, _, touched = oracle_lib.preprocess_f32(p, view)
+    rng = np.random.default_rng(5)
+    u = 2.0 ** -24
+    agree = inside = 0
+    for g in np.nonzero(touched[0])[0]:
+        r = rec[0, g].astype(np.float64)
+        for _ in range(40):
+            # pixel centres around the footprint edge (alpha near 1/255)
+            ang = rng.uniform(0, 2 * np.pi)
+            rad = rng.uniform(0.7, 1.1)
+            px = np.floor(r[0] + rad * r[7] * np.cos(ang)) + 0.5
+            py = np.floor(r[1] + rad * r[11] * np.sin(ang)) + 0.5
+            dx, dy = px - r[0], py - r[1]
+            power = min(-0.5 * (r[2] * dx * dx + r[4] * dy * dy) - r[3] * dx * dy, 0.0)
+            S = 0.5 * (abs(r[2]) * dx * dx + abs(r[4]) * dy * dy) + abs(r[3] * dx * dy)
+            alpha = min(0.99, r[5] * np.exp(power))
+            skip32 = oracle_lib.floor_skip_f32(r, px, py)
+            window = (1e-6 + 8 * u * S) * (1 / 255)
+            if abs(alpha - 1 / 255) > window:
+                assert skip32 == int(alpha < 1 / 255), (g, px, py, alpha)
+                agree += 1
+            else:
+                inside += 1
+    assert agree > 5000
+    assert inside < 0.01 * agree

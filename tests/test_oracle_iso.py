@@ -74,7 +74,7 @@ def test_velocity_matches_rotor_form_of_same_covariance():
 def _loss_and_sig(p, vs, w):
     rec, rect, touched = oracle.preprocess_iso_f64(p, vs)
     keys, vals, ranges = oracle.bin_sort(rect, touched, oracle.depth_bits(rec), vs)
-    out = oracle.render_fwd(rec, vs, vals, ranges, signature=True)
+    out = oracle.render_fwd(rec, vs, vals, ranges, signature=True, f32=False)
     return float((w * out["image"]).sum()), out["sig"], (rec, vals, ranges)
 
 
@@ -98,7 +98,7 @@ def test_iso_backward_vs_central_differences(seed, n_views):
                    for i in range(n_views)])
     w = synth.linear_loss_weights(n_views, 40, 48, seed=seed).astype(np.float64)
     L0, sig0, (rec, vals, ranges) = _loss_and_sig(p, vs, w)
-    grec = oracle.render_bwd(rec, vs, vals, ranges, w)
+    grec = oracle.render_bwd(rec, vs, vals, ranges, w, f32=False)
     grad = oracle.preprocess_iso_bwd(p, vs, grec)
     _, _, touched = oracle.preprocess_iso_f64(p, vs)
     vis = np.nonzero(touched.sum(axis=0) > 0)[0]
