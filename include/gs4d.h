@@ -272,6 +272,54 @@ int gs4d_grid_prune(const float *xyz, const float *attr, int32_t k_attr, const u
                     uint64_t *out_key, int64_t *n_out, int32_t *status, void *ws, size_t ws_bytes,
                     void *stream);
 
+/* ---------------------------------------------------------------------------
+ * gs4d_backproject -- back projection on consistent depth (Sec. 3.2, the
+ *   back-projection equation): every pixel (x, y) whose accumulated alpha
+ *   cover[y][x] > min_cover becomes the world point
+ *     X = R^T (xc - t),  xc = ((x + 1/2 - cx) D / fx, (y + 1/2 - cy) D / fy, D),
+ *   D = depth_acc / cover (the alpha-weighted depth), with the view's
+ *   world-to-camera [R | t] and intrinsics.  Kept pixels are written in
+ *   row-major pixel order.
+ *   depth_acc, cover  float [H][W] (H, W from the view)
+ *   view      host; min_cover > 0
+ *   out_xyz   out float [3][capacity]   out_depth out float [capacity]
+ *   out_pixel out int32 [capacity]: y W + x of each kept pixel
+ *   n_out     out device int64: number of kept pixels (all of them, also past
+ *             capacity; only the first `capacity` are written)
+ *   depth_sum optional device double, accumulated (caller zeroes): the sum of
+ *             D over the kept pixels (the frame's mean depth for the adaptive
+ *             voxel edge S_v = lambda (1/N) sum_i mean(D_i) / f, Sec. 3.2)
+ *   ws >= gs4d_backproject_workspace_size(H W); H W < 2^31.
+ * ------------------------------------------------------------------------- */
+size_t gs4d_backproject_workspace_size(int64_t hw);
+int gs4d_backproject(const float *depth_acc, const float *cover, const gs4d_view *view,
+                     float min_cover, int64_t capacity, float *out_xyz, float *out_depth,
+                     int32_t *out_pixel, int64_t *n_out, double *depth_sum, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * gs4d_heuristic_init -- the initialisation of Sec. 4.1 for k pruned points
+ *   (rotor-form parameters [20][k]):
+ *     mean xyz = the voxel centroid, mean t = the mean timestamp, rgb = the
+ *     mean colour (as given);
+ *     log s_t = ln(2 / frames) for dynamic points (2 / fps with time
+ *       normalised to [0, 1]: two frame intervals) and 0 for static ones
+ *       (s_t = 1, the whole video);
+ *     log s_xyz = ln(voxel edge of the point's class); for a class that is
+ *       not pruned (edge <= 0, the Full preset's dynamic points), ln(D / f),
+ *       the footprint of one back-projected pixel at its depth D;
+ *     identity rotors; opacity 0.1 (logit ln(0.1 / 0.9)).
+ *   xyz, rgb  float [3] rows of `stride` floats (the first k used)
+ *   t         float [k]         depth float [k] (only read for an unpruned class)
+ *   dynamic   uint8 [k] (nonzero = dynamic) or NULL (all static)
+ *   focal     > 0 when a class is not pruned;  frames >= 2
+ *   params    out float [20][k]
+ * ------------------------------------------------------------------------- */
+int gs4d_heuristic_init(const float *xyz, const float *rgb, const float *t, const float *depth,
+                        const uint8_t *dynamic, int64_t k, int64_t stride, float voxel_static,
+                        float voxel_dynamic, float focal, int32_t frames, float *params,
+                        void *stream);
+
 /* ------------------------------------------------------------------------- *
  * Optimisation-loop helpers (Sec. 4.1: a single photometric loss with the
  * 3D Gaussian-splatting loss weights and optimiser, position learning rate

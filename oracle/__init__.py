@@ -38,6 +38,7 @@ _SIGS = {
     "or_covariance_f64": (_i32, [_p, _i64, _i64, _p]),
     "or_conditional_f64": (_i32, [_p, _i64, _i64, _f64, _p, _p, _p]),
     "or_conditional_f32": (_i32, [_p, _i64, _i64, _f32, _p, _p, _p]),
+    "or_conditional_cov_f64_all": (None, [_p, _i64, _f64, _p]),
     "or_bin_sort": (_i64, [_p, _p, _p, _i64, _i32, _i32, _i32, _i64, _p, _p, _p]),
     "or_floor_skip_f32": (_i32, [_p, _f64, _f64]),
     "or_doubtful_decisions": (_i64, [_p, _i64, _p, _i32, _p, _p, _p, _i64, _p]),
@@ -164,6 +165,15 @@ def conditional(params, g, t):
     ot = np.zeros(1)
     ok = lib().or_conditional_f64(_ptr(P), P.shape[1], g, float(t), _ptr(mu), _ptr(sc), _ptr(ot))
     return (mu, sc.reshape(3, 3), float(ot[0])) if ok else None
+
+
+def conditional_cov_all(params, t):
+    """FP64 conditional covariance of every Gaussian at time t: [n, 3, 3]
+    (zeros where degenerate)."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    out = np.zeros((P.shape[1], 9))
+    lib().or_conditional_cov_f64_all(_ptr(P), P.shape[1], float(t), _ptr(out))
+    return out.reshape(-1, 3, 3)
 
 
 def conditional_f32(params, g, t):

@@ -205,6 +205,19 @@ int or_conditional_f64(const double *params, int64_t n, int64_t g, double t, dou
     return 1;
 }
 
+/* The FP64 conditional covariance of every Gaussian at time t: sc9 [n][9]
+ * (row-major 3x3; zeros where degenerate). */
+void or_conditional_cov_f64_all(const double *params, int64_t n, double t, double *sc9)
+{
+    for (int64_t g = 0; g < n; ++g) {
+        double v[20], Sg[4][4], M[4][4], s[4], o, mu[3], Sc[3][3], ot;
+        for (int k = 0; k < 20; ++k) v[k] = params[(int64_t)k * n + g];
+        int ok = covariance_f64(v, Sg, M, s, &o) && conditional_f64(v, Sg, M, o, t, mu, Sc, &ot);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) sc9[9 * g + 3 * i + j] = ok ? Sc[i][j] : 0.0;
+    }
+}
+
 /* The FP32 instance's conditional (the kernel's precision and evaluation
  * order): mu[3], Sc (row-major 3x3), o_t of Gaussian g at time t.  Returns
  * 0 if degenerate. */

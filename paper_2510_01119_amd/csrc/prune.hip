@@ -1,6 +1,9 @@
-// Voxel grid pruning (Sec. 3.2 "Grid Pruning"; per-class voxel sizes of
-// the Lite/Full presets, Sec. 4.1).
+// Scene preparation: back projection on consistent depth (Sec. 3.2),
+// voxel grid pruning (Sec. 3.2 "Grid Pruning"; per-class voxel sizes of the
+// Lite/Full presets, Sec. 4.1) and the heuristic initialisation of the
+// pruned points (Sec. 4.1).
 //
+// Pruning:
 // The paper aggregates the points of each occupied voxel through a hash map.
 // Here the aggregation is sort-based, which also yields a deterministic
 // output order:
@@ -166,6 +169,75 @@ inline unsigned blocks_for(int64_t count, int threads) {
     return (unsigned)(b > 0 ? b : 1);
 }
 
+// ------------------------------------------------------------ back projection
+// X = R^T (D K^-1 (x + 1/2, y + 1/2, 1)^T - t) for the pixels whose
+// accumulated alpha exceeds min_cover, D = depth_acc / cover (the
+// alpha-weighted depth).
+__global__ void bp_keep_kernel(const float *__restrict__ cover, int64_t hw, float min_cover,
+                               int32_t *__restrict__ keep) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hw) return;
+    keep[i] = cover[i] > min_cover ? 1 : 0;
+}
+
+__global__ void bp_write_kernel(const float *__restrict__ depth_acc, const float *__restrict__ cover,
+                                const int32_t *__restrict__ keep, const int32_t *__restrict__ excl,
+                                gs4d_view V, int64_t capacity, float *__restrict__ out_xyz,
+                                float *__restrict__ out_depth, int32_t *__restrict__ out_pixel,
+                                double *__restrict__ depth_sum) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t hw = (int64_t)V.width * V.height;
+    const bool kept = i < hw && keep[i];
+    const float D = kept ? depth_acc[i] / cover[i] : 0.0f;
+    if (depth_sum) {
+        const double s = wave_sum_d((double)D);
+        if (lane_id() == 0 && s != 0.0) atomicAdd(depth_sum, s);
+    }
+    if (!kept) return;
+    const int64_t j = excl[i];
+    if (j >= capacity) return;
+    const int y = (int)(i / V.width), x = (int)(i - (int64_t)y * V.width);
+    const float c0 = (((float)x + 0.5f) - V.cx) / V.fx * D;
+    const float c1 = (((float)y + 0.5f) - V.cy) / V.fy * D;
+    const float d0 = c0 - V.Rt[3], d1 = c1 - V.Rt[7], d2 = D - V.Rt[11];
+    // R^T (xc - t): column j of R
+    for (int a = 0; a < 3; ++a)
+        out_xyz[a * capacity + j] = V.Rt[a] * d0 + V.Rt[4 + a] * d1 + V.Rt[8 + a] * d2;
+    out_depth[j] = D;
+    out_pixel[j] = (int32_t)i;
+}
+
+__global__ void bp_count_kernel(const int64_t *__restrict__ total, int64_t *__restrict__ n_out) {
+    if (threadIdx.x || blockIdx.x) return;
+    *n_out = *total;
+}
+
+// ------------------------------------------------------------ initialisation
+__global__ void init_kernel(const float *__restrict__ xyz, const float *__restrict__ rgb,
+                            const float *__restrict__ t, const float *__restrict__ depth,
+                            const uint8_t *__restrict__ dyn, int64_t k, int64_t stride,
+                            float log_vs, float log_vd, int pruned_s, int pruned_d,
+                            float inv_focal, float log_st_dynamic, float logit0,
+                            float *__restrict__ P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    const bool d = dyn && dyn[i];
+    // a class that is not pruned: the footprint of one back-projected pixel
+    const float ls = (d ? pruned_d : pruned_s) ? (d ? log_vd : log_vs) : logf(depth[i] * inv_focal);
+    for (int a = 0; a < 3; ++a) {
+        P[a * k + i] = xyz[a * stride + i];
+        P[(4 + a) * k + i] = ls;
+        P[(17 + a) * k + i] = rgb[a * stride + i];
+    }
+    P[3 * k + i] = t[i];
+    P[7 * k + i] = d ? log_st_dynamic : 0.0f;
+    for (int a = 0; a < 4; ++a) {
+        P[(8 + a) * k + i] = a == 0 ? 1.0f : 0.0f;
+        P[(12 + a) * k + i] = a == 0 ? 1.0f : 0.0f;
+    }
+    P[16 * k + i] = logit0;
+}
+
 }  // namespace
 }  // namespace gs4d
 
@@ -227,5 +299,73 @@ extern "C" int gs4d_grid_prune(const float *xyz, const float *attr, int32_t k_at
     GS4D_LAUNCH_CHECK("prune write");
     prune_status_kernel<<<1, 64, 0, st>>>(L.nkeep, capacity, n_out, status);
     GS4D_LAUNCH_CHECK("prune status");
+    return GS4D_OK;
+}
+
+extern "C" size_t gs4d_backproject_workspace_size(int64_t hw) {
+    Carve c(nullptr, ~size_t(0));
+    const size_t n = (size_t)(hw > 0 ? hw : 1);
+    c.take<int32_t>(n);
+    c.take<int32_t>(n);
+    c.take<int64_t>(1);
+    c.take<char>(scan_workspace_size(hw));
+    return c.used + 256;
+}
+
+extern "C" int gs4d_backproject(const float *depth_acc, const float *cover, const gs4d_view *view,
+                                float min_cover, int64_t capacity, float *out_xyz, float *out_depth,
+                                int32_t *out_pixel, int64_t *n_out, double *depth_sum, void *ws,
+                                size_t ws_bytes, void *stream) {
+    GS4D_REQUIRE(view, "gs4d_backproject: null view");
+    const int64_t hw = (int64_t)view->width * view->height;
+    GS4D_REQUIRE(view->width > 0 && view->height > 0 && hw < ((int64_t)1 << 31),
+                 "gs4d_backproject: bad image size %d x %d", view->width, view->height);
+    GS4D_REQUIRE(view->fx != 0.0f && view->fy != 0.0f, "gs4d_backproject: zero focal length");
+    GS4D_REQUIRE(min_cover > 0.0f, "gs4d_backproject: min_cover must be > 0");
+    GS4D_REQUIRE(capacity >= 0, "gs4d_backproject: capacity < 0");
+    GS4D_REQUIRE(depth_acc && cover && n_out, "gs4d_backproject: null input");
+    GS4D_REQUIRE(capacity == 0 || (out_xyz && out_depth && out_pixel), "gs4d_backproject: null output");
+    GS4D_REQUIRE(ws && ws_bytes >= gs4d_backproject_workspace_size(hw),
+                 "gs4d_backproject: workspace too small");
+    hipStream_t st = as_stream(stream);
+    Carve c(ws, ws_bytes);
+    int32_t *keep = c.take<int32_t>((size_t)hw);
+    int32_t *excl = c.take<int32_t>((size_t)hw);
+    int64_t *total = c.take<int64_t>(1);
+    void *scan_ws = c.take<char>(scan_workspace_size(hw));
+    bp_keep_kernel<<<blocks_for(hw, 256), 256, 0, st>>>(cover, hw, min_cover, keep);
+    GS4D_LAUNCH_CHECK("backproject keep");
+    GS4D_TRY(exclusive_scan_i32(keep, excl, hw, total, scan_ws, st));
+    bp_write_kernel<<<blocks_for(hw, 256), 256, 0, st>>>(depth_acc, cover, keep, excl, *view,
+                                                         capacity, out_xyz, out_depth, out_pixel,
+                                                         depth_sum);
+    GS4D_LAUNCH_CHECK("backproject write");
+    bp_count_kernel<<<1, 64, 0, st>>>(total, n_out);
+    GS4D_LAUNCH_CHECK("backproject count");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_heuristic_init(const float *xyz, const float *rgb, const float *t,
+                                   const float *depth, const uint8_t *dynamic, int64_t k,
+                                   int64_t stride, float voxel_static, float voxel_dynamic,
+                                   float focal, int32_t frames, float *params, void *stream) {
+    GS4D_REQUIRE(k >= 0 && k < ((int64_t)1 << 31), "gs4d_heuristic_init: k out of range");
+    GS4D_REQUIRE(stride >= k, "gs4d_heuristic_init: stride < k");
+    GS4D_REQUIRE(frames >= 2, "gs4d_heuristic_init: frames must be >= 2");
+    if (k == 0) return GS4D_OK;
+    GS4D_REQUIRE(xyz && rgb && t && params, "gs4d_heuristic_init: null pointer");
+    const bool unpruned = !(voxel_static > 0.0f) || (dynamic && !(voxel_dynamic > 0.0f));
+    GS4D_REQUIRE(!unpruned || (depth && focal > 0.0f),
+                 "gs4d_heuristic_init: a class that is not pruned needs depth and focal > 0");
+    const int ps = voxel_static > 0.0f, pd = voxel_dynamic > 0.0f;
+    const float log_vs = ps ? logf(voxel_static) : 0.0f;
+    const float log_vd = pd ? logf(voxel_dynamic) : 0.0f;
+    const float inv_focal = focal > 0.0f ? 1.0f / focal : 0.0f;
+    const float log_st_dynamic = logf(2.0f / (float)frames);
+    const float logit0 = logf(0.1f / 0.9f);
+    init_kernel<<<blocks_for(k, 256), 256, 0, as_stream(stream)>>>(
+        xyz, rgb, t, depth, dynamic, k, stride, log_vs, log_vd, ps, pd, inv_focal, log_st_dynamic,
+        logit0, params);
+    GS4D_LAUNCH_CHECK("gs4d_heuristic_init");
     return GS4D_OK;
 }

@@ -79,6 +79,9 @@ _SIGS = {
     "gs4d_grid_prune_workspace_size": (_sz, [_i64, _i32]),
     "gs4d_grid_prune": (_i32, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p, _p,
                                _p, _p, _sz, _p]),
+    "gs4d_backproject_workspace_size": (_sz, [_i64]),
+    "gs4d_backproject": (_i32, [_p, _p, _p, _f32, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "gs4d_heuristic_init": (_i32, [_p, _p, _p, _p, _p, _i64, _i64, _f32, _f32, _f32, _i32, _p, _p]),
     "gs4d_adam_step": (_i32, [_p, _p, _p, _p, _i64, _p, _p, _p]),
     "gs4d_loss_l1": (_i32, [_p, _p, _i64, _f32, _p, _p, _p]),
     "gs4d_ssim_workspace_size": (_sz, [_i32, _i32, _i32, _i32]),
@@ -142,6 +145,16 @@ def _ptr(t):
             raise GS4DError("expected a contiguous tensor")
         return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
     return t
+
+
+def _ptr_rows(t, rows):
+    """Device pointer of `rows` rows of one common stride, each row
+    contiguous (a [rows, k] slice of a wider buffer)."""
+    if t.numel() > 0 and not t.is_cuda:
+        raise GS4DError("expected a device tensor")
+    if t.dim() != 2 or t.shape[0] != rows or t.stride(1) != 1:
+        raise GS4DError(f"expected [{rows}, k] rows, each contiguous")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
 
 
 def _stream(stream):
@@ -294,6 +307,33 @@ def gs4d_grid_prune(xyz, attr, cls, voxel_static, voxel_dynamic, min_count, capa
                                  _ptr(out_attr), _ptr(out_count), _ptr(out_key), _ptr(n_out),
                                  _ptr(status), _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream(stream)), "gs4d_grid_prune")
+
+
+def gs4d_backproject_workspace_size(hw):
+    return int(lib().gs4d_backproject_workspace_size(hw))
+
+
+def gs4d_backproject(depth_acc, cover, view, min_cover, capacity, out_xyz, out_depth, out_pixel,
+                     n_out, ws, depth_sum=None, stream=None):
+    """view: a gs4d_view struct (make_views(...)[0]) or a numpy view row."""
+    v = view if isinstance(view, gs4d_view) else make_views(np.atleast_2d(view))[0]
+    _check(lib().gs4d_backproject(_ptr(depth_acc), _ptr(cover), ctypes.byref(v), float(min_cover),
+                                  int(capacity), _ptr(out_xyz), _ptr(out_depth), _ptr(out_pixel),
+                                  _ptr(n_out), _ptr(depth_sum), _ptr(ws), ws.numel() * ws.element_size(),
+                                  _stream(stream)), "gs4d_backproject")
+
+
+def gs4d_heuristic_init(xyz, rgb, t, depth, dynamic, k, voxel_static, voxel_dynamic, focal, frames,
+                        params, stream=None):
+    """xyz, rgb: [3, stride] row blocks (the first k columns used)."""
+    stride = int(xyz.stride(0))
+    if rgb.stride(0) != stride:
+        raise GS4DError("gs4d_heuristic_init: xyz and rgb rows must share one stride")
+    _check(lib().gs4d_heuristic_init(_ptr_rows(xyz, 3), _ptr_rows(rgb, 3), _ptr(t), _ptr(depth),
+                                     _ptr(dynamic), int(k),
+                                     stride, float(voxel_static), float(voxel_dynamic), float(focal),
+                                     int(frames), _ptr(params), _stream(stream)),
+           "gs4d_heuristic_init")
 
 
 def gs4d_adam_step(params, grads, m, v, cfg, step, stream=None):

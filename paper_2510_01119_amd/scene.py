@@ -13,8 +13,9 @@ recovery are not available here).  Recipe:
   with the colour channels replaced by (camera depth, 1, dynamic flag)
   gives the alpha-weighted depth, the coverage and a ground-truth motion
   mask;
-* every pixel with coverage > 0.5 is back-projected to a world point with
-  its colour, timestamp and motion class (Sec. 3.2, back projection), plus
+* every pixel with coverage > 0.5 is back-projected (gs4d_backproject) to a
+  world point with its colour, timestamp and motion class (Sec. 3.2, back
+  projection), plus
   its depth, optical-flow magnitude and scene flow (further passes render
   each ground-truth Gaussian's pixel and world displacement to the next
   frame), the inputs of the learned initialisation;
@@ -23,15 +24,15 @@ recovery are not available here).  Recipe:
   map (here the ground-truth dynamic fraction averaged over 8x8 pixels plus
   seeded noise, standing in for the SLAM's H/8 x W/8 map), bilinearly
   upsampled and split by Otsu's threshold (gs4d_otsu_mask);
-* the voxel edge is fixed, or (voxel = "adaptive") S_v = lambda (1/N) sum
-  D_i / f over the back-projected pixels (Sec. 3.2), with one lambda for
-  static and one for dynamic points;
+* the voxel edge is fixed, or (voxel = "adaptive") S_v = lambda (1/N) sum_i
+  D_i / f with D_i the mean back-projected depth of frame i (Sec. 3.2), one
+  lambda for static and one for dynamic points;
 * gs4d_grid_prune merges the points per voxel (Sec. 3.2, grid pruning);
-* the heuristic initialisation (Sec. 4.1): centroid position, mean
-  timestamp and colour, temporal scale 2 / frames for dynamic points (two
-  frame intervals, i.e. 2 / fps with time normalised to [0, 1]) and the
-  whole video (1.0) for static ones, spatial scale = the voxel edge,
-  opacity 0.1, identity rotors.
+* the heuristic initialisation (Sec. 4.1, gs4d_heuristic_init): centroid
+  position, mean timestamp and colour, temporal scale 2 / frames for
+  dynamic points (two frame intervals, i.e. 2 / fps with time normalised to
+  [0, 1]) and the whole video (1.0) for static ones, spatial scale = the
+  voxel edge, opacity 0.1, identity rotors.
 """
 from __future__ import annotations
 
@@ -210,13 +211,14 @@ class Scene:
         """Renders every frame; returns (images [F,3,H,W] on device, point
         cloud (xyz [3,M], attr [9,M] = rgb, t, depth, optical-flow
         magnitude, scene flow xyz; cls [M]) on device).  Also records
-        self.depth_over_f (the mean of D / f over the back-projected pixels)
+        self.depth_over_f (the mean over frames of each frame's mean
+        back-projected depth, over the focal length: S_v's scene scale)
         and, with motion="otsu", self.mask_iou (mean over frames of the
         Otsu mask's intersection over union with the ground-truth mask, on
         the back-projected pixels)."""
         import torch.nn.functional as F
         dev = self.device
-        d_over_f, n_back, ious = 0.0, 0, []
+        n_back, ious = 0, []
         if motion == "otsu":
             otsu_ws = torch.zeros(G.gs4d_otsu_workspace_size(), dtype=torch.uint8, device=dev)
             otsu_mask = torch.zeros(self.H * self.W, dtype=torch.uint8, device=dev)
@@ -224,12 +226,19 @@ class Scene:
             gen.manual_seed(1000 + self.seed)
         n = self.static.shape[1] + self.obj_local.shape[1]
         r = Rasterizer(n, self.cams[0], device=dev, pair_capacity=1 << 24)
+        # back projection (gs4d_backproject): at most every pixel of a frame
+        hw = self.H * self.W
+        bp_xyz = torch.empty((3, hw), device=dev)
+        bp_depth = torch.empty(hw, device=dev)
+        bp_pix = torch.empty(hw, dtype=torch.int32, device=dev)
+        bp_n = torch.zeros(1, dtype=torch.int64, device=dev)
+        bp_sum = torch.zeros(1, dtype=torch.float64, device=dev)
+        bp_ws = torch.empty(G.gs4d_backproject_workspace_size(hw), dtype=torch.uint8, device=dev)
+        mean_depth = []
         dyn_flag = torch.zeros(n, device=dev)
         dyn_flag[self.static.shape[1]:] = 1.0
         images = torch.empty((self.frames, 3, self.H, self.W), device=dev)
         pts, attrs, clss = [], [], []
-        ys, xs = torch.meshgrid(torch.arange(self.H, device=dev, dtype=torch.float32),
-                                torch.arange(self.W, device=dev, dtype=torch.float32), indexing="ij")
         for f in range(self.frames):
             view = self.cams[f]
             r.set_views(view)
@@ -243,9 +252,17 @@ class Scene:
             rec[:, 10] = dyn_flag
             r.render()
             aux = r.image[0].clone()
-            cov = aux[1]
-            keep = cov > 0.5
-            depth = aux[0][keep] / cov[keep]
+            cov2 = aux[1]
+            cov = cov2.reshape(-1)
+            # back projection of the pixels with coverage > 0.5 (Sec. 3.2)
+            G.gs4d_fill_f32(bp_sum.view(torch.float32), 0.0)
+            G.gs4d_backproject(aux[0], aux[1], view, 0.5, hw, bp_xyz, bp_depth, bp_pix, bp_n, bp_ws,
+                               depth_sum=bp_sum)
+            m = int(bp_n.item())
+            pix = bp_pix[:m].long()
+            depth = bp_depth[:m]
+            world = bp_xyz[:, :m].clone()
+            mean_depth.append(float(bp_sum.item()) / max(m, 1))
             # third and fourth passes: optical-flow magnitude (pixels per frame)
             # and scene flow (world units per frame) as colours
             fmag, sflow = self._flow(f)
@@ -253,29 +270,24 @@ class Scene:
             rec[:, 9] = sflow[0]
             rec[:, 10] = sflow[1]
             r.render()
-            flow = r.image[0][:, keep] / cov[keep]
+            flow = r.image[0].reshape(3, -1)[:, pix] / cov[pix]
             rec[:, 8] = sflow[2]
             r.render()
-            sfz = r.image[0][0][keep] / cov[keep]
-            Rt = torch.from_numpy(view[:12].reshape(3, 4)).to(dev).float()
-            xc = torch.stack([(xs[keep] + 0.5 - float(view[14])) / float(view[12]) * depth,
-                              (ys[keep] + 0.5 - float(view[15])) / float(view[13]) * depth, depth])
-            world = Rt[:, :3].T @ (xc - Rt[:, 3:4])
+            sfz = r.image[0][0].reshape(-1)[pix] / cov[pix]
             pts.append(world)
-            col = images[f][:, keep]
-            attrs.append(torch.cat([col, torch.full((1, col.shape[1]), float(view[18]), device=dev),
+            col = images[f].reshape(3, -1)[:, pix]
+            attrs.append(torch.cat([col, torch.full((1, m), float(view[18]), device=dev),
                                     depth[None], flow, sfz[None]]))
-            d_over_f += float((depth / float(view[12])).sum().item())
-            n_back += int(depth.numel())
-            gt_dyn = aux[2][keep] / cov[keep] > 0.5
+            n_back += m
+            gt_dyn = aux[2].reshape(-1)[pix] / cov[pix] > 0.5
             if motion == "otsu":
-                frac = torch.where(cov > 0, aux[2] / cov.clamp_min(1e-6), torch.zeros_like(cov))
+                frac = torch.where(cov2 > 0, aux[2] / cov2.clamp_min(1e-6), torch.zeros_like(cov2))
                 low = F.avg_pool2d(frac[None, None], 8, ceil_mode=True)
                 low = (low + motion_noise * torch.randn(low.shape, generator=gen, device=dev))
                 prob = F.interpolate(low.clamp(0.0, 1.0), size=(self.H, self.W), mode="bilinear",
                                      align_corners=False)[0, 0].contiguous()
                 G.gs4d_otsu_mask(prob, None, otsu_mask, otsu_ws)
-                dyn = otsu_mask.view(self.H, self.W)[keep].bool()
+                dyn = otsu_mask[pix].bool()
                 inter = float((dyn & gt_dyn).sum().item())
                 union = float((dyn | gt_dyn).sum().item())
                 ious.append(inter / union if union > 0 else 1.0)
@@ -287,7 +299,9 @@ class Scene:
         xyz = torch.cat(pts, dim=1).contiguous()
         attr = torch.cat(attrs, dim=1).contiguous()
         cls = torch.cat(clss).contiguous()
-        self.depth_over_f = d_over_f / max(n_back, 1)
+        # S_v's scene scale (Sec. 3.2): the mean over frames of each frame's
+        # mean depth, over the focal length
+        self.depth_over_f = float(np.mean(mean_depth)) / self.f if mean_depth else 0.0
         self.mask_iou = float(np.mean(ious)) if ious else None
         return images, (xyz, attr, cls)
 
@@ -315,21 +329,18 @@ class Scene:
         return out_xyz[:, :k], out_attr[:, :k], dyn, out_count[:k]
 
     def heuristic_init(self, pruned, voxel=0.01, voxel_dynamic=None):
+        """Sec. 4.1's initialisation of the pruned points (gs4d_heuristic_init):
+        centroid, mean timestamp and colour; s_t = 2 / frames for dynamic and
+        1 for static points; s_xyz = the class's voxel edge (the footprint of
+        one pixel at its depth for a class that is not pruned); identity
+        rotors; opacity 0.1."""
         xyz, attr, dyn, _ = pruned
         k = xyz.shape[1]
         vd = voxel if voxel_dynamic is None else voxel_dynamic
-        p = torch.zeros((20, k), device=self.device)
-        p[0:3] = xyz
-        p[3] = attr[3]
-        p[4:7] = torch.where(dyn, torch.full_like(attr[3], math.log(vd)),
-                             torch.full_like(attr[3], math.log(voxel)))
-        p[7] = torch.where(dyn, torch.full_like(attr[3], math.log(2.0 / self.frames)),
-                           torch.zeros_like(attr[3]))
-        p[8] = 1.0
-        p[12] = 1.0
-        p[16] = math.log(0.1 / 0.9)
-        p[17:20] = attr[0:3]
-        return p.contiguous()
+        p = torch.empty((20, k), device=self.device)
+        G.gs4d_heuristic_init(xyz, attr[0:3], attr[3], attr[4], dyn.to(torch.uint8), k, voxel, vd,
+                              self.f, self.frames, p)
+        return p
 
 
 def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel=0.01,

@@ -116,9 +116,9 @@ def test_crop_gradients(scale, crop_ref):
     # this crop composites ~35,000 entries per tile.  Behind alphas near
     # 0.99 the FP32 transmittance carries ~1e-4 relative error, which a
     # gradient summed with cancelling signs over hundreds of pixels can lift
-    # past 1e-3: at most 0.1% of the entries may exceed the bar, none by
+    # past 1e-3: at most 0.02% of the entries may exceed the bar, none by
     # more than 10x (counted and printed)
-    check_gradients("1M crop", d, ref, c["grad_b"], max_outliers=1e-3)
+    check_gradients("1M crop", d, ref, c["grad_b"], max_outliers=2e-4)
 
 
 def test_central_differences(scale, crop_ref):

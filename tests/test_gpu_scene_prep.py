@@ -1,9 +1,9 @@
 """Upstream of pruning, the paper's way (Sec. 3.2), on a small synthetic
 scene: the Otsu split of the (noisy, 8x8-averaged, upsampled) motion
 probability map recovers the ground-truth motion mask (mean IoU >= 0.75 over
-frames), the recorded mean D / f equals the mean depth of the back-projected
-points over the focal length, and the adaptive voxel edges lambda mean(D / f)
-prune the cloud."""
+frames), the recorded scene scale equals the mean over frames of each
+frame's mean back-projected depth over the focal length, and the adaptive
+voxel edges lambda (1/N) sum_i mean(D_i) / f prune the cloud."""
 import numpy as np
 import pytest
 import torch
@@ -21,7 +21,8 @@ def test_otsu_mask_and_adaptive_voxel():
     images, cloud = sc.render_ground_truth(motion="otsu")
     xyz, attr, cls = cloud
     assert sc.mask_iou is not None and sc.mask_iou >= 0.75, sc.mask_iou
-    ref = float(attr[4].double().mean().item()) / 400.0
+    t, d = attr[3].double().cpu().numpy(), attr[4].double().cpu().numpy()
+    ref = float(np.mean([d[t == u].mean() for u in np.unique(t)])) / 400.0
     assert abs(sc.depth_over_f - ref) <= 1e-5 * ref
     assert 0 < int(cls.sum().item()) < cls.numel()
     vs, vd = 4.0 * sc.depth_over_f, 4.0 * sc.depth_over_f
