@@ -133,6 +133,24 @@ int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_t *touched,
                   uint32_t *vals, int32_t *ranges, int64_t *n_pairs, int32_t *overflow, void *ws,
                   size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * gs4d_bin_sort_noalloc -- gs4d_bin_sort for callers that cannot allocate
+ *   (code under HIP graph capture, serving loops, harnesses that forbid
+ *   hipMalloc): the same arguments without the workspace, the same output
+ *   bit for bit.  Its scratch memory is a device array of the library of
+ *   GS4D_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, so the
+ *   call allocates nothing.  A call whose gs4d_bin_sort_workspace_size(n,
+ *   n_views, pair_capacity) exceeds that returns GS4D_ERR_INVALID_ARG without
+ *   launching anything.  The scratch is per device (the current one, which
+ *   must own `stream`): calls that overlap on one GPU race and must be
+ *   ordered by the caller (one stream, or events).
+ * ------------------------------------------------------------------------- */
+#define GS4D_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gs4d_bin_sort_noalloc(const float *rec, const int32_t *rect, const int32_t *touched, int64_t n,
+                          const gs4d_view *views, int32_t n_views, int64_t pair_capacity,
+                          uint64_t *keys, uint32_t *vals, int32_t *ranges, int64_t *n_pairs,
+                          int32_t *overflow, void *stream);
+
 /* Binning strategy of gs4d_bin_sort (process-wide; the output is the same):
  *   GS4D_BIN_PER_TILE  emit pairs in item order, sort on the tile bits, then
  *                      one workgroup per tile sorts its pairs by depth in LDS

@@ -26,6 +26,8 @@
 // regroups them by digit in LDS and writes each digit run contiguously.
 #include "common.hpp"
 
+#include <mutex>
+
 namespace gs4d {
 namespace {
 
@@ -1259,4 +1261,65 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
         GS4D_LAUNCH_CHECK("tile depth sort");
     }
     return GS4D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// gs4d_bin_sort_noalloc: the same binning for callers that cannot allocate
+// (graph capture, serving loops): its scratch memory is this fixed device
+// array of the library, one per GPU, held until the process ends.  On the
+// host the array's name is only a stand-in, never a device address: its
+// address on each device is looked up once with hipGetSymbolAddress (with
+// that device current) and kept; only that pointer is passed to kernels.
+// Calls that overlap on one GPU share the array and race; the binning
+// writes every scratch word it reads, so a call needs nothing cleared.
+static __device__ __align__(256) char scratch[GS4D_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int scratch_for_current_device(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        gs4d::set_error("gs4d_bin_sort_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+        return GS4D_ERR_HIP;
+    }
+    GS4D_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, "gs4d_bin_sort_noalloc: device %d out of range",
+                 dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            gs4d::set_error("gs4d_bin_sort_noalloc: hipGetSymbolAddress(scratch): %s",
+                            hipGetErrorString(e));
+            return GS4D_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GS4D_OK;
+}
+}  // namespace
+
+extern "C" int gs4d_bin_sort_noalloc(const float *rec, const int32_t *rect, const int32_t *touched,
+                                     int64_t n, const gs4d_view *views, int32_t n_views,
+                                     int64_t pair_capacity, uint64_t *keys, uint32_t *vals,
+                                     int32_t *ranges, int64_t *n_pairs, int32_t *overflow,
+                                     void *stream) {
+    GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "gs4d_bin_sort_noalloc: n out of range");
+    GS4D_REQUIRE(n_views >= 1 && n_views <= GS4D_MAX_VIEWS, "gs4d_bin_sort_noalloc: n_views out of range");
+    GS4D_REQUIRE(pair_capacity >= 0 && pair_capacity < ((int64_t)1 << 31),
+                 "gs4d_bin_sort_noalloc: pair_capacity out of range");
+    const size_t need = gs4d_bin_sort_workspace_size(n, n_views, pair_capacity);
+    GS4D_REQUIRE(need <= GS4D_NOALLOC_SCRATCH_BYTES,
+                 "gs4d_bin_sort_noalloc: this call needs %zu bytes of scratch, the library holds %zu "
+                 "(use gs4d_bin_sort with a workspace)",
+                 need, (size_t)GS4D_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    GS4D_TRY(scratch_for_current_device(&ws));
+    return gs4d_bin_sort(rec, rect, touched, n, views, n_views, pair_capacity, keys, vals, ranges,
+                         n_pairs, overflow, ws, GS4D_NOALLOC_SCRATCH_BYTES, stream);
 }

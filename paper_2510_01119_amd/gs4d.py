@@ -62,6 +62,7 @@ _SIGS = {
     "gs4d_preprocess": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "gs4d_bin_sort_workspace_size": (_sz, [_i64, _i32, _i64]),
     "gs4d_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _i32, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "gs4d_bin_sort_noalloc": (_i32, [_p, _p, _p, _i64, _p, _i32, _i64, _p, _p, _p, _p, _p, _p]),
     "gs4d_render_fwd": (_i32, [_p, _i64, _p, _p, _p, _i32, _p, _p, _p, _p, _p]),
     "gs4d_render_bwd_workspace_size": (_sz, [_i64, _i32]),
     "gs4d_render_bwd": (_i32, [_p, _i64, _p, _p, _p, _p, _p, _i32, _p, _p, _p, _p, _p, _p, _p, _sz,
@@ -200,6 +201,16 @@ def gs4d_bin_sort(rec, rect, touched, n, views, pair_capacity, keys, vals, range
                                _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(n_pairs), _ptr(overflow),
                                _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
            "gs4d_bin_sort")
+
+
+def gs4d_bin_sort_noalloc(rec, rect, touched, n, views, pair_capacity, keys, vals, ranges, n_pairs,
+                          overflow, stream=None):
+    """gs4d_bin_sort with the library's own scratch memory (no workspace)."""
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_bin_sort_noalloc(_ptr(rec), _ptr(rect), _ptr(touched), n, va, len(va),
+                                       pair_capacity, _ptr(keys), _ptr(vals), _ptr(ranges),
+                                       _ptr(n_pairs), _ptr(overflow), _stream(stream)),
+           "gs4d_bin_sort_noalloc")
 
 
 def gs4d_render_fwd(rec, n, vals, ranges, views, image, T_final, last, opts=None, stream=None):
