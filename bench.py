@@ -36,8 +36,57 @@ HBM_PEAK_GBS = 8000.0
 EVENT_EVERY = 4
 # FP32 vector peak without packed FP32 (the library is built with packed FP32
 # disabled): 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6
-# TFLOP/s (packed FP32 would double it to 157.3)
+# TFLOP/s; the published figure counts packed FP32: 157.3 TFLOP/s
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+ALU_PEAK_PUBLISHED_TFLOPS = 157.3
+# Algorithmic FP32 flops of compositing (FMA = 2; exp and division 1 each).
+# Per evaluated (pixel, entry): offset (2), quadratic form (9), exp and the
+# product with o_t (2).  Per forward blend: 1 - alpha and the transmittance
+# product (2), alpha T and the three colour FMAs (7).  Per backward blend:
+# transmittance recovery (2), colour gradients (7), dC/dalpha (9), colour
+# behind (6), opacity (2), exponent gradient (1), conic (11), mean (10).
+FLOPS_EVAL = 13
+FLOPS_BLEND_FWD = 9
+FLOPS_BLEND_BWD = 48
+
+
+class ProfileRegion:
+    """roctxProfilerResume(0) / roctxProfilerPause(0) around a timed region:
+    under `rocprofv3 --selected-regions` only what runs inside is collected,
+    so a profile covers exactly the launches a bench line times.  Without a
+    profiler (or the ROCTx library) both calls do nothing."""
+
+    def __init__(self, active):
+        self.lib = None
+        if active:
+            import ctypes
+            for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+                try:
+                    self.lib = ctypes.CDLL(name)
+                    break
+                except OSError:
+                    continue
+            if self.lib is not None:
+                self.lib.roctxProfilerResume.argtypes = [ctypes.c_uint64]
+                self.lib.roctxProfilerPause.argtypes = [ctypes.c_uint64]
+                self.lib.roctxProfilerResume.restype = ctypes.c_int
+                self.lib.roctxProfilerPause.restype = ctypes.c_int
+            else:
+                log("bench: ROCTx library not found; profiling regions are not marked")
+
+    def __enter__(self):
+        if self.lib is not None:
+            rc = self.lib.roctxProfilerResume(0)
+            if rc:
+                log(f"bench: roctxProfilerResume returned {rc}")
+        return self
+
+    def __exit__(self, *exc):
+        if self.lib is not None:
+            rc = self.lib.roctxProfilerPause(0)
+            if rc:
+                log(f"bench: roctxProfilerPause returned {rc}")
+        return False
 
 
 def log(msg):
@@ -87,30 +136,50 @@ def _build_workload(name, device):
     return params, sc.cams, images, info, pruned[:3]
 
 
-def cpu_baseline(params_np, views, target_np, budget_s=30.0):
+def host_cores():
+    """(cores this process may use, capped at 16 -- the host share of one
+    GPU --, nproc, CPU model)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(usable, 16), os.cpu_count(), model
+
+
+def cpu_baseline(params_np, views, targets_np, budget_s=20.0):
     """The oracle's training step (FP32-decided preprocess, FP64 compositing
-    and backward, numpy loss and Adam), timed on one host thread."""
-    import oracle
-    from oracle import adam as oadam
-    from oracle import losses as olosses
-    t0 = time.perf_counter()
+    and chain rule, numpy loss and Adam), as it stands: one single-threaded
+    oracle process per usable host core, each repeating steps on its own
+    frame for budget_s seconds; the rate is the sum of their steps over the
+    wall time."""
+    import subprocess
+    import tempfile
+    cores, nproc, model = host_cores()
+    with tempfile.TemporaryDirectory(prefix="gs4d_cpu_") as d:
+        np.save(os.path.join(d, "params.npy"), params_np.astype(np.float32))
+        np.save(os.path.join(d, "views.npy"), np.asarray(views, np.float64))
+        np.save(os.path.join(d, "targets.npy"), np.asarray(targets_np, np.float64))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        t0 = time.perf_counter()
+        procs = [subprocess.Popen([sys.executable, "-m", "oracle.bench_worker", d, str(i),
+                                   str(budget_s)], cwd=ROOT, env=env, stdout=subprocess.PIPE,
+                                  stderr=subprocess.PIPE, text=True) for i in range(cores)]
+        outs = [p.communicate() for p in procs]
+        wall = time.perf_counter() - t0
     steps = 0
-    p = params_np.astype(np.float64)
-    m = np.zeros_like(p)
-    v = np.zeros_like(p)
-    while True:
-        view = views[steps % len(views)]
-        fwd = oracle.forward(p.astype(np.float32), view, "f32")
-        img = fwd["image"][0]
-        _, g = olosses.scene_loss(img, target_np[steps % len(views)])
-        d, _ = oracle.backward(p.astype(np.float32), view, g[None], fwd=fwd)
-        p, m, v = oadam.adam_step(p, d, m, v, steps + 1, [1e-5] * 4 + [5e-3] * 4 + [1e-3] * 8
-                                  + [5e-2] + [2.5e-3] * 3)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 3:
-            break
-    dt = time.perf_counter() - t0
-    return steps / dt, steps, dt
+    for p, (out, err) in zip(procs, outs):
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed: {err[-500:]}")
+        steps += json.loads(out.strip().splitlines()[-1])["steps"]
+    return steps / wall, steps, wall, cores, nproc, model
 
 
 def main():
@@ -120,6 +189,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="scene", choices=["scene", "small", "batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 8-view batched leg (500k Gaussians, 960x540)")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR leg")
     ap.add_argument("--no-fps", action="store_true",
                     help="skip the forward-only frame-rate leg at display sizes")
@@ -130,7 +201,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters); it "
+                         "runs inside the profiled region")
+    ap.add_argument("--profile-region", default="scene", choices=["scene", "batched", "none"],
+                    help="the timed region bracketed for rocprofv3 --selected-regions")
     ap.add_argument("--scene-cache", default=None,
                     help="save/load the synthesised scene here (e.g. /tmp/gs4d_scene.pt)")
     args = ap.parse_args()
@@ -146,18 +220,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     G.lib()
     dev = torch.device("cuda:0")
-    if args.calib_copy:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per byte
-        # calibrates the counters read for the gs4d kernels
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("bench: calibration copy 256 MiB x 2 done")
     if args.workload == "batched":
-        return run_batched(args, dev)
+        out = run_batched(args, dev, ProfileRegion(args.profile_region == "batched"))
+        print(json.dumps(out), flush=True)
+        return
     log(f"bench: building workload {args.workload}")
     params, views, images, info, pruned = build_workload(args.workload, dev, args.scene_cache)
     n = params.shape[1]
@@ -185,10 +251,11 @@ def main():
 
     # ---- timed region: exactly `steps` training steps --------------------
     # Graph mode: each frame's step was captured as one HIP graph and again
-    # as three ([forward + loss], [render backward], [preprocess backward +
-    # Adam]).  Every EVENT_EVERY-th step replays the three, with HIP events on
-    # the launch stream bracketing the render backward; the others replay the
-    # single graph.
+    # as three ([forward + loss + clearing the 2D-gradient accumulator],
+    # [render backward kernel], [preprocess backward + Adam]).  Every
+    # EVENT_EVERY-th step replays the three, with HIP events on the launch
+    # stream bracketing the render backward; the others replay the single
+    # graph.
     use_graph = not args.eager
     if use_graph:
         t_cap = time.perf_counter()
@@ -200,31 +267,49 @@ def main():
             tr.step_graph(int(seq[i]), events=(torch.cuda.Event(enable_timing=True),
                                                torch.cuda.Event(enable_timing=True)))
     bwd_ev = []
+    region = ProfileRegion(args.profile_region == "scene")
+    if args.calib_copy:
+        # a plain copy of known size inside the profiled region: its
+        # FETCH_SIZE / WRITE_SIZE per byte calibrates the counters read for
+        # the gs4d kernels
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        with region:
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        del src, dst
+        log("bench: calibration copy 256 MiB done")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        f = int(seq[args.warmup + i])
-        if use_graph and i % EVENT_EVERY:
-            tr.step_graph(f)
-            continue
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        if use_graph:
-            tr.step_graph(f, events=(a, b))
-        else:
-            tr.stage_forward(f)
-            a.record()
-            tr.stage_render_bwd(f)
-            b.record()
-            tr.stage_update(f)
-        bwd_ev.append((a, b))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with region:
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            f = int(seq[args.warmup + i])
+            if use_graph and i % EVENT_EVERY:
+                tr.step_graph(f)
+                continue
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            if use_graph:
+                tr.step_graph(f, events=(a, b))
+            else:
+                tr.stage_forward(f)
+                a.record()
+                tr.stage_render_bwd(f)
+                b.record()
+                tr.stage_update(f)
+            bwd_ev.append((a, b))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     if int(tr.overflow_seen.item()) != 0:
         raise RuntimeError("pair capacity overflowed during the timed region")
     elapsed = t1 - t0
     its = args.steps / elapsed
     bwd_ms_timed = float(np.mean([x.elapsed_time(y) for x, y in bwd_ev]))
+    # blends per step in the state of the timed region: the forward counters
+    # over its first (up to) 50 frames, untimed
+    counts = count_blends(r, tr.params, [tr.cviews[int(f)] for f in seq[args.warmup:]][:50])
+    pairs_per_step = counts.pop("pairs")
 
     # ---- per-stage breakdown: eager replay of the same frames with events --
     ev = {s_: [] for s_ in stages}
@@ -241,9 +326,9 @@ def main():
         mark("preprocess", lambda: r.preprocess(tr.params))
         mark("bin_sort", lambda: r.bin_sort(check=False))
         mark("render_fwd", lambda: r.render())
-
         mark("loss", lambda: G.gs4d_photometric_loss(r.image, tr.targets[f:f + 1], 1.0, tr.ssim_w,
                                                      tr.loss, tr.dimg, tr.ssim_ws))
+        r.zero_grad2d()
         mark("render_bwd", lambda: tr.stage_render_bwd(f))
         mark("preprocess_bwd", lambda: G.gs4d_preprocess_bwd(tr.params, r.touched, r.grad2d,
                                                              tr.cviews[f], r.dparams))
@@ -257,33 +342,17 @@ def main():
     log(f"bench: {its:.1f} it/s ({'graph' if use_graph else 'eager'}); render_bwd timed "
         f"{bwd_ms_timed:.4f} ms; eager stage ms {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
 
-    # blends per step over the same frame sequence (untimed, counters on)
-    r.counters = torch.zeros(2, dtype=torch.int64, device=dev)
-    evals = blends = 0
-    pairs = []
-    for i in range(min(args.steps, 50)):
-        f = int(seq[args.warmup + i])
-        r.set_views(tr.cviews[f])
-        r.preprocess(tr.params)
-        r.bin_sort(check=False)
-        r.render()
-        c = r.counters.cpu().numpy()
-        evals += int(c[0])
-        blends += int(c[1])
-        pairs.append(int(r.n_pairs.item()))
-    k = min(args.steps, 50)
-    blends_per_step, evals_per_step = blends / k, evals / k
-    pairs_per_step = float(np.mean(pairs))
-    r.counters = None
-
     # roofline of the dominant kernel
     dominant = max(stage_ms, key=stage_ms.get)
     HW = info["width"] * info["height"]
     dom_ms = bwd_ms_timed if dominant == "render_bwd" else stage_ms[dominant]
-    roof = roofline_for(dominant, dom_ms, n, pairs_per_step, evals_per_step, blends_per_step, HW)
+    roof = roofline_for(dominant, dom_ms, n, pairs_per_step, counts, HW)
     roof["ms_per_launch"] = round(dom_ms, 4)
-    roof["timing"] = (f"HIP events around every {EVENT_EVERY}th launch in the timed region"
+    roof["timing"] = (f"HIP events around every {EVENT_EVERY}th launch in the timed region (the "
+                      f"render backward kernel alone)"
                       if dominant == "render_bwd" else "HIP events, eager replay of the timed frames")
+    roof["units"] = (f"{FLOPS_EVAL} flops per evaluated (pixel, entry) + {FLOPS_BLEND_BWD} per blend "
+                     f"(FMA = 2), per launch; peak = unpacked FP32 FMA rate")
 
     line = {
         "metric": METRIC,
@@ -300,11 +369,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": info["workload"], "n_gaussians": n, "width": info["width"],
                    "height": info["height"], "frames": info["frames"],
-                   "loss": "L1 + 0.2(1-SSIM)" if args.workload == "scene" else "L1 + 0.2(1-SSIM)",
-                   "n_raw_points": info.get("n_raw_points")},
-        "blends_per_s": round(blends_per_step * its, 1),
-        "evaluated_per_s": round(evals_per_step * its, 1),
-        "blends_per_step": round(blends_per_step, 1),
+                   "loss": "L1 + 0.2(1-SSIM)", "n_raw_points": info.get("n_raw_points"),
+                   "state": f"parameters after {args.warmup} warm-up + 2 autotune steps; timed "
+                            f"frames seed {args.seed}"},
+        "blends_per_s": round(counts["blends"] * its, 1),
+        "evaluated_per_s": round(counts["evaluated"] * its, 1),
+        "blends_per_step": round(counts["blends"], 1),
+        "evaluated_per_step": round(counts["evaluated"], 1),
+        "evaluated_to_last_blend_per_step": round(counts["evaluated_to_last"], 1),
         "pairs_per_step": round(pairs_per_step, 1),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "launch": ("hip graphs" if use_graph else "eager") + f", {choice.get('mode', 'grid')} (autotuned)",
@@ -318,18 +390,23 @@ def main():
         line["render_fps"] = render_fps_leg(tr.params, views)
 
     if not args.no_cpu_baseline:
-        from paper_2510_01119_amd import synth  # noqa: F401
         p_np = tr.params.detach().cpu().numpy()
-        fsel = [int(seq[0])]
+        fsel = [int(f) for f in seq[args.warmup:args.warmup + 16]]
         tgt = images[fsel].cpu().numpy()
         v_np = np.stack([views[f] for f in fsel])
-        log("bench: cpu baseline (oracle) ...")
-        rate, steps_done, secs = cpu_baseline(p_np, v_np, tgt)
-        line["cpu_baseline"] = {"value": round(rate, 6), "unit": "iters/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"{steps_done} full training step(s) of the same workload "
-                                          f"(one frame, {n} Gaussians) in {secs:.1f} s on one host "
-                                          f"thread"}
+        log("bench: cpu baseline (oracle workers) ...")
+        rate, steps_done, secs, cores, nproc, model = cpu_baseline(p_np, v_np, tgt)
+        line["cpu_baseline"] = {
+            "value": round(rate, 6), "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps_done} full training steps of the same workload ({n} Gaussians, one "
+                      f"960x540 frame each) in {secs:.1f} s wall, one single-threaded oracle process "
+                      f"per core on {cores} cores",
+            "host": {"nproc": nproc, "usable_cores": cores, "cpu": model}}
+        del p_np
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        line["batched"] = run_batched(args, dev, ProfileRegion(args.profile_region == "batched"))
+        torch.cuda.empty_cache()
     if args.workload == "scene" and not args.no_ttp and pruned is not None:
         line["time_to_psnr"] = time_to_psnr_leg(params, views, images, pruned)
     if args.workload == "scene" and not args.no_iso:
@@ -337,6 +414,27 @@ def main():
     if args.workload == "scene" and not args.no_scene_prep:
         line["scene_prep"] = scene_prep_leg(params, views, images, args.seed)
     print(json.dumps(line), flush=True)
+
+
+def count_blends(r, params, cviews):
+    """Forward counters over the given frames (untimed): per step averages of
+    evaluated (pixel, entry) pairs, blends, evaluated pairs up to each
+    pixel's last blend (what the backward re-evaluates), and pairs."""
+    import torch
+    r.counters = torch.zeros(3, dtype=torch.int64, device=params.device)
+    tot = np.zeros(3)
+    pairs = []
+    for cv in cviews:
+        r.set_views(cv)
+        r.preprocess(params)
+        r.bin_sort(check=False)
+        r.render()
+        tot += r.counters.cpu().numpy()
+        pairs.append(int(r.n_pairs.item()))
+    r.counters = None
+    k = max(len(cviews), 1)
+    return {"evaluated": tot[0] / k, "blends": tot[1] / k, "evaluated_to_last": tot[2] / k,
+            "pairs": float(np.mean(pairs))}
 
 
 def iso_leg(params, views, images, seed, steps=200, warmup=20, budget=1500):
@@ -502,10 +600,13 @@ def profiled_traffic(kernel):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def run_batched(args, dev):
-    """8 views per launch from 500k Gaussians (uneven visible counts), fused
-    per-view L1, persistent largest-first launches, autotuned batch size and
-    block shape, each step replayed from HIP graphs."""
+def run_batched(args, dev, region):
+    """The batched configuration: 8 views per launch from 500k Gaussians
+    (uneven visible counts), fused per-view L1, persistent largest-first
+    launches, autotuned batch size and block shape, each step replayed from
+    HIP graphs; `args.steps` steps timed after `args.warmup`.  Returns its
+    figures (iterations/s, views/s, blends/s, the render backward's
+    roofline)."""
     import torch
     from paper_2510_01119_amd import autotune, synth
     from paper_2510_01119_amd.rasterizer import Rasterizer
@@ -526,79 +627,83 @@ def run_batched(args, dev):
         tr.step()
     torch.cuda.synchronize()
     choice = autotune.tune(tr.rast, tr.params, tr.rast.dL_dimage)
-    log(f"bench: autotune {json.dumps(choice)}")
+    log(f"bench: batched autotune {json.dumps(choice)}")
     tr.capture()
     for _ in range(3):
         tr.step_graph()
     ev = []
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(args.steps):
-        if i % EVENT_EVERY:
-            tr.step_graph()
-            continue
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        tr.step_graph(events=(a, b))
-        ev.append((a, b))
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    with region:
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            if i % EVENT_EVERY:
+                tr.step_graph()
+                continue
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            tr.step_graph(events=(a, b))
+            ev.append((a, b))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
     if int(tr.overflow_seen.item()) != 0:
         raise RuntimeError("pair capacity overflowed during the timed region")
     its = args.steps / (t2 - t1)
     bwd_ms = float(np.mean([x.elapsed_time(y) for x, y in ev]))
-    # blend counts (untimed)
     r = tr.rast
-    r.counters = torch.zeros(2, dtype=torch.int64, device=dev)
-    tr.stage_forward()
-    c = r.counters.cpu().numpy()
-    r.counters = None
-    pairs = int(r.n_pairs.item())
-    roof = roofline_for("render_bwd", bwd_ms, params.shape[1], pairs, float(c[0]), float(c[1]),
-                        960 * 540 * len(views))
+    counts = count_blends(r, tr.params, [r.cviews])
+    pairs = counts.pop("pairs")
+    roof = roofline_for("render_bwd", bwd_ms, params.shape[1], pairs, counts, 960 * 540 * len(views))
     roof["ms_per_launch"] = round(bwd_ms, 4)
     roof["timing"] = (f"HIP events around every {EVENT_EVERY}th render-backward graph replay in "
-                      "the timed region")
-    roof["traffic"] = None          # counters were taken on the scene-scale workload
+                      "the timed region (the render backward kernel alone)")
+    roof["traffic"] = None          # the HBM counters were taken on the scene workload
     roof.pop("traffic_GBps", None)
-    line = {
-        "metric": METRIC, "value": round(its, 3), "unit": "iters/s", "n_gpus": 1,
+    out = {
+        "workload": "batched: 8 views per persistent launch, 500k 4D Gaussians, 960x540, "
+                    "fused per-view L1",
+        "iters_per_s": round(its, 3), "ms_per_step": round(1000.0 * (t2 - t1) / args.steps, 4),
         "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * (t2 - t1) / args.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched: 8 views per persistent launch, 500k 4D Gaussians, 960x540, "
-                               "fused per-view L1", "n_gaussians": int(params.shape[1]),
-                   "views": len(views), "visible_per_view": vis, "width": 960, "height": 540},
         "views_per_s": round(its * len(views), 2),
-        "blends_per_s": round(float(c[1]) * its, 1),
-        "pairs_per_step": pairs,
+        "n_gaussians": int(params.shape[1]), "views": len(views), "visible_per_view": vis,
+        "width": 960, "height": 540,
+        "blends_per_s": round(counts["blends"] * its, 1),
+        "blends_per_step": round(counts["blends"], 1),
+        "pairs_per_step": round(pairs, 1),
         "launch": f"hip graphs, {choice.get('mode', 'grid')} (autotuned)",
         "autotune": {"fwd_batch": choice["batch"], "bwd_pixels_per_lane": choice["bwd_pixels_per_lane"],
-                     "mode": choice.get("mode"), "mode_ms": choice.get("mode_ms"),
-                     "workgroups_per_cu": choice.get("workgroups_per_cu"),
-                     "wg_ms": choice.get("wg_ms")},
+                     "mode": choice.get("mode"), "workgroups_per_cu": choice.get("workgroups_per_cu")},
         "loss_per_view": [round(float(x), 5) for x in tr.loss_per_view()],
         "roofline": roof,
     }
-    print(json.dumps(line), flush=True)
+    log(f"bench: batched {its:.1f} it/s, render_bwd {bwd_ms:.4f} ms")
+    del tr
+    return out
 
 
-def roofline_for(kernel, ms, n, pairs, evals, blends, hw):
+def roofline_for(kernel, ms, n, pairs, counts, hw):
     """Algorithmic work of one launch of `kernel` over its measured time.
 
-    render_fwd / render_bwd are bound by the FP32 vector ALU.  Algorithmic
-    FP32 operations (exp counted as one): forward 20 per evaluated
-    (pixel, Gaussian); backward 20 per evaluated plus 45 per blended one.
-    Evaluated and blended counts come from the forward's counters over the
-    same frames.  Other kernels: algorithmic HBM bytes."""
+    render_fwd / render_bwd are bound by the FP32 vector ALU: algorithmic
+    flops (FMA = 2, exp and division 1) of the forward, FLOPS_EVAL per
+    evaluated (pixel, entry) and FLOPS_BLEND_FWD per blend; of the backward,
+    FLOPS_EVAL per (pixel, entry) it re-evaluates (those up to each pixel's
+    last blend) and FLOPS_BLEND_BWD per blend -- counts from the forward's
+    counters over the same frames -- against the unpacked FP32 FMA rate.
+    Other kernels: algorithmic HBM bytes against 8 TB/s."""
     s = ms / 1000.0
     if kernel in ("render_fwd", "render_bwd"):
-        flops = 20.0 * evals if kernel == "render_fwd" else 20.0 * evals + 45.0 * blends
+        if kernel == "render_fwd":
+            flops = FLOPS_EVAL * counts["evaluated"] + FLOPS_BLEND_FWD * counts["blends"]
+        else:
+            flops = FLOPS_EVAL * counts["evaluated_to_last"] + FLOPS_BLEND_BWD * counts["blends"]
         achieved = flops / s / 1e12
         traffic = profiled_traffic(kernel)
         return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
                 "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                "peak_published": ALU_PEAK_PUBLISHED_TFLOPS,
+                "frac_published": round(achieved / ALU_PEAK_PUBLISHED_TFLOPS, 4),
+                "flops_per_launch": round(flops),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_GBps": None if traffic is None else round(traffic / s / 1e9, 1)}
     bytes_per = {

@@ -167,6 +167,7 @@ int gs4d_bin_sort_noalloc(const float *rec, const int32_t *rect, const int32_t *
 int gs4d_set_bin_strategy(int32_t strategy);
 
 /* Render options.  Zero-initialise and set what is needed. */
+#define GS4D_RENDER_GRAD2D_ZEROED 1
 typedef struct gs4d_render_opts {
     int32_t batch;          /* Gaussians staged in LDS per round: 64, 128 or 256 (0 -> 256) */
     int32_t persistent;     /* 0: one workgroup per (view, tile); 1: persistent workgroups
@@ -174,12 +175,16 @@ typedef struct gs4d_render_opts {
                                static assignment (workgroup i takes positions i and
                                2G-1-i of every 2G, G workgroups), no queue            */
     int32_t n_workgroups;   /* persistent launch size (0 -> 4 per CU)                       */
-    int32_t reserved;
+    int32_t flags;          /* GS4D_RENDER_GRAD2D_ZEROED: gs4d_render_bwd_2d's grad2d is
+                               already zero (the call then launches the backward kernel
+                               only, no clearing fill); other bits must be 0            */
     const float *target;    /* optional [n_views][3][H][W]: fused per-view L1 loss          */
     float l1_weight;        /* weight of the fused L1 term                                  */
     float *loss_per_view;   /* out [n_views], accumulated (caller zeroes), needs target     */
     float *dL_dimage;       /* out [n_views][3][H][W] dL1/dimage * l1_weight, needs target  */
-    uint64_t *counters;     /* optional out [2], accumulated: evaluated entries, blends     */
+    uint64_t *counters;     /* optional out [3], accumulated: evaluated (pixel, entry)
+                               pairs, blends, and evaluated pairs up to each pixel's last
+                               blend (the entries its backward re-evaluates)          */
     const int32_t *order;   /* optional [n_views*tiles_per_view] tile processing order (persistent) */
     int32_t *queue;         /* device int32 work counter for persistent mode 1 (caller zeroes) */
 } gs4d_render_opts;

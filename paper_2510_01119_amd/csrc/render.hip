@@ -182,7 +182,7 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     int32_t last = -1;
-    uint32_t n_eval = 0, n_blend = 0;
+    uint32_t n_eval = 0, n_blend = 0, n_eval_last = 0;
     bool done = !inside;
 
     for (int start = rg.x; start < rg.y; start += BATCH) {
@@ -218,6 +218,7 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
             if (COUNT) {
                 n_eval += live ? 1u : 0u;
                 n_blend += blend ? 1u : 0u;
+                n_eval_last = blend ? n_eval : n_eval_last;
             }
         };
 #pragma unroll
@@ -274,9 +275,11 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
     if (COUNT) {
         const uint32_t e = wave_sum_u32(n_eval);
         const uint32_t bl = wave_sum_u32(n_blend);
+        const uint32_t el = wave_sum_u32(n_eval_last);
         if (lane == 0) {
             atomicAdd((unsigned long long *)&o.counters[0], (unsigned long long)e);
             atomicAdd((unsigned long long *)&o.counters[1], (unsigned long long)bl);
+            atomicAdd((unsigned long long *)&o.counters[2], (unsigned long long)el);
         }
     }
 }
@@ -763,9 +766,11 @@ extern "C" int gs4d_render_bwd_2d(const float *rec, int64_t n, const uint32_t *v
     if (opts) o = *opts;
     GS4D_REQUIRE(o.persistent >= 0 && o.persistent <= 2, "gs4d_render_bwd_2d: persistent must be 0, 1 or 2");
     GS4D_REQUIRE(o.persistent != 1 || o.queue, "gs4d_render_bwd_2d: persistent mode 1 needs a queue counter");
+    GS4D_REQUIRE((o.flags & ~GS4D_RENDER_GRAD2D_ZEROED) == 0, "gs4d_render_bwd_2d: unknown flags");
     if (n == 0) return GS4D_OK;
     hipStream_t st = as_stream(stream);
-    GS4D_TRY(launch_fill<float>(grad2d, 0.0f, n * n_views * 9, st));
+    if (!(o.flags & GS4D_RENDER_GRAD2D_ZEROED))
+        GS4D_TRY(launch_fill<float>(grad2d, 0.0f, n * n_views * 9, st));
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
     unsigned grid = (unsigned)n_tiles;
     if (o.persistent) {

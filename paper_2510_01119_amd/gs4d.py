@@ -24,6 +24,7 @@ REC_FLOATS = 12
 GRAD2D_FLOATS = 9
 TILE = 16
 MAX_VIEWS = 16
+RENDER_GRAD2D_ZEROED = 1   # gs4d_render_opts.flags
 
 
 class GS4DError(RuntimeError):
@@ -39,7 +40,7 @@ class gs4d_view(ctypes.Structure):
 
 class gs4d_render_opts(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("n_workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_workgroups", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("target", ctypes.c_void_p), ("l1_weight", ctypes.c_float),
                 ("loss_per_view", ctypes.c_void_p), ("dL_dimage", ctypes.c_void_p),
                 ("counters", ctypes.c_void_p), ("order", ctypes.c_void_p),

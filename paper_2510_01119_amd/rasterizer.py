@@ -49,7 +49,7 @@ class Rasterizer:
             self.dparams = torch.zeros((G.N_FIELDS, max(n, 1)), dtype=torch.float32, device=dev)
             self.grad2d = torch.zeros((V, max(n, 1), G.GRAD2D_FLOATS), dtype=torch.float32,
                                       device=dev)
-        self.counters = torch.zeros(2, dtype=torch.int64, device=dev) if count_blends else None
+        self.counters = torch.zeros(3, dtype=torch.int64, device=dev) if count_blends else None
         # persistent launches: largest-first tile order + one work counter per kernel
         self.persistent = persistent
         self.order_tiles = True      # persistent: largest tiles first (else index order)
@@ -163,13 +163,21 @@ class Rasterizer:
         G.gs4d_render_fwd(self.rec, self.n, self.vals, self.ranges, self.cviews, self.image,
                           self.T_final, self.last, opts)
 
-    def render_bwd_2d(self, dL_dimage):
+    def zero_grad2d(self):
+        """Clear the 2D-gradient accumulator ahead of time: the next
+        render_bwd_2d(pre_zeroed=True) then launches the backward kernel only."""
+        G.gs4d_fill_f32(self.grad2d, 0.0)
+
+    def render_bwd_2d(self, dL_dimage, pre_zeroed=False):
         if self.forward_only:
             raise RuntimeError("forward-only rasterizer: no state for a backward")
         if self.persistent:
             self._bwd_queue()
+        opts = self._opts(1)
+        if pre_zeroed:
+            opts.flags = G.RENDER_GRAD2D_ZEROED
         G.gs4d_render_bwd_2d(self.rec, self.n, self.vals, self.ranges, self.cviews, dL_dimage,
-                             self.T_final, self.last, self.grad2d, self._opts(1))
+                             self.T_final, self.last, self.grad2d, opts)
 
     def forward(self, params: torch.Tensor, check: bool = True, opts=None):
         assert params.shape in ((G.N_FIELDS, self.n), (G.ISO_FIELDS, self.n))

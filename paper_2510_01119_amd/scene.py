@@ -37,6 +37,7 @@ recovery are not available here).  Recipe:
 from __future__ import annotations
 
 import math
+import sys
 
 import numpy as np
 import torch
@@ -295,7 +296,8 @@ class Scene:
                 dyn = gt_dyn
             clss.append(dyn.to(torch.uint8))
             if verbose and f % 50 == 0:
-                print(f"scene: frame {f}/{self.frames} pairs={int(r.n_pairs.item())}", flush=True)
+                print(f"scene: frame {f}/{self.frames} pairs={int(r.n_pairs.item())}",
+                      file=sys.stderr, flush=True)
         xyz = torch.cat(pts, dim=1).contiguous()
         attr = torch.cat(attrs, dim=1).contiguous()
         cls = torch.cat(clss).contiguous()

@@ -127,9 +127,12 @@ class Trainer:
     def stage_forward(self, f: int):
         self.forward_loss(f)
         torch.maximum(self.overflow_seen, self.rast.overflow, out=self.overflow_seen)
+        # the render backward's accumulator, cleared here so that the
+        # backward stage is the backward kernel alone
+        self.rast.zero_grad2d()
 
     def stage_render_bwd(self, f: int):
-        self.rast.render_bwd_2d(self.dimg)
+        self.rast.render_bwd_2d(self.dimg, pre_zeroed=True)
 
     def stage_update(self, f: int):
         r = self.rast
@@ -235,10 +238,11 @@ class BatchedTrainer:
         r.bin_sort(check=False)
         r.render()
         torch.maximum(self.overflow_seen, r.overflow, out=self.overflow_seen)
+        r.zero_grad2d()
 
     def stage_render_bwd(self):
         r = self.rast
-        r.render_bwd_2d(r.dL_dimage)
+        r.render_bwd_2d(r.dL_dimage, pre_zeroed=True)
 
     def stage_update(self):
         r = self.rast
