@@ -319,20 +319,22 @@ typedef struct {
  * threshold.  With f32 decisions the oracle takes them on an FP32 shadow of
  * the kernel's per-entry arithmetic, in the kernel's fixed order:
  *   dx = (x + 1/2) - mx, dy likewise,
- *   power = min(0, fma(-1/2, fma(a dx, dx, (c dy) dy), -(b dx) dy)),
- *   skip iff power < lo, lo = -ln(255 o_t) (project-defined logarithm; in
- *     exact arithmetic the same as alpha < 1/255),
- *   at = o_t * 2^(power * log2 e), alpha = min(0.99, at),
+ *   qx = fma(a, dx, b dy), qy = fma(c, dy, b dx),
+ *   arg = min(0, fma(dx, qx, dy qy) * (-(1/2) log2 e))   (the exponent in log2 units),
+ *   skip iff arg < lo, lo = ln(255 o_t) * (-log2 e) with the project-defined
+ *     logarithm (in exact arithmetic the same as alpha < 1/255),
+ *   at = o_t 2^arg, alpha = min(0.99, at),
  *   clamped iff at > 0.99, stop iff T (1 - alpha) < 1e-4 (T in FP32),
- * with 2^x correctly rounded where the kernel uses the hardware exp2 (a few
- * ulp apart).  Colour, transmittance and gradients stay FP64.  The floor
- * is then the same bit for bit; clamp and stop can differ only where the
+ * with 2^x correctly rounded where the kernel uses the hardware exp2 (within
+ * an ulp).  Colour, transmittance and gradients stay FP64.  The floor is
+ * then the same bit for bit; clamp and stop can differ only where the
  * shadow lies within the hardware exp2's ulps of the threshold (see
  * or_doubtful_decisions). */
-static const float LOG2E_F32 = 1.44269502162933349609375f;   /* log2 e rounded to FP32 */
+static const float NEG_HALF_LOG2E_F32 = -0.72134752044448170368f;   /* -(1/2) log2 e */
+static const float NEG_LOG2E_F32 = -1.44269504088896340736f;        /* -log2 e */
 
 typedef struct {
-    float power, lo, at;
+    float arg, lo, at;
 } or_shadow;
 
 static void shadow_entry(const double *r, double px, double py, or_shadow *sh)
@@ -340,11 +342,11 @@ static void shadow_entry(const double *r, double px, double py, or_shadow *sh)
     const float mx = (float)r[0], my = (float)r[1];
     const float a = (float)r[2], b = (float)r[3], c = (float)r[4], ot = (float)r[5];
     const float dx = (float)px - mx, dy = (float)py - my;
-    const float t1 = a * dx, t2 = c * dy;
-    const float q = fmaf(t1, dx, t2 * dy);
-    sh->power = fminf(fmaf(-0.5f, q, -(b * dx) * dy), 0.0f);
-    sh->lo = -or_logf(255.0f * ot);
-    const float ex = (float)exp2((double)(sh->power * LOG2E_F32));
+    const float qx = fmaf(a, dx, b * dy);
+    const float qy = fmaf(c, dy, b * dx);
+    sh->arg = fminf(fmaf(dx, qx, dy * qy) * NEG_HALF_LOG2E_F32, 0.0f);
+    sh->lo = or_logf(255.0f * ot) * NEG_LOG2E_F32;
+    const float ex = (float)exp2((double)sh->arg);
     sh->at = ot * ex;
 }
 
@@ -352,7 +354,7 @@ static int floor_skip_f32(const double *r, double px, double py)
 {
     or_shadow sh;
     shadow_entry(r, px, py, &sh);
-    return sh.power < sh.lo;
+    return sh.arg < sh.lo;
 }
 
 int32_t or_floor_skip_f32(const double *rec12, double px, double py)
@@ -389,7 +391,7 @@ static int64_t composite_pixel_ex(const double *rec_view, const uint32_t *ids, i
         int clamped = f32 ? sh.at > 0.99f : atil > 0.99;
         if (e == force_e && force_kind == 2) clamped = !clamped;
         const double alpha = clamped ? 0.99 : atil;
-        int skip = f32 ? sh.power < sh.lo : alpha < 1.0 / 255.0;
+        int skip = f32 ? sh.arg < sh.lo : alpha < 1.0 / 255.0;
         if (e == force_e && force_kind == 1) skip = !skip;
         if (skip) continue;
         const double Tn = T * (1.0 - alpha);
@@ -454,7 +456,7 @@ int64_t or_doubtful_decisions(const double *rec, int64_t n, const double *views,
                     const double *r = rv + (int64_t)vals[k] * OR_REC;
                     or_shadow sh;
                     shadow_entry(r, px, py, &sh);
-                    if (sh.power < sh.lo) continue;
+                    if (sh.arg < sh.lo) continue;
                     const int clamped = sh.at > 0.99f;
                     int kind = 0;
                     if (fabsf(sh.at - 0.99f) <= 0.99f * EPS_AT) kind = 2;

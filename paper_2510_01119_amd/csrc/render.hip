@@ -43,24 +43,35 @@ __device__ __forceinline__ TileInfo tile_info(int64_t tile, const ViewPack &vp) 
     return ti;
 }
 
-// The exact same instruction sequence decides skip / blend in the forward
-// and the backward.  The conic of a visible record is positive definite
-// (positive determinant, 0.3 px^2 dilation on the diagonal), so the
-// exponent is <= 0 in exact arithmetic; the min with 0 only absorbs
-// rounding (alpha never exceeds o_t, and the pixel stays continuous where
-// the exponent passes 0).  Its derivative is the exponent's own.
-__device__ __forceinline__ float gauss_power(float4 a, float cc, float dx, float dy) {
-    const float t1 = a.z * dx;   // conic.a dx
-    const float t2 = cc * dy;    // conic.c dy
-    const float q = fmaf(t1, dx, t2 * dy);
-    return fminf(fmaf(-0.5f, q, -(a.w * dx) * dy), 0.0f);
+// The exponent of a Gaussian at pixel offset d = (dx, dy), in log2 units so
+// that it feeds the hardware exp2 directly:
+//   arg = min(0, -(1/2) log2(e) (dx qx + dy qy)),  (qx, qy) = Q d,
+// Q = [[a, b], [b, c]] the conic; alpha~ = o_t 2^arg.  The conic of a visible
+// record is positive definite (positive determinant, 0.3 px^2 dilation on
+// the diagonal), so the quadratic form is >= 0 in exact arithmetic; the min
+// with 0 only absorbs rounding (alpha never exceeds o_t, and the pixel stays
+// continuous where the form passes 0).  Its derivative is the form's own.
+// (qx, qy) are returned: the exponent's gradient with respect to the mean
+// is -(1/2) of d/dd of the form, i.e. +Q d in natural units.  The forward
+// and the backward evaluate this same instruction sequence.
+constexpr float NEG_HALF_LOG2E = -0.72134752044448170368f;   // -(1/2) log2 e
+constexpr float NEG_LOG2E = -1.44269504088896340736f;        // -log2 e
+constexpr float LN2 = 0.69314718055994530942f;
+
+__device__ __forceinline__ float gauss_arg(float4 a, float cc, float dx, float dy, float &qx,
+                                           float &qy) {
+    qx = fmaf(a.z, dx, a.w * dy);
+    qy = fmaf(cc, dy, a.w * dx);
+    return fminf(fmaf(dx, qx, dy * qy) * NEG_HALF_LOG2E, 0.0f);
 }
 
-// The alpha >= 1/255 floor as a bound on the exponent: o_t e^power >= 1/255
-// iff power >= lo = -ln(255 o_t).  Both operands are FP32 values with a fixed
-// evaluation order (gauss_power; the project-defined logarithm), so the
-// decision to skip an entry is reproducible bit for bit.
-__device__ __forceinline__ float alpha_floor(float o_t) { return -fixed_log(255.0f * o_t); }
+// The alpha >= 1/255 floor as a bound on the exponent: o_t 2^arg >= 1/255
+// iff arg >= lo = -log2(255 o_t) = -ln(255 o_t) log2 e.  Both operands are
+// FP32 values with a fixed evaluation order (gauss_arg; the project-defined
+// logarithm), so the decision to skip an entry is reproducible bit for bit.
+__device__ __forceinline__ float alpha_floor(float o_t) {
+    return fixed_log(255.0f * o_t) * NEG_LOG2E;
+}
 
 // Each wave owns a block of pixels of the tile.  For a staged batch, every
 // wave marks (one ballot per 64 entries) the entries whose alpha >= 1/255
@@ -100,10 +111,11 @@ __device__ __forceinline__ void strip_masks(const float4 *sA, const float4 *sB, 
                 // a bound on its FP32 rounding (its terms can cancel), and tau
                 // carries the footprint's padding, so no entry that reaches
                 // alpha >= 1/255 at a pixel of the block is dropped.
-                // tau = 2 ln(255 o_t) = -2 lo, padded like the footprint (relative
-                // and absolute 2^-10) plus 2^-12
+                // tau = 2 ln(255 o_t) = -2 lo ln 2, padded like the footprint
+                // (relative and absolute 2^-10) plus 2^-12
                 const float ca = a.z, cb = a.w, cc = sB[j].x;
-                const float tau = fmaf(-2.0f * c.y, 1.0f + 1.25f / 1024.0f, 1.25f / 1024.0f);
+                const float tau =
+                    fmaf(-2.0f * LN2 * c.y, 1.0f + 1.25f / 1024.0f, 1.25f / 1024.0f);
                 const float X0 = x0 - a.x, X1 = x1 - a.x, Y0 = y0 - a.y, Y1 = y1 - a.y;
                 const bool inside = X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f;
                 const float ia = __builtin_amdgcn_rcpf(ca), ic = __builtin_amdgcn_rcpf(cc);
@@ -136,8 +148,8 @@ __device__ __forceinline__ void stage_batch(const float4 *__restrict__ recv,
         const float4 r2 = recv[3 * (int64_t)g + 2];
         sA[t] = r0;                                       // mx my ca cb
         sB[t] = make_float4(r1.x, r1.y, r2.x, r2.y);      // cc o_t r g
-        // b, lo, hx, hy.  lo = -ln(255 o_t): alpha = o_t e^power >= 1/255 iff
-        // power >= lo, the form in which the floor is decided (FP32, the
+        // b, lo, hx, hy.  lo = -log2(255 o_t): alpha = o_t 2^arg >= 1/255 iff
+        // arg >= lo, the form in which the floor is decided (FP32, the
         // project-defined logarithm, so the decision is reproducible bit for bit)
         sC[t] = make_float4(r2.z, alpha_floor(r1.y), r1.w, r2.w);
         if (sG) sG[t] = g;
@@ -200,10 +212,11 @@ __device__ __forceinline__ void render_tile_fwd(int64_t tile, const float4 *__re
         auto blend_one = [&](int j, float4 a, float4 b, float2 c) {
             const bool live = !done;
             const float dx = fx - a.x, dy = fy - a.y;
-            const float power = gauss_power(a, b.x, dx, dy);
-            const float at = b.y * __expf(power);
+            float qx, qy;
+            const float arg = gauss_arg(a, b.x, dx, dy, qx, qy);
+            const float at = b.y * __builtin_amdgcn_exp2f(arg);
             const float alpha = fminf(ALPHA_MAX, at);
-            const bool ok = live && !(power < c.y);   // alpha >= 1/255
+            const bool ok = live && !(arg < c.y);   // alpha >= 1/255
             const float cb_ = c.x;
             const float Tn = T * (1.0f - alpha);
             const bool stop = ok && (Tn < T_EPS);
@@ -465,7 +478,10 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
     const gs4d_view &V = vp.v[ti.v];
 
     int my_last[PPL];
-    float T[PPL], g0[PPL], g1[PPL], g2[PPL], B0[PPL], B1[PPL], B2[PPL], fy[PPL];
+    // gB: the upstream colour gradient dotted with the colour behind the
+    // current entry (g . B, linear in B, so one scalar replaces B's three
+    // channels in dC/dalpha = T (g . c - g . B) and in B's update)
+    float T[PPL], g0[PPL], g1[PPL], g2[PPL], gB[PPL], fy[PPL];
     int lane_last = -1;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -483,9 +499,7 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             g1[k] = d[HW];
             g2[k] = d[2 * HW];
         }
-        B0[k] = V.bg[0];
-        B1[k] = V.bg[1];
-        B2[k] = V.bg[2];
+        gB[k] = fmaf(g2[k], V.bg[2], fmaf(g1[k], V.bg[1], g0[k] * V.bg[0]));
         lane_last = max(lane_last, my_last[k]);
     }
     if (t == 0) smax = -1;
@@ -542,11 +556,12 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 const float dx = fx - a.x, dy = fy[k] - a.y;
-                const float power = gauss_power(a, b.x, dx, dy);
-                const float ex = __expf(power);
+                float qx, qy;
+                const float arg = gauss_arg(a, b.x, dx, dy, qx, qy);
+                const float ex = __builtin_amdgcn_exp2f(arg);
                 const float at = b.y * ex;
                 const float alpha = fminf(ALPHA_MAX, at);
-                const bool ok = (idx <= my_last[k]) && !(power < c.y);   // alpha >= 1/255
+                const bool ok = (idx <= my_last[k]) && !(arg < c.y);   // alpha >= 1/255
                 any = any || ok;
                 // transmittance in front of this entry
                 const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
@@ -555,21 +570,23 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
                 d[6] = fmaf(wgt, g0[k], d[6]);
                 d[7] = fmaf(wgt, g1[k], d[7]);
                 d[8] = fmaf(wgt, g2[k], d[8]);
-                const float dal = Tk * (g0[k] * (b.z - B0[k]) + g1[k] * (b.w - B1[k]) +
-                                        g2[k] * (cbl - B2[k]));
-                const float am = ok ? alpha : 0.0f;
-                B0[k] = fmaf(am, b.z - B0[k], B0[k]);
-                B1[k] = fmaf(am, b.w - B1[k], B1[k]);
-                B2[k] = fmaf(am, cbl - B2[k], B2[k]);
+                // dC/dalpha . g = T (g . c - g . B); then B <- B + alpha (c - B)
+                const float gc = fmaf(g2[k], cbl, fmaf(g1[k], b.w, g0[k] * b.z));
+                const float diff = gc - gB[k];
+                gB[k] = fmaf(ok ? alpha : 0.0f, diff, gB[k]);
                 // no gradient through the 0.99 clamp
-                const float dalpha = (ok && at <= ALPHA_MAX) ? dal : 0.0f;
-                const float dpow = dalpha * at;
+                const float dalpha = (ok && at <= ALPHA_MAX) ? Tk * diff : 0.0f;
+                const float dpow = dalpha * at;   // dL / d(natural exponent)
                 d[5] = fmaf(dalpha, ex, d[5]);
-                d[2] = fmaf(-0.5f * dpow * dx, dx, d[2]);
-                d[3] = fmaf(-dpow * dx, dy, d[3]);
-                d[4] = fmaf(-0.5f * dpow * dy, dy, d[4]);
-                d[0] = fmaf(dpow, a.z * dx + a.w * dy, d[0]);
-                d[1] = fmaf(dpow, b.x * dy + a.w * dx, d[1]);
+                // conic terms without their constant factors (-1/2, -1, -1/2:
+                // applied once per (tile, Gaussian, term) at the atomic); mean
+                // terms dpow Q d
+                const float pdx = dpow * dx, pdy = dpow * dy;
+                d[2] = fmaf(pdx, dx, d[2]);
+                d[3] = fmaf(pdx, dy, d[3]);
+                d[4] = fmaf(pdy, dy, d[4]);
+                d[0] = fmaf(dpow, qx, d[0]);
+                d[1] = fmaf(dpow, qy, d[1]);
             }
             if (__ballot(any) == 0) return;   // no lane of this wave blends the entry
             wr[j >> 6] |= 1ull << (j & 63);
@@ -614,7 +631,9 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             for (int ww = 0; ww < NW; ++ww) {
                 if (written[ww][e >> 6] & bit) sum += part[ww][i];
             }
-            if (sum != 0.0f) atomicAdd(gview + (int64_t)sG[e] * 9 + q, sum);
+            // the conic terms' factors: d power / d(a, b, c) = (-dx^2/2, -dx dy, -dy^2/2)
+            const float fac = (q == 2 || q == 4) ? -0.5f : (q == 3 ? -1.0f : 1.0f);
+            if (sum != 0.0f) atomicAdd(gview + (int64_t)sG[e] * 9 + q, sum * fac);
         }
     }
 }

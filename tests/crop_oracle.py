@@ -90,6 +90,15 @@ class CropFD:
         # blend-decision signature of every crop pixel for the base set
         self.sig0 = oracle.render_fwd(self.rec, crop.view, vals, crop.restrict(ranges),
                                       signature=True, f32=False)["sig"][0]
+        self._vals, self._ranges = vals, crop.restrict(ranges)
+
+    def analytic(self):
+        """The oracle's FP64 chain rule of L at the FP64 records, in their
+        order and with FP64 decisions: the model the central differences
+        differentiate."""
+        grec = oracle.render_bwd(self.rec, self.crop.view, self._vals, self._ranges, self.w,
+                                 f32=False)
+        return oracle.preprocess_bwd(self.p, self.crop.view, grec)
 
     def _tiles_of(self, rect_row, touched_v):
         c = self.crop

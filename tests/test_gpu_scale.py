@@ -15,7 +15,9 @@ through the slice, projection, sort and compositing.
   misses the crop gets an exactly zero gradient;
 * 64 random (Gaussian, parameter) entries of Gaussians that blend in the
   crop match central differences (h = 1e-3) of the oracle's FP64 forward;
-  entries whose +-h step changes a blend decision are redrawn.
+  entries whose +-h step changes a blend decision, or whose gradient
+  depends on the FP32 rounding of the records (depth near-ties ordered
+  differently, needles), are redrawn.
 """
 import numpy as np
 import pytest
@@ -122,13 +124,33 @@ def test_crop_gradients(scale, crop_ref):
 
 
 def test_central_differences(scale, crop_ref):
+    """Central differences differentiate the oracle's FP64 model: records
+    computed in FP64 and sorted by their FP64 depths.  The kernel's records
+    are FP32; at this density every crop tile holds depth near-ties that the
+    two roundings order differently, and a Gaussian behind such a pair (or a
+    needle whose conic FP32 cannot resolve) has a gradient that depends on
+    the rounding itself.  Entries whose FP64-record gradient and FP32-record
+    gradient (both by the oracle's chain rule) differ by more than 1e-4 of
+    their scale are redrawn, like those whose +-h step changes a decision;
+    they stay under 10% of the contributing entries (counted and printed)."""
     p, crop, w = scale["p"], scale["crop"], scale["w"]
     sub, ref = crop_ref["sub"], crop_ref["d"]
     d = scale["gpu"]["d"][:, sub]
     fd = CropFD(p[:, sub].astype(np.float64), crop, w)
     contrib = np.nonzero(np.abs(ref[17]) > 0)[0]
+    scale_k = np.maximum(1e-3 * np.abs(d).max(axis=1, keepdims=True), 1e-6)
+    a64 = fd.analytic()
+    rounding = np.abs(a64 - ref) > 1e-4 * np.maximum(np.abs(ref), scale_k)
+    frac = rounding[:, contrib].mean()
+    print(f"central differences: {frac:.2%} of contributing entries depend on the FP32 "
+          "rounding of the records", flush=True)
+    assert frac < 0.1
     rng = np.random.default_rng(9)
-    cands = [(int(rng.choice(contrib)), int(rng.integers(0, 20))) for _ in range(640)]
+    cands = []
+    while len(cands) < 640:
+        gi, k = int(rng.choice(contrib)), int(rng.integers(0, 20))
+        if not rounding[k, gi]:
+            cands.append((gi, k))
     res = fd.fd_many(cands, 1e-3)
     checked = 0
     for (gi, k), (val, same) in zip(cands, res):
