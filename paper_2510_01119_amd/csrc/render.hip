@@ -549,9 +549,15 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
         auto grad_one = [&](int j, float4 a, float4 b, float2 c) {
             const int idx = start + j;
             const float cbl = c.x;
+            // the nine per-entry terms, summed over this lane's pixels (the
+            // first pixel assigns, so no add of zero is issued):
+            //   0, 1: dpow dx, dpow dy          (mean: Q times their sums)
+            //   2, 3, 4: dpow dx^2, dx dy, dy^2 (conic, factors at the atomic)
+            //   5: dpow                         (opacity: sum / o_t)
+            //   6, 7, 8: alpha T g              (colour)
+            // with dpow = dL/dalpha * alpha~, the gradient with respect to the
+            // exponent in natural units
             float d[9];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) d[q] = 0.0f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
@@ -560,33 +566,43 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
                 const float arg = gauss_arg(a, b.x, dx, dy, qx, qy);
                 const float ex = __builtin_amdgcn_exp2f(arg);
                 const float at = b.y * ex;
-                const float alpha = fminf(ALPHA_MAX, at);
                 const bool ok = (idx <= my_last[k]) && !(arg < c.y);   // alpha >= 1/255
                 any = any || ok;
+                // alpha of a blended entry, 0 otherwise (then it changes nothing below)
+                const float alpha = ok ? fminf(ALPHA_MAX, at) : 0.0f;
                 // transmittance in front of this entry
                 const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
                 T[k] = ok ? Tk : T[k];
-                const float wgt = ok ? alpha * Tk : 0.0f;
-                d[6] = fmaf(wgt, g0[k], d[6]);
-                d[7] = fmaf(wgt, g1[k], d[7]);
-                d[8] = fmaf(wgt, g2[k], d[8]);
+                const float wgt = alpha * Tk;
                 // dC/dalpha . g = T (g . c - g . B); then B <- B + alpha (c - B)
                 const float gc = fmaf(g2[k], cbl, fmaf(g1[k], b.w, g0[k] * b.z));
                 const float diff = gc - gB[k];
-                gB[k] = fmaf(ok ? alpha : 0.0f, diff, gB[k]);
+                gB[k] = fmaf(alpha, diff, gB[k]);
                 // no gradient through the 0.99 clamp
                 const float dalpha = (ok && at <= ALPHA_MAX) ? Tk * diff : 0.0f;
-                const float dpow = dalpha * at;   // dL / d(natural exponent)
-                d[5] = fmaf(dalpha, ex, d[5]);
-                // conic terms without their constant factors (-1/2, -1, -1/2:
-                // applied once per (tile, Gaussian, term) at the atomic); mean
-                // terms dpow Q d
+                const float dpow = dalpha * at;
                 const float pdx = dpow * dx, pdy = dpow * dy;
-                d[2] = fmaf(pdx, dx, d[2]);
-                d[3] = fmaf(pdx, dy, d[3]);
-                d[4] = fmaf(pdy, dy, d[4]);
-                d[0] = fmaf(dpow, qx, d[0]);
-                d[1] = fmaf(dpow, qy, d[1]);
+                if (k == 0) {
+                    d[0] = pdx;
+                    d[1] = pdy;
+                    d[2] = pdx * dx;
+                    d[3] = pdx * dy;
+                    d[4] = pdy * dy;
+                    d[5] = dpow;
+                    d[6] = wgt * g0[k];
+                    d[7] = wgt * g1[k];
+                    d[8] = wgt * g2[k];
+                } else {
+                    d[0] += pdx;
+                    d[1] += pdy;
+                    d[2] = fmaf(pdx, dx, d[2]);
+                    d[3] = fmaf(pdx, dy, d[3]);
+                    d[4] = fmaf(pdy, dy, d[4]);
+                    d[5] += dpow;
+                    d[6] = fmaf(wgt, g0[k], d[6]);
+                    d[7] = fmaf(wgt, g1[k], d[7]);
+                    d[8] = fmaf(wgt, g2[k], d[8]);
+                }
             }
             if (__ballot(any) == 0) return;   // no lane of this wave blends the entry
             wr[j >> 6] |= 1ull << (j & 63);
@@ -622,18 +638,34 @@ __device__ __forceinline__ void render_tile_bwd(int64_t tile, const float4 *__re
             for (int k = 0; k < NK; ++k) written[w][k] = wr[k];
         }
         __syncthreads();
-        // one thread per (entry, term): sum the written slots, one atomic
+        // one thread per (entry, term): sum the written slots, one atomic.
+        // Terms 0 and 1 hold the moments S = sum dpow d; the mean's gradient
+        // is Q S (d exponent / d mean = Q d), so their threads sum both.
         for (int i = t; i < cnt * 9; i += NT) {
             const int e = i / 9, q = i - 9 * e;
             const uint64_t bit = 1ull << (e & 63);
-            float sum = 0.0f;
+            const int i0 = (q < 2) ? i - q : i;
+            float sum = 0.0f, sum1 = 0.0f;
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
-                if (written[ww][e >> 6] & bit) sum += part[ww][i];
+                if (written[ww][e >> 6] & bit) {
+                    sum += part[ww][i0];
+                    if (q < 2) sum1 += part[ww][i0 + 1];
+                }
             }
-            // the conic terms' factors: d power / d(a, b, c) = (-dx^2/2, -dx dy, -dy^2/2)
-            const float fac = (q == 2 || q == 4) ? -0.5f : (q == 3 ? -1.0f : 1.0f);
-            if (sum != 0.0f) atomicAdd(gview + (int64_t)sG[e] * 9 + q, sum * fac);
+            float g;
+            if (q < 2) {
+                // (a, b) = sA.zw, c = sB.x
+                const float4 a = sA[e];
+                g = (q == 0) ? fmaf(a.z, sum, a.w * sum1) : fmaf(a.w, sum, sB[e].x * sum1);
+            } else if (q == 5) {
+                g = sum / sB[e].y;   // d alpha~ / d o_t = alpha~ / o_t
+            } else {
+                // the conic terms' factors: d exponent / d(a, b, c) = (-dx^2/2, -dx dy, -dy^2/2)
+                const float fac = (q == 2 || q == 4) ? -0.5f : (q == 3 ? -1.0f : 1.0f);
+                g = sum * fac;
+            }
+            if (g != 0.0f) atomicAdd(gview + (int64_t)sG[e] * 9 + q, g);
         }
     }
 }
