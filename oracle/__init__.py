@@ -39,6 +39,7 @@ _SIGS = {
     "or_conditional_f64": (_i32, [_p, _i64, _i64, _f64, _p, _p, _p]),
     "or_conditional_f32": (_i32, [_p, _i64, _i64, _f32, _p, _p, _p]),
     "or_conditional_cov_f64_all": (None, [_p, _i64, _f64, _p]),
+    "or_conditional_mean_f64_all": (None, [_p, _i64, _f64, _p]),
     "or_bin_sort": (_i64, [_p, _p, _p, _i64, _i32, _i32, _i32, _i64, _p, _p, _p]),
     "or_floor_skip_f32": (_i32, [_p, _f64, _f64]),
     "or_doubtful_decisions": (_i64, [_p, _i64, _p, _i32, _p, _p, _p, _i64, _p]),
@@ -49,6 +50,7 @@ _SIGS = {
     "or_pixel_variant": (_i64, [_p, _i64, _p, _i32, _p, _p, _i32, _i32, _i64, _i32, _p, _p, _p, _p,
                                 _i32]),
     "or_preprocess_bwd": (None, [_p, _i64, _p, _i32, _p, _p]),
+    "or_preprocess_bwd_mu": (None, [_p, _i64, _p, _i32, _p, _p, _p]),
     "or_preprocess_iso_bwd": (None, [_p, _i64, _p, _i32, _p, _p]),
     "or_grid_prune": (_i64, [_p, _p, _i32, _p, _i64, _f32, _f32, _i32, _i64, _p, _p, _p, _p]),
 }
@@ -174,6 +176,17 @@ def conditional_cov_all(params, t):
     out = np.zeros((P.shape[1], 9))
     lib().or_conditional_cov_f64_all(_ptr(P), P.shape[1], float(t), _ptr(out))
     return out.reshape(-1, 3, 3)
+
+
+def conditional_mean_all(params, views):
+    """FP64 conditional mean of every Gaussian at each view's time: [V, n, 3]
+    (zeros where degenerate)."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    v = _views(views)
+    out = np.zeros((v.shape[0], P.shape[1], 3))
+    for vi in range(v.shape[0]):
+        lib().or_conditional_mean_f64_all(_ptr(P), P.shape[1], float(v[vi, 18]), _ptr(out[vi]))
+    return out
 
 
 def conditional_f32(params, g, t):
@@ -338,13 +351,21 @@ def render_bwd(rec64, views, vals, ranges, dL_dimage, *, f32):
     return g
 
 
-def preprocess_bwd(params, views, grad_rec):
+def preprocess_bwd(params, views, grad_rec, grad_mu3=None):
+    """Chain rule (FP64) from grad_rec [V, n, 9] = d(mean2D, conic, o_t, rgb)
+    to d params [20, n]; grad_mu3 [V, n, 3] (optional) is a further gradient
+    with respect to the conditional mean at each view's time."""
     P = np.ascontiguousarray(params, dtype=np.float64)
     v = _views(views)
     n = P.shape[1]
     d = np.zeros((20, n))
-    lib().or_preprocess_bwd(_ptr(P), n, _ptr(v), v.shape[0],
-                            _ptr(np.ascontiguousarray(grad_rec, np.float64)), _ptr(d))
+    if grad_mu3 is None:
+        lib().or_preprocess_bwd(_ptr(P), n, _ptr(v), v.shape[0],
+                                _ptr(np.ascontiguousarray(grad_rec, np.float64)), _ptr(d))
+    else:
+        lib().or_preprocess_bwd_mu(_ptr(P), n, _ptr(v), v.shape[0],
+                                   _ptr(np.ascontiguousarray(grad_rec, np.float64)),
+                                   _ptr(np.ascontiguousarray(grad_mu3, np.float64)), _ptr(d))
     return d
 
 

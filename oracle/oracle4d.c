@@ -218,6 +218,18 @@ void or_conditional_cov_f64_all(const double *params, int64_t n, double t, doubl
     }
 }
 
+/* The FP64 conditional mean of every Gaussian at time t: mu3 [n][3] (zeros
+ * where degenerate). */
+void or_conditional_mean_f64_all(const double *params, int64_t n, double t, double *mu3)
+{
+    for (int64_t g = 0; g < n; ++g) {
+        double v[20], Sg[4][4], M[4][4], s[4], o, mu[3], Sc[3][3], ot;
+        for (int k = 0; k < 20; ++k) v[k] = params[(int64_t)k * n + g];
+        int ok = covariance_f64(v, Sg, M, s, &o) && conditional_f64(v, Sg, M, o, t, mu, Sc, &ot);
+        for (int i = 0; i < 3; ++i) mu3[3 * g + i] = ok ? mu[i] : 0.0;
+    }
+}
+
 /* The FP32 instance's conditional (the kernel's precision and evaluation
  * order): mu[3], Sc (row-major 3x3), o_t of Gaussian g at time t.  Returns
  * 0 if degenerate. */
@@ -786,10 +798,14 @@ static void proj_bwd_f64(const double *vw, const double mu[3], double Sc[3][3], 
 /* ------------------------------------------------------------------------- *
  * Preprocess backward (FP64): chain rule from d(mean2D, conic, o_t, rgb) per
  * (view, Gaussian) to the 20 raw parameters, summed over views.
+ * grad_mu3 (may be NULL): [n_views][n][3], a further gradient of the loss
+ * with respect to the conditional mean at the view's time (a colour that
+ * depends on the viewing direction puts one there); it joins the
+ * projection's before the conditional's chain rule.
  * dparams: [20][n], overwritten.
  * ------------------------------------------------------------------------- */
-void or_preprocess_bwd(const double *params, int64_t n, const double *views, int32_t n_views,
-                       const double *grad_rec, double *dparams)
+void or_preprocess_bwd_mu(const double *params, int64_t n, const double *views, int32_t n_views,
+                          const double *grad_rec, const double *grad_mu3, double *dparams)
 {
     memset(dparams, 0, sizeof(double) * 20 * (size_t)n);
     for (int32_t vi = 0; vi < n_views; ++vi) {
@@ -840,6 +856,8 @@ void or_preprocess_bwd(const double *params, int64_t n, const double *views, int
             const double ot = o * ef;
             double Gmu[3], GSc[3][3];
             proj_bwd_f64(vw, mu, Sc, G, Gmu, GSc);
+            if (grad_mu3)
+                for (i = 0; i < 3; ++i) Gmu[i] += grad_mu3[((int64_t)vi * n + g) * 3 + i];
             /* conditional -> Sigma blocks, mean, opacity */
             const double go = G[5];
             double Gmua = Gmu[0] * a3[0] + Gmu[1] * a3[1] + Gmu[2] * a3[2];
@@ -906,6 +924,12 @@ void or_preprocess_bwd(const double *params, int64_t n, const double *views, int
             for (k = 0; k < 3; ++k) dp[(int64_t)(17 + k) * n + g] += G[6 + k];
         }
     }
+}
+
+void or_preprocess_bwd(const double *params, int64_t n, const double *views, int32_t n_views,
+                       const double *grad_rec, double *dparams)
+{
+    or_preprocess_bwd_mu(params, n, views, n_views, grad_rec, NULL, dparams);
 }
 
 /* ------------------------------------------------------------------------- *
