@@ -112,6 +112,47 @@ int gs4d_preprocess_iso_bwd(const float *params, int64_t n, const gs4d_view *vie
                             float *dparams, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Sphericylindrical-harmonic (SCH) appearance: the view- and time-dependent
+ * colour of 4D Gaussian splatting that the paper replaces by one RGB value
+ * per Gaussian and ablates (Sec. 3.1, SCH equation; Sec. 4.4, the "w/o RGB"
+ * ablation).  Basis Z_{nl}^m(t, d) = cos(2 pi n t / T) Y_l^m(d), n = 0..N,
+ * l = 0..L, Y_l^m the real spherical harmonics (orthonormal on the sphere,
+ * no Condon-Shortley phase: Y_{1,1} = sqrt(3/4pi) x, Y_{1,-1} = sqrt(3/4pi) y),
+ * d the unit direction from the camera centre -R^T t to the Gaussian's
+ * conditional mean at the view's t.  Basis index b = n (L+1)^2 + l^2 + l + m;
+ * coefficients coef float [3 K][n], K = (N+1)(L+1)^2, row 3 b + channel;
+ * colour_c = sum_b coef[3 b + c] Z_b (no offset, no clamp).
+ *   gs4d_sch_rows(L, N)  rows of coef, 3 K (-1 if L or N is out of range)
+ *   gs4d_preprocess_sch  gs4d_preprocess of rotor-form params [20][n] whose
+ *       rows 17-19 are ignored: record slots 8-10 hold the SCH colour;
+ *       a (view, Gaussian) whose colour is not finite is culled.
+ *   gs4d_preprocess_sch_bwd  chain rule from grad2d [n_views][n][9]: dparams
+ *       [20][n] (rows 17-19 zero; the colour's dependence on the direction
+ *       joins the conditional mean's gradient) and dcoef [3 K][n], both
+ *       overwritten, summed over views.
+ *   gs4d_sch_from_rgb  coef with colour rgb [3][rgb_stride] (only the
+ *       n = 0, l = 0 row set: rgb / Y_00).
+ * ------------------------------------------------------------------------- */
+#define GS4D_SCH_MAX_DEGREE 3
+#define GS4D_SCH_MAX_FREQ 2
+typedef struct gs4d_sch {
+    int32_t degree;     /* L, 0..GS4D_SCH_MAX_DEGREE                      */
+    int32_t n_freq;     /* N, 0..GS4D_SCH_MAX_FREQ                        */
+    float period;       /* T > 0, in the views' time units                */
+    int32_t reserved;   /* must be 0                                      */
+} gs4d_sch;
+int64_t gs4d_sch_rows(int32_t degree, int32_t n_freq);
+int gs4d_preprocess_sch(const float *params, const float *coef, int64_t n, const gs4d_sch *sch,
+                        const gs4d_view *views, int32_t n_views, float *rec, int32_t *rect,
+                        int32_t *touched, void *stream);
+int gs4d_preprocess_sch_bwd(const float *params, const float *coef, int64_t n,
+                            const gs4d_sch *sch, const gs4d_view *views, int32_t n_views,
+                            const int32_t *touched, const float *grad2d, float *dparams,
+                            float *dcoef, void *stream);
+int gs4d_sch_from_rgb(const float *rgb, int64_t rgb_stride, int64_t n, const gs4d_sch *sch,
+                      float *coef, void *stream);
+
+/* ---------------------------------------------------------------------------
  * gs4d_bin_sort -- duplicate each visible (view, Gaussian) once per touched
  *   tile and sort the pairs by (tile, depth) (Sec. 3.1, the tile-based
  *   splatting renderer).

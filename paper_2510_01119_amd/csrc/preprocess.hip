@@ -13,6 +13,8 @@
 // square roots are the correctly rounded IEEE operations, and exp / ln are
 // the two project-defined FP32 routines below.  One thread handles one
 // (view, Gaussian); parameters are read as coalesced SoA planes.
+#include <cmath>
+
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -300,6 +302,86 @@ __device__ __forceinline__ void project_bwd(const gs4d_view &V, const Slice &S, 
     for (int j = 0; j < 3; ++j) Gmu[j] = Rt[j] * gx + Rt[4 + j] * gy + Rt[8 + j] * gz;
 }
 
+// Chain rule of one (view, Gaussian) of the rotor form from the gradients of
+// its conditional mean (Gmu), conditional covariance (GSc) and temporal
+// opacity (go) to the raw parameters 0-16 (mean, log scales, both
+// quaternions, opacity logit), added to acc.
+__device__ __forceinline__ void rotor_chain(const Slice &S, const float (&Gmu)[3],
+                                            const float (&GSc)[3][3], const float go,
+                                            float (&acc)[20]) {
+    // conditional -> (M, mu_t, opacity).  With K = [I | -a/c] the
+    // covariance part of the Sigma gradient is K^T GSc K, and since
+    // K M = P, its share of dL/dM = 2 G4 M is 2 K^T GSc P: rows 0-2 are
+    // 2 GSc P, row 3 is -2 (a/c)^T GSc P (no cancelling terms when
+    // s_t >> s_xyz).  The conditional mean and o_t add
+    // G4_mo = [[0, g/2], [g^T/2, h]] with g = Gmu dt / c and
+    // h = -(Gmu.a) dt / c^2 + go o_t dt^2 / (2 c^2).
+    const float c = S.Sg[3][3], ic = 1.0f / c;
+    const float dt = S.dt;
+    float Gmua = 0.0f;
+    for (int i = 0; i < 3; ++i) Gmua += Gmu[i] * S.Sg[i][3];
+    for (int i = 0; i < 3; ++i) acc[i] += Gmu[i];
+    acc[3] += -Gmua * ic + go * S.ot * dt * ic;
+    const float Gdo = go * S.ef;
+    float gv[3], kv[3];
+    for (int i = 0; i < 3; ++i) {
+        gv[i] = Gmu[i] * dt * ic;
+        kv[i] = S.Sg[i][3] * ic;
+    }
+    const float h = (-Gmua * dt + 0.5f * go * S.ot * dt * dt) * ic * ic;
+    float GM[4][4];
+    for (int j = 0; j < 4; ++j) {
+        float GP[3];
+        for (int i = 0; i < 3; ++i)
+            GP[i] = GSc[i][0] * S.P[0][j] + GSc[i][1] * S.P[1][j] + GSc[i][2] * S.P[2][j];
+        for (int i = 0; i < 3; ++i) GM[i][j] = 2.0f * GP[i] + gv[i] * S.M[3][j];
+        GM[3][j] = -2.0f * (kv[0] * GP[0] + kv[1] * GP[1] + kv[2] * GP[2]) +
+                   (gv[0] * S.M[0][j] + gv[1] * S.M[1][j] + gv[2] * S.M[2][j]) +
+                   2.0f * h * S.M[3][j];
+    }
+    float GR[4][4], Gs[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            GR[i][j] = GM[i][j] * S.s[j];
+            Gs[j] += GM[i][j] * S.R[i][j];
+        }
+    // R = Pi (A B) Pi^T
+    const int perm[4] = {1, 2, 3, 0};
+    float GQ[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) GQ[perm[i]][perm[j]] = GR[i][j];
+    float GA[4][4], GB[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            GA[i][j] = GQ[i][0] * S.B[j][0] + GQ[i][1] * S.B[j][1] + GQ[i][2] * S.B[j][2] +
+                       GQ[i][3] * S.B[j][3];
+            GB[i][j] = S.A[0][i] * GQ[0][j] + S.A[1][i] * GQ[1][j] + S.A[2][i] * GQ[2][j] +
+                       S.A[3][i] * GQ[3][j];
+        }
+    // each matrix entry is +- one quaternion component
+    float gl[4], gr[4];
+    gl[0] = GA[0][0] + GA[1][1] + GA[2][2] + GA[3][3];
+    gl[1] = -GA[0][1] + GA[1][0] - GA[2][3] + GA[3][2];
+    gl[2] = -GA[0][2] + GA[1][3] + GA[2][0] - GA[3][1];
+    gl[3] = -GA[0][3] - GA[1][2] + GA[2][1] + GA[3][0];
+    gr[0] = GB[0][0] + GB[1][1] + GB[2][2] + GB[3][3];
+    gr[1] = -GB[0][1] + GB[1][0] + GB[2][3] - GB[3][2];
+    gr[2] = -GB[0][2] - GB[1][3] + GB[2][0] + GB[3][1];
+    gr[3] = -GB[0][3] + GB[1][2] - GB[2][1] + GB[3][0];
+    float dl = 0.0f, dr = 0.0f;
+    for (int k = 0; k < 4; ++k) {
+        dl += S.ql[k] * gl[k];
+        dr += S.qr[k] * gr[k];
+    }
+    const float inl = 1.0f / S.nl, inr = 1.0f / S.nr;
+    for (int k = 0; k < 4; ++k) {
+        acc[4 + k] += Gs[k] * S.s[k];
+        acc[8 + k] += (gl[k] - S.ql[k] * dl) * inl;
+        acc[12 + k] += (gr[k] - S.qr[k] * dr) * inr;
+    }
+    acc[16] += Gdo * S.o * (1.0f - S.o);
+}
+
 // Backward: d(mean2D, conic, o_t, rgb) per (view, Gaussian) -> d(raw params),
 // summed over views.  Follows the forward above term by term (chain rule):
 // conic -> Sigma2D (dS = -Q dQ Q), Sigma2D -> (T, Sc), T = J W -> J -> camera
@@ -331,78 +413,7 @@ preprocess_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
         float Gmu[3], GSc[3][3];
         project_bwd(V, S, G, Gmu, GSc);
 
-        // conditional -> (M, mu_t, opacity).  With K = [I | -a/c] the
-        // covariance part of the Sigma gradient is K^T GSc K, and since
-        // K M = P, its share of dL/dM = 2 G4 M is 2 K^T GSc P: rows 0-2 are
-        // 2 GSc P, row 3 is -2 (a/c)^T GSc P (no cancelling terms when
-        // s_t >> s_xyz).  The conditional mean and o_t add
-        // G4_mo = [[0, g/2], [g^T/2, h]] with g = Gmu dt / c and
-        // h = -(Gmu.a) dt / c^2 + go o_t dt^2 / (2 c^2).
-        const float c = S.Sg[3][3], ic = 1.0f / c;
-        const float go = G[5];
-        const float dt = S.dt;
-        float Gmua = 0.0f;
-        for (int i = 0; i < 3; ++i) Gmua += Gmu[i] * S.Sg[i][3];
-        for (int i = 0; i < 3; ++i) acc[i] += Gmu[i];
-        acc[3] += -Gmua * ic + go * S.ot * dt * ic;
-        const float Gdo = go * S.ef;
-        float gv[3], kv[3];
-        for (int i = 0; i < 3; ++i) {
-            gv[i] = Gmu[i] * dt * ic;
-            kv[i] = S.Sg[i][3] * ic;
-        }
-        const float h = (-Gmua * dt + 0.5f * go * S.ot * dt * dt) * ic * ic;
-        float GM[4][4];
-        for (int j = 0; j < 4; ++j) {
-            float GP[3];
-            for (int i = 0; i < 3; ++i)
-                GP[i] = GSc[i][0] * S.P[0][j] + GSc[i][1] * S.P[1][j] + GSc[i][2] * S.P[2][j];
-            for (int i = 0; i < 3; ++i) GM[i][j] = 2.0f * GP[i] + gv[i] * S.M[3][j];
-            GM[3][j] = -2.0f * (kv[0] * GP[0] + kv[1] * GP[1] + kv[2] * GP[2]) +
-                       (gv[0] * S.M[0][j] + gv[1] * S.M[1][j] + gv[2] * S.M[2][j]) +
-                       2.0f * h * S.M[3][j];
-        }
-        float GR[4][4], Gs[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) {
-                GR[i][j] = GM[i][j] * S.s[j];
-                Gs[j] += GM[i][j] * S.R[i][j];
-            }
-        // R = Pi (A B) Pi^T
-        const int perm[4] = {1, 2, 3, 0};
-        float GQ[4][4];
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) GQ[perm[i]][perm[j]] = GR[i][j];
-        float GA[4][4], GB[4][4];
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) {
-                GA[i][j] = GQ[i][0] * S.B[j][0] + GQ[i][1] * S.B[j][1] + GQ[i][2] * S.B[j][2] +
-                           GQ[i][3] * S.B[j][3];
-                GB[i][j] = S.A[0][i] * GQ[0][j] + S.A[1][i] * GQ[1][j] + S.A[2][i] * GQ[2][j] +
-                           S.A[3][i] * GQ[3][j];
-            }
-        // each matrix entry is +- one quaternion component
-        float gl[4], gr[4];
-        gl[0] = GA[0][0] + GA[1][1] + GA[2][2] + GA[3][3];
-        gl[1] = -GA[0][1] + GA[1][0] - GA[2][3] + GA[3][2];
-        gl[2] = -GA[0][2] + GA[1][3] + GA[2][0] - GA[3][1];
-        gl[3] = -GA[0][3] - GA[1][2] + GA[2][1] + GA[3][0];
-        gr[0] = GB[0][0] + GB[1][1] + GB[2][2] + GB[3][3];
-        gr[1] = -GB[0][1] + GB[1][0] + GB[2][3] - GB[3][2];
-        gr[2] = -GB[0][2] - GB[1][3] + GB[2][0] + GB[3][1];
-        gr[3] = -GB[0][3] + GB[1][2] - GB[2][1] + GB[3][0];
-        float dl = 0.0f, dr = 0.0f;
-        for (int k = 0; k < 4; ++k) {
-            dl += S.ql[k] * gl[k];
-            dr += S.qr[k] * gr[k];
-        }
-        const float inl = 1.0f / S.nl, inr = 1.0f / S.nr;
-        for (int k = 0; k < 4; ++k) {
-            acc[4 + k] += Gs[k] * S.s[k];
-            acc[8 + k] += (gl[k] - S.ql[k] * dl) * inl;
-            acc[12 + k] += (gr[k] - S.qr[k] * dr) * inr;
-        }
-        acc[16] += Gdo * S.o * (1.0f - S.o);
+        rotor_chain(S, Gmu, GSc, G[5], acc);
         acc[17] += G[6];
         acc[18] += G[7];
         acc[19] += G[8];
@@ -495,6 +506,245 @@ preprocess_iso_bwd_kernel(const float *__restrict__ P, int64_t n, ViewPack vp,
     for (int k = 0; k < GS4D_ISO_FIELDS; ++k) dP[(int64_t)k * n + g] = acc[k];
 }
 
+
+// ---------------------------------------------------------------- SCH colour
+// The sphericylindrical-harmonic appearance of 4D Gaussian splatting (Sec.
+// 3.1, SCH equation): Z_{nl}^m(t, d) = cos(2 pi n t / T) Y_l^m(d) for
+// degrees l <= L and temporal frequencies n <= N, d the unit direction from
+// the camera centre to the conditional mean.  Y_l^m are the real spherical
+// harmonics, orthonormal on the sphere, without the Condon-Shortley phase
+// (Y_{1,1} = +c x, Y_{1,-1} = +c y), index l^2 + l + m, written as
+// polynomials in (x, y, z); basis b = n (L+1)^2 + l^2 + l + m, coefficient
+// row 3 b + channel.
+
+// normalisation constants: sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), times sqrt(2)
+// for m != 0, times the integer factor of each polynomial
+#define SH_C0 0.28209479177387814f   // 1 / (2 sqrt(pi))
+#define SH_C1 0.48860251190291992f   // sqrt(3 / (4 pi))
+#define SH_C2A 1.0925484305920792f   // sqrt(15 / (4 pi))
+#define SH_C2B 0.31539156525252005f  // sqrt(5 / (16 pi))
+#define SH_C2C 0.54627421529603959f  // sqrt(15 / (16 pi))
+#define SH_C3A 0.59004358992664352f  // sqrt(35 / (32 pi))
+#define SH_C3B 2.8906114426405538f   // sqrt(105 / (4 pi))
+#define SH_C3C 0.45704579946446572f  // sqrt(21 / (32 pi))
+#define SH_C3D 0.37317633259011540f  // sqrt(7 / (16 pi))
+#define SH_C3E 1.4453057213202769f   // sqrt(105 / (16 pi))
+
+template <int L>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float (&Y)[(L + 1) * (L + 1)]) {
+    Y[0] = SH_C0;
+    if constexpr (L >= 1) {
+        Y[1] = SH_C1 * y;
+        Y[2] = SH_C1 * z;
+        Y[3] = SH_C1 * x;
+    }
+    if constexpr (L >= 2) {
+        Y[4] = SH_C2A * (x * y);
+        Y[5] = SH_C2A * (y * z);
+        Y[6] = SH_C2B * (3.0f * (z * z) - 1.0f);
+        Y[7] = SH_C2A * (x * z);
+        Y[8] = SH_C2C * (x * x - y * y);
+    }
+    if constexpr (L >= 3) {
+        const float z5 = 5.0f * (z * z) - 1.0f;
+        Y[9] = SH_C3A * (y * (3.0f * (x * x) - y * y));
+        Y[10] = SH_C3B * (x * y * z);
+        Y[11] = SH_C3C * (y * z5);
+        Y[12] = SH_C3D * (z * (5.0f * (z * z) - 3.0f));
+        Y[13] = SH_C3C * (x * z5);
+        Y[14] = SH_C3E * (z * (x * x - y * y));
+        Y[15] = SH_C3A * (x * (x * x - 3.0f * (y * y)));
+    }
+}
+
+// sum_b w[b] grad Y_b at (x, y, z): the Cartesian gradient of the
+// polynomials above (their tangential part is what the normalisation of
+// the direction passes on)
+template <int L>
+__device__ __forceinline__ void sh_grad(float x, float y, float z,
+                                        const float (&w)[(L + 1) * (L + 1)], float (&g)[3]) {
+    g[0] = 0.0f;
+    g[1] = 0.0f;
+    g[2] = 0.0f;
+    if constexpr (L >= 1) {
+        g[0] += SH_C1 * w[3];
+        g[1] += SH_C1 * w[1];
+        g[2] += SH_C1 * w[2];
+    }
+    if constexpr (L >= 2) {
+        g[0] += SH_C2A * (w[4] * y + w[7] * z) + 2.0f * SH_C2C * w[8] * x;
+        g[1] += SH_C2A * (w[4] * x + w[5] * z) - 2.0f * SH_C2C * w[8] * y;
+        g[2] += SH_C2A * (w[5] * y + w[7] * x) + 6.0f * SH_C2B * w[6] * z;
+    }
+    if constexpr (L >= 3) {
+        const float z5 = 5.0f * (z * z) - 1.0f;
+        const float xx_yy = 3.0f * (x * x) - 3.0f * (y * y);
+        g[0] += SH_C3A * (6.0f * w[9] * (x * y) + w[15] * xx_yy) + SH_C3B * w[10] * (y * z) +
+                SH_C3C * w[13] * z5 + 2.0f * SH_C3E * w[14] * (x * z);
+        g[1] += SH_C3A * (w[9] * xx_yy - 6.0f * w[15] * (x * y)) + SH_C3B * w[10] * (x * z) +
+                SH_C3C * w[11] * z5 - 2.0f * SH_C3E * w[14] * (y * z);
+        g[2] += SH_C3B * w[10] * (x * y) + 10.0f * SH_C3C * z * (w[11] * y + w[13] * x) +
+                SH_C3D * w[12] * (15.0f * (z * z) - 3.0f) + SH_C3E * w[14] * (x * x - y * y);
+    }
+}
+
+// Unnormalised viewing direction v = mu_c - C (C = -R^T t the camera
+// centre), its length and unit direction.
+__device__ __forceinline__ void view_dir(const gs4d_view &V, const float (&mu)[3], float (&d)[3],
+                                         float &len) {
+    const float *Rt = V.Rt;
+    float v[3];
+    for (int j = 0; j < 3; ++j) {
+        const float Cj = -(Rt[j] * Rt[3] + Rt[4 + j] * Rt[7] + Rt[8 + j] * Rt[11]);
+        v[j] = mu[j] - Cj;
+    }
+    len = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const float il = 1.0f / len;
+    for (int j = 0; j < 3; ++j) d[j] = v[j] * il;
+}
+
+__device__ __forceinline__ float sch_time_factor(int f, float t, float period) {
+    return f == 0 ? 1.0f : cosf((6.28318530717958648f * (float)f) * t / period);
+}
+
+template <int L>
+__global__ void __launch_bounds__(256)
+preprocess_sch_fwd_kernel(const float *__restrict__ P, const float *__restrict__ coef, int64_t n,
+                          int n_freq, float period, ViewPack vp, float4 *__restrict__ rec,
+                          int4 *__restrict__ rect, int32_t *__restrict__ touched) {
+    constexpr int NB = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int vi = blockIdx.y;
+    if (g >= n) return;
+    float p[20];
+#pragma unroll
+    for (int k = 0; k < 17; ++k) p[k] = P[(int64_t)k * n + g];
+    p[17] = p[18] = p[19] = 0.0f;   // the colour comes from the coefficients
+    Slice S;
+    int4 rc = make_int4(0, 0, 0, 0);
+    const gs4d_view &V = vp.v[vi];
+    const int vis = slice_project(p, V, S, &rc);
+    const int64_t o = (int64_t)vi * n + g;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    int tt = 0;
+    if (vis) {
+        float d[3], len;
+        view_dir(V, S.mu, d, len);
+        float Y[NB];
+        sh_eval<L>(d[0], d[1], d[2], Y);
+        float col[3] = {0.0f, 0.0f, 0.0f};
+        for (int f = 0; f <= n_freq; ++f) {
+            const float tf = sch_time_factor(f, V.t, period);
+            const float *cf = coef + (int64_t)(f * NB) * 3 * n + g;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float w = tf * Y[b];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) col[c] += w * cf[(int64_t)(3 * b + c) * n];
+            }
+        }
+        if (isfinite(col[0]) && isfinite(col[1]) && isfinite(col[2])) {
+            r0 = make_float4(S.mx, S.my, S.ca, S.cb);
+            r1 = make_float4(S.cc, S.ot, S.xc[2], S.hx);
+            r2 = make_float4(col[0], col[1], col[2], S.hy);
+            tt = (rc.z - rc.x) * (rc.w - rc.y);
+        } else {
+            rc = make_int4(0, 0, 0, 0);   // non-finite coefficients: culled
+        }
+    } else {
+        rc = make_int4(0, 0, 0, 0);
+    }
+    rec[3 * o + 0] = r0;
+    rec[3 * o + 1] = r1;
+    rec[3 * o + 2] = r2;
+    rect[o] = rc;
+    touched[o] = tt;
+}
+
+// Backward of the SCH form, summed over views: the colour gradient g_c of
+// each (view, Gaussian) gives d coef_{b,c} = Z_b g_c and, through the
+// viewing direction, d mu_c = (I - d d^T) / |v| sum_b w_b grad Y_b with
+// w_b = sum_n cos(.) sum_c g_c coef; that joins the projection's d mu_c
+// ahead of the rotor form's chain rule.  dparams rows 17-19 are zero.
+template <int L>
+__global__ void __launch_bounds__(128, 3)
+preprocess_sch_bwd_kernel(const float *__restrict__ P, const float *__restrict__ coef, int64_t n,
+                          int n_freq, float period, ViewPack vp,
+                          const int32_t *__restrict__ touched, const float *__restrict__ grad2d,
+                          float *__restrict__ dP, float *__restrict__ dcoef) {
+    constexpr int NB = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    float p[20];
+#pragma unroll
+    for (int k = 0; k < 17; ++k) p[k] = P[(int64_t)k * n + g];
+    p[17] = p[18] = p[19] = 0.0f;
+    float acc[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) acc[k] = 0.0f;
+    const int64_t rows = (int64_t)(n_freq + 1) * NB * 3;
+    bool first = true;
+
+    for (int vi = 0; vi < vp.n_views; ++vi) {
+        const int64_t o = (int64_t)vi * n + g;
+        if (touched[o] == 0) continue;
+        const gs4d_view &V = vp.v[vi];
+        Slice S;
+        if (!slice_project(p, V, S, nullptr)) continue;
+        float G[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) G[k] = grad2d[o * 9 + k];
+        float Gmu[3], GSc[3][3];
+        project_bwd(V, S, G, Gmu, GSc);
+
+        float d[3], len;
+        view_dir(V, S.mu, d, len);
+        float Y[NB], w[NB];
+        sh_eval<L>(d[0], d[1], d[2], Y);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) w[b] = 0.0f;
+        for (int f = 0; f <= n_freq; ++f) {
+            const float tf = sch_time_factor(f, V.t, period);
+            const int64_t base = (int64_t)(f * NB) * 3 * n + g;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float wc = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t idx = base + (int64_t)(3 * b + c) * n;
+                    wc += G[6 + c] * coef[idx];
+                    const float dv = (tf * Y[b]) * G[6 + c];
+                    dcoef[idx] = first ? dv : dcoef[idx] + dv;
+                }
+                w[b] += tf * wc;
+            }
+        }
+        first = false;
+        float gd[3];
+        sh_grad<L>(d[0], d[1], d[2], w, gd);
+        const float radial = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+        const float il = 1.0f / len;
+        for (int j = 0; j < 3; ++j) Gmu[j] += (gd[j] - d[j] * radial) * il;
+
+        rotor_chain(S, Gmu, GSc, G[5], acc);
+    }
+    if (first)
+        for (int64_t r = 0; r < rows; ++r) dcoef[r * n + g] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 20; ++k) dP[(int64_t)k * n + g] = acc[k];
+}
+
+// Coefficients whose colour is the constant rgb: only the n = 0, l = 0
+// basis, coef = rgb / Y_00 = 2 sqrt(pi) rgb; every other row zero.
+__global__ void __launch_bounds__(256)
+sch_from_rgb_kernel(const float *__restrict__ rgb, int64_t rgb_stride, int64_t n, int64_t rows,
+                    float *__restrict__ coef) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    for (int c = 0; c < 3; ++c) coef[(int64_t)c * n + g] = rgb[c * rgb_stride + g] / SH_C0;
+    for (int64_t r = 3; r < rows; ++r) coef[r * n + g] = 0.0f;
+}
+
 }  // namespace
 
 }  // namespace gs4d
@@ -560,5 +810,86 @@ extern "C" int gs4d_preprocess_iso_bwd(const float *params, int64_t n, const gs4
     preprocess_iso_bwd_kernel<<<blocks, 128, 0, as_stream(stream)>>>(params, n, vp, touched,
                                                                      grad2d, dparams);
     GS4D_LAUNCH_CHECK("gs4d_preprocess_iso_bwd");
+    return GS4D_OK;
+}
+
+namespace {
+int check_sch(const gs4d_sch *sch, const char *what) {
+    GS4D_REQUIRE(sch != nullptr, "%s: null gs4d_sch", what);
+    GS4D_REQUIRE(sch->degree >= 0 && sch->degree <= GS4D_SCH_MAX_DEGREE,
+                 "%s: SCH degree %d outside [0, %d]", what, sch->degree, GS4D_SCH_MAX_DEGREE);
+    GS4D_REQUIRE(sch->n_freq >= 0 && sch->n_freq <= GS4D_SCH_MAX_FREQ,
+                 "%s: SCH temporal frequencies %d outside [0, %d]", what, sch->n_freq,
+                 GS4D_SCH_MAX_FREQ);
+    GS4D_REQUIRE(sch->period > 0.0f && std::isfinite(sch->period), "%s: SCH period must be > 0", what);
+    GS4D_REQUIRE(sch->reserved == 0, "%s: gs4d_sch.reserved must be 0", what);
+    return GS4D_OK;
+}
+}  // namespace
+
+extern "C" int64_t gs4d_sch_rows(int32_t degree, int32_t n_freq) {
+    if (degree < 0 || degree > GS4D_SCH_MAX_DEGREE || n_freq < 0 || n_freq > GS4D_SCH_MAX_FREQ)
+        return -1;
+    return (int64_t)3 * (n_freq + 1) * (degree + 1) * (degree + 1);
+}
+
+extern "C" int gs4d_preprocess_sch(const float *params, const float *coef, int64_t n,
+                                   const gs4d_sch *sch, const gs4d_view *views, int32_t n_views,
+                                   float *rec, int32_t *rect, int32_t *touched, void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_TRY(check_sch(sch, "gs4d_preprocess_sch"));
+    GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "gs4d_preprocess_sch: n out of range");
+    if (n == 0) return GS4D_OK;
+    GS4D_REQUIRE(params && coef && rec && rect && touched, "gs4d_preprocess_sch: null pointer");
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
+    hipStream_t st = as_stream(stream);
+    float4 *r4 = reinterpret_cast<float4 *>(rec);
+    int4 *q4 = reinterpret_cast<int4 *>(rect);
+    switch (sch->degree) {
+    case 0: preprocess_sch_fwd_kernel<0><<<grid, 256, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, r4, q4, touched); break;
+    case 1: preprocess_sch_fwd_kernel<1><<<grid, 256, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, r4, q4, touched); break;
+    case 2: preprocess_sch_fwd_kernel<2><<<grid, 256, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, r4, q4, touched); break;
+    default: preprocess_sch_fwd_kernel<3><<<grid, 256, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, r4, q4, touched); break;
+    }
+    GS4D_LAUNCH_CHECK("gs4d_preprocess_sch");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_preprocess_sch_bwd(const float *params, const float *coef, int64_t n,
+                                       const gs4d_sch *sch, const gs4d_view *views,
+                                       int32_t n_views, const int32_t *touched,
+                                       const float *grad2d, float *dparams, float *dcoef,
+                                       void *stream) {
+    ViewPack vp;
+    GS4D_TRY(make_view_pack(views, n_views, &vp));
+    GS4D_TRY(check_sch(sch, "gs4d_preprocess_sch_bwd"));
+    GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "gs4d_preprocess_sch_bwd: n out of range");
+    if (n == 0) return GS4D_OK;
+    GS4D_REQUIRE(params && coef && touched && grad2d && dparams && dcoef,
+                 "gs4d_preprocess_sch_bwd: null pointer");
+    const unsigned blocks = (unsigned)((n + 127) / 128);
+    hipStream_t st = as_stream(stream);
+    switch (sch->degree) {
+    case 0: preprocess_sch_bwd_kernel<0><<<blocks, 128, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, touched, grad2d, dparams, dcoef); break;
+    case 1: preprocess_sch_bwd_kernel<1><<<blocks, 128, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, touched, grad2d, dparams, dcoef); break;
+    case 2: preprocess_sch_bwd_kernel<2><<<blocks, 128, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, touched, grad2d, dparams, dcoef); break;
+    default: preprocess_sch_bwd_kernel<3><<<blocks, 128, 0, st>>>(params, coef, n, sch->n_freq, sch->period, vp, touched, grad2d, dparams, dcoef); break;
+    }
+    GS4D_LAUNCH_CHECK("gs4d_preprocess_sch_bwd");
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_sch_from_rgb(const float *rgb, int64_t rgb_stride, int64_t n,
+                                 const gs4d_sch *sch, float *coef, void *stream) {
+    GS4D_TRY(check_sch(sch, "gs4d_sch_from_rgb"));
+    GS4D_REQUIRE(n >= 0 && n <= (int64_t)0x7fffffff, "gs4d_sch_from_rgb: n out of range");
+    GS4D_REQUIRE(rgb_stride >= n, "gs4d_sch_from_rgb: rgb_stride < n");
+    if (n == 0) return GS4D_OK;
+    GS4D_REQUIRE(rgb && coef, "gs4d_sch_from_rgb: null pointer");
+    const int64_t rows = gs4d_sch_rows(sch->degree, sch->n_freq);
+    sch_from_rgb_kernel<<<(unsigned)((n + 255) / 256), 256, 0, as_stream(stream)>>>(
+        rgb, rgb_stride, n, rows, coef);
+    GS4D_LAUNCH_CHECK("gs4d_sch_from_rgb");
     return GS4D_OK;
 }

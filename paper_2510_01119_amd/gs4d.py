@@ -47,6 +47,17 @@ class gs4d_render_opts(ctypes.Structure):
                 ("queue", ctypes.c_void_p)]
 
 
+class gs4d_sch(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("n_freq", ctypes.c_int32), ("period", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
+def make_sch(degree: int, n_freq: int, period: float) -> gs4d_sch:
+    s = gs4d_sch()
+    s.degree, s.n_freq, s.period, s.reserved = int(degree), int(n_freq), float(period), 0
+    return s
+
+
 class gs4d_adam_cfg(ctypes.Structure):
     _fields_ = [("lr0", ctypes.c_float * N_FIELDS), ("lr1", ctypes.c_float * N_FIELDS),
                 ("budget", ctypes.c_int32), ("rows", ctypes.c_int32), ("beta1", ctypes.c_float),
@@ -74,6 +85,10 @@ _SIGS = {
     "gs4d_preprocess_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "gs4d_preprocess_iso": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
     "gs4d_preprocess_iso_bwd": (_i32, [_p, _i64, _p, _i32, _p, _p, _p, _p]),
+    "gs4d_sch_rows": (_i64, [_i32, _i32]),
+    "gs4d_preprocess_sch": (_i32, [_p, _p, _i64, _p, _p, _i32, _p, _p, _p, _p]),
+    "gs4d_preprocess_sch_bwd": (_i32, [_p, _p, _i64, _p, _p, _i32, _p, _p, _p, _p, _p]),
+    "gs4d_sch_from_rgb": (_i32, [_p, _i64, _i64, _p, _p, _p]),
     "gs4d_otsu_workspace_size": (_sz, []),
     "gs4d_otsu_mask": (_i32, [_p, _i64, _p, _p, _p, _sz, _p]),
     "gs4d_set_bwd_variant": (_i32, [_i32]),
@@ -269,6 +284,45 @@ def gs4d_preprocess_iso_bwd(params, touched, grad2d, views, dparams, stream=None
                                          _ptr(touched), _ptr(grad2d), _ptr(dparams),
                                          _stream(stream)),
            "gs4d_preprocess_iso_bwd")
+
+
+def gs4d_sch_rows(degree, n_freq):
+    return int(lib().gs4d_sch_rows(degree, n_freq))
+
+
+def _sch_shape(coef, sch, n):
+    rows = gs4d_sch_rows(sch.degree, sch.n_freq)
+    if tuple(coef.shape) != (rows, n):
+        raise GS4DError(f"SCH coefficients must be [{rows}, {n}], got {tuple(coef.shape)}")
+
+
+def gs4d_preprocess_sch(params, coef, sch, views, rec, rect, touched, stream=None):
+    """Preprocess with the SCH colour: rotor-form params [20][n] (rows 17-19
+    ignored), coefficients [3 K][n]."""
+    _sch_shape(coef, sch, params.shape[1])
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_preprocess_sch(_ptr(params), _ptr(coef), params.shape[1], ctypes.byref(sch),
+                                     va, len(va), _ptr(rec), _ptr(rect), _ptr(touched),
+                                     _stream(stream)), "gs4d_preprocess_sch")
+
+
+def gs4d_preprocess_sch_bwd(params, coef, sch, touched, grad2d, views, dparams, dcoef,
+                            stream=None):
+    _sch_shape(coef, sch, params.shape[1])
+    _sch_shape(dcoef, sch, params.shape[1])
+    va = views if isinstance(views, ctypes.Array) else make_views(views)
+    _check(lib().gs4d_preprocess_sch_bwd(_ptr(params), _ptr(coef), params.shape[1],
+                                         ctypes.byref(sch), va, len(va), _ptr(touched),
+                                         _ptr(grad2d), _ptr(dparams), _ptr(dcoef),
+                                         _stream(stream)), "gs4d_preprocess_sch_bwd")
+
+
+def gs4d_sch_from_rgb(rgb, sch, coef, stream=None):
+    """rgb: [3, n] view of a parameter block (row stride rgb.stride(0))."""
+    n = rgb.shape[1]
+    _sch_shape(coef, sch, n)
+    _check(lib().gs4d_sch_from_rgb(_ptr_rows(rgb, 3), rgb.stride(0), n, ctypes.byref(sch), _ptr(coef),
+                                   _stream(stream)), "gs4d_sch_from_rgb")
 
 
 def gs4d_otsu_workspace_size():

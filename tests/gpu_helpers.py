@@ -47,7 +47,7 @@ def near_threshold_pixels(rec64, views, vals, ranges):
     return oracle.doubtful_decisions(rec64, views, vals, ranges)[0]
 
 
-def decision_bounds(params, views, rec64, vals, ranges, dL_dimage, iso=False):
+def decision_bounds(params, views, rec64, vals, ranges, dL_dimage, iso=False, chain=None):
     """What each doubtful decision can change, computed by the oracle: the
     pixel re-composited with that one decision inverted, against the pixel as
     the oracle takes it (its decisions taken on the FP32 shadow of the
@@ -57,18 +57,25 @@ def decision_bounds(params, views, rec64, vals, ranges, dL_dimage, iso=False):
     final transmittance, grad [F, n]: the summed |change| of each
     parameter's gradient, chained through the preprocess backward (FP64)).
     An FP32 render that takes any of these decisions the other way differs
-    from the oracle by at most these amounts (plus its own rounding)."""
+    from the oracle by at most these amounts (plus its own rounding).
+    chain(v, g [1, n, 9]) -> [F, n], if given, is the (linear) chain rule
+    from view v's record gradient to the parameters, in place of the rotor
+    or isotropic preprocess backward."""
     views = np.atleast_2d(views)
     V, n, _ = rec64.shape
     flag, found = oracle.doubtful_decisions(rec64, views, vals, ranges)
     H, W = flag.shape[1:]
     img = np.zeros((V, H, W))
     Tb = np.zeros((V, H, W))
-    F = oracle.ISO_FIELDS if iso else 20
+    if chain is None:
+        bwd = oracle.preprocess_iso_bwd if iso else oracle.preprocess_bwd
+
+        def chain(v, g):
+            return bwd(params.astype(np.float64), views[v:v + 1], g)
+    F = chain(0, np.zeros((1, n, 9))).shape[0]
     grad = np.zeros((F, n))
     if not found:
         return flag, img, Tb, grad
-    bwd = oracle.preprocess_iso_bwd if iso else oracle.preprocess_bwd
     tx, ty = (W + 15) // 16, (H + 15) // 16
     # the preprocess backward is linear in the record gradient: its
     # columns per view, from one call per record term
@@ -78,7 +85,7 @@ def decision_bounds(params, views, rec64, vals, ranges, dL_dimage, iso=False):
         for j in range(9):
             g = np.zeros((1, n, 9))
             g[0, :, j] = 1.0
-            cols.append(bwd(params.astype(np.float64), views[v:v + 1], g))
+            cols.append(chain(v, g))
         J[v] = np.stack(cols)                       # [9, F, n]
     base = {}
     for v, x, y, e, kind in found:

@@ -85,6 +85,22 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.gs4d_adam_step(d, d, d, d, 10, ctypes.byref(cfg), d, None) == -1
     # ssim: bad shape
     assert lib.gs4d_ssim(d, d, 0, 3, 8, 8, 1.0, d, None, None, 0, None) == -1
+    # SCH: degree, frequencies, period, reserved word; row counts
+    assert lib.gs4d_sch_rows(3, 2) == 3 * 3 * 16
+    assert lib.gs4d_sch_rows(0, 0) == 3
+    assert lib.gs4d_sch_rows(4, 0) == -1 and lib.gs4d_sch_rows(0, 3) == -1
+    for deg, nf, per, res in ((4, 0, 1.0, 0), (0, -1, 1.0, 0), (1, 1, 0.0, 0),
+                              (1, 1, float("inf"), 0), (1, 1, 1.0, 7)):
+        sch = gs4d.gs4d_sch()
+        sch.degree, sch.n_freq, sch.period, sch.reserved = deg, nf, per, res
+        st = lib.gs4d_preprocess_sch(d, d, 10, ctypes.byref(sch), views, 1, d, d, d, None)
+        assert st == -1 and b"SCH" in lib.gs4d_last_error() or b"reserved" in lib.gs4d_last_error()
+        st = lib.gs4d_preprocess_sch_bwd(d, d, 10, ctypes.byref(sch), views, 1, d, d, d, d, None)
+        assert st == -1
+    sch = gs4d.make_sch(2, 1, 2.0)
+    st = lib.gs4d_preprocess_sch_bwd(d, d, 10, ctypes.byref(sch), views, 1, d, d, d, None, None)
+    assert st == -1 and b"null" in lib.gs4d_last_error()
+    assert lib.gs4d_sch_from_rgb(d, 5, 10, ctypes.byref(sch), d, None) == -1
 
 
 def test_workspace_queries(lib):
