@@ -196,6 +196,8 @@ def main():
                     help="skip the forward-only frame-rate leg at display sizes")
     ap.add_argument("--no-iso", action="store_true",
                     help="skip the isotropic, motion-aware form's leg (throughput and ablation)")
+    ap.add_argument("--no-sch", action="store_true",
+                    help="skip the SCH colour's leg (throughput and the w/o-RGB ablation)")
     ap.add_argument("--no-scene-prep", action="store_true",
                     help="skip the leg that builds the scene with the Otsu split and adaptive voxels")
     ap.add_argument("--seed", type=int, default=1)
@@ -411,6 +413,8 @@ def main():
         line["time_to_psnr"] = time_to_psnr_leg(params, views, images, pruned)
     if args.workload == "scene" and not args.no_iso:
         line["iso_form"] = iso_leg(params, views, images, args.seed)
+    if args.workload == "scene" and not args.no_sch:
+        line["sch_form"] = sch_leg(params, views, images, args.seed)
     if args.workload == "scene" and not args.no_scene_prep:
         line["scene_prep"] = scene_prep_leg(params, views, images, args.seed)
     print(json.dumps(line), flush=True)
@@ -495,41 +499,118 @@ def iso_leg(params, views, images, seed, steps=200, warmup=20, budget=1500):
     return out
 
 
-def scene_prep_leg(params_gt, views, images_gt, seed, steps=1500):
-    """The same synthetic scene prepared the paper's way (Sec. 3.2): the
-    motion class from the Otsu split of a noisy low-resolution motion
-    probability map, and adaptive voxel edges S_v = 4 mean(D / f) for static
-    and dynamic points (the Lite setting).  Reports the build time, S_v, the
-    mask's IoU with the ground truth, the pruned count, and the held-out
-    PSNR after `steps` single-frame steps beside the default preparation
-    (ground-truth mask, 0.01 voxels)."""
+def sch_leg(params, views, images, seed, steps=200, warmup=20, budget=1500, degree=3, n_freq=2,
+            period=2.0):
+    """The sphericylindrical-harmonic colour the paper ablates (Sec. 4.4,
+    "w/o RGB"; Sec. 3.1, SCH equation) on the same scene and heuristic
+    initialisation, coefficients started from its RGB: training
+    iterations/s (graph replays, render launches autotuned as for the RGB
+    form) and, at a fixed budget of `budget` single-frame steps in the same
+    frame order, held-out PSNR (every 10th frame) of RGB against SCH of
+    degree `degree` with `n_freq` temporal frequencies (period `period`,
+    twice the sequence in normalised time)."""
     import torch
-    from paper_2510_01119_amd.scene import build_scene
+    from paper_2510_01119_amd import autotune
+    from paper_2510_01119_amd import gs4d as G
     from paper_2510_01119_amd.train import Trainer
+    F = len(views)
+    rng = np.random.default_rng(seed + 11)
+    sample = range(0, F, max(1, F // 20))
+    sch = G.make_sch(degree, n_freq, period)
+    rows = G.gs4d_sch_rows(degree, n_freq)
+    tr = Trainer(params.clone(), views, images, budget=5000, sch=sch)
+    tr.size_pairs(sample, margin=2.0)
+    seq = rng.integers(0, F, warmup + steps)
+    for i in range(warmup):
+        tr.step(int(seq[i]))
+    tr.forward_loss(int(seq[0]))
+    autotune.tune(tr.rast, tr.params, tr.dimg)
+    tr.capture(sorted(set(int(f) for f in seq[warmup:])))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sc, images, params, info = build_scene(seed=0, device="cuda", motion="otsu", voxel="adaptive")
+    for i in range(steps):
+        tr.step_graph(int(seq[warmup + i]))
     torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    F = len(views)
-    rng = np.random.default_rng(seed + 9)
+    dt = time.perf_counter() - t0
+    if int(tr.overflow_seen.item()) != 0:
+        raise RuntimeError("pair capacity overflowed in the SCH form's timed steps")
+    out = {"iters_per_s": round(steps / dt, 1), "ms_per_step": round(1e3 * dt / steps, 4),
+           "degree": degree, "n_freq": n_freq, "period": period,
+           "floats_per_gaussian": 17 + rows}
+    del tr
+    torch.cuda.empty_cache()
     held = list(range(5, F, 10))
-    order = rng.choice([f for f in range(F) if f % 10 != 5], size=steps)
+    order = rng.choice([f for f in range(F) if f % 10 != 5], size=budget)
     psnr = {}
-    for name, p0, imgs in (("paper (otsu, adaptive voxels)", params, images),
-                           ("default (ground-truth mask, 0.01 voxels)", params_gt, images_gt)):
-        t = Trainer(p0.clone(), views, imgs, budget=steps)
-        t.size_pairs(range(0, F, max(1, F // 20)), margin=2.0)
+    for name, s in (("rgb (the paper's)", None),
+                    (f"SCH degree {degree}, {n_freq} temporal frequencies (w/o RGB)", sch)):
+        t = Trainer(params.clone(), views, images, budget=budget, sch=s)
+        t.size_pairs(sample, margin=2.0)
         for f in order:
             t.step(int(f))
         psnr[name] = round(t.psnr(held), 3) if int(t.overflow_seen.item()) == 0 else None
         del t
         torch.cuda.empty_cache()
-    out = {"build_s": round(build_s, 2), "voxel_static": round(info["voxel_static"], 6),
-           "voxel_dynamic": round(info["voxel_dynamic"], 6),
-           "depth_over_f": round(info["depth_over_f"], 7), "mask_iou": round(info["mask_iou"], 4),
-           "n_raw_points": info["n_raw_points"], "n_gaussians": info["n_gaussians"],
-           "n_dynamic": info["n_dynamic"], "psnr_db_after_steps": steps, "psnr_db": psnr}
+    out["ablation"] = {"steps": budget, "heldout_frames": len(held), "psnr_db": psnr}
+    log(f"bench: SCH form {json.dumps(out)}")
+    return out
+
+
+def scene_prep_leg(params_gt, views, images_gt, seed, steps=1500):
+    """The same synthetic scene prepared the paper's ways (Sec. 3.2, Sec.
+    4.1): the motion class from the Otsu split of a noisy low-resolution
+    motion-probability map, adaptive voxel edges S_v = lambda mean(D / f),
+    and the two settings -- Lite (lambda 4 for static and dynamic points)
+    and Full (lambda 1 for static points, dynamic points unpruned).  Per
+    preset: build time, S_v, the mask's IoU with the ground truth, the
+    Gaussian counts, training iterations/s and the held-out PSNR after
+    `steps` single-frame steps (one frame order for all), beside the default
+    preparation (ground-truth mask, 0.01 voxels)."""
+    import torch
+    from paper_2510_01119_amd.scene import build_scene
+    from paper_2510_01119_amd.train import Trainer
+    F = len(views)
+    rng = np.random.default_rng(seed + 9)
+    held = list(range(5, F, 10))
+    order = rng.choice([f for f in range(F) if f % 10 != 5], size=steps)
+
+    def train(p0, imgs):
+        t = Trainer(p0.clone(), views, imgs, budget=steps)
+        t.size_pairs(range(0, F, max(1, F // 20)), margin=2.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in order:
+            t.step(int(f))
+        torch.cuda.synchronize()
+        rate = steps / (time.perf_counter() - t0)
+        ok = int(t.overflow_seen.item()) == 0
+        psnr = round(t.psnr(held), 3) if ok else None
+        del t
+        torch.cuda.empty_cache()
+        return psnr, round(rate, 1)
+
+    out = {"psnr_db_after_steps": steps, "presets": {}}
+    for preset in ("lite", "full"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sc, images, params, info = build_scene(seed=0, device="cuda", preset=preset)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        del sc
+        psnr, rate = train(params, images)
+        out["presets"][preset] = {
+            "build_s": round(build_s, 2), "voxel_static": round(info["voxel_static"], 6),
+            "voxel_dynamic": round(info["voxel_dynamic"], 6), "mask_iou": round(info["mask_iou"], 4),
+            "n_gaussians": info["n_gaussians"], "n_dynamic": info["n_dynamic"],
+            "iters_per_s": rate, "psnr_db": psnr}
+        out["depth_over_f"] = round(info["depth_over_f"], 7)
+        out["n_raw_points"] = info["n_raw_points"]
+        del images, params
+        torch.cuda.empty_cache()
+    psnr, rate = train(params_gt, images_gt)
+    out["default"] = {"motion": "ground-truth mask", "voxel": 0.01,
+                      "n_gaussians": int(params_gt.shape[1]), "iters_per_s": rate,
+                      "psnr_db": psnr}
     log(f"bench: scene prep {json.dumps(out)}")
     return out
 

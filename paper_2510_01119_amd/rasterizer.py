@@ -71,6 +71,9 @@ class Rasterizer:
         # bumped by every forward: the state a backward reads belongs to the
         # latest forward only
         self.generation = 0
+        # SCH appearance (set_sch): the colour comes from these coefficients
+        self.sch = None
+        self.coef = None
         self._alloc_pairs(pair_capacity if pair_capacity else max(1 << 16, 8 * n * V))
 
     def set_views(self, views):
@@ -92,11 +95,25 @@ class Rasterizer:
         ws = G.gs4d_bin_sort_workspace_size(self.n, self.V, self.capacity)
         self.ws = torch.zeros(ws, dtype=torch.uint8, device=dev)
 
+    def set_sch(self, sch, coef):
+        """Take the colour of rotor-form parameters from sphericylindrical-
+        harmonic coefficients coef [3 K, n] (gs4d_preprocess_sch) instead of
+        their rows 17-19; sch=None returns to the RGB colour."""
+        if sch is not None:
+            assert tuple(coef.shape) == (G.gs4d_sch_rows(sch.degree, sch.n_freq), self.n)
+        self.sch, self.coef = sch, coef
+
     # ------------------------------------------------------------------ stages
     def preprocess(self, params: torch.Tensor):
         """Rotor-form parameters [20, n], or the isotropic, motion-aware form
-        [13, n] (gs4d_preprocess_iso); the outputs are the same."""
-        if params.shape[0] == G.ISO_FIELDS:
+        [13, n] (gs4d_preprocess_iso); the outputs are the same.  With
+        set_sch, rotor-form parameters take their colour from the SCH
+        coefficients."""
+        if self.sch is not None:
+            assert params.shape[0] == G.N_FIELDS
+            G.gs4d_preprocess_sch(params, self.coef, self.sch, self.cviews, self.rec, self.rect,
+                                  self.touched)
+        elif params.shape[0] == G.ISO_FIELDS:
             G.gs4d_preprocess_iso(params, self.cviews, self.rec, self.rect, self.touched)
         else:
             G.gs4d_preprocess(params, self.cviews, self.rec, self.rect, self.touched)
@@ -191,9 +208,10 @@ class Rasterizer:
     def backward(self, params: torch.Tensor, dL_dimage: torch.Tensor):
         if self.forward_only:
             raise RuntimeError("forward-only rasterizer: no state for a backward")
-        if params.shape[0] != G.N_FIELDS:
-            raise ValueError("backward() takes rotor-form parameters; for the isotropic form "
-                             "use render_bwd_2d and gs4d_preprocess_iso_bwd")
+        if params.shape[0] != G.N_FIELDS or self.sch is not None:
+            raise ValueError("backward() takes rotor-form RGB parameters; for the isotropic "
+                             "form or the SCH colour use render_bwd_2d and the form's "
+                             "preprocess backward")
         if self.persistent:
             self._bwd_queue()
         G.gs4d_render_bwd(params, self.rec, self.touched, self.vals, self.ranges, self.cviews,

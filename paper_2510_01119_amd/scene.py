@@ -308,10 +308,13 @@ class Scene:
         return images, (xyz, attr, cls)
 
     def prune(self, cloud, voxel=0.01, min_count=1, voxel_dynamic=None):
+        """gs4d_grid_prune of the cloud; an edge <= 0 leaves that class
+        unpruned (every point kept)."""
         xyz, attr, cls = cloud
         dev = self.device
         m = xyz.shape[1]
-        cap = min(m, 4_000_000)
+        vd = voxel if voxel_dynamic is None else voxel_dynamic
+        cap = m if not (voxel > 0 and vd > 0) else min(m, 4_000_000)
         out_xyz = torch.empty((3, cap), device=dev)
         out_attr = torch.empty((attr.shape[0], cap), device=dev)
         out_count = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -320,7 +323,6 @@ class Scene:
         status = torch.zeros(1, dtype=torch.int32, device=dev)
         ws = torch.empty(G.gs4d_grid_prune_workspace_size(m, attr.shape[0]), dtype=torch.uint8,
                          device=dev)
-        vd = voxel if voxel_dynamic is None else voxel_dynamic
         G.gs4d_grid_prune(xyz, attr, cls, voxel, vd, min_count, cap, out_xyz, out_attr,
                           out_count, out_key, n_out, status, ws)
         st, k = int(status.item()), int(n_out.item())
@@ -345,19 +347,37 @@ class Scene:
         return p
 
 
+# The paper's two initialisation settings (Sec. 4.1, implementation
+# details): Lite prunes static and dynamic points on adaptive voxels with
+# lambda_s = lambda_d = 4; Full uses lambda_s = 1 and leaves the dynamic
+# points unpruned.  Both take the motion class from the Otsu split (Sec.
+# 3.2).
+PRESETS = {
+    "lite": dict(motion="otsu", voxel="adaptive", lambda_static=4.0, lambda_dynamic=4.0),
+    "full": dict(motion="otsu", voxel="adaptive", lambda_static=1.0, lambda_dynamic=None),
+}
+
+
 def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel=0.01,
                 device="cuda", verbose=False, keep_pruned=False, motion="gt",
-                lambda_static=4.0, lambda_dynamic=4.0):
+                lambda_static=4.0, lambda_dynamic=4.0, preset=None):
     """Ground-truth frames and the pruned, heuristically initialised set
     (with keep_pruned, also the pruned cloud: xyz, attr, dynamic flag,
     count).  voxel: an edge length, or "adaptive" for S_v = lambda mean(D / f)
-    with lambda_static / lambda_dynamic (the paper's Lite setting is 4 and
-    4); motion: "gt" (ground-truth mask) or "otsu" (the paper's split)."""
+    with lambda_static / lambda_dynamic (None: that class is not pruned);
+    motion: "gt" (ground-truth mask) or "otsu" (the paper's split); preset
+    "lite" or "full" sets motion, voxel and both lambdas as the paper's
+    settings of those names (PRESETS)."""
+    if preset is not None:
+        cfg = PRESETS[preset]
+        motion, voxel = cfg["motion"], cfg["voxel"]
+        lambda_static, lambda_dynamic = cfg["lambda_static"], cfg["lambda_dynamic"]
     sc = Scene(seed, n_gt, frames, width, height, device=device)
     images, cloud = sc.render_ground_truth(verbose, motion=motion)
     n_raw = cloud[0].shape[1]
     if voxel == "adaptive":
-        vs, vd = lambda_static * sc.depth_over_f, lambda_dynamic * sc.depth_over_f
+        vs = lambda_static * sc.depth_over_f if lambda_static is not None else 0.0
+        vd = lambda_dynamic * sc.depth_over_f if lambda_dynamic is not None else 0.0
     else:
         vs = vd = float(voxel)
     pruned = sc.prune(cloud, vs, voxel_dynamic=vd)
@@ -365,7 +385,8 @@ def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel
     params = sc.heuristic_init(pruned, vs, vd)
     info = dict(n_raw_points=n_raw, n_gaussians=params.shape[1],
                 n_dynamic=int(pruned[2].sum().item()), voxel_static=vs, voxel_dynamic=vd,
-                depth_over_f=sc.depth_over_f, motion=motion, mask_iou=sc.mask_iou)
+                depth_over_f=sc.depth_over_f, motion=motion, mask_iou=sc.mask_iou,
+                preset=preset)
     if keep_pruned:
         return sc, images, params, info, pruned
     return sc, images, params, info

@@ -32,6 +32,12 @@ LR_DEFAULTS = {
     # of normalised time); 1e-2 beat 3e-3 and 1e-3 on held-out PSNR after
     # 1,500 scene steps
     "velocity": (1e-2, 1e-4),
+    # SCH colour only: the constant (n = 0, l = 0) coefficient at the RGB
+    # rate in colour units (the basis value Y_00 = 1 / (2 sqrt(pi)) scales
+    # it), every higher coefficient at 1/20 of that (the 3D Gaussian-
+    # splatting ratio of its higher spherical-harmonic bands)
+    "sch_dc": (2.5e-3 * 2.0 * math.sqrt(math.pi), 2.5e-3 * 2.0 * math.sqrt(math.pi)),
+    "sch_rest": (2.5e-3 * 2.0 * math.sqrt(math.pi) / 20, 2.5e-3 * 2.0 * math.sqrt(math.pi) / 20),
 }
 
 ROTOR_ROWS = (["mean_xyz"] * 3 + ["mean_t"] + ["log_scale"] * 4 + ["rotors"] * 8 + ["opacity"]
@@ -49,9 +55,10 @@ def to_iso(params: torch.Tensor) -> torch.Tensor:
                      dim=0).contiguous()
 
 
-def adam_config(budget: int, lrs=None, iso: bool = False) -> G.gs4d_adam_cfg:
+def adam_config(budget: int, lrs=None, iso: bool = False, rows=None) -> G.gs4d_adam_cfg:
     lrs = dict(LR_DEFAULTS, **(lrs or {}))
-    rows = ISO_ROWS if iso else ROTOR_ROWS
+    if rows is None:
+        rows = ISO_ROWS if iso else ROTOR_ROWS
     cfg = G.gs4d_adam_cfg()
     for k, name in enumerate(rows):
         cfg.lr0[k], cfg.lr1[k] = lrs[name]
@@ -71,11 +78,15 @@ def _capture(fn, stream):
 class Trainer:
     """Single-view training on a fixed set of frames (views [F, 23],
     targets [F, 3, H, W] on the device).  Parameters in rotor form [20, N] or
-    in the isotropic, motion-aware form [13, N] (chosen by their rows)."""
+    in the isotropic, motion-aware form [13, N] (chosen by their rows).
+    With sch (a gs4d_sch), rotor-form parameters take their colour from
+    sphericylindrical-harmonic coefficients (self.coef [3 K, N], started
+    from the parameters' RGB by gs4d_sch_from_rgb and trained with them;
+    rows 17-19 of the parameters are then unused)."""
 
     def __init__(self, params: torch.Tensor, views, targets: torch.Tensor, budget: int = 5000,
                  ssim_weight: float = 0.2, pair_capacity: int | None = None, lrs=None,
-                 batch: int = 256):
+                 batch: int = 256, sch=None):
         self.params = params.contiguous()
         dev = self.params.device
         self.n = self.params.shape[1]
@@ -99,6 +110,23 @@ class Trainer:
         self.ssim_ws = torch.zeros(G.gs4d_photometric_loss_workspace_size(1, 3, H, W),
                                    dtype=torch.uint8, device=dev)
         self.overflow_seen = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.sch = sch
+        if sch is not None:
+            assert not self.iso, "the SCH colour is built on the rotor form"
+            rows = G.gs4d_sch_rows(sch.degree, sch.n_freq)
+            self.coef = torch.empty((rows, self.n), device=dev)
+            G.gs4d_sch_from_rgb(self.params[17:20], sch, self.coef)
+            self.dcoef = torch.zeros_like(self.coef)
+            self.cm = torch.zeros_like(self.coef)
+            self.cv = torch.zeros_like(self.coef)
+            # two Adam groups of one row each: the constant coefficients
+            # (3 N values) and the higher ones, each with its own step count
+            self.coef_groups = [(sl, adam_config(budget, lrs, rows=[name]),
+                                 torch.zeros(1, dtype=torch.int32, device=dev))
+                                for sl, name in ((slice(0, 3), "sch_dc"),
+                                                 (slice(3, rows), "sch_rest"))
+                                if sl.stop > sl.start]
+            self.rast.set_sch(sch, self.coef)
 
     def size_pairs(self, frames=None, margin=1.5):
         """Measure the pair count over some frames and size the pair buffers."""
@@ -136,8 +164,16 @@ class Trainer:
 
     def stage_update(self, f: int):
         r = self.rast
-        bwd = G.gs4d_preprocess_iso_bwd if self.iso else G.gs4d_preprocess_bwd
-        bwd(self.params, r.touched, r.grad2d, self.cviews[f], self.dparams)
+        if self.sch is not None:
+            G.gs4d_preprocess_sch_bwd(self.params, self.coef, self.sch, r.touched, r.grad2d,
+                                      self.cviews[f], self.dparams, self.dcoef)
+            for sl, cfg, step in self.coef_groups:
+                flat = lambda t: t[sl].view(1, -1)
+                G.gs4d_adam_step(flat(self.coef), flat(self.dcoef), flat(self.cm), flat(self.cv),
+                                 cfg, step)
+        else:
+            bwd = G.gs4d_preprocess_iso_bwd if self.iso else G.gs4d_preprocess_bwd
+            bwd(self.params, r.touched, r.grad2d, self.cviews[f], self.dparams)
         G.gs4d_adam_step(self.params, self.dparams, self.m, self.v, self.cfg, self.step_dev)
 
     def step(self, f: int):

@@ -30,3 +30,33 @@ def test_otsu_mask_and_adaptive_voxel():
     assert 0 < pxyz.shape[1] < xyz.shape[1] // 5
     assert int(count.sum().item()) == xyz.shape[1]
     assert 0 < int(dyn.sum().item()) < pxyz.shape[1]
+
+
+def test_lite_and_full_presets():
+    """The paper's two settings (Sec. 4.1) on one small scene: Lite prunes
+    both classes at 4 mean(D / f); Full prunes static points at 1 mean(D / f)
+    and keeps every dynamic point as its own Gaussian, whose spatial scale is
+    then the footprint of its pixel (depth / f)."""
+    need_gpu()
+    from paper_2510_01119_amd.scene import build_scene
+    out = {}
+    for preset in ("lite", "full"):
+        sc, _, params, info, pruned = build_scene(seed=3, n_gt=200_000, frames=12, width=480,
+                                                  height=270, preset=preset, keep_pruned=True)
+        out[preset] = (sc, params, info, pruned)
+    (sl, pl, il, _), (sf, pf, inf, (fxyz, fattr, fdyn, fcount)) = out["lite"], out["full"]
+    assert sl.depth_over_f == sf.depth_over_f and il["mask_iou"] == inf["mask_iou"]
+    assert il["voxel_static"] == pytest.approx(4.0 * sl.depth_over_f, rel=1e-6)
+    assert il["voxel_dynamic"] == pytest.approx(4.0 * sl.depth_over_f, rel=1e-6)
+    assert inf["voxel_static"] == pytest.approx(sf.depth_over_f, rel=1e-6)
+    assert inf["voxel_dynamic"] == 0.0
+    assert torch.all(fcount[fdyn] == 1)
+    assert inf["n_dynamic"] > 4 * il["n_dynamic"] and inf["n_gaussians"] > il["n_gaussians"]
+    # unpruned dynamic points: spatial log-scale = log(depth / f); pruned
+    # static ones: the voxel edge
+    d = fdyn.cpu().numpy()
+    ls = pf[4].double().cpu().numpy()
+    depth = fattr[4].double().cpu().numpy()
+    assert np.allclose(ls[d], np.log(depth[d] / sf.f), atol=1e-5)
+    assert np.allclose(ls[~d], np.log(inf["voxel_static"]), atol=1e-5)
+    assert torch.isfinite(pl).all() and torch.isfinite(pf).all()

@@ -192,3 +192,35 @@ def test_sch_from_rgb_equals_rgb_form():
     assert np.abs(a[..., 8:11] - b[..., 8:11]).max() <= 2.0 ** -22
     assert torch.equal(r1.ranges, r2.ranges)
     assert (r1.image - r2.image).abs().max().item() <= 1e-6
+
+
+def test_sch_trainer_starts_as_rgb_and_trains():
+    """Trainer with the SCH colour (degree 3, two frequencies), started from
+    the RGB parameters: its first forward equals the RGB trainer's to FP32
+    rounding; twenty steps lower the loss, move the higher coefficients off
+    zero and keep everything finite."""
+    need_gpu()
+    from paper_2510_01119_amd.train import Trainer
+    p = torch.from_numpy(synth.small_set(3000, 2)).cuda()
+    views = np.stack([synth.front_view(64, 48, 60.0, 3.0, t) for t in (0.3, 0.6)])
+    tgt = p.clone()
+    tgt[17:20] = torch.flip(tgt[17:20], dims=[0])
+    r = Rasterizer(p.shape[1], views)
+    r.forward(tgt)
+    targets = r.image.clone()
+    rgb = Trainer(p.clone(), views, targets, budget=100)
+    sch = Trainer(p.clone(), views, targets, budget=100, sch=G.make_sch(3, 2, PERIOD))
+    rgb.forward_loss(0)
+    a = rgb.rast.image.clone()
+    sch.forward_loss(0)
+    torch.cuda.synchronize()
+    assert (sch.rast.image - a).abs().max().item() <= 1e-6
+    l0 = sch.loss_value()
+    for i in range(20):
+        sch.step(i % 2)
+    sch.forward_loss(0)
+    torch.cuda.synchronize()
+    assert sch.loss_value() < 0.9 * l0
+    assert torch.isfinite(sch.coef).all() and torch.isfinite(sch.params).all()
+    assert sch.coef[3:].abs().max().item() > 0.0
+    assert torch.equal(sch.params[17:20], p[17:20])
