@@ -596,6 +596,7 @@ def scene_prep_leg(params_gt, views, images_gt, seed, steps=1500):
         sc, images, params, info = build_scene(seed=0, device="cuda", preset=preset)
         torch.cuda.synchronize()
         build_s = time.perf_counter() - t0
+        iou_frames = np.array(sc.mask_iou_frames)
         del sc
         psnr, rate = train(params, images)
         out["presets"][preset] = {
@@ -607,6 +608,20 @@ def scene_prep_leg(params_gt, views, images_gt, seed, steps=1500):
         out["n_raw_points"] = info["n_raw_points"]
         del images, params
         torch.cuda.empty_cache()
+    # the motion maps' sequence ends with and without pseudo-frames (the
+    # presets use them): mask IoU of the first and last frames, and of the
+    # rest
+    from paper_2510_01119_amd.scene import Scene
+    sc = Scene(0, device="cuda")
+    sc.render_ground_truth(motion="otsu", pseudo_frames=False)
+    plain = np.array(sc.mask_iou_frames)
+    del sc
+    torch.cuda.empty_cache()
+    out["pseudo_frames"] = {
+        "mask_iou_ends": round(float(iou_frames[[0, -1]].mean()), 4),
+        "mask_iou_ends_without": round(float(plain[[0, -1]].mean()), 4),
+        "mask_iou_interior": round(float(iou_frames[1:-1].mean()), 4),
+        "mask_iou_interior_without": round(float(plain[1:-1].mean()), 4)}
     psnr, rate = train(params_gt, images_gt)
     out["default"] = {"motion": "ground-truth mask", "voxel": 0.01,
                       "n_gaussians": int(params_gt.shape[1]), "iters_per_s": rate,

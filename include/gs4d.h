@@ -544,6 +544,12 @@ int gs4d_motion_of(const float *params, int64_t n, float *out, void *stream);
  *   The split is decided on integer class sums with one fixed FP64
  *   evaluation per candidate, so it is reproducible bit for bit.
  * ------------------------------------------------------------------------- */
+/* gs4d_threshold_mask -- mask uint8 [count] = 1 where bin(prob) >= k, with
+ *   k / 256 the device float `threshold` that gs4d_otsu_mask wrote (bins as
+ *   there): one threshold chosen over several maps (a sequence's frames
+ *   pooled) applied to each of them. */
+int gs4d_threshold_mask(const float *prob, int64_t count, const float *threshold, uint8_t *mask,
+                        void *stream);
 size_t gs4d_otsu_workspace_size(void);
 int gs4d_otsu_mask(const float *prob, int64_t count, float *threshold, uint8_t *mask, void *ws,
                    size_t ws_bytes, void *stream);

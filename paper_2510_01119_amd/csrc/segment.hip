@@ -111,6 +111,16 @@ otsu_mask_kernel(const float *__restrict__ prob, int64_t count, const int32_t *_
         mask[i] = otsu_bin(prob[i]) >= k ? 1 : 0;
 }
 
+// mask = bin(x) >= k for a threshold k / 256 written by gs4d_otsu_mask
+__global__ void __launch_bounds__(256)
+threshold_mask_kernel(const float *__restrict__ prob, int64_t count,
+                      const float *__restrict__ threshold, uint8_t *__restrict__ mask) {
+    const int k = (int)(*threshold * 256.0f);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        mask[i] = otsu_bin(prob[i]) >= k ? 1 : 0;
+}
+
 struct OtsuWs {
     uint32_t *hist;
     int32_t *kstar;
@@ -160,5 +170,18 @@ extern "C" int gs4d_otsu_mask(const float *prob, int64_t count, float *threshold
         otsu_mask_kernel<<<(unsigned)blocks, 256, 0, st>>>(prob, count, W.kstar, mask);
         GS4D_LAUNCH_CHECK("gs4d_otsu_mask mask");
     }
+    return GS4D_OK;
+}
+
+extern "C" int gs4d_threshold_mask(const float *prob, int64_t count, const float *threshold,
+                                   uint8_t *mask, void *stream) {
+    GS4D_REQUIRE(count >= 0, "gs4d_threshold_mask: count < 0");
+    if (count == 0) return GS4D_OK;
+    GS4D_REQUIRE(prob && threshold && mask, "gs4d_threshold_mask: null pointer");
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    threshold_mask_kernel<<<(unsigned)blocks, 256, 0, as_stream(stream)>>>(prob, count, threshold,
+                                                                           mask);
+    GS4D_LAUNCH_CHECK("gs4d_threshold_mask");
     return GS4D_OK;
 }

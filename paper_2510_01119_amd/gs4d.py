@@ -90,6 +90,7 @@ _SIGS = {
     "gs4d_preprocess_sch_bwd": (_i32, [_p, _p, _i64, _p, _p, _i32, _p, _p, _p, _p, _p]),
     "gs4d_sch_from_rgb": (_i32, [_p, _i64, _i64, _p, _p, _p]),
     "gs4d_otsu_workspace_size": (_sz, []),
+    "gs4d_threshold_mask": (_i32, [_p, _i64, _p, _p, _p]),
     "gs4d_otsu_mask": (_i32, [_p, _i64, _p, _p, _p, _sz, _p]),
     "gs4d_set_bwd_variant": (_i32, [_i32]),
     "gs4d_set_bin_strategy": (_i32, [_i32]),
@@ -323,6 +324,14 @@ def gs4d_sch_from_rgb(rgb, sch, coef, stream=None):
     _sch_shape(coef, sch, n)
     _check(lib().gs4d_sch_from_rgb(_ptr_rows(rgb, 3), rgb.stride(0), n, ctypes.byref(sch), _ptr(coef),
                                    _stream(stream)), "gs4d_sch_from_rgb")
+
+
+def gs4d_threshold_mask(prob, threshold, mask, stream=None):
+    """mask = 1 where bin(prob) >= 256 * threshold (a device float written
+    by gs4d_otsu_mask)."""
+    assert mask.numel() == prob.numel() and mask.dtype == torch.uint8
+    _check(lib().gs4d_threshold_mask(_ptr(prob), prob.numel(), _ptr(threshold), _ptr(mask),
+                                     _stream(stream)), "gs4d_threshold_mask")
 
 
 def gs4d_otsu_workspace_size():

@@ -20,10 +20,11 @@ recovery are not available here).  Recipe:
   each ground-truth Gaussian's pixel and world displacement to the next
   frame), the inputs of the learned initialisation;
 * the motion class of a point is either the ground-truth mask or (motion =
-  "otsu") the paper's segmentation: a low-resolution motion-probability
-  map (here the ground-truth dynamic fraction averaged over 8x8 pixels plus
-  seeded noise, standing in for the SLAM's H/8 x W/8 map), bilinearly
-  upsampled and split by Otsu's threshold (gs4d_otsu_mask);
+  "otsu") the paper's segmentation: low-resolution motion-probability maps
+  (motion_probability: a sliding-window stand-in for the SLAM's H/8 x W/8
+  maps, with pseudo-frames at both ends of the sequence), bilinearly
+  upsampled and split by one Otsu threshold over the whole sequence
+  (gs4d_otsu_mask on the pooled maps, gs4d_threshold_mask per frame);
 * the voxel edge is fixed, or (voxel = "adaptive") S_v = lambda (1/N) sum_i
   D_i / f with D_i the mean back-projected depth of frame i (Sec. 3.2), one
   lambda for static and one for dynamic points;
@@ -56,6 +57,55 @@ def _catmull_rom(P, u):
     p0, p1, p2, p3 = (P[(i + d) % k] for d in (-1, 0, 1, 2))
     return 0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t ** 2
                   + (-p0 + 3 * p1 - 3 * p2 + p3) * t ** 3)
+
+
+def pseudo_frame(j: int, frames: int) -> int:
+    """The real frame that slot j of a sequence extended by pseudo-frames at
+    both ends holds (Sec. 3.2, motion probability estimation): the
+    extension mirrors the sequence about its first and last frame, so frame
+    -d is frame d and frame (F-1)+d is frame (F-1)-d."""
+    F = frames
+    while j < 0 or j > F - 1:
+        j = -j if j < 0 else 2 * (F - 1) - j
+    return j
+
+
+def motion_probability(dyn_low, window=2, noise=0.2, pseudo_frames=True, gen=None):
+    """Stand-in for the SLAM's low-resolution motion-probability maps
+    (dyn_low [F, h, w]: each frame's ground-truth dynamic fraction at H/8 x
+    W/8), as a sliding-window estimator: frame i's map is the mean over its
+    2 * window neighbour slots j = i-window..i+window (j != i) of a per-pair
+    evidence clamp(s_i + noise * eps, 0, 1), with eps seeded N(0, 1), one
+    draw per unordered pair of real frames.  A slot outside the sequence
+    holds no evidence (0): the first and last frames see half a window, and
+    their moving objects come out at half the interior's probability.  With
+    pseudo_frames the sequence is first extended at both ends
+    (pseudo_frame), so every slot holds a frame -- a pseudo-frame is a copy,
+    so its pair repeats its mirror's evidence, and a slot holding a copy of
+    frame i itself shows no motion (0) -- and the first and last frames'
+    maps are on the interior's scale."""
+    F = dyn_low.shape[0]
+    dev = dyn_low.device
+    if gen is None:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(0)
+    # eps[a, d - 1]: the pair (a, a + d)
+    eps = torch.randn((F, window) + tuple(dyn_low.shape[1:]), generator=gen, device=dev)
+    out = torch.zeros_like(dyn_low)
+    for i in range(F):
+        acc = torch.zeros_like(dyn_low[i])
+        for d in range(1, window + 1):
+            for j in (i - d, i + d):
+                if not 0 <= j < F:
+                    if not pseudo_frames:
+                        continue
+                    j = pseudo_frame(j, F)
+                if j == i:
+                    continue
+                a, b = min(i, j), max(i, j)
+                acc += (dyn_low[i] + noise * eps[a, b - a - 1]).clamp(0.0, 1.0)
+        out[i] = acc / (2 * window)
+    return out
 
 
 def _rot_y(a):
@@ -208,23 +258,26 @@ class Scene:
             mus.append(mu)
         return torch.linalg.norm(px[1] - px[0], dim=0), mus[1] - mus[0]
 
-    def render_ground_truth(self, verbose=False, motion="gt", motion_noise=0.1):
+    def render_ground_truth(self, verbose=False, motion="gt", motion_noise=0.2,
+                            pseudo_frames=True, motion_window=2):
         """Renders every frame; returns (images [F,3,H,W] on device, point
         cloud (xyz [3,M], attr [9,M] = rgb, t, depth, optical-flow
         magnitude, scene flow xyz; cls [M]) on device).  Also records
         self.depth_over_f (the mean over frames of each frame's mean
         back-projected depth, over the focal length: S_v's scene scale)
-        and, with motion="otsu", self.mask_iou (mean over frames of the
-        Otsu mask's intersection over union with the ground-truth mask, on
-        the back-projected pixels)."""
+        and, with motion="otsu", self.mask_iou_frames (per frame, the Otsu
+        mask's intersection over union with the ground-truth mask on the
+        back-projected pixels) and self.mask_iou (their mean)."""
         import torch.nn.functional as F
         dev = self.device
         n_back, ious = 0, []
         if motion == "otsu":
             otsu_ws = torch.zeros(G.gs4d_otsu_workspace_size(), dtype=torch.uint8, device=dev)
             otsu_mask = torch.zeros(self.H * self.W, dtype=torch.uint8, device=dev)
+            otsu_thr = torch.zeros(1, device=dev)
             gen = torch.Generator(device=dev)
             gen.manual_seed(1000 + self.seed)
+            lows, pixs, gt_dyns = [], [], []
         n = self.static.shape[1] + self.obj_local.shape[1]
         r = Rasterizer(n, self.cams[0], device=dev, pair_capacity=1 << 24)
         # back projection (gs4d_backproject): at most every pixel of a frame
@@ -282,28 +335,40 @@ class Scene:
             n_back += m
             gt_dyn = aux[2].reshape(-1)[pix] / cov[pix] > 0.5
             if motion == "otsu":
+                # the class is decided once every frame's map is known
                 frac = torch.where(cov2 > 0, aux[2] / cov2.clamp_min(1e-6), torch.zeros_like(cov2))
-                low = F.avg_pool2d(frac[None, None], 8, ceil_mode=True)
-                low = (low + motion_noise * torch.randn(low.shape, generator=gen, device=dev))
-                prob = F.interpolate(low.clamp(0.0, 1.0), size=(self.H, self.W), mode="bilinear",
-                                     align_corners=False)[0, 0].contiguous()
-                G.gs4d_otsu_mask(prob, None, otsu_mask, otsu_ws)
-                dyn = otsu_mask[pix].bool()
-                inter = float((dyn & gt_dyn).sum().item())
-                union = float((dyn | gt_dyn).sum().item())
-                ious.append(inter / union if union > 0 else 1.0)
+                lows.append(F.avg_pool2d(frac[None, None], 8, ceil_mode=True)[0, 0])
+                pixs.append(bp_pix[:m].clone())
+                gt_dyns.append(gt_dyn)
             else:
-                dyn = gt_dyn
-            clss.append(dyn.to(torch.uint8))
+                clss.append(gt_dyn.to(torch.uint8))
             if verbose and f % 50 == 0:
                 print(f"scene: frame {f}/{self.frames} pairs={int(r.n_pairs.item())}",
                       file=sys.stderr, flush=True)
+        if motion == "otsu":
+            # one Otsu threshold over the whole sequence's maps, applied to
+            # each frame's bilinearly upsampled map
+            low = motion_probability(torch.stack(lows), motion_window, motion_noise,
+                                     pseudo_frames, gen).contiguous()
+            G.gs4d_otsu_mask(low.reshape(-1), otsu_thr, None, otsu_ws)
+            for f in range(self.frames):
+                prob = F.interpolate(low[f][None, None], size=(self.H, self.W), mode="bilinear",
+                                     align_corners=False)[0, 0].contiguous()
+                G.gs4d_threshold_mask(prob, otsu_thr, otsu_mask)
+                dyn = otsu_mask[pixs[f].long()].bool()
+                gt_dyn = gt_dyns[f]
+                inter = float((dyn & gt_dyn).sum().item())
+                union = float((dyn | gt_dyn).sum().item())
+                ious.append(inter / union if union > 0 else 1.0)
+                clss.append(dyn.to(torch.uint8))
+            del lows, pixs, gt_dyns
         xyz = torch.cat(pts, dim=1).contiguous()
         attr = torch.cat(attrs, dim=1).contiguous()
         cls = torch.cat(clss).contiguous()
         # S_v's scene scale (Sec. 3.2): the mean over frames of each frame's
         # mean depth, over the focal length
         self.depth_over_f = float(np.mean(mean_depth)) / self.f if mean_depth else 0.0
+        self.mask_iou_frames = ious if ious else None
         self.mask_iou = float(np.mean(ious)) if ious else None
         return images, (xyz, attr, cls)
 
@@ -360,7 +425,7 @@ PRESETS = {
 
 def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel=0.01,
                 device="cuda", verbose=False, keep_pruned=False, motion="gt",
-                lambda_static=4.0, lambda_dynamic=4.0, preset=None):
+                lambda_static=4.0, lambda_dynamic=4.0, preset=None, pseudo_frames=True):
     """Ground-truth frames and the pruned, heuristically initialised set
     (with keep_pruned, also the pruned cloud: xyz, attr, dynamic flag,
     count).  voxel: an edge length, or "adaptive" for S_v = lambda mean(D / f)
@@ -373,7 +438,7 @@ def build_scene(seed=0, n_gt=1_000_000, frames=200, width=960, height=540, voxel
         motion, voxel = cfg["motion"], cfg["voxel"]
         lambda_static, lambda_dynamic = cfg["lambda_static"], cfg["lambda_dynamic"]
     sc = Scene(seed, n_gt, frames, width, height, device=device)
-    images, cloud = sc.render_ground_truth(verbose, motion=motion)
+    images, cloud = sc.render_ground_truth(verbose, motion=motion, pseudo_frames=pseudo_frames)
     n_raw = cloud[0].shape[1]
     if voxel == "adaptive":
         vs = lambda_static * sc.depth_over_f if lambda_static is not None else 0.0

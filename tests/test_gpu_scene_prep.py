@@ -60,3 +60,24 @@ def test_lite_and_full_presets():
     assert np.allclose(ls[d], np.log(depth[d] / sf.f), atol=1e-5)
     assert np.allclose(ls[~d], np.log(inf["voxel_static"]), atol=1e-5)
     assert torch.isfinite(pl).all() and torch.isfinite(pf).all()
+
+
+def test_pseudo_frames_repair_the_sequence_ends():
+    """The sliding-window motion maps see half a window at the first and
+    last frames, whose moving objects then fall below the sequence's Otsu
+    threshold; pseudo-frames at both ends (Sec. 3.2) restore them, and the
+    interior frames stay as they were."""
+    need_gpu()
+    ious = {}
+    for pf in (False, True):
+        sc = Scene(seed=3, n_gt=200_000, frames=12, width=480, height=270, focal=400.0)
+        sc.render_ground_truth(motion="otsu", pseudo_frames=pf)
+        ious[pf] = np.array(sc.mask_iou_frames)
+        del sc
+        torch.cuda.empty_cache()
+    ends = [0, len(ious[True]) - 1]
+    print(f"mask IoU per frame without pseudo-frames {np.round(ious[False], 3).tolist()}, "
+          f"with {np.round(ious[True], 3).tolist()}", flush=True)
+    assert ious[True][ends].min() >= 0.75
+    assert ious[True][ends].mean() >= ious[False][ends].mean() + 0.1
+    assert abs(ious[True][2:-2].mean() - ious[False][2:-2].mean()) <= 0.05

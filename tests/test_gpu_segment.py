@@ -38,3 +38,33 @@ def test_otsu_matches_oracle(name):
         torch.cuda.synchronize()
         assert float(thr.item()) == np.float32(k_ref) / np.float32(256)
         assert np.array_equal(mask.cpu().numpy(), m_ref)
+
+
+def test_pooled_threshold_applied_per_map():
+    """One Otsu threshold over several maps pooled (gs4d_otsu_mask on their
+    concatenation), applied to each map and to a map outside the pool by
+    gs4d_threshold_mask: the oracle's bins against the oracle's k*, bit for
+    bit (a NaN reads as 0; k* = 256, no split, masks nothing)."""
+    need_gpu()
+    rng = np.random.default_rng(9)
+    maps = [np.clip(rng.normal(0.2 + 0.5 * (i % 2), 0.15, 20000), 0, 1).astype(np.float32)
+            for i in range(5)]
+    maps[3][::13] = np.nan
+    pooled = np.concatenate(maps)
+    k_ref, _ = O.otsu(pooled)
+    thr = torch.zeros(1, device="cuda")
+    ws = torch.zeros(G.gs4d_otsu_workspace_size(), dtype=torch.uint8, device="cuda")
+    G.gs4d_otsu_mask(torch.from_numpy(pooled).cuda(), thr, None, ws)
+    other = rng.uniform(0, 1, 777).astype(np.float32)
+    for m in maps + [other]:
+        mask = torch.full((m.size,), 9, dtype=torch.uint8, device="cuda")
+        G.gs4d_threshold_mask(torch.from_numpy(m).cuda(), thr, mask)
+        torch.cuda.synchronize()
+        assert np.array_equal(mask.cpu().numpy(), (O.bins_of(m) >= k_ref).astype(np.uint8))
+    # no split: k* = 256, nothing is dynamic
+    const = np.full(1000, 0.4, np.float32)
+    G.gs4d_otsu_mask(torch.from_numpy(const).cuda(), thr, None, ws)
+    mask = torch.full((other.size,), 9, dtype=torch.uint8, device="cuda")
+    G.gs4d_threshold_mask(torch.from_numpy(other).cuda(), thr, mask)
+    torch.cuda.synchronize()
+    assert float(thr.item()) == 1.0 and int(mask.sum().item()) == 0
