@@ -465,11 +465,14 @@ int gs4d_knn8(const float *xyz, int64_t n, float cell, int32_t *nbr, float *d2, 
 
 /* gs4d_init_features -- the network's 16 inputs per point, standardised
  *   as (f - shift[i]) * scale[i]:
- *     0-2 xyz, 3 depth, 4 2D optical-flow magnitude, 5-7 mean and 8-10
- *     per-axis variance of the offsets to the 8 neighbours, 11-13 scene
- *     flow (world displacement per frame), 14 t, 15 motion class (1 dynamic).
- *   attr float [9][n] = (r, g, b, t, depth, flow magnitude, scene flow x, y,
- *   z), the per-voxel means of the pruned cloud (colour is not an input);
+ *     0-2 xyz, 3 depth, 4 2D optical-flow magnitude, then statistics of the
+ *     space-time offsets (x_j - x, t_j - t) to the 8 neighbours (population
+ *     moments): 5-7 mean spatial offset, 8-10 per-axis variance, 11-13
+ *     covariance of each spatial axis with the time offset, 14 variance of
+ *     the time offset; 15 motion class (1 dynamic).  On a trail
+ *     x = x0 + v (t - t0), features 11-13 over 14 are v.
+ *   attr float [>= 6][n] = (r, g, b, t, depth, flow magnitude, ...), the
+ *   per-voxel means of the pruned cloud (colour is not an input);
  *   dyn uint8 [n] or NULL; nbr from gs4d_knn8 (entries -1 are skipped; no
  *   neighbour gives offset mean and variance 0).
  *   shift, scale: host float [16].  feat out float [16][n]. */

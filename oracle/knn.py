@@ -8,16 +8,20 @@ the learned initialisation.
     0-2   position xyz (the voxel centroid after grid pruning, Sec. 3.2)
     3     mean camera depth of the back-projected pixels of the voxel
     4     mean 2D optical-flow magnitude of those pixels (pixels per frame)
-    5-7   mean of the offsets x_nbr - x over the 8 neighbours
+    5-7   mean of the spatial offsets x_nbr - x over the 8 neighbours
     8-10  variance (population, per axis) of those offsets
-    11-13 mean scene flow (world displacement per frame)
-    14    mean timestamp (normalised to [0, 1])
+    11-13 covariance (population) of each spatial offset with the time
+          offset t_nbr - t (the neighbours' mean timestamps against the
+          point's)
+    14    variance (population) of the time offsets
     15    motion class (1 dynamic, 0 static)
-  then standardised: (f - shift) * scale per feature.
+  then standardised: (f - shift) * scale per feature.  Features 5-14 are
+  the mean and (co)variances of the neighbours' space-time offsets; for
+  points on a trail x = x0 + v (t - t0), features 11-13 over feature 14 are
+  the slope v (a least-squares regression of offset on time).
 The pruned-point attributes averaged per voxel are those the grid pruning
-of Sec. 3.2 carries (timestamp, motion probability) plus depth, optical-flow
-magnitude and scene flow (optical flow back-projected with depth and
-camera poses).
+of Sec. 3.2 carries (timestamp, motion probability) plus depth and
+optical-flow magnitude.
 
 Only ``tests/`` may import this module.
 """
@@ -53,27 +57,31 @@ def knn(xyz, k=K, queries=None, chunk=None):
     return ids, d2s
 
 
-def features(xyz, depth, flow, sflow, t, dyn, nbr):
+def features(xyz, depth, flow, t, dyn, nbr):
     """Raw (unstandardised) features [16, N] from pruned points (xyz [3, N],
-    depth [N], flow [N], scene flow [3, N], t [N], dyn [N]) and their neighbour
-    ids nbr [N, 8] (-1 = no neighbour; with none, offset mean and variance
-    are 0)."""
+    depth [N], flow [N], timestamps t [N], dyn [N]) and their neighbour ids
+    nbr [N, 8] (-1 = no neighbour; with none, every offset statistic is 0)."""
     X = np.asarray(xyz, np.float64)
+    T = np.asarray(t, np.float64)
     nbr = np.asarray(nbr)
     ok = nbr >= 0                                   # missing neighbours (-1) are skipped
     cnt = ok.sum(axis=1)
-    off = np.where(ok[None], X[:, np.where(ok, nbr, 0)] - X[:, :, None], 0.0)   # [3, N, 8]
+    j = np.where(ok, nbr, 0)
+    off = np.where(ok[None], X[:, j] - X[:, :, None], 0.0)            # [3, N, 8]
+    offt = np.where(ok, T[j] - T[:, None], 0.0)                        # [N, 8]
     den = np.maximum(cnt, 1)
     mean = off.sum(axis=2) / den
-    var = np.where(ok[None], (off - mean[:, :, None]) ** 2, 0.0).sum(axis=2) / den
+    meant = offt.sum(axis=1) / den
+    dx = np.where(ok[None], off - mean[:, :, None], 0.0)
+    dt = np.where(ok, offt - meant[:, None], 0.0)
     F = np.zeros((N_FEATURES, X.shape[1]))
     F[0:3] = X
     F[3] = depth
     F[4] = flow
     F[5:8] = mean
-    F[8:11] = var
-    F[11:14] = sflow
-    F[14] = t
+    F[8:11] = (dx * dx).sum(axis=2) / den
+    F[11:14] = (dx * dt[None]).sum(axis=2) / den
+    F[14] = (dt * dt).sum(axis=1) / den
     F[15] = np.asarray(dyn, np.float64)
     return F
 

@@ -174,9 +174,10 @@ __global__ void features_kernel(const float *__restrict__ xyz, const float *__re
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float px = xyz[i], py = xyz[n + i], pz = xyz[2 * n + i];
-    float ox[KNN], oy[KNN], oz[KNN];
+    const float pt = attr[3 * n + i];
+    float ox[KNN], oy[KNN], oz[KNN], ot[KNN];
     int cnt = 0;
-    float mx = 0.0f, my = 0.0f, mz = 0.0f;
+    float mx = 0.0f, my = 0.0f, mz = 0.0f, mt = 0.0f;
 #pragma unroll
     for (int k = 0; k < KNN; ++k) {
         const int32_t j = nbr[(int64_t)k * n + i];
@@ -184,23 +185,32 @@ __global__ void features_kernel(const float *__restrict__ xyz, const float *__re
         ox[k] = ok ? xyz[j] - px : 0.0f;
         oy[k] = ok ? xyz[n + j] - py : 0.0f;
         oz[k] = ok ? xyz[2 * n + j] - pz : 0.0f;
+        ot[k] = ok ? attr[3 * n + j] - pt : 0.0f;
         cnt += ok ? 1 : 0;
         mx += ox[k];
         my += oy[k];
         mz += oz[k];
+        mt += ot[k];
     }
     const float inv = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
     mx *= inv;
     my *= inv;
     mz *= inv;
-    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+    mt *= inv;
+    // (co)variances of the space-time offsets: per spatial axis, each
+    // spatial axis with time, and time
+    float vx = 0.0f, vy = 0.0f, vz = 0.0f, cx = 0.0f, cy = 0.0f, cz = 0.0f, vt = 0.0f;
 #pragma unroll
     for (int k = 0; k < KNN; ++k) {
         const bool ok = nbr[(int64_t)k * n + i] >= 0;
-        const float ax = ox[k] - mx, ay = oy[k] - my, az = oz[k] - mz;
+        const float ax = ox[k] - mx, ay = oy[k] - my, az = oz[k] - mz, at = ot[k] - mt;
         vx += ok ? ax * ax : 0.0f;
         vy += ok ? ay * ay : 0.0f;
         vz += ok ? az * az : 0.0f;
+        cx += ok ? ax * at : 0.0f;
+        cy += ok ? ay * at : 0.0f;
+        cz += ok ? az * at : 0.0f;
+        vt += ok ? at * at : 0.0f;
     }
     float f[16];
     f[0] = px;
@@ -214,10 +224,10 @@ __global__ void features_kernel(const float *__restrict__ xyz, const float *__re
     f[8] = vx * inv;
     f[9] = vy * inv;
     f[10] = vz * inv;
-    f[11] = attr[6 * n + i];
-    f[12] = attr[7 * n + i];
-    f[13] = attr[8 * n + i];
-    f[14] = attr[3 * n + i];
+    f[11] = cx * inv;
+    f[12] = cy * inv;
+    f[13] = cz * inv;
+    f[14] = vt * inv;
     f[15] = (dyn != nullptr && dyn[i] != 0) ? 1.0f : 0.0f;
 #pragma unroll
     for (int k = 0; k < 16; ++k) feat[(int64_t)k * n + i] = (f[k] - st.shift[k]) * st.scale[k];

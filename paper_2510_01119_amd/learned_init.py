@@ -76,8 +76,8 @@ def neighbours(xyz, cell=KNN_CELL):
 
 
 def features(pruned, shift=None, scale=None, cell=KNN_CELL):
-    """[16, N] features of the pruned cloud (xyz, attr [9] = rgb, t, depth,
-    flow magnitude, scene flow, dynamic flag); raw when shift/scale are None."""
+    """[16, N] features of the pruned cloud (xyz, attr [6] = rgb, t, depth,
+    flow magnitude, dynamic flag); raw when shift/scale are None."""
     xyz, attr, dyn = pruned[0].contiguous(), pruned[1].contiguous(), pruned[2]
     nbr, _ = neighbours(xyz, cell)
     feat = torch.empty((16, xyz.shape[1]), device=xyz.device)
@@ -94,15 +94,21 @@ def predict(model: InitModel, feat, w_bf16=None):
     return pred
 
 
-def apply(params, pruned, model: InitModel | None = None, path=MODEL_PATH):
+def apply(params, pruned, model: InitModel | None = None, path=MODEL_PATH, classes=None):
     """Learned initialisation in place on heuristic parameters [20, N]; with
-    no model (and no model file) the heuristic initialisation stands."""
+    no model (and no model file) the heuristic initialisation stands.
+    classes: "all" points, or "dynamic" only (static points keep the
+    heuristic initialisation; gs4d_motion_init leaves a column whose
+    prediction is not finite as it was); default: the model's own setting."""
     if model is None:
         if not os.path.exists(path):
             return params
         model = InitModel.load(path)
+    classes = classes or model.meta.get("classes", "all")
     feat = features(pruned, model.shift, model.scale)
     pred = predict(model, feat)
+    if classes == "dynamic":
+        pred[:, ~pruned[2]] = float("nan")
     G.gs4d_motion_init(params, pred)
     return params
 
@@ -275,6 +281,10 @@ def cmd_train(args):
 
 
 def cmd_eval(args):
+    """Per held-out scene: with --gain-only, held-out PSNR after a fixed
+    budget of batched steps from the heuristic and from the learned
+    initialisation; else the time to the plain form's PSNR.  Prints one
+    JSON line per scene and a summary (mean, spread, wins)."""
     from .pipeline import init_gain, time_to_psnr
     from .scene import build_scene
     model = InitModel.load(args.model) if args.model else None
@@ -284,18 +294,39 @@ def cmd_eval(args):
         sc, images, params0, info, pruned = build_scene(seed=seed, keep_pruned=True)
         if args.gain_only:
             r = init_gain(sc, images, params0, pruned, model, budget=args.budget,
-                          lr_mult=args.lr_mult, group=args.group, decay=args.decay)
+                          lr_mult=args.lr_mult, group=args.group, decay=args.decay,
+                          classes=args.classes)
         else:
             r = time_to_psnr(sc, images, params0, pruned, model, budget=args.budget,
-                             lr_mult=args.lr_mult, decay=args.decay, group=args.group)
+                             lr_mult=args.lr_mult, decay=args.decay, group=args.group,
+                             classes=args.classes)
         r.update(seed=seed, n_gaussians=int(params0.shape[1]))
         _log("eval: " + json.dumps({k: v for k, v in r.items() if k != "history"}))
         results.append(r)
         del sc, images, params0, pruned
         torch.cuda.empty_cache()
+    if args.gain_only:
+        gain = np.array([r["learned"]["psnr"][-1] - r["heuristic"]["psnr"][-1] for r in results])
+        summary = dict(kind="fixed-budget PSNR gain (learned - heuristic), dB",
+                       steps=args.budget, views_per_step=args.group, scenes=len(results),
+                       mean=round(float(gain.mean()), 3), std=round(float(gain.std()), 3),
+                       min=round(float(gain.min()), 3), max=round(float(gain.max()), 3),
+                       wins=int((gain > 0).sum()),
+                       per_scene={r["seed"]: round(float(g), 3) for r, g in zip(results, gain)})
+    else:
+        su = {k: np.array([r[k]["speedup"] or 0.0 for r in results])
+              for k in ("heuristic", "learned") if k in results[0]}
+        summary = dict(kind="time to the plain form's PSNR - 0.1 dB", scenes=len(results),
+                       views_per_step=args.group,
+                       **{f"speedup_{k}_median": round(float(np.median(v)), 3)
+                          for k, v in su.items()},
+                       **{f"speedup_{k}_min": round(float(v.min()), 3) for k, v in su.items()},
+                       reached_learned=int(sum(bool(r.get("learned", {}).get("reached"))
+                                               for r in results)))
+    _log("eval summary: " + json.dumps(summary))
     if args.out:
         with open(args.out, "w") as f:
-            json.dump(results, f)
+            json.dump({"summary": summary, "scenes": results}, f)
 
 
 def main(argv=None):
@@ -323,6 +354,7 @@ def main(argv=None):
     e.add_argument("--decay", type=float, default=P.BATCHED_DECAY)
     e.add_argument("--group", type=int, default=P.BATCHED_GROUP)
     e.add_argument("--gain-only", action="store_true")
+    e.add_argument("--classes", default=None, choices=["all", "dynamic"])
     args = ap.parse_args(argv)
     {"gen": cmd_gen, "train": cmd_train, "eval": cmd_eval}[args.cmd](args)
 

@@ -218,7 +218,7 @@ BATCHED_GROUP, BATCHED_LR_MULT, BATCHED_DECAY, BATCHED_BUDGET = 4, 6.0, 0.03, 15
 def time_to_psnr(sc, images, params0, pruned, model=None, plain_budget=5000,
                  budget=BATCHED_BUDGET, lr_mult=BATCHED_LR_MULT, decay=BATCHED_DECAY,
                  group=BATCHED_GROUP,
-                 seed=0, log=None):
+                 seed=0, log=None, classes=None):
     """The plain single-view form (heuristic init, `plain_budget` steps) fixes
     the reference PSNR on the held-out frames; the batched form from the
     heuristic and from the learned initialisation then trains until it is
@@ -243,7 +243,7 @@ def time_to_psnr(sc, images, params0, pruned, model=None, plain_budget=5000,
     if model is not None:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        p_l = LI.apply(params0.clone(), pruned, model)
+        p_l = LI.apply(params0.clone(), pruned, model, classes=classes)
         torch.cuda.synchronize()
         out["learned_init_s"] = round(time.perf_counter() - t0, 4)
         runs["learned"] = p_l
@@ -267,14 +267,15 @@ def time_to_psnr(sc, images, params0, pruned, model=None, plain_budget=5000,
 
 
 def init_gain(sc, images, params0, pruned, model, budget=300, lr_mult=2.0, group=8, seed=0,
-              decay=1.0):
+              decay=1.0, classes=None):
     """PSNR after a fixed batched budget from the heuristic and from the
     learned initialisation."""
     from . import learned_init as LI
     train_f, held_f = split_frames(sc.frames)
     ev = Evaluator(params0.shape[1], sc.cams, images, held_f)
     res = {}
-    for name, p in (("heuristic", params0), ("learned", LI.apply(params0.clone(), pruned, model))):
+    for name, p in (("heuristic", params0),
+                    ("learned", LI.apply(params0.clone(), pruned, model, classes=classes))):
         hist, _, _ = batched_run(p, sc.cams, images, train_f, ev, budget, lr_mult, group,
                                  eval_every=budget // 3, seed=seed, decay=decay)
         res[name] = dict(psnr_init=round(ev.psnr(p), 3), psnr=[round(h[2], 3) for h in hist])

@@ -16,9 +16,9 @@ recovery are not available here).  Recipe:
 * every pixel with coverage > 0.5 is back-projected (gs4d_backproject) to a
   world point with its colour, timestamp and motion class (Sec. 3.2, back
   projection), plus
-  its depth, optical-flow magnitude and scene flow (further passes render
-  each ground-truth Gaussian's pixel and world displacement to the next
-  frame), the inputs of the learned initialisation;
+  its depth and optical-flow magnitude (a further pass renders each
+  ground-truth Gaussian's pixel displacement to the next frame: the stand-in
+  for an optical-flow estimate), inputs of the learned initialisation;
 * the motion class of a point is either the ground-truth mask or (motion =
   "otsu") the paper's segmentation: low-resolution motion-probability maps
   (motion_probability: a sliding-window stand-in for the SLAM's H/8 x W/8
@@ -240,13 +240,12 @@ class Scene:
 
     # ------------------------------------------------------------ synthesis
     def _flow(self, f):
-        """Per ground-truth Gaussian, from frame f to the next frame (from
-        the previous one for the last frame): the pixel displacement of its
-        centre (optical-flow magnitude: camera and object motion together)
-        and its world-space displacement (scene flow: what back-projecting
-        the optical flow with depth and camera poses recovers)."""
+        """Per ground-truth Gaussian, the pixel displacement of its centre
+        from frame f to the next frame (from the previous one for the last
+        frame): the optical-flow magnitude, camera and object motion
+        together."""
         a, b = (f, f + 1) if f + 1 < self.frames else (f - 1, f)
-        px, mus = [], []
+        px = []
         for k in (a, b):
             v = self.cams[k]
             mu = self.gt_params(float(v[18]))[0:3]
@@ -255,14 +254,13 @@ class Scene:
             z = xc[2].clamp_min(1e-3)
             px.append(torch.stack([float(v[12]) * xc[0] / z + float(v[14]),
                                    float(v[13]) * xc[1] / z + float(v[15])]))
-            mus.append(mu)
-        return torch.linalg.norm(px[1] - px[0], dim=0), mus[1] - mus[0]
+        return torch.linalg.norm(px[1] - px[0], dim=0)
 
     def render_ground_truth(self, verbose=False, motion="gt", motion_noise=0.2,
                             pseudo_frames=True, motion_window=2):
         """Renders every frame; returns (images [F,3,H,W] on device, point
-        cloud (xyz [3,M], attr [9,M] = rgb, t, depth, optical-flow
-        magnitude, scene flow xyz; cls [M]) on device).  Also records
+        cloud (xyz [3,M], attr [6,M] = rgb, t, depth, optical-flow
+        magnitude; cls [M]) on device).  Also records
         self.depth_over_f (the mean over frames of each frame's mean
         back-projected depth, over the focal length: S_v's scene scale)
         and, with motion="otsu", self.mask_iou_frames (per frame, the Otsu
@@ -317,21 +315,16 @@ class Scene:
             depth = bp_depth[:m]
             world = bp_xyz[:, :m].clone()
             mean_depth.append(float(bp_sum.item()) / max(m, 1))
-            # third and fourth passes: optical-flow magnitude (pixels per frame)
-            # and scene flow (world units per frame) as colours
-            fmag, sflow = self._flow(f)
-            rec[:, 8] = fmag
-            rec[:, 9] = sflow[0]
-            rec[:, 10] = sflow[1]
+            # third pass: optical-flow magnitude (pixels per frame) as a colour
+            rec[:, 8] = self._flow(f)
+            rec[:, 9] = 0.0
+            rec[:, 10] = 0.0
             r.render()
-            flow = r.image[0].reshape(3, -1)[:, pix] / cov[pix]
-            rec[:, 8] = sflow[2]
-            r.render()
-            sfz = r.image[0][0].reshape(-1)[pix] / cov[pix]
+            flow = r.image[0][0].reshape(-1)[pix] / cov[pix]
             pts.append(world)
             col = images[f].reshape(3, -1)[:, pix]
             attrs.append(torch.cat([col, torch.full((1, m), float(view[18]), device=dev),
-                                    depth[None], flow, sfz[None]]))
+                                    depth[None], flow[None]]))
             n_back += m
             gt_dyn = aux[2].reshape(-1)[pix] / cov[pix] > 0.5
             if motion == "otsu":

@@ -118,7 +118,7 @@ def test_features_on_oracle_neighbours():
     nbr, _ = OK.knn(X)
     nbr[7, :] = -1                      # missing neighbours are skipped
     nbr[:, 3] = -1
-    attr = rng.uniform(0, 1, (9, n))
+    attr = rng.uniform(0, 1, (6, n))
     dyn = (rng.uniform(0, 1, n) < 0.4).astype(np.uint8)
     shift = rng.normal(0, 0.1, 16)
     scale = rng.uniform(0.5, 2.0, 16)
@@ -131,7 +131,7 @@ def test_features_on_oracle_neighbours():
     got = feat.cpu().numpy().astype(np.float64)
     X32 = X.astype(np.float32).astype(np.float64)
     a32 = attr.astype(np.float32).astype(np.float64)
-    ref = OK.features(X32, a32[4], a32[5], a32[6:9], a32[3], dyn, nbr)
+    ref = OK.features(X32, a32[4], a32[5], a32[3], dyn, nbr)
     ref = OK.standardise(ref, shift, scale)
     tol = 1e-5 * (1 + np.abs(ref))
     assert np.all(np.abs(got - ref) <= tol), np.abs(got - ref).max()

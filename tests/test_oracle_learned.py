@@ -187,8 +187,7 @@ def test_knn_cube_corners_closed_form():
     ids, d2 = K.knn(X, queries=[9])
     assert sorted(ids[0].tolist()) == list(range(1, 9))
     assert np.allclose(d2[0], 3 * (h / 2) ** 2, rtol=1e-15)
-    F = K.features(X, np.zeros(12), np.zeros(12), np.zeros((3, 12)), np.zeros(12), np.zeros(12),
-                   K.knn(X)[0])
+    F = K.features(X, np.zeros(12), np.zeros(12), np.zeros(12), np.zeros(12), K.knn(X)[0])
     assert np.allclose(F[5:8, 9], 0.0, atol=1e-18)
     assert np.allclose(F[8:11, 9], (h / 2) ** 2, rtol=1e-12)
 
@@ -219,8 +218,33 @@ def test_knn_against_kdtree():
 def test_features_missing_neighbours():
     X = np.array([[0.0, 1.0, 3.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
     nbr = np.array([[1, 2, -1, -1, -1, -1, -1, -1], [-1] * 8, [0, -1, -1, -1, -1, -1, -1, -1]])
-    F = K.features(X, np.zeros(3), np.zeros(3), np.zeros((3, 3)), np.zeros(3), np.zeros(3), nbr)
-    # point 0: offsets 1 and 3 -> mean 2, variance 1; point 1: none -> 0, 0
+    t = np.array([0.5, 0.25, 1.0])
+    F = K.features(X, np.zeros(3), np.zeros(3), t, np.zeros(3), nbr)
+    # point 0: offsets 1 and 3 at time offsets -0.25 and +0.5 -> mean 2,
+    # variance 1, time-offset mean 0.125 and variance 0.140625, covariance
+    # ((1 - 2)(-0.25 - 0.125) + (3 - 2)(0.5 - 0.125)) / 2 = 0.375; point 1:
+    # no neighbour -> all offset statistics 0; point 2: one neighbour ->
+    # mean -3, every (co)variance 0
     assert np.allclose(F[5:8, 0], [2, 0, 0]) and np.allclose(F[8:11, 0], [1, 0, 0])
-    assert np.all(F[5:11, 1] == 0)
-    assert np.allclose(F[5:8, 2], [-3, 0, 0]) and np.all(F[8:11, 2] == 0)
+    assert np.allclose(F[11:14, 0], [0.375, 0, 0]) and np.isclose(F[14, 0], 0.140625)
+    assert np.all(F[5:15, 1] == 0)
+    assert np.allclose(F[5:8, 2], [-3, 0, 0]) and np.all(F[8:15, 2] == 0)
+
+
+def test_features_trail_slope_is_the_velocity():
+    """Neighbours on a trail x = x0 + v (t - t0) (points of one moving
+    surface back-projected at different frames): the space-time covariance
+    over the time-offset variance is v exactly, for any spacing in time;
+    static neighbours (v = 0) give covariance 0."""
+    rng = np.random.default_rng(4)
+    v = np.array([0.3, -0.1, 0.05])
+    tt = np.sort(rng.uniform(0, 1, 9))
+    X = (np.array([0.2, 0.1, -0.4])[:, None] + v[:, None] * (tt - tt[4])[None])
+    ids, _ = K.knn(X, queries=[4])
+    F = K.features(X, np.zeros(9), np.zeros(9), tt, np.ones(9), np.tile(ids, (9, 1)))
+    assert sorted(ids[0].tolist()) == [0, 1, 2, 3, 5, 6, 7, 8]
+    assert np.allclose(F[11:14, 4] / F[14, 4], v, rtol=1e-12)
+    assert np.allclose(F[14, 4], np.var(tt[ids[0]] - tt[4]), rtol=1e-12)
+    Xs = np.tile(X[:, 4:5], (1, 9)) + rng.normal(0, 1e-3, (3, 9))
+    Fs = K.features(Xs, np.zeros(9), np.zeros(9), tt, np.zeros(9), np.tile(ids, (9, 1)))
+    assert np.all(np.abs(Fs[11:14, 4]) < 1e-3 * np.sqrt(Fs[14, 4]) * 3)
