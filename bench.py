@@ -52,12 +52,17 @@ FLOPS_BLEND_BWD = 48
 
 class ProfileRegion:
     """roctxProfilerResume(0) / roctxProfilerPause(0) around a timed region:
-    under `rocprofv3 --selected-regions` only what runs inside is collected,
-    so a profile covers exactly the launches a bench line times.  Without a
-    profiler (or the ROCTx library) both calls do nothing."""
+    under `rocprofv3 --marker-trace --selected-regions` only what runs inside
+    is collected, so a profile covers exactly the launches a bench line
+    times.  Counter runs cannot trace markers, so the region is also
+    bracketed by one short torch spin kernel on each side (drained before
+    the region's clock starts): in a `--pmc` dispatch list the launches
+    between the two spin kernels are the region's.  Without a profiler (or
+    the ROCTx library) the calls do nothing."""
 
     def __init__(self, active):
         self.lib = None
+        self.active = active
         if active:
             import ctypes
             for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
@@ -74,7 +79,14 @@ class ProfileRegion:
             else:
                 log("bench: ROCTx library not found; profiling regions are not marked")
 
+    def _sentinel(self):
+        import torch
+        torch.cuda._sleep(64)
+        torch.cuda.synchronize()
+
     def __enter__(self):
+        if self.active:
+            self._sentinel()
         if self.lib is not None:
             rc = self.lib.roctxProfilerResume(0)
             if rc:
@@ -86,6 +98,8 @@ class ProfileRegion:
             rc = self.lib.roctxProfilerPause(0)
             if rc:
                 log(f"bench: roctxProfilerPause returned {rc}")
+        if self.active:
+            self._sentinel()
         return False
 
 
