@@ -252,7 +252,10 @@ int gs4d_render_fwd(const float *rec, int64_t n, const uint32_t *vals, const int
 
 /* ---------------------------------------------------------------------------
  * gs4d_render_bwd -- analytic backward of gs4d_render_fwd and
- *   gs4d_preprocess down to the 20 raw parameters.  Per pixel the entries are
+ *   gs4d_preprocess down to the 20 raw parameters: the optimisation loop's
+ *   backward pass through the splatting renderer (Sec. 3.1; Table B-1,
+ *   "Backward") and through the slice of Sec. 3.3 Eq. "4dgs" and its
+ *   temporal opacity.  Per pixel the entries are
  *   replayed back to front from `last`; each transmittance is recovered as
  *   T_i = T_{i+1} / (1 - alpha_i) from T_final, never stored.  Gradients are
  *   zero through the 0.99 clamp, skipped entries and clamped guard-band
