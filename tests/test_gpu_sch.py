@@ -224,3 +224,47 @@ def test_sch_trainer_starts_as_rgb_and_trains():
     assert torch.isfinite(sch.coef).all() and torch.isfinite(sch.params).all()
     assert sch.coef[3:].abs().max().item() > 0.0
     assert torch.equal(sch.params[17:20], p[17:20])
+
+
+def test_sch_trainer_graph_replays_match_eager():
+    """The SCH trainer's step captured as HIP graphs (as the benchmark
+    replays it): replays with eager work and synchronisations between them
+    reproduce the eager trainer -- the first forward bit for bit, then the
+    parameters and coefficients up to the reordering of the backward's float
+    atomics."""
+    need_gpu()
+    from paper_2510_01119_amd.train import Trainer
+    p = torch.from_numpy(synth.small_set(2500, 6)).cuda()
+    views = np.stack([synth.front_view(64, 48, 60.0, 3.0, t) for t in (0.25, 0.5, 0.75)])
+    tgt = p.clone()
+    tgt[0:3] += 0.01
+    r = Rasterizer(p.shape[1], views[0])
+    targets = []
+    for v in views:
+        r.set_views(v)
+        r.forward(tgt)
+        targets.append(r.image.clone())
+    targets = torch.cat(targets)
+    sch = G.make_sch(2, 1, PERIOD)
+    eager = Trainer(p.clone(), views, targets, budget=50, sch=sch)
+    graph = Trainer(p.clone(), views, targets, budget=50, sch=sch)
+    eager.size_pairs(margin=2.0)
+    graph.size_pairs(margin=2.0)
+    graph.rast._alloc_pairs(eager.rast.capacity)
+    c0 = eager.coef.clone()
+    frames = [0, 2, 1, 0, 2]
+    graph.capture(sorted(set(frames)))
+    for i, f in enumerate(frames):
+        eager.step(f)
+        graph.step_graph(f)
+        torch.cuda.synchronize()
+        _ = (eager.coef * 2).sum().item()          # eager work between replays
+        if i == 0:
+            assert torch.equal(eager.rast.image, graph.rast.image)
+        for a, b, ref in ((eager.params, graph.params, p), (eager.coef, graph.coef, c0)):
+            d = (a - b).abs().max().item()
+            scale = (a - ref).abs().max().item()
+            assert d <= 1e-3 * scale + 1e-7, (i, d, scale)
+    assert int(graph.step_dev.item()) == len(frames)
+    assert all(int(s_.item()) == len(frames) for _, _, s_ in graph.coef_groups)
+    assert int(graph.overflow_seen.item()) == 0
