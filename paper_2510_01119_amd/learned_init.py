@@ -234,8 +234,9 @@ def cmd_train(args):
     Xs, Ts, seeds = [], [], []
     for f in files:
         with np.load(f, allow_pickle=False) as d:
-            Xs.append(d["X"])
-            Ts.append(d["T"])
+            keep = d["dyn"] != 0 if args.classes == "dynamic" else slice(None)
+            Xs.append(d["X"][:, keep])
+            Ts.append(d["T"][:, keep])
             seeds.append(json.loads(str(d["meta"]))["seed"])
     n_val = max(1, len(files) // 10)
     Xtr, Ttr = np.concatenate(Xs[:-n_val], 1), np.concatenate(Ts[:-n_val], 1)
@@ -275,7 +276,7 @@ def cmd_train(args):
     meta = dict(train_scenes=seeds[:-n_val], val_scenes=seeds[-n_val:], n_train=int(n),
                 steps=args.steps, batch=args.batch, lr=args.lr, val_loss=val,
                 val_loss_of_mean=base, train_seconds=round(time.time() - t0, 2),
-                knn_cell=KNN_CELL)
+                knn_cell=KNN_CELL, classes=args.classes)
     InitModel(shift, scale, master, meta).save(args.out)
     _log(f"train: saved {args.out}: {json.dumps(meta)}")
 
@@ -344,6 +345,9 @@ def main(argv=None):
     t.add_argument("--batch", type=int, default=8192)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--classes", default="all", choices=["all", "dynamic"],
+                   help="train on every sampled point or on the dynamic ones only (the points "
+                        "the prediction is applied to with classes=dynamic)")
     from . import pipeline as P
     e = sub.add_parser("eval")
     e.add_argument("--seeds", required=True)
