@@ -689,11 +689,11 @@ def time_to_psnr_leg(params, views, images, pruned):
     return out
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if there is none or the kernel's source changed since."""
+def profiled_field(path, field):
+    """A machine-read field of a committed rocprofv3 summary, or None if there
+    is none or the profiled kernel's source changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_scene_960x540_traffic.md")
+    path = os.path.join(ROOT, "profiles", path)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -702,12 +702,17 @@ def profiled_traffic(kernel):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     src = fields.get("kernel_source")
-    if not src or "traffic_bytes_per_launch" not in fields:
+    if not src or field not in fields:
         return None
     digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
     if digest != fields.get("kernel_source_sha256_16"):
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[field])
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary (or None)."""
+    return profiled_field(f"{kernel}_scene_960x540_traffic.md", "traffic_bytes_per_launch")
 
 
 def run_batched(args, dev, region):
@@ -808,6 +813,19 @@ def roofline_for(kernel, ms, n, pairs, counts, hw):
             flops = FLOPS_EVAL * counts["evaluated_to_last"] + FLOPS_BLEND_BWD * counts["blends"]
         achieved = flops / s / 1e12
         traffic = profiled_traffic(kernel)
+        # the issue-rate view: the kernel's VALU instructions per launch
+        # (committed SQ-counter summary of the same kernel source, scene
+        # state) over the SIMDs' wave64 issue capacity in the measured time
+        # (1,024 SIMDs, 4 cycles per wave64 instruction, 2.4 GHz)
+        valu = (profiled_field("render_scene_960x540_valu_lds.md", f"{kernel}_valu_instructions_per_launch")
+                if hw == 960 * 540 else None)
+        issue = None
+        if valu is not None:
+            issue = {"valu_instructions": round(valu),
+                     "issue_frac": round(valu * 4 / (1024 * 2.4e9 * s), 4),
+                     "lane_instructions_per_evaluation": round(
+                         valu * 64 / (counts["evaluated_to_last"] if kernel == "render_bwd"
+                                      else counts["evaluated"]), 1)}
         return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
                 "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
@@ -815,7 +833,8 @@ def roofline_for(kernel, ms, n, pairs, counts, hw):
                 "frac_published": round(achieved / ALU_PEAK_PUBLISHED_TFLOPS, 4),
                 "flops_per_launch": round(flops),
                 "traffic": None if traffic is None else round(traffic),
-                "traffic_GBps": None if traffic is None else round(traffic / s / 1e9, 1)}
+                "traffic_GBps": None if traffic is None else round(traffic / s / 1e9, 1),
+                "valu_issue": issue}
     bytes_per = {
         "preprocess": 80.0 * n + 68.0 * n,
         "bin_sort": 40.0 * pairs + 64.0 * n,
