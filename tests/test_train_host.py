@@ -39,3 +39,29 @@ def test_to_iso_takes_the_tied_rows():
     assert torch.all(q[4] == -4.0) and torch.all(q[5] == -1.5)
     assert torch.all(q[6:9] == 0.0)
     assert torch.all(q[9] == 0.3) and torch.all(q[10:13] == 0.25)
+
+
+def test_stated_constants():
+    """The constants the paper states (Sec. 4.1): position learning rate 1e-5;
+    Lite prunes static and dynamic points with lambda 4, Full static points
+    with lambda 1 and dynamic points not at all; both take the motion class
+    from the Otsu split and adaptive voxels."""
+    from paper_2510_01119_amd.scene import PRESETS
+    from paper_2510_01119_amd.train import LR_POSITION
+    assert LR_POSITION == 1e-5 and LR_DEFAULTS["mean_xyz"][0] == 1e-5
+    assert PRESETS["lite"]["lambda_static"] == 4.0 and PRESETS["lite"]["lambda_dynamic"] == 4.0
+    assert PRESETS["full"]["lambda_static"] == 1.0 and PRESETS["full"]["lambda_dynamic"] is None
+    for p in PRESETS.values():
+        assert p["motion"] == "otsu" and p["voxel"] == "adaptive"
+
+
+def test_sch_rates_and_groups():
+    """The SCH colour's Adam groups: the constant coefficient at the RGB rate
+    in colour units (the basis value Y_00 scales a coefficient's colour), the
+    higher ones 20 times slower."""
+    import math
+    y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+    assert np.isclose(LR_DEFAULTS["sch_dc"][0] * y00, LR_DEFAULTS["rgb"][0])
+    assert np.isclose(LR_DEFAULTS["sch_rest"][0] * 20.0, LR_DEFAULTS["sch_dc"][0])
+    cfg = adam_config(100, rows=["sch_dc"])
+    assert cfg.rows == 1 and np.isclose(cfg.lr0[0], LR_DEFAULTS["sch_dc"][0])
