@@ -225,8 +225,8 @@ def main():
                     help="save/load the synthesised scene here (e.g. /tmp/gs4d_scene.pt)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 (sharding the "
+                                   "step over GPUs by view is not implemented)"}))
         sys.exit(2)
 
     import torch

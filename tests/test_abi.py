@@ -21,7 +21,7 @@ def _declared():
 def lib():
     from paper_2510_01119_amd import gs4d
     if not os.path.exists(gs4d.LIB_PATH):
-        pytest.fail("libgs4d.so is not built (run __graft_entry__.build())")
+        pytest.fail("libgs4d.so is not built (run paper_2510_01119_amd/build.py)")
     return gs4d.lib()
 
 
