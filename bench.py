@@ -81,7 +81,9 @@ class ProfileRegion:
 
     def _sentinel(self):
         import torch
-        torch.cuda._sleep(64)
+        spin = getattr(torch.cuda, "_sleep", None)
+        if spin is not None:
+            spin(64)
         torch.cuda.synchronize()
 
     def __enter__(self):
