@@ -65,6 +65,8 @@ def pseudo_frame(j: int, frames: int) -> int:
     extension mirrors the sequence about its first and last frame, so frame
     -d is frame d and frame (F-1)+d is frame (F-1)-d."""
     F = frames
+    if F <= 1:
+        return 0          # a single frame mirrors onto itself
     while j < 0 or j > F - 1:
         j = -j if j < 0 else 2 * (F - 1) - j
     return j

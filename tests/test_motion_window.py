@@ -15,6 +15,10 @@ def test_pseudo_frame_mirrors_the_ends():
     assert [pseudo_frame(j, F) for j in range(F, F + 3)] == [4, 3, 2]
     # a window wider than the sequence folds back in
     assert pseudo_frame(-7, 4) == 1 and pseudo_frame(9, 4) == 3
+    # one frame: every slot mirrors onto it (it shows no motion against itself)
+    assert pseudo_frame(-1, 1) == 0 and pseudo_frame(2, 1) == 0
+    s = torch.rand((1, 3, 3), generator=torch.Generator().manual_seed(2))
+    assert torch.all(motion_probability(s, 2, 0.3, True) == 0)
 
 
 def test_window_without_noise():
