@@ -840,6 +840,16 @@ def roofline_for(kernel, ms, n, pairs, counts, hw):
                      "lane_instructions_per_evaluation": round(
                          valu * 64 / (counts["evaluated_to_last"] if kernel == "render_bwd"
                                       else counts["evaluated"]), 1)}
+        # LDS against its peak: the kernel's LDS wave instructions per launch
+        # (committed counter summary) over one per compute unit per cycle
+        lds_n = (profiled_field("render_scene_960x540_lds.md", f"{kernel}_lds_instructions_per_launch")
+                 if hw == 960 * 540 else None)
+        lds = None
+        if lds_n is not None:
+            lds = {"lds_instructions": round(lds_n),
+                   "issue_frac": round(lds_n / (256 * 2.4e9 * s), 4),
+                   "bank_conflict_share": profiled_field("render_scene_960x540_lds.md",
+                                                         f"{kernel}_lds_conflict_share")}
         return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
                 "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
@@ -848,7 +858,7 @@ def roofline_for(kernel, ms, n, pairs, counts, hw):
                 "flops_per_launch": round(flops),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_GBps": None if traffic is None else round(traffic / s / 1e9, 1),
-                "valu_issue": issue}
+                "valu_issue": issue, "lds": lds}
     bytes_per = {
         "preprocess": 80.0 * n + 68.0 * n,
         "bin_sort": 40.0 * pairs + 64.0 * n,
