@@ -200,11 +200,17 @@ int gs4d_bin_sort_noalloc(const float *rec, const int32_t *rect, const int32_t *
  *   GS4D_BIN_PRESORT   sort the items by depth on the device first, emit in
  *                      that order, then sort on the tile bits (suits tiles of
  *                      tens of thousands of pairs)
- *   GS4D_BIN_AUTO      per tile while pair_capacity <= 4096 * tiles, else
- *                      presort (the default) */
+ *   GS4D_BIN_COUNT     count the pairs per (tile, block of Gaussians), scan
+ *                      the counts, write every pair straight into its tile,
+ *                      then the per-tile depth sort (four launches; for up
+ *                      to 8192 tiles per view, else as GS4D_BIN_PER_TILE)
+ *   GS4D_BIN_AUTO      while pair_capacity <= 4096 * tiles: counting where
+ *                      it applies, else per tile; above that presort (the
+ *                      default) */
 #define GS4D_BIN_AUTO 0
 #define GS4D_BIN_PER_TILE 1
 #define GS4D_BIN_PRESORT 2
+#define GS4D_BIN_COUNT 3
 int gs4d_set_bin_strategy(int32_t strategy);
 
 /* Render options.  Zero-initialise and set what is needed. */

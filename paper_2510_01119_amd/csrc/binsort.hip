@@ -4,8 +4,13 @@
 // tile, as (key, value) = ((global tile << 32) | bits(FP32 depth), Gaussian)
 // sorted ascending by (key, value).
 //
-// Work plan (one GPU, no host synchronisation), per tile (the default while
-// tiles hold up to a few thousand pairs):
+// Counting (the default while tiles hold up to a few thousand pairs and a
+// view has at most 8,192 tiles): per-(tile, block of Gaussians) pair counts,
+// their scan, every pair written straight into its tile, then the per-tile
+// depth sort of step 5 below, which also puts equal depths in Gaussian
+// order -- four launches; see "counting strategy" further down.
+//
+// Per-tile radix (for larger tile grids):
 //   1. device-wide exclusive scan of tiles-touched over the (view, Gaussian)
 //      items -> each item's first pair slot, the pair count P and the
 //      capacity flag (on device).
@@ -636,12 +641,13 @@ __global__ void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *
 }
 
 // ---------------------------------------------------------------- per-tile depth order
-// After the stable tile sort a tile's pairs sit in Gaussian order; one
-// workgroup per tile sorts them stably on the 32 depth bits (LSD, 8-bit
-// digits), giving the ascending (depth bits, Gaussian) order inside the
-// tile.  A tile of at most SEG_CAP pairs is sorted in registers and LDS; a
-// longer one passes through global memory SEG_CAP pairs at a time, with the
-// spare pair buffer as the other side of each pass.  A digit pass in which
+// One workgroup per tile sorts its pairs stably on the 32 depth bits (LSD,
+// 8-bit digits); runs of equal depth bits are then put in Gaussian order
+// (the pairs may arrive in any order), giving the ascending (depth bits,
+// Gaussian) order inside the tile.  A tile of at most SEG_CAP pairs is
+// sorted in registers and LDS; a longer one passes through global memory
+// SEG_CAP pairs at a time, with the spare pair buffer as the other side of
+// each pass.  A digit pass in which
 // every pair has the same digit leaves the order as it is and is skipped.
 //
 // Pair layout inside a chunk of R * 256 pairs: wave w owns pairs
@@ -653,6 +659,7 @@ constexpr int SEG_THREADS = 256;
 constexpr int SEG_WAVES = SEG_THREADS / 64;
 constexpr int SEG_ITEMS = 8;
 constexpr int SEG_CAP = SEG_THREADS * SEG_ITEMS;
+constexpr int SEG_RUN = 32;   // longest run of equal keys put in order in place
 
 struct SegShared {
     uint32_t key[SEG_CAP];
@@ -661,6 +668,7 @@ struct SegShared {
     uint32_t base[256];                // long tiles: start of each digit's next run
     uint32_t kmin[SEG_WAVES], kmax[SEG_WAVES];
     int skip;
+    int ties;   // equal depth keys seen in the tile
 };
 
 template <int CTRL, int ROW_MASK, bool MAX>
@@ -784,10 +792,13 @@ __device__ __forceinline__ void seg_store(uint64_t *keys, uint32_t *vals, uint64
     }
 }
 
-// a tile longer than SEG_CAP: four passes through global memory
-__device__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
-                               uint32_t *__restrict__ vals, uint64_t *__restrict__ spill,
-                               int64_t start, int len, uint64_t tile_hi) {
+// Four 8-bit passes through global memory for a tile longer than SEG_CAP,
+// keyed on the depth bits or (BY_VALUE) on the Gaussian index; the pairs
+// start and end in the output arrays.
+template <bool BY_VALUE>
+__device__ __forceinline__ void long_tile_passes(SegShared &sh, uint64_t *__restrict__ keys,
+                                 uint32_t *__restrict__ vals, uint64_t *__restrict__ spill,
+                                 int64_t start, int len, uint64_t tile_hi) {
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     bool in_spill = false;
     uint32_t k[SEG_ITEMS], v[SEG_ITEMS], rank[SEG_ITEMS];
@@ -799,7 +810,7 @@ __device__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
         for (int e = t; e < len; e += SEG_THREADS) {
             uint32_t ke, ve;
             seg_load(keys, vals, spill, in_spill, start + e, ke, ve);
-            atomicAdd(&sh.base[(ke >> shift) & 0xFFu], 1u);
+            atomicAdd(&sh.base[((BY_VALUE ? ve : ke) >> shift) & 0xFFu], 1u);
         }
         __syncthreads();
         if (w == 0) {
@@ -818,10 +829,14 @@ __device__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
 #pragma unroll
             for (int i = 0; i < SEG_ITEMS; ++i) {
                 const int e = c0 + (w * SEG_ITEMS + i) * 64 + l;
-                if (e < len) seg_load(keys, vals, spill, in_spill, start + e, k[i], v[i]);
-                else k[i] = 0;
+                if (e < len) {
+                    seg_load(keys, vals, spill, in_spill, start + e, k[i], v[i]);
+                } else {
+                    k[i] = 0;
+                    v[i] = 0;
+                }
             }
-            rank_items(k, rank, SEG_ITEMS, c0, len, shift, 8, c);
+            rank_items(BY_VALUE ? v : k, rank, SEG_ITEMS, c0, len, shift, 8, c);
             __syncthreads();
             // digit t: starts of its run in each wave of this chunk; the next
             // chunk's counters are cleared
@@ -842,7 +857,8 @@ __device__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
             for (int i = 0; i < SEG_ITEMS; ++i) {
                 const int e = c0 + (w * SEG_ITEMS + i) * 64 + l;
                 if (e < len) {
-                    const uint32_t pos = c[w][(k[i] >> shift) & 0xFFu] + rank[i];
+                    const uint32_t d = ((BY_VALUE ? v[i] : k[i]) >> shift) & 0xFFu;
+                    const uint32_t pos = c[w][d] + rank[i];
                     seg_store(keys, vals, spill, !in_spill, start + pos, tile_hi, k[i], v[i]);
                 }
             }
@@ -858,69 +874,45 @@ __device__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
             seg_store(keys, vals, spill, false, start + e, tile_hi, ke, ve);
         }
     }
+    __syncthreads();
 }
 
-// six waves per SIMD (80 VGPRs, a few spilled in the long-tile path): the
-// batched set's 16k tiles run in fewer rounds of workgroups
-__global__ void __launch_bounds__(SEG_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
-tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                       const int2 *__restrict__ ranges, uint64_t *__restrict__ spill) {
-    __shared__ SegShared sh;
-    const int2 r = ranges[blockIdx.x];
-    const int len = r.y - r.x;
-    if (len <= 1) return;
-    const int64_t start = r.x;
-    const uint64_t tile_hi = (uint64_t)blockIdx.x << 32;
-    if (len > SEG_CAP) {
-        long_tile_sort(sh, keys, vals, spill, start, len, tile_hi);
-        return;
-    }
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const int R = (len + SEG_THREADS - 1) / SEG_THREADS;   // items per lane, <= SEG_ITEMS
-    uint32_t k[SEG_ITEMS], v[SEG_ITEMS], rank[SEG_ITEMS];
-    uint32_t lo = 0xFFFFFFFFu, hi = 0;
-#pragma unroll
-    for (int i = 0; i < SEG_ITEMS; ++i) {
-        const int e = (w * R + i) * 64 + l;
-        k[i] = 0;
-        v[i] = 0;
-        if (i < R && e < len) {
-            k[i] = (uint32_t)keys[start + e];
-            v[i] = vals[start + e];
-            lo = k[i] < lo ? k[i] : lo;
-            hi = k[i] > hi ? k[i] : hi;
-        }
-    }
-    // The tile's keys lie in [kmin, kmax]: sorting k - kmin on its
-    // bit_width(kmax - kmin) low bits gives the same order in fewer digit
-    // bits (depths inside one tile span a narrow range).
-    lo = wave_extreme<false>(lo);
-    hi = wave_extreme<true>(hi);
-    if (l == 0) {
-        sh.kmin[w] = lo;
-        sh.kmax[w] = hi;
-    }
-    for (int i = t; i < 2 * SEG_WAVES * 256; i += SEG_THREADS) (&sh.cnt[0][0][0])[i] = 0;
+// a long tile: sorted on the depth bits; where equal depths remain, sorted
+// again on (Gaussian, then depth), so that equal depths end up in Gaussian
+// order whatever order the pairs arrived in
+__device__ __forceinline__ void long_tile_sort(SegShared &sh, uint64_t *__restrict__ keys,
+                               uint32_t *__restrict__ vals, uint64_t *__restrict__ spill,
+                               int64_t start, int len, uint64_t tile_hi) {
+    long_tile_passes<false>(sh, keys, vals, spill, start, len, tile_hi);
+    bool tie = false;
+    for (int e = threadIdx.x + 1; e < len; e += SEG_THREADS)
+        tie |= (uint32_t)keys[start + e] == (uint32_t)keys[start + e - 1];
+    if (__ballot(tie) != 0 && (threadIdx.x & 63) == 0) sh.ties = 1;
     __syncthreads();
-    uint32_t kmin = sh.kmin[0], kmax = sh.kmax[0];
-#pragma unroll
-    for (int ww = 1; ww < SEG_WAVES; ++ww) {
-        kmin = sh.kmin[ww] < kmin ? sh.kmin[ww] : kmin;
-        kmax = sh.kmax[ww] > kmax ? sh.kmax[ww] : kmax;
-    }
-    const int bits = kmax == kmin ? 0 : 32 - __builtin_clz(kmax - kmin);
-#pragma unroll
-    for (int i = 0; i < SEG_ITEMS; ++i) k[i] -= kmin;
-    for (int p = 0; 8 * p < bits; ++p) {
+    if (!sh.ties) return;
+    long_tile_passes<true>(sh, keys, vals, spill, start, len, tile_hi);
+    long_tile_passes<false>(sh, keys, vals, spill, start, len, tile_hi);
+}
+
+// One stable LSD sort of a short tile held in registers (item i of lane l
+// of wave w: pair (w*R + i)*64 + l) on the `bits` low bits of key[], with
+// pay[] carried along; the counter set `par & 1` is zero on entry.  Returns
+// the counter parity for the next sort.
+__device__ __forceinline__ int seg_lsd(SegShared &sh, uint32_t (&key)[SEG_ITEMS],
+                                       uint32_t (&pay)[SEG_ITEMS], int R, int len, int bits,
+                                       int par, bool &tie) {
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    uint32_t rank[SEG_ITEMS];
+    for (int p = 0; 8 * p < bits; ++p, ++par) {
         const int shift = 8 * p;
         const int nbits = bits - shift < 8 ? bits - shift : 8;
-        uint32_t (*c)[256] = sh.cnt[p & 1];
-        rank_items(k, rank, R, 0, len, shift, nbits, c);
+        uint32_t (*c)[256] = sh.cnt[par & 1];
+        rank_items(key, rank, R, 0, len, shift, nbits, c);
         __syncthreads();
         // wave 0 turns the counts into starts; the next pass's counters are
         // cleared meanwhile
 #pragma unroll
-        for (int ww = 0; ww < SEG_WAVES; ++ww) sh.cnt[(p + 1) & 1][ww][t] = 0;
+        for (int ww = 0; ww < SEG_WAVES; ++ww) sh.cnt[(par + 1) & 1][ww][t] = 0;
         if (w == 0) {
             uint32_t tot[4], st[4];
 #pragma unroll
@@ -949,29 +941,510 @@ tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
 #pragma unroll
         for (int i = 0; i < SEG_ITEMS; ++i) {
             if (i < R && (w * R + i) * 64 + l < len) {
-                const uint32_t pos = c[w][(k[i] >> shift) & 0xFFu] + rank[i];
-                sh.key[pos] = k[i];
-                sh.val[pos] = v[i];
+                const uint32_t pos = c[w][(key[i] >> shift) & 0xFFu] + rank[i];
+                sh.key[pos] = key[i];
+                sh.val[pos] = pay[i];
             }
         }
         __syncthreads();
+        // read back in sorted order; `tie`: this thread's pair equals the one
+        // before it (the last pass that moved the pairs decides)
+        tie = false;
 #pragma unroll
         for (int i = 0; i < SEG_ITEMS; ++i) {
             const int e = (w * R + i) * 64 + l;
             if (i < R && e < len) {
-                k[i] = sh.key[e];
-                v[i] = sh.val[e];
+                key[i] = sh.key[e];
+                pay[i] = sh.val[e];
+                tie |= e >= 1 && sh.key[e - 1] == key[i];
             }
         }
     }
+    return par;
+}
+
+// minimum of lo and maximum of hi over the block (every thread passes its
+// values; all get the results); earlier readers of kmin / kmax must be done
+__device__ __forceinline__ void block_min_max(SegShared &sh, uint32_t &lo, uint32_t &hi) {
+    const int w = threadIdx.x >> 6;
+    lo = wave_extreme<false>(lo);
+    hi = wave_extreme<true>(hi);
+    if ((threadIdx.x & 63) == 0) {
+        sh.kmin[w] = lo;
+        sh.kmax[w] = hi;
+    }
+    __syncthreads();
+    lo = sh.kmin[0];
+    hi = sh.kmax[0];
+#pragma unroll
+    for (int ww = 1; ww < SEG_WAVES; ++ww) {
+        lo = sh.kmin[ww] < lo ? sh.kmin[ww] : lo;
+        hi = sh.kmax[ww] > hi ? sh.kmax[ww] : hi;
+    }
+}
+
+// six waves per SIMD (80 VGPRs, a few spilled in the long-tile path): the
+// batched set's 16k tiles run in fewer rounds of workgroups
+__global__ void __launch_bounds__(SEG_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
+tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                       const int2 *__restrict__ ranges, uint64_t *__restrict__ spill) {
+    __shared__ SegShared sh;
+    const int2 r = ranges[blockIdx.x];
+    const int len = r.y - r.x;
+    if (len <= 1) return;
+    const int64_t start = r.x;
+    const uint64_t tile_hi = (uint64_t)blockIdx.x << 32;
+    if (threadIdx.x == 0) sh.ties = 0;
+    if (len > SEG_CAP) {
+        long_tile_sort(sh, keys, vals, spill, start, len, tile_hi);
+        return;
+    }
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int R = (len + SEG_THREADS - 1) / SEG_THREADS;   // items per lane, <= SEG_ITEMS
+    uint32_t k[SEG_ITEMS], v[SEG_ITEMS];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0;
+#pragma unroll
+    for (int i = 0; i < SEG_ITEMS; ++i) {
+        const int e = (w * R + i) * 64 + l;
+        k[i] = 0;
+        v[i] = 0;
+        if (i < R && e < len) {
+            k[i] = (uint32_t)keys[start + e];
+            v[i] = vals[start + e];
+            lo = k[i] < lo ? k[i] : lo;
+            hi = k[i] > hi ? k[i] : hi;
+        }
+    }
+    for (int i = t; i < 2 * SEG_WAVES * 256; i += SEG_THREADS) (&sh.cnt[0][0][0])[i] = 0;
+    // The tile's keys lie in [kmin, kmax]: sorting k - kmin on its
+    // bit_width(kmax - kmin) low bits gives the same order in fewer digit
+    // bits (depths inside one tile span a narrow range).
+    block_min_max(sh, lo, hi);
+    const uint32_t kmin = lo, kmax = hi;
+    const int bits = kmax == kmin ? 0 : 32 - __builtin_clz(kmax - kmin);
+#pragma unroll
+    for (int i = 0; i < SEG_ITEMS; ++i) k[i] -= kmin;
+    // all keys equal (bits 0): every pair ties
+    bool tie = bits == 0;
+    int par = seg_lsd(sh, k, v, R, len, bits, 0, tie);
+    // Equal depths: their pairs may have arrived in any order and must end
+    // in Gaussian order.  A run of at most SEG_RUN equal keys is put in order
+    // in place (each pair's place in its run = run start + the number of its
+    // run's values below its own); a tile with a longer run is sorted again,
+    // on the Gaussian index (minus its minimum) first and on the depth after.
+    if (__syncthreads_or(tie)) {
+#pragma unroll
+        for (int i = 0; i < SEG_ITEMS; ++i) {
+            const int e = (w * R + i) * 64 + l;
+            if (i < R && e < len) {
+                sh.key[e] = k[i];
+                sh.val[e] = v[i];
+            }
+        }
+        __syncthreads();
+        // the counters are free now: they take the values of the runs in
+        // their new order
+        uint32_t *perm = &sh.cnt[0][0][0];
+        uint32_t moved = 0;   // bit i: item i is in a run, its value at perm[e]
+        bool long_run = false;
+#pragma unroll
+        for (int i = 0; i < SEG_ITEMS; ++i) {
+            const int e = (w * R + i) * 64 + l;
+            if (i < R && e < len) {
+                const bool in_run = (e >= 1 && sh.key[e - 1] == k[i]) ||
+                                    (e + 1 < len && sh.key[e + 1] == k[i]);
+                if (in_run) {
+                    int s0 = e, s1 = e;
+                    while (s0 > 0 && e - s0 < SEG_RUN && sh.key[s0 - 1] == k[i]) --s0;
+                    while (s1 + 1 < len && s1 - e < SEG_RUN && sh.key[s1 + 1] == k[i]) ++s1;
+                    if (s1 - s0 + 1 > SEG_RUN) {
+                        long_run = true;
+                    } else {
+                        int below = 0;
+                        for (int j = s0; j <= s1; ++j) below += sh.val[j] < v[i] ? 1 : 0;
+                        perm[s0 + below] = v[i];
+                        moved |= 1u << i;
+                    }
+                }
+            }
+        }
+        if (__syncthreads_or(long_run)) {
+            for (int i = t; i < 2 * SEG_WAVES * 256; i += SEG_THREADS) (&sh.cnt[0][0][0])[i] = 0;
+            uint32_t vlo = 0xFFFFFFFFu, vhi = 0;
+#pragma unroll
+            for (int i = 0; i < SEG_ITEMS; ++i) {
+                if (i < R && (w * R + i) * 64 + l < len) {
+                    vlo = v[i] < vlo ? v[i] : vlo;
+                    vhi = v[i] > vhi ? v[i] : vhi;
+                }
+            }
+            block_min_max(sh, vlo, vhi);
+            const uint32_t vmin = vlo, vmax = vhi;
+            const int vbits = vmax == vmin ? 0 : 32 - __builtin_clz(vmax - vmin);
+#pragma unroll
+            for (int i = 0; i < SEG_ITEMS; ++i) v[i] -= vmin;
+            bool unused = false;
+            par = seg_lsd(sh, v, k, R, len, vbits, par, unused);
+#pragma unroll
+            for (int i = 0; i < SEG_ITEMS; ++i) v[i] += vmin;
+            seg_lsd(sh, k, v, R, len, bits, par, unused);
+        } else {
+#pragma unroll
+            for (int i = 0; i < SEG_ITEMS; ++i)
+                if ((moved >> i) & 1u) v[i] = perm[(w * R + i) * 64 + l];
+        }
+    }
+    // out through LDS in a loop of its own (the load addresses need not
+    // stay live across the sort)
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < SEG_ITEMS; ++i) {
         const int e = (w * R + i) * 64 + l;
         if (i < R && e < len) {
-            keys[start + e] = tile_hi | (k[i] + kmin);
-            vals[start + e] = v[i];
+            sh.key[e] = k[i];
+            sh.val[e] = v[i];
         }
     }
+    __syncthreads();
+    for (int e = t; e < len; e += SEG_THREADS) {
+        keys[start + e] = tile_hi | (sh.key[e] + kmin);
+        vals[start + e] = sh.val[e];
+    }
+}
+
+// ---------------------------------------------------------------- counting strategy
+// Binning without a sort on the tile bits.  The items of one view are cut
+// into blocks of CT_THREADS * ipt; with hist[T][e] the number of pairs of
+// block e in global tile T:
+//   1. ct_count_kernel: each block counts its pairs per tile in LDS and
+//      writes its column of hist.
+//   2. ct_scan_kernel: one wave per tile turns its row of hist into
+//      exclusive prefixes and writes the row total.
+//   3. ct_emit_kernel: each block scans the row totals of its view into the
+//      tiles' first slots (adding the pairs of earlier views), walks its
+//      pairs again and writes each to its tile's next slot (a per-tile LDS
+//      cursor started at tile start + hist prefix); block 0 of each view
+//      writes that view's ranges, the first block the pair count and the
+//      capacity flag.
+//   4. tile_depth_sort_kernel orders each tile by (depth bits, Gaussian).
+// Inside a tile the pairs of a block arrive in no fixed order; the depth
+// sort resolves equal depths by the Gaussian index, so the output is the
+// same (key, value) order as the other strategies, bit for bit.
+//
+// Launch: a 1-D grid of n_views * nbp blocks (nbp = blocks per view rounded
+// up to a multiple of 8; the extra blocks hold no items).  Workgroups go to
+// the 8 XCDs in turn, so block b is given column (b % 8) * (grid / 8) + b / 8:
+// neighbouring columns of hist -- one cache line of a row -- are written and
+// read by blocks of one XCD, whose L2 merges them.
+constexpr int CT_THREADS = 512;
+constexpr int CT_WAVES = CT_THREADS / 64;
+constexpr int CT_MAX_TPV = 8192;         // tiles per view held as LDS counters
+constexpr int CT_MAX_IPT = 128;          // items per thread and block
+constexpr int64_t CT_TARGET_BLOCKS = 320;
+constexpr int CT_SCAN_LOADS = 16;
+constexpr int CT_LOADS = 8;
+constexpr int CT_XCDS = 8;
+
+// (view, column) of block b of a grid of nb blocks (nb a multiple of 8)
+__device__ __forceinline__ void ct_block(int64_t nbp, int64_t &vi, int64_t &e) {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t c = (b % CT_XCDS) * (nb / CT_XCDS) + b / CT_XCDS;
+    vi = c / nbp;
+    e = c - vi * nbp;
+}
+
+// exclusive prefix sum over the block; *total gets the block's sum
+__device__ __forceinline__ int64_t ct_block_scan(int64_t x, int64_t *total) {
+    __shared__ int64_t ws[CT_WAVES];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    int64_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(incl, off, 64);
+        if (l >= off) incl += y;
+    }
+    if (l == 63) ws[w] = incl;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < CT_WAVES; ++k) {
+        if (k < w) off += ws[k];
+        tot += ws[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - x;
+}
+
+// The tiles of one wave's items, one pair per lane and step.  The wave's
+// pairs are numbered in lane order (item j's from the exclusive prefix of
+// the counts over lanes < j on); at step C lane l takes pair C + l, owned by
+// the highest lane whose first pair is at or before it (found as in
+// emit_wave_pairs).  Every lane calls f(active, src, tile) at every step:
+// src is the owning lane, tile the tile's index inside the view.
+template <class F>
+__device__ __forceinline__ void wave_tiles(bool valid, int32_t cnt, int4 r, int32_t tiles_x,
+                                           int32_t *mark, F &&f) {
+    const int lane = threadIdx.x & 63;
+    valid = valid && cnt > 0;
+    const uint32_t c = valid ? (uint32_t)cnt : 0u;
+    const uint32_t incl = wave_incl_scan(c);
+    const int32_t off = (int32_t)(incl - c);
+    const int32_t total = __builtin_amdgcn_readlane((int)incl, 63);
+    for (int32_t C = 0; C < total; C += 64) {
+        const int32_t rel = off - C;
+        if (valid && rel >= 0 && rel < 64) mark[rel] = lane;
+        __builtin_amdgcn_wave_barrier();
+        int own = mark[lane];
+        __builtin_amdgcn_wave_barrier();
+        mark[lane] = -1;
+        const uint64_t before = __ballot(valid && rel < 0);
+        const int carry = before ? 63 - __builtin_clzll(before) : -1;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(own, d, 64);
+            if (lane >= d) own = max(own, y);
+        }
+        own = max(own, carry);
+        const int src = own < 0 ? 0 : own;
+        const int32_t ooff = __shfl(off, src, 64);
+        const int x0 = __shfl(r.x, src, 64), y0 = __shfl(r.y, src, 64);
+        const int w = __shfl(r.z, src, 64) - x0;
+        const int32_t slot = C + lane;
+        const bool active = own >= 0 && w > 0 && slot < total;
+        int tile = 0;
+        if (active) {
+            const int local = slot - ooff;
+            const int ty = local / w, tx = local - ty * w;
+            tile = (y0 + ty) * tiles_x + (x0 + tx);
+        }
+        f(active, src, tile);
+    }
+}
+
+__global__ void __launch_bounds__(CT_THREADS)
+ct_count_kernel(const int32_t *__restrict__ touched, const int4 *__restrict__ rect, int64_t n,
+                int32_t tiles_x, int32_t tpv, int32_t ipt, int64_t nbp,
+                uint32_t *__restrict__ hist) {
+    __shared__ uint32_t cnt[CT_MAX_TPV];
+    __shared__ int32_t mark[CT_WAVES][64];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    int64_t vi, e;
+    ct_block(nbp, vi, e);
+    for (int i = t; i < tpv; i += CT_THREADS) cnt[i] = 0;
+    mark[w][l] = -1;
+    __syncthreads();
+    for (int r = 0; r < ipt; ++r) {
+        const int64_t g = (e * ipt + r) * CT_THREADS + t;
+        int32_t c = 0;
+        int4 rc = make_int4(0, 0, 0, 0);
+        if (g < n) {
+            const int64_t o = vi * n + g;
+            c = touched[o];
+            if (c > 0) rc = rect[o];
+        }
+        wave_tiles(c > 0, c, rc, tiles_x, mark[w], [&](bool active, int, int tile) {
+            if (active && (unsigned)tile < (unsigned)tpv) atomicAdd(&cnt[tile], 1u);
+        });
+    }
+    __syncthreads();
+    for (int i = t; i < tpv; i += CT_THREADS) hist[(vi * tpv + i) * nbp + e] = cnt[i];
+}
+
+// grid ceil(n_tiles / CT_WAVES): wave w of block b scans tile CT_WAVES b + w
+__global__ void __launch_bounds__(CT_THREADS)
+ct_scan_kernel(uint32_t *__restrict__ hist, int64_t nbp, int64_t n_tiles,
+               uint32_t *__restrict__ row_total) {
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int64_t T = (int64_t)blockIdx.x * CT_WAVES + w;
+    if (T >= n_tiles) return;
+    uint32_t running = 0;
+    uint32_t *row = hist + T * nbp;
+    for (int64_t c0 = 0; c0 < nbp; c0 += 64 * CT_SCAN_LOADS) {
+        // clamped indexes: unconditional loads, all in flight together
+        uint32_t x[CT_SCAN_LOADS];
+#pragma unroll
+        for (int i = 0; i < CT_SCAN_LOADS; ++i) {
+            const int64_t idx = c0 + i * 64 + l;
+            x[i] = row[idx < nbp ? idx : nbp - 1];
+        }
+#pragma unroll
+        for (int i = 0; i < CT_SCAN_LOADS; ++i) {
+            if (c0 + i * 64 + l >= nbp) x[i] = 0u;
+            const uint32_t incl = wave_incl_scan(x[i]);
+            const int64_t idx = c0 + i * 64 + l;
+            if (idx < nbp) row[idx] = running + incl - x[i];
+            running += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        }
+    }
+    if (l == 0) row_total[T] = running;
+}
+
+// the grid of ct_count_kernel
+__global__ void __launch_bounds__(CT_THREADS)
+ct_emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
+               const int4 *__restrict__ rect, int64_t n, int32_t n_views, int32_t tiles_x,
+               int32_t tpv, int32_t ipt, int64_t nbp, const uint32_t *__restrict__ hist,
+               const uint32_t *__restrict__ row_total, int64_t capacity,
+               int64_t *__restrict__ n_pairs, int32_t *__restrict__ overflow,
+               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+               int2 *__restrict__ ranges) {
+    __shared__ uint32_t next[CT_MAX_TPV];
+    __shared__ int32_t mark[CT_WAVES][64];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    int64_t vi, e;
+    ct_block(nbp, vi, e);
+    const int64_t t0 = vi * tpv, n_tiles = (int64_t)n_views * tpv;
+    // this view's tiles: first slots inside the view (next[]) and its total;
+    // CT_LOADS loads per thread at a time, at clamped indexes so that all
+    // are in flight together
+    int64_t carry = 0;
+    for (int i0 = 0; i0 < tpv; i0 += CT_THREADS * CT_LOADS) {
+        const int b0 = i0 + t * CT_LOADS;   // CT_LOADS consecutive tiles per thread
+        uint32_t x[CT_LOADS];
+        int64_t sx = 0;
+#pragma unroll
+        for (int j = 0; j < CT_LOADS; ++j) x[j] = row_total[t0 + (b0 + j < tpv ? b0 + j : tpv - 1)];
+#pragma unroll
+        for (int j = 0; j < CT_LOADS; ++j) {
+            if (b0 + j >= tpv) x[j] = 0u;
+            sx += x[j];
+        }
+        int64_t tot;
+        int64_t run = carry + ct_block_scan(sx, &tot);
+#pragma unroll
+        for (int j = 0; j < CT_LOADS; ++j) {
+            if (b0 + j < tpv) next[b0 + j] = (uint32_t)run;
+            run += x[j];
+        }
+        carry += tot;
+    }
+    // pairs of the earlier views and of all views
+    int64_t before = 0, all = carry;
+    if (n_views > 1) {
+        int64_t sb = 0, sa = 0;
+        for (int64_t i0 = 0; i0 < n_tiles; i0 += (int64_t)CT_THREADS * CT_LOADS) {
+            uint32_t x[CT_LOADS];
+#pragma unroll
+            for (int j = 0; j < CT_LOADS; ++j) {
+                const int64_t i = i0 + (int64_t)j * CT_THREADS + t;
+                x[j] = row_total[i < n_tiles ? i : n_tiles - 1];
+            }
+#pragma unroll
+            for (int j = 0; j < CT_LOADS; ++j) {
+                const int64_t i = i0 + (int64_t)j * CT_THREADS + t;
+                if (i < t0) sb += x[j];
+                else if (i >= t0 + tpv && i < n_tiles) sa += x[j];
+            }
+        }
+        int64_t tb, ta;
+        ct_block_scan(sb, &tb);
+        ct_block_scan(sa, &ta);
+        before = tb;
+        all = tb + carry + ta;
+    }
+    const bool over = all > capacity;
+    if (vi == 0 && e == 0 && t == 0) {
+        *n_pairs = all;
+        *overflow = over ? 1 : 0;
+    }
+    __syncthreads();   // next[] complete
+    if (e == 0) {
+        // over capacity, every tile stays empty
+        for (int i0 = 0; i0 < tpv; i0 += CT_THREADS * CT_LOADS) {
+            uint32_t c[CT_LOADS];
+#pragma unroll
+            for (int j = 0; j < CT_LOADS; ++j) {
+                const int i = i0 + j * CT_THREADS + t;
+                c[j] = row_total[t0 + (i < tpv ? i : tpv - 1)];
+            }
+#pragma unroll
+            for (int j = 0; j < CT_LOADS; ++j) {
+                const int i = i0 + j * CT_THREADS + t;
+                if (i < tpv) {
+                    const int64_t s0 = before + next[i];
+                    const bool empty = over || c[j] == 0 || s0 + c[j] > capacity;
+                    ranges[t0 + i] = empty ? make_int2(0, 0) : make_int2((int)s0, (int)(s0 + c[j]));
+                }
+            }
+        }
+    }
+    if (over) return;
+    for (int i0 = 0; i0 < tpv; i0 += CT_THREADS * CT_LOADS) {
+        uint32_t h[CT_LOADS];
+#pragma unroll
+        for (int j = 0; j < CT_LOADS; ++j) {
+            const int i = i0 + j * CT_THREADS + t;
+            h[j] = hist[(t0 + (i < tpv ? i : tpv - 1)) * nbp + e];
+        }
+#pragma unroll
+        for (int j = 0; j < CT_LOADS; ++j) {
+            const int i = i0 + j * CT_THREADS + t;
+            if (i < tpv) next[i] += (uint32_t)before + h[j];
+        }
+    }
+    mark[w][l] = -1;
+    __syncthreads();
+    for (int r = 0; r < ipt; ++r) {
+        const int64_t g = (e * ipt + r) * CT_THREADS + t;
+        int32_t c = 0;
+        int4 rc = make_int4(0, 0, 0, 0);
+        uint32_t lo = 0;
+        if (g < n) {
+            const int64_t o = vi * n + g;
+            c = touched[o];
+            if (c > 0) {
+                rc = rect[o];
+                lo = __float_as_uint(rec[3 * o + 1].z);
+            }
+        }
+        wave_tiles(c > 0, c, rc, tiles_x, mark[w], [&](bool active, int src, int tile) {
+            const uint32_t olo = (uint32_t)__shfl((int)lo, src, 64);
+            const uint32_t og = (uint32_t)__shfl((int)(uint32_t)g, src, 64);
+            if (active && (unsigned)tile < (unsigned)tpv) {
+                const uint32_t pos = atomicAdd(&next[tile], 1u);
+                if ((int64_t)pos < capacity) {
+                    keys[pos] = ((uint64_t)(t0 + tile) << 32) | olo;
+                    vals[pos] = og;
+                }
+            }
+        });
+    }
+}
+
+// items per thread of the counting strategy: enough blocks to fill the
+// device while the block count stays near CT_TARGET_BLOCKS
+inline int ct_ipt(int64_t n, int32_t n_views) {
+    int ipt = 1;
+    while (ipt < CT_MAX_IPT &&
+           (int64_t)n_views * ((n + (int64_t)CT_THREADS * ipt - 1) / ((int64_t)CT_THREADS * ipt)) >
+               CT_TARGET_BLOCKS)
+        ipt *= 2;
+    return ipt;
+}
+
+struct CountPlan {
+    int ipt = 0;
+    int64_t nbp = 0;   // columns of hist per view (a multiple of CT_XCDS)
+    uint32_t *hist = nullptr, *row_total = nullptr;
+};
+
+// the counting strategy's buffers inside `bytes` of workspace at ws (false
+// if they do not fit with any block size)
+bool ct_plan(void *ws, size_t bytes, int64_t n, int32_t n_views, int64_t n_tiles, CountPlan *P) {
+    for (int ipt = ct_ipt(n, n_views); ipt <= CT_MAX_IPT; ipt *= 2) {
+        const int64_t nbv = (n + (int64_t)CT_THREADS * ipt - 1) / ((int64_t)CT_THREADS * ipt);
+        const int64_t nbp = ((nbv > 0 ? nbv : 1) + CT_XCDS - 1) / CT_XCDS * CT_XCDS;
+        Carve c(ws, bytes);
+        P->hist = c.take<uint32_t>((size_t)(n_tiles * nbp));
+        P->row_total = c.take<uint32_t>((size_t)n_tiles);
+        if (c.ok()) {
+            P->ipt = ipt;
+            P->nbp = nbp;
+            return true;
+        }
+    }
+    return false;
 }
 
 inline unsigned grid_for(int64_t count, int threads) {
@@ -1120,9 +1593,14 @@ struct BinLayout {
     uint64_t *pk;                       // alternate pair buffers
     uint32_t *pv;
     void *radix_ws;
+    size_t ct_bytes;                    // bytes from ik0 on free for the counting strategy
 };
 
-BinLayout carve_bin(void *ws, int64_t m, int64_t cap, size_t *used) {
+// The counting strategy reuses the span from ik0 to the end of ct_room (the
+// item buffers it does not need) for its per-block tile counts; ct_room
+// alone holds them for the smallest grid (CT_XCDS columns per view) at the
+// largest tile grid.
+BinLayout carve_bin(void *ws, int64_t m, int32_t n_views, int64_t cap, size_t *used) {
     Carve c(ws, ~size_t(0));
     BinLayout L;
     const size_t mm = (size_t)(m > 0 ? m : 1);
@@ -1133,6 +1611,8 @@ BinLayout carve_bin(void *ws, int64_t m, int64_t cap, size_t *used) {
     L.offs = c.take<int32_t>(mm);
     L.scan_ws = c.take<char>(scan_workspace_size(m));
     L.total = c.take<int64_t>(1);
+    c.take<char>((size_t)(n_views > 0 ? n_views : 1) * CT_MAX_TPV * (4 * CT_XCDS + 4) + 1024);
+    L.ct_bytes = c.used;
     L.pk = c.take<uint64_t>((size_t)(cap > 0 ? cap : 1));
     L.pv = c.take<uint32_t>((size_t)(cap > 0 ? cap : 1));
     L.radix_ws = c.take<char>(radix_workspace_size(m > cap ? m : cap));
@@ -1158,15 +1638,15 @@ using namespace gs4d;
 
 extern "C" int gs4d_set_bin_strategy(int32_t strategy) {
     GS4D_REQUIRE(strategy == GS4D_BIN_AUTO || strategy == GS4D_BIN_PER_TILE ||
-                     strategy == GS4D_BIN_PRESORT,
-                 "gs4d_set_bin_strategy: strategy must be 0, 1 or 2");
+                     strategy == GS4D_BIN_PRESORT || strategy == GS4D_BIN_COUNT,
+                 "gs4d_set_bin_strategy: strategy must be 0, 1, 2 or 3");
     g_bin_strategy = strategy;
     return GS4D_OK;
 }
 
 extern "C" size_t gs4d_bin_sort_workspace_size(int64_t n, int32_t n_views, int64_t pair_capacity) {
     size_t used = 0;
-    carve_bin(nullptr, n * (int64_t)(n_views > 0 ? n_views : 1), pair_capacity, &used);
+    carve_bin(nullptr, n * (int64_t)(n_views > 0 ? n_views : 1), n_views, pair_capacity, &used);
     return used + 256;
 }
 
@@ -1190,7 +1670,7 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
                  ws_bytes, need);
     hipStream_t st = as_stream(stream);
     size_t used = 0;
-    BinLayout L = carve_bin(ws, m, pair_capacity, &used);
+    BinLayout L = carve_bin(ws, m, n_views, pair_capacity, &used);
     const int64_t n_tiles = (int64_t)vp.tiles_per_view * n_views;
 
     if (m == 0) {
@@ -1212,8 +1692,31 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
     // through global memory).  Automatic choice from the pair capacity per
     // tile, known on the host.
     const bool per_tile = g_bin_strategy == GS4D_BIN_PER_TILE ||
+                          g_bin_strategy == GS4D_BIN_COUNT ||
                           (g_bin_strategy == GS4D_BIN_AUTO &&
                            pair_capacity <= (int64_t)BIN_PER_TILE_MAX_MEAN * n_tiles);
+    // Counting: fewest launches; where it applies (tiles per view held in
+    // LDS) it is the per-tile default.
+    CountPlan cp;
+    if (per_tile && g_bin_strategy != GS4D_BIN_PER_TILE && vp.tiles_per_view <= CT_MAX_TPV &&
+        ct_plan(ws, L.ct_bytes, n, n_views, n_tiles, &cp)) {
+        const unsigned grid = (unsigned)(cp.nbp * n_views);
+        ct_count_kernel<<<grid, CT_THREADS, 0, st>>>(touched, reinterpret_cast<const int4 *>(rect),
+                                                     n, vp.tiles_x, vp.tiles_per_view, cp.ipt,
+                                                     cp.nbp, cp.hist);
+        ct_scan_kernel<<<grid_for(n_tiles, CT_WAVES), CT_THREADS, 0, st>>>(cp.hist, cp.nbp, n_tiles,
+                                                                          cp.row_total);
+        ct_emit_kernel<<<grid, CT_THREADS, 0, st>>>(
+            reinterpret_cast<const float4 *>(rec), touched, reinterpret_cast<const int4 *>(rect), n,
+            n_views, vp.tiles_x, vp.tiles_per_view, cp.ipt, cp.nbp, cp.hist, cp.row_total,
+            pair_capacity, n_pairs, overflow, keys, vals, reinterpret_cast<int2 *>(ranges));
+        GS4D_LAUNCH_CHECK("count binning");
+        if (pair_capacity == 0) return GS4D_OK;
+        tile_depth_sort_kernel<<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
+            keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk);
+        GS4D_LAUNCH_CHECK("tile depth sort");
+        return GS4D_OK;
+    }
     int alt = 0;
     if (per_tile) {
         // pair offsets of the items, pair count and capacity flag

@@ -345,12 +345,12 @@ def gs4d_otsu_mask(prob, threshold, mask, ws, stream=None):
                                 ws.numel(), _stream(stream)), "gs4d_otsu_mask")
 
 
-BIN_AUTO, BIN_PER_TILE, BIN_PRESORT = 0, 1, 2
+BIN_AUTO, BIN_PER_TILE, BIN_PRESORT, BIN_COUNT = 0, 1, 2, 3
 
 
 def gs4d_set_bin_strategy(strategy):
     """Binning strategy of gs4d_bin_sort (process-wide): BIN_AUTO,
-    BIN_PER_TILE or BIN_PRESORT; the output is the same."""
+    BIN_PER_TILE, BIN_PRESORT or BIN_COUNT; the output is the same."""
     _check(lib().gs4d_set_bin_strategy(int(strategy)), "gs4d_set_bin_strategy")
 
 

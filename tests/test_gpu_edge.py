@@ -7,10 +7,12 @@ finite differences.
 * GS4DRasterize under torch.autograd matches gs4d_render_bwd;
 * gradients against central differences (h = 1e-3) of the oracle's FP64
   forward on 64 random parameters;
-* the binning's corner cases against the oracle's, bit for bit, under both
-  strategies (per-tile depth sort, device-wide depth presort): equal depths
-  (ties broken by Gaussian index), a tile of more than 2,048 pairs, tiles
-  whose keys are all equal.
+* the binning's corner cases against the oracle's, bit for bit, under every
+  strategy (counting, per-tile radix, device-wide depth presort): equal
+  depths (ties broken by Gaussian index), a tile of more than 2,048 pairs,
+  tiles whose keys are all equal;
+* tile grids at the counting strategy's limit of 8,192 tiles per view and
+  just above it (where the per-tile radix path takes over), bit for bit.
 """
 import numpy as np
 import pytest
@@ -189,7 +191,7 @@ def _depth_sort_corner_set(seed=11):
     return p.astype(np.float32)
 
 
-@pytest.mark.parametrize("strategy", [G.BIN_AUTO, G.BIN_PER_TILE, G.BIN_PRESORT])
+@pytest.mark.parametrize("strategy", [G.BIN_AUTO, G.BIN_PER_TILE, G.BIN_PRESORT, G.BIN_COUNT])
 def test_depth_sort_ties_long_and_equal_tiles(strategy):
     need_gpu()
     G.gs4d_set_bin_strategy(strategy)
@@ -217,3 +219,21 @@ def _depth_sort_case():
     assert np.array_equal(g["ranges"].reshape(-1, 2), ranges)
     assert np.array_equal(g["keys"], keys)
     assert np.array_equal(g["vals"], vals)
+
+
+@pytest.mark.parametrize("width,height", [(1920, 1088), (2048, 1088)])
+def test_tile_grid_at_the_counting_limit(width, height):
+    """120 x 68 = 8,160 tiles per view (counting strategy) and 128 x 68 =
+    8,704 (beyond its LDS counters: the per-tile radix path), two views
+    each: pairs, values and ranges bit for bit."""
+    need_gpu()
+    p = synth.small_set(3000, 8)
+    vs = np.stack([synth.front_view(width, height, 0.6 * width, 3.0, t) for t in (0.3, 0.7)])
+    r, _ = gpu_forward(p, vs)
+    g = to_np(r)
+    o = oracle.forward(p, vs, "f32")
+    assert (width // 16) * (height // 16) * 2 == g["ranges"].reshape(-1, 2).shape[0]
+    assert g["n_pairs"] == len(o["keys"]) > 3000
+    assert np.array_equal(g["keys"], o["keys"])
+    assert np.array_equal(g["vals"], o["vals"])
+    assert np.array_equal(g["ranges"], o["ranges"])

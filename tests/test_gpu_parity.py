@@ -15,6 +15,7 @@ import pytest
 import torch
 
 import oracle
+from paper_2510_01119_amd import gs4d as G
 from paper_2510_01119_amd import synth
 
 from gpu_helpers import check_gradients, check_image, decision_bounds, gpu_forward, need_gpu, to_np
@@ -60,6 +61,22 @@ def test_preprocess_bitexact(case):
 
 def test_binsort_bitexact(case):
     g, o = case["gpu"], case["ref"]
+    assert g["n_pairs"] == len(o["keys"])
+    assert np.array_equal(g["keys"], o["keys"])
+    assert np.array_equal(g["vals"], o["vals"])
+    assert np.array_equal(g["ranges"], o["ranges"])
+
+
+@pytest.mark.parametrize("strategy", [G.BIN_PER_TILE, G.BIN_PRESORT, G.BIN_COUNT])
+def test_binsort_strategies_bitexact(case, strategy):
+    """Every binning strategy gives the oracle's pairs, values and ranges."""
+    G.gs4d_set_bin_strategy(strategy)
+    try:
+        r, _ = gpu_forward(case["params"], case["views"])
+        g = to_np(r)
+    finally:
+        G.gs4d_set_bin_strategy(G.BIN_AUTO)
+    o = case["ref"]
     assert g["n_pairs"] == len(o["keys"])
     assert np.array_equal(g["keys"], o["keys"])
     assert np.array_equal(g["vals"], o["vals"])
