@@ -985,17 +985,42 @@ __device__ __forceinline__ void block_min_max(SegShared &sh, uint32_t &lo, uint3
 
 // six waves per SIMD (80 VGPRs, a few spilled in the long-tile path): the
 // batched set's 16k tiles run in fewer rounds of workgroups
+// Where the pairs' depth bits come from when only their values were written
+// (GATHER): item (view, g)'s word, view = tile / tiles_per_view.
+struct DepthSource {
+    const uint32_t *dbits = nullptr;   // [view][n] depth bits of the visible items
+    int64_t n = 0;
+    int32_t tiles_per_view = 1;
+};
+
+__device__ __forceinline__ uint32_t gathered_depth(const DepthSource &src, int64_t vi,
+                                                   uint32_t g) {
+    return src.dbits[vi * src.n + g];
+}
+
+template <bool GATHER>
 __global__ void __launch_bounds__(SEG_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
 tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                       const int2 *__restrict__ ranges, uint64_t *__restrict__ spill) {
+                       const int2 *__restrict__ ranges, uint64_t *__restrict__ spill,
+                       DepthSource src) {
     __shared__ SegShared sh;
     const int2 r = ranges[blockIdx.x];
     const int len = r.y - r.x;
-    if (len <= 1) return;
     const int64_t start = r.x;
     const uint64_t tile_hi = (uint64_t)blockIdx.x << 32;
+    const int64_t vi = GATHER ? (int64_t)blockIdx.x / src.tiles_per_view : 0;
+    if (len <= 0) return;
+    if (len == 1) {
+        if (GATHER && threadIdx.x == 0) keys[start] = tile_hi | gathered_depth(src, vi, vals[start]);
+        return;
+    }
     if (threadIdx.x == 0) sh.ties = 0;
     if (len > SEG_CAP) {
+        if (GATHER) {
+            for (int e = threadIdx.x; e < len; e += SEG_THREADS)
+                keys[start + e] = tile_hi | gathered_depth(src, vi, vals[start + e]);
+            __syncthreads();
+        }
         long_tile_sort(sh, keys, vals, spill, start, len, tile_hi);
         return;
     }
@@ -1009,8 +1034,8 @@ tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
         k[i] = 0;
         v[i] = 0;
         if (i < R && e < len) {
-            k[i] = (uint32_t)keys[start + e];
             v[i] = vals[start + e];
+            k[i] = GATHER ? gathered_depth(src, vi, v[i]) : (uint32_t)keys[start + e];
             lo = k[i] < lo ? k[i] : lo;
             hi = k[i] > hi ? k[i] : hi;
         }
@@ -1117,16 +1142,19 @@ tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
 // into blocks of CT_THREADS * ipt; with hist[T][e] the number of pairs of
 // block e in global tile T:
 //   1. ct_count_kernel: each block counts its pairs per tile in LDS and
-//      writes its column of hist.
+//      writes its column of hist, and the depth bits of its items into a
+//      compact array (one word per item).
 //   2. ct_scan_kernel: one wave per tile turns its row of hist into
 //      exclusive prefixes and writes the row total.
 //   3. ct_emit_kernel: each block scans the row totals of its view into the
 //      tiles' first slots (adding the pairs of earlier views), walks its
-//      pairs again and writes each to its tile's next slot (a per-tile LDS
-//      cursor started at tile start + hist prefix); block 0 of each view
-//      writes that view's ranges, the first block the pair count and the
-//      capacity flag.
-//   4. tile_depth_sort_kernel orders each tile by (depth bits, Gaussian).
+//      pairs again and writes each one's value (the Gaussian) to its tile's
+//      next slot (a per-tile LDS cursor started at tile start + hist
+//      prefix); block 0 of each view writes that view's ranges, the first
+//      block the pair count and the capacity flag.  Scattered stores bound
+//      this kernel, so the keys are left to step 4.
+//   4. tile_depth_sort_kernel reads each pair's depth bits from the compact
+//      array, orders the tile by (depth bits, Gaussian) and writes the keys.
 // Inside a tile the pairs of a block arrive in no fixed order; the depth
 // sort resolves equal depths by the Gaussian index, so the output is the
 // same (key, value) order as the other strategies, bit for bit.
@@ -1223,9 +1251,10 @@ __device__ __forceinline__ void wave_tiles(bool valid, int32_t cnt, int4 r, int3
 }
 
 __global__ void __launch_bounds__(CT_THREADS)
-ct_count_kernel(const int32_t *__restrict__ touched, const int4 *__restrict__ rect, int64_t n,
-                int32_t tiles_x, int32_t tpv, int32_t ipt, int64_t nbp,
-                uint32_t *__restrict__ hist) {
+ct_count_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
+                const int4 *__restrict__ rect, int64_t n, int32_t tiles_x, int32_t tpv,
+                int32_t ipt, int64_t nbp, uint32_t *__restrict__ hist,
+                uint32_t *__restrict__ dbits) {
     __shared__ uint32_t cnt[CT_MAX_TPV];
     __shared__ int32_t mark[CT_WAVES][64];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
@@ -1241,7 +1270,10 @@ ct_count_kernel(const int32_t *__restrict__ touched, const int4 *__restrict__ re
         if (g < n) {
             const int64_t o = vi * n + g;
             c = touched[o];
-            if (c > 0) rc = rect[o];
+            if (c > 0) {
+                rc = rect[o];
+                dbits[o] = __float_as_uint(rec[3 * o + 1].z);
+            }
         }
         wave_tiles(c > 0, c, rc, tiles_x, mark[w], [&](bool active, int, int tile) {
             if (active && (unsigned)tile < (unsigned)tpv) atomicAdd(&cnt[tile], 1u);
@@ -1282,13 +1314,11 @@ ct_scan_kernel(uint32_t *__restrict__ hist, int64_t nbp, int64_t n_tiles,
 
 // the grid of ct_count_kernel
 __global__ void __launch_bounds__(CT_THREADS)
-ct_emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touched,
-               const int4 *__restrict__ rect, int64_t n, int32_t n_views, int32_t tiles_x,
-               int32_t tpv, int32_t ipt, int64_t nbp, const uint32_t *__restrict__ hist,
-               const uint32_t *__restrict__ row_total, int64_t capacity,
-               int64_t *__restrict__ n_pairs, int32_t *__restrict__ overflow,
-               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-               int2 *__restrict__ ranges) {
+ct_emit_kernel(const int32_t *__restrict__ touched, const int4 *__restrict__ rect, int64_t n,
+               int32_t n_views, int32_t tiles_x, int32_t tpv, int32_t ipt, int64_t nbp,
+               const uint32_t *__restrict__ hist, const uint32_t *__restrict__ row_total,
+               int64_t capacity, int64_t *__restrict__ n_pairs, int32_t *__restrict__ overflow,
+               uint32_t *__restrict__ vals, int2 *__restrict__ ranges) {
     __shared__ uint32_t next[CT_MAX_TPV];
     __shared__ int32_t mark[CT_WAVES][64];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
@@ -1389,24 +1419,16 @@ ct_emit_kernel(const float4 *__restrict__ rec, const int32_t *__restrict__ touch
         const int64_t g = (e * ipt + r) * CT_THREADS + t;
         int32_t c = 0;
         int4 rc = make_int4(0, 0, 0, 0);
-        uint32_t lo = 0;
         if (g < n) {
             const int64_t o = vi * n + g;
             c = touched[o];
-            if (c > 0) {
-                rc = rect[o];
-                lo = __float_as_uint(rec[3 * o + 1].z);
-            }
+            if (c > 0) rc = rect[o];
         }
         wave_tiles(c > 0, c, rc, tiles_x, mark[w], [&](bool active, int src, int tile) {
-            const uint32_t olo = (uint32_t)__shfl((int)lo, src, 64);
             const uint32_t og = (uint32_t)__shfl((int)(uint32_t)g, src, 64);
             if (active && (unsigned)tile < (unsigned)tpv) {
                 const uint32_t pos = atomicAdd(&next[tile], 1u);
-                if ((int64_t)pos < capacity) {
-                    keys[pos] = ((uint64_t)(t0 + tile) << 32) | olo;
-                    vals[pos] = og;
-                }
+                if ((int64_t)pos < capacity) vals[pos] = og;
             }
         });
     }
@@ -1426,7 +1448,7 @@ inline int ct_ipt(int64_t n, int32_t n_views) {
 struct CountPlan {
     int ipt = 0;
     int64_t nbp = 0;   // columns of hist per view (a multiple of CT_XCDS)
-    uint32_t *hist = nullptr, *row_total = nullptr;
+    uint32_t *hist = nullptr, *row_total = nullptr, *dbits = nullptr;
 };
 
 // the counting strategy's buffers inside `bytes` of workspace at ws (false
@@ -1436,6 +1458,7 @@ bool ct_plan(void *ws, size_t bytes, int64_t n, int32_t n_views, int64_t n_tiles
         const int64_t nbv = (n + (int64_t)CT_THREADS * ipt - 1) / ((int64_t)CT_THREADS * ipt);
         const int64_t nbp = ((nbv > 0 ? nbv : 1) + CT_XCDS - 1) / CT_XCDS * CT_XCDS;
         Carve c(ws, bytes);
+        P->dbits = c.take<uint32_t>((size_t)(n * n_views > 0 ? n * n_views : 1));
         P->hist = c.take<uint32_t>((size_t)(n_tiles * nbp));
         P->row_total = c.take<uint32_t>((size_t)n_tiles);
         if (c.ok()) {
@@ -1701,19 +1724,20 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
     if (per_tile && g_bin_strategy != GS4D_BIN_PER_TILE && vp.tiles_per_view <= CT_MAX_TPV &&
         ct_plan(ws, L.ct_bytes, n, n_views, n_tiles, &cp)) {
         const unsigned grid = (unsigned)(cp.nbp * n_views);
-        ct_count_kernel<<<grid, CT_THREADS, 0, st>>>(touched, reinterpret_cast<const int4 *>(rect),
-                                                     n, vp.tiles_x, vp.tiles_per_view, cp.ipt,
-                                                     cp.nbp, cp.hist);
+        ct_count_kernel<<<grid, CT_THREADS, 0, st>>>(
+            reinterpret_cast<const float4 *>(rec), touched, reinterpret_cast<const int4 *>(rect), n,
+            vp.tiles_x, vp.tiles_per_view, cp.ipt, cp.nbp, cp.hist, cp.dbits);
         ct_scan_kernel<<<grid_for(n_tiles, CT_WAVES), CT_THREADS, 0, st>>>(cp.hist, cp.nbp, n_tiles,
                                                                           cp.row_total);
         ct_emit_kernel<<<grid, CT_THREADS, 0, st>>>(
-            reinterpret_cast<const float4 *>(rec), touched, reinterpret_cast<const int4 *>(rect), n,
-            n_views, vp.tiles_x, vp.tiles_per_view, cp.ipt, cp.nbp, cp.hist, cp.row_total,
-            pair_capacity, n_pairs, overflow, keys, vals, reinterpret_cast<int2 *>(ranges));
+            touched, reinterpret_cast<const int4 *>(rect), n, n_views, vp.tiles_x,
+            vp.tiles_per_view, cp.ipt, cp.nbp, cp.hist, cp.row_total, pair_capacity, n_pairs,
+            overflow, vals, reinterpret_cast<int2 *>(ranges));
         GS4D_LAUNCH_CHECK("count binning");
         if (pair_capacity == 0) return GS4D_OK;
-        tile_depth_sort_kernel<<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
-            keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk);
+        tile_depth_sort_kernel<true><<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
+            keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk,
+            DepthSource{cp.dbits, n, vp.tiles_per_view});
         GS4D_LAUNCH_CHECK("tile depth sort");
         return GS4D_OK;
     }
@@ -1759,8 +1783,8 @@ extern "C" int gs4d_bin_sort(const float *rec, const int32_t *rect, const int32_
     GS4D_LAUNCH_CHECK("ranges");
     if (per_tile) {
         // depth order inside each tile (the pair buffer L.pk is free again)
-        tile_depth_sort_kernel<<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
-            keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk);
+        tile_depth_sort_kernel<false><<<(unsigned)n_tiles, SEG_THREADS, 0, st>>>(
+            keys, vals, reinterpret_cast<const int2 *>(ranges), L.pk, DepthSource{});
         GS4D_LAUNCH_CHECK("tile depth sort");
     }
     return GS4D_OK;
