@@ -101,12 +101,22 @@ def test_invalid_arguments_rejected_on_host(lib):
     st = lib.gs4d_preprocess_sch_bwd(d, d, 10, ctypes.byref(sch), views, 1, d, d, d, None, None)
     assert st == -1 and b"null" in lib.gs4d_last_error()
     assert lib.gs4d_sch_from_rgb(d, 5, 10, ctypes.byref(sch), d, None) == -1
+    # binning strategies 0-3 (auto, per-tile radix, presort, counting)
+    for strategy in (gs4d.BIN_COUNT, gs4d.BIN_PRESORT, gs4d.BIN_PER_TILE, gs4d.BIN_AUTO):
+        assert lib.gs4d_set_bin_strategy(strategy) == 0
+    assert lib.gs4d_set_bin_strategy(4) == -1 and b"strategy" in lib.gs4d_last_error()
+    assert lib.gs4d_set_bin_strategy(-1) == -1
+    assert lib.gs4d_set_bin_strategy(gs4d.BIN_AUTO) == 0
 
 
 def test_workspace_queries(lib):
     a = lib.gs4d_bin_sort_workspace_size(1000, 1, 10000)
     b = lib.gs4d_bin_sort_workspace_size(1000, 1, 100000)
     assert b > a > 0
+    # room for the counting strategy's per-tile counts: 8 columns of 4 B plus
+    # a row total for each of up to 8,192 tiles per view
+    for views in (1, 3):
+        assert lib.gs4d_bin_sort_workspace_size(10, views, 0) >= views * 8192 * 36
     assert lib.gs4d_render_bwd_workspace_size(1000, 2) >= 1000 * 2 * 9 * 4
     assert lib.gs4d_grid_prune_workspace_size(10 ** 6, 5) > 10 ** 6 * 24
     assert lib.gs4d_ssim_workspace_size(1, 3, 64, 64) >= 3 * 3 * 64 * 64 * 4
