@@ -221,11 +221,11 @@ def _depth_sort_case():
     assert np.array_equal(g["vals"], vals)
 
 
-@pytest.mark.parametrize("width,height", [(1920, 1088), (2048, 1088)])
+@pytest.mark.parametrize("width,height", [(2048, 1024), (2048, 1088)])
 def test_tile_grid_at_the_counting_limit(width, height):
-    """120 x 68 = 8,160 tiles per view (counting strategy) and 128 x 68 =
-    8,704 (beyond its LDS counters: the per-tile radix path), two views
-    each: pairs, values and ranges bit for bit."""
+    """128 x 64 = 8,192 tiles per view (the counting strategy's largest
+    grid) and 128 x 68 = 8,704 (beyond its LDS counters: the per-tile radix
+    path), two views each: pairs, values and ranges bit for bit."""
     need_gpu()
     p = synth.small_set(3000, 8)
     vs = np.stack([synth.front_view(width, height, 0.6 * width, 3.0, t) for t in (0.3, 0.7)])
