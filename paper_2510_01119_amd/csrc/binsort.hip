@@ -1008,7 +1008,7 @@ tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
     const int len = r.y - r.x;
     const int64_t start = r.x;
     const uint64_t tile_hi = (uint64_t)blockIdx.x << 32;
-    const int64_t vi = GATHER ? (int64_t)blockIdx.x / src.tiles_per_view : 0;
+    const int64_t vi = GATHER ? (int64_t)(blockIdx.x / (uint32_t)src.tiles_per_view) : 0;
     if (len <= 0) return;
     if (len == 1) {
         if (GATHER && threadIdx.x == 0) keys[start] = tile_hi | gathered_depth(src, vi, vals[start]);
