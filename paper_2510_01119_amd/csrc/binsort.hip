@@ -983,8 +983,10 @@ __device__ __forceinline__ void block_min_max(SegShared &sh, uint32_t &lo, uint3
     }
 }
 
-// six waves per SIMD (80 VGPRs, a few spilled in the long-tile path): the
-// batched set's 16k tiles run in fewer rounds of workgroups
+// five waves per SIMD (96 VGPRs): with the run fix for equal depths the
+// kernel needs more than the 80 VGPRs of six waves, and spilling there wrote
+// about 70 B of scratch per lane back to HBM (27 MB per launch at scene
+// scale); the batched set's 16k tiles took 162 us at six waves, 152 at five
 // Where the pairs' depth bits come from when only their values were written
 // (GATHER): item (view, g)'s word, view = tile / tiles_per_view.
 struct DepthSource {
@@ -999,7 +1001,7 @@ __device__ __forceinline__ uint32_t gathered_depth(const DepthSource &src, int64
 }
 
 template <bool GATHER>
-__global__ void __launch_bounds__(SEG_THREADS) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(SEG_THREADS) __attribute__((amdgpu_waves_per_eu(5)))
 tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                        const int2 *__restrict__ ranges, uint64_t *__restrict__ spill,
                        DepthSource src) {
@@ -1119,21 +1121,13 @@ tile_depth_sort_kernel(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                 if ((moved >> i) & 1u) v[i] = perm[(w * R + i) * 64 + l];
         }
     }
-    // out through LDS in a loop of its own (the load addresses need not
-    // stay live across the sort)
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < SEG_ITEMS; ++i) {
         const int e = (w * R + i) * 64 + l;
         if (i < R && e < len) {
-            sh.key[e] = k[i];
-            sh.val[e] = v[i];
+            keys[start + e] = tile_hi | (k[i] + kmin);
+            vals[start + e] = v[i];
         }
-    }
-    __syncthreads();
-    for (int e = t; e < len; e += SEG_THREADS) {
-        keys[start + e] = tile_hi | (sh.key[e] + kmin);
-        vals[start + e] = sh.val[e];
     }
 }
 
