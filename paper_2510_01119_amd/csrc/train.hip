@@ -132,6 +132,20 @@ __device__ __forceinline__ void load_row14(const float *row, int c0, float v[16]
     }
 }
 
+// The tile (column, row, plane) of this block.  Workgroups go to the 8 XCDs
+// in turn; block b takes tile (b mod 8) (nb8 / 8) + b div 8 of the first
+// nb8 = 8 floor(nb / 8) tiles in row-major order (the rest stay in place), so
+// that each XCD's blocks cover a run of neighbouring tiles and find the
+// halo rows they share in its own L2.
+__device__ __forceinline__ uint3 ssim_tile() {
+    const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+    const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned nb8 = nb & ~7u;
+    const unsigned t = b < nb8 ? (b & 7u) * (nb8 >> 3) + (b >> 3) : b;
+    const unsigned q = t / gridDim.x;
+    return make_uint3(t - q * gridDim.x, q % gridDim.y, q / gridDim.y);
+}
+
 // Forward: per pixel SSIM and its partial derivatives with respect to the
 // windowed statistics mu_x, E[x^2], E[xy] (written to three maps).  Each
 // block stores its SSIM sum (and, when fused, its L1 sum) as a partial;
@@ -149,8 +163,9 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
     // (E[y^2], E[xy]) -- 30.9 KB of LDS in all
     __shared__ __align__(16) float hs[3][SS_E][SS_T];
     const int t = threadIdx.x;
-    const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
-    const int64_t plane = (int64_t)blockIdx.z * h * w;
+    const uint3 tb = ssim_tile();
+    const int ox = tb.x * SS_T - SS_R, oy = tb.y * SS_T - SS_R;
+    const int64_t plane = (int64_t)tb.z * h * w;
     for (int i = t; i < SS_E * SS_EP; i += 256) {
         const int r = i / SS_EP, c = i - r * SS_EP;
         const int gy = oy + r, gx = ox + c;
@@ -211,10 +226,10 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
         }
     }
     float sv = 0.0f, lv = 0.0f;
-    const int gx = blockIdx.x * SS_T + c;
+    const int gx = tb.x * SS_T + c;
 #pragma unroll
     for (int o = 0; o < SS_O; ++o) {
-        const int r = r0 + o, gy = blockIdx.y * SS_T + r;
+        const int r = r0 + o, gy = tb.y * SS_T + r;
         if (gx < w && gy < h) {
             const float mx = m[0][o], my = m[1][o];
             const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
@@ -239,7 +254,7 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
             }
         }
     }
-    const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned bid = tb.x + gridDim.x * (tb.y + gridDim.y * tb.z);
     sv = block_sum(sv);
     if (part_l1) lv = block_sum(lv);
     if (t == 0) {
@@ -301,8 +316,9 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
     __shared__ __align__(16) float sp[SS_E][SS_EP];
     __shared__ __align__(16) float hs[SS_E][SS_T];
     const int t = threadIdx.x;
-    const int ox = blockIdx.x * SS_T - SS_R, oy = blockIdx.y * SS_T - SS_R;
-    const int64_t plane = (int64_t)blockIdx.z * h * w;
+    const uint3 tb = ssim_tile();
+    const int ox = tb.x * SS_T - SS_R, oy = tb.y * SS_T - SS_R;
+    const int64_t plane = (int64_t)tb.z * h * w;
     const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
     auto fetch = [&](const float *Pj, float (&pre)[SS_PER]) {
 #pragma unroll
@@ -353,10 +369,10 @@ ssim_bwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
         // the next map's row pass writes hs only after the barrier that
         // follows its staging, so this column pass needs none of its own
     }
-    const int gx = blockIdx.x * SS_T + c;
+    const int gx = tb.x * SS_T + c;
 #pragma unroll
     for (int o = 0; o < SS_O; ++o) {
-        const int gy = blockIdx.y * SS_T + r0 + o;
+        const int gy = tb.y * SS_T + r0 + o;
         if (gx < w && gy < h) {
             const int64_t po = plane + (int64_t)gy * w + gx;
             const float x = X[po], y = Y[po];
