@@ -166,12 +166,32 @@ ssim_fwd_kernel(const float *__restrict__ X, const float *__restrict__ Y, int h,
     const uint3 tb = ssim_tile();
     const int ox = tb.x * SS_T - SS_R, oy = tb.y * SS_T - SS_R;
     const int64_t plane = (int64_t)tb.z * h * w;
-    for (int i = t; i < SS_E * SS_EP; i += 256) {
-        const int r = i / SS_EP, c = i - r * SS_EP;
-        const int gy = oy + r, gx = ox + c;
-        const bool in = c < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
-        sx[r][c] = in ? X[plane + (int64_t)gy * w + gx] : 0.0f;
-        sy[r][c] = in ? Y[plane + (int64_t)gy * w + gx] : 0.0f;
+    {
+        // every load issued before the first is used: outside the image (or
+        // in a row's padding) a load reads the plane's first pixel and its
+        // value is replaced by 0
+        constexpr int SS_LD = (SS_E * SS_EP + 255) / 256;
+        float xl[SS_LD], yl[SS_LD];
+        bool inl[SS_LD];
+#pragma unroll
+        for (int k = 0; k < SS_LD; ++k) {
+            const int i = t + 256 * k;
+            const int r = i / SS_EP, c = i - r * SS_EP;
+            const int gy = oy + r, gx = ox + c;
+            inl[k] = i < SS_E * SS_EP && c < SS_E && gx >= 0 && gx < w && gy >= 0 && gy < h;
+            const int64_t idx = inl[k] ? plane + (int64_t)gy * w + gx : plane;
+            xl[k] = X[idx];
+            yl[k] = Y[idx];
+        }
+#pragma unroll
+        for (int k = 0; k < SS_LD; ++k) {
+            const int i = t + 256 * k;
+            if (i < SS_E * SS_EP) {
+                const int r = i / SS_EP, c = i - r * SS_EP;
+                sx[r][c] = inl[k] ? xl[k] : 0.0f;
+                sy[r][c] = inl[k] ? yl[k] : 0.0f;
+            }
+        }
     }
     __syncthreads();
     const int c = t % SS_T, r0 = (t / SS_T) * SS_O;
